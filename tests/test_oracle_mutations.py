@@ -1,0 +1,77 @@
+"""Plant plausible mistakes in the oracle (on the CPU only) and check that the
+pins catch each one: the pins must not pass for a wrong oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import moff
+import tests.test_oracle_pins as pins
+
+_transform = moff.transform
+_products = moff.products
+_kernel_taps = moff.kernel_taps
+_grad = moff.grad_gains
+
+
+def _wrong_sign(a):
+    return np.fft.fft2(a, axes=(-2, -1))
+
+
+def _transposed(a):
+    return np.swapaxes(_transform(a), -1, -2)
+
+
+def _unscaled(a):
+    return np.fft.ifft2(a, axes=(-2, -1))
+
+
+def _xy_without_conj(F):
+    out = _products(F)
+    if F.shape[1] == 2:
+        out[:, 1] = F[:, 0] * F[:, 1]
+        out[:, 2] = np.conj(out[:, 1])
+    return out
+
+
+def _sigma_not_squared(X, Y, grid_n, support=3, sigma_cells=0.5):
+    ii, jj, w = _kernel_taps(X, Y, grid_n, support, sigma_cells)
+    d2 = (ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2
+    return ii, jj, np.exp(-d2 / (2.0 * sigma_cells))
+
+
+def _taps_rounded_down(X, Y, grid_n, support=3, sigma_cells=0.5):
+    """Nearest cell taken as floor(X) instead of floor(X + 1/2)."""
+    ii, jj, _ = _kernel_taps(X - 0.5, Y - 0.5, grid_n, support, sigma_cells)
+    d2 = (ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2
+    return ii, jj, np.exp(-d2 / (2.0 * sigma_cells ** 2))
+
+
+def _grad_half(*a, **k):
+    return 0.5 * _grad(*a, **k)
+
+
+MUTATIONS = {
+    "transform with the -i sign": ("transform", _wrong_sign,
+                                   [pins.test_p1_transform_sign_single_cell]),
+    "rows and columns swapped": ("transform", _transposed,
+                                 [lambda: pins.test_p2_plane_wave_lands_on_its_pixel(8, 0)]),
+    "transform normalised by 1/n_g": ("transform", _unscaled, [pins.test_p3_parseval]),
+    "XY without the conjugate": ("products", _xy_without_conj,
+                                 [lambda: pins.test_p5_fx_form_equals_moff(21, 32, 16, 2, 2, 6)]),
+    "kernel width not squared": ("kernel_taps", _sigma_not_squared,
+                                 [pins.test_kernel_weights_closed_form]),
+    "taps centred half a cell off": ("kernel_taps", _taps_rounded_down,
+                                     [pins.test_p2_zenith_closed_form_off_cell]),
+    "gradient without the factor 2": ("grad_gains", _grad_half,
+                                      [lambda: pins.test_p10_gradient_matches_finite_differences(1)]),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTATIONS))
+def test_pins_catch_planted_mistake(name, monkeypatch):
+    attr, fn, checks = MUTATIONS[name]
+    monkeypatch.setattr(moff, attr, fn)
+    monkeypatch.setattr(oracle, attr, fn)
+    for check in checks:
+        with pytest.raises(AssertionError):
+            check()

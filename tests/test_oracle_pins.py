@@ -1,0 +1,347 @@
+"""Pins of the FP64 oracle to facts that do not come from the oracle itself:
+hand-derived values, closed forms, the definition of the DFT evaluated by brute
+force, Parseval, the autocorrelation (van Cittert-Zernike) identity, the
+visibility (FX) form of the same image, symmetries and invariances.
+
+Each test names the part of the oracle a plausible mistake would break.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+E2 = np.exp(-2.0)       # Gaussian sigma = 0.5 cell, one cell away: exp(-1 / (2 * 0.25))
+E4 = np.exp(-4.0)
+
+
+def _rng(s):
+    return np.random.default_rng(s)
+
+
+# ------------------------------------------------------------------ O1
+def test_unpack_byte_table():
+    """High nibble = real, low nibble = imaginary, two's complement (hand table)."""
+    cases = {0x00: 0 + 0j, 0x7F: 7 - 1j, 0x80: -8 + 0j, 0xF8: -1 - 8j, 0x12: 1 + 2j,
+             0x9C: -7 - 4j, 0x08: 0 - 8j, 0x77: 7 + 7j, 0xFF: -1 - 1j, 0x88: -8 - 8j}
+    b = np.array(list(cases), dtype=np.uint8)
+    got = oracle.unpack_ci4(b)
+    assert np.array_equal(got, np.array(list(cases.values())))
+    allb = oracle.unpack_ci4(np.arange(256, dtype=np.uint8))
+    assert allb.real.min() == -8 and allb.real.max() == 7
+    assert allb.imag.min() == -8 and allb.imag.max() == 7
+    assert len(set(allb.tolist())) == 256
+
+
+def test_pack_roundtrip():
+    re = np.arange(-8, 8).repeat(16)
+    im = np.tile(np.arange(-8, 8), 16)
+    b = synth.pack_ci4(re, im)
+    e = oracle.unpack_ci4(b)
+    assert np.array_equal(e.real, re) and np.array_equal(e.imag, im)
+
+
+# ------------------------------------------------------------------ O3
+def test_geometry_centre_and_scale():
+    """lambda/2 cells: an antenna at +one cell east lands one column right of centre."""
+    f = np.array([50e6])
+    cell = oracle.C0 / 50e6 * 0.5
+    xy = np.array([[0.0, 0.0], [cell, 0.0], [0.0, -2 * cell]])
+    X, Y = oracle.antenna_cells(xy, f, 32)
+    assert np.allclose(X[0], [16, 17, 16], atol=1e-12)
+    assert np.allclose(Y[0], [16, 16, 14], atol=1e-12)
+
+
+def test_kernel_weights_closed_form():
+    """On a cell centre: 1, exp(-2), exp(-4); half-cell offsets round up."""
+    ii, jj, w = oracle.kernel_taps(np.array([[16.0]]), np.array([[10.0]]), 32)
+    expect = np.array([E4, E2, E4, E2, 1.0, E2, E4, E2, E4])
+    assert np.allclose(w[0, 0], expect, rtol=1e-14)
+    assert list(ii[0, 0]) == [15, 16, 17] * 3
+    assert list(jj[0, 0]) == [9] * 3 + [10] * 3 + [11] * 3
+    ii, jj, w = oracle.kernel_taps(np.array([[16.5]]), np.array([[10.0]]), 32)
+    assert list(ii[0, 0][:3]) == [16, 17, 18]
+    wx = np.array([np.exp(-0.5), np.exp(-0.5), np.exp(-4.5)])
+    wy = np.array([E2, 1.0, E2])
+    assert np.allclose(w[0, 0], np.outer(wy, wx).ravel(), rtol=1e-14)
+
+
+def test_offgrid_raises():
+    with pytest.raises(oracle.OffGridError):
+        oracle.kernel_taps(np.array([[0.2]]), np.array([[10.0]]), 32)
+    with pytest.raises(oracle.OffGridError):
+        oracle.kernel_taps(np.array([[30.6]]), np.array([[10.0]]), 32)
+    oracle.kernel_taps(np.array([[1.4]]), np.array([[30.4]]), 32)      # last legal cells
+
+
+# ------------------------------------------------------------------ P1
+@pytest.mark.parametrize("n", [8, 16, 32])
+def test_p1_transform_equals_direct_dft(n):
+    a = _rng(n).normal(size=(2, n, n)) + 1j * _rng(n + 1).normal(size=(2, n, n))
+    f = oracle.transform(a)
+    d = oracle.direct_dft(a)
+    assert np.linalg.norm(f - d) / np.linalg.norm(d) < 1e-12
+
+
+def test_p1_transform_sign_single_cell():
+    """A single unit cell at (j, i) = (0, 1): F[km, kl] = exp(+2 pi i kl / N)."""
+    n = 16
+    a = np.zeros((n, n), complex)
+    a[0, 1] = 1.0
+    f = oracle.transform(a)
+    k = np.arange(n)
+    assert np.allclose(f, np.exp(2j * np.pi * k / n)[None, :].repeat(n, 0), atol=1e-13)
+
+
+# ------------------------------------------------------------------ P2
+def _on_cell_plane_wave(n_ant, ql, qm, s, n_time=3, seed=0, gains=None):
+    """Antennas on whole cells of a 32 grid, a plane wave whose per-antenna phase
+    is a multiple of 90 degrees, so its int4 bytes are exact."""
+    N = 32
+    rng = _rng(seed)
+    cell = oracle.C0 / 50e6 * 0.5
+    cells = set()
+    while len(cells) < n_ant:
+        cells.add(tuple(rng.integers(-8, 9, size=2)))
+    cxy = np.array(sorted(cells), dtype=float)                  # cells rel. to centre
+    xy = cxy * cell
+    # exp(-2 pi i (u l0 + v m0)), u l0 = cx * ql / N with l0 = ql / (N du)
+    turns = -(cxy[:, 0] * ql + cxy[:, 1] * qm) / N              # multiples of 1/4
+    assert np.allclose(turns * 4, np.round(turns * 4))
+    ph = np.exp(2j * np.pi * turns)
+    e = s * ph
+    b = synth.pack_ci4(np.round(e.real), np.round(e.imag))
+    ef = np.broadcast_to(b[None, None, None, :], (n_time, 1, 1, n_ant)).copy()
+    g = np.ones((1, 1, n_ant), np.complex64) if gains is None else gains
+    return xy, np.array([50e6]), g, ef
+
+
+@pytest.mark.parametrize("ql,qm", [(8, 0), (0, -8), (-8, 8), (8, 8), (0, 0)])
+def test_p2_plane_wave_lands_on_its_pixel(ql, qm):
+    """Value at the predicted pixel = T |s|^2 A^2 B(k0)^2, where B is the hand-derived
+    transform of the 3x3 Gaussian (sigma 1/2 cell):
+    B(k) = (1 + 2 e^-2 cos(2 pi kl/N)) (1 + 2 e^-2 cos(2 pi km/N)); and the
+    image divided by B^2 peaks there.  Catches sign, orientation, shift, scale."""
+    N, A, T, s = 32, 24, 3, 3 + 1j
+    xy, f, g, ef = _on_cell_plane_wave(A, ql, qm, s, T)
+    img = oracle.image(xy, f, g, ef, N)[0, 0].real
+    k = np.arange(N) - N // 2                                    # shifted pixel order
+    b1 = 1 + 2 * E2 * np.cos(2 * np.pi * k / N)
+    B2 = np.outer(b1, b1) ** 2
+    row, col = qm + N // 2, ql + N // 2
+    expect = T * abs(s) ** 2 * A ** 2 * B2[row, col]
+    assert abs(img[row, col] - expect) / expect < 1e-12
+    q = np.unravel_index(np.argmax(img / B2), img.shape)
+    assert q == (row, col)
+
+
+def test_p2_zenith_closed_form_off_cell():
+    """Zenith source on arbitrary (off-cell) antennas: every antenna sees the same
+    integer sample s, so XX(zenith) = T |s|^2 |sum_a g_a sum_taps w_a|^2."""
+    rng = _rng(7)
+    A, N, T = 10, 32, 4
+    xy = rng.uniform(-9, 9, size=(A, 2))
+    f = np.array([50e6])
+    g = synth.random_gains(rng, (1, 1, A))
+    s = -5 + 2j
+    ef = np.full((T, 1, 1, A), synth.pack_ci4(np.array(s.real), np.array(s.imag)), np.uint8)
+    img = oracle.image(xy, f, g, ef, N)[0, 0]
+    cell = oracle.C0 / 50e6 * 0.5
+    X = xy[:, 0] / cell + N / 2
+    Y = xy[:, 1] / cell + N / 2
+    wsum = np.zeros(A)
+    for a in range(A):                       # the Gaussian's definition, per tap
+        i0, j0 = np.floor(X[a] + 0.5), np.floor(Y[a] + 0.5)
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                wsum[a] += np.exp(-2.0 * ((i0 + di - X[a]) ** 2 + (j0 + dj - Y[a]) ** 2))
+    expect = T * abs(s) ** 2 * abs(np.sum(g[0, 0].astype(complex) * wsum)) ** 2
+    assert abs(img[N // 2, N // 2].real - expect) / expect < 1e-12
+    assert abs(img[N // 2, N // 2].imag) < 1e-9 * expect
+
+
+# ------------------------------------------------------------------ P3
+def test_p3_parseval():
+    inp = synth.random_problem(11, 32, 12, 2, 2, 5, fill=0.4)
+    img = oracle.image_from(inp)
+    X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, 32)
+    ii, jj, w = oracle.kernel_taps(X, Y, 32)
+    e = oracle.unpack_ci4(inp.efield)
+    ng = 32 * 32
+    for c in range(2):
+        A = oracle.grid_efield(inp.gains[c].astype(complex)[None] * e[:, c], ii[c], jj[c], w[c], 32)
+        ax, ay = A[:, 0], A[:, 1]
+        pxx = ng * np.sum(np.abs(ax) ** 2)
+        pyy = ng * np.sum(np.abs(ay) ** 2)
+        pxy = ng * np.sum(ax * np.conj(ay))
+        assert abs(img[c, 0].sum() - pxx) / pxx < 1e-12
+        assert abs(img[c, 3].sum() - pyy) / pyy < 1e-12
+        assert abs(img[c, 1].sum() - pxy) / abs(pxy) < 1e-11
+        assert abs(img[c, 2].sum() - np.conj(pxy)) / abs(pxy) < 1e-11
+
+
+# ------------------------------------------------------------------ P4
+def test_p4_autocorrelation_identity():
+    """I_PQ(k) = sum_delta C_PQ(delta) e^{+2 pi i delta k / N}, C the circular
+    correlation of the gridded fields summed over time, by direct sums."""
+    N = 16
+    inp = synth.random_problem(12, N, 6, 1, 2, 3, fill=0.45)
+    img = np.fft.ifftshift(oracle.image_from(inp)[0], axes=(-2, -1))
+    X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
+    ii, jj, w = oracle.kernel_taps(X, Y, N)
+    e = oracle.unpack_ci4(inp.efield)
+    A = oracle.grid_efield(inp.gains[0].astype(complex)[None] * e[:, 0], ii[0], jj[0], w[0], N)
+    pairs = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    for n, (p, q) in enumerate(pairs):
+        C = np.zeros((N, N), complex)
+        for dy in range(N):
+            for dx in range(N):
+                shifted = np.roll(A[:, p], shift=(-dy, -dx), axis=(-2, -1))   # A_P(h + delta)
+                C[dy, dx] = np.sum(shifted * np.conj(A[:, q]))
+        I = oracle.direct_dft(C)
+        assert np.linalg.norm(I - img[n]) / np.linalg.norm(img[n]) < 1e-11
+
+
+# ------------------------------------------------------------------ P5
+@pytest.mark.parametrize("seed,N,A,C,P,T", [(21, 32, 16, 2, 2, 6), (22, 32, 9, 1, 1, 4),
+                                          (23, 16, 5, 3, 2, 2)])
+def test_p5_fx_form_equals_moff(seed, N, A, C, P, T):
+    """The MOFF image equals the visibility-based image (paper §2, Eq. (1) <-> (5))."""
+    inp = synth.random_problem(seed, N, A, C, P, T, fill=0.45)
+    img = oracle.image_from(inp)
+    fx = oracle.image_fx(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N)
+    assert np.linalg.norm(fx - img) / np.linalg.norm(img) < 1e-11
+
+
+# ------------------------------------------------------------------ P6
+def test_p6_linearity_and_single_antenna():
+    inp = synth.random_problem(31, 32, 8, 1, 2, 4)
+    img = oracle.image_from(inp)
+    s = 0.7 - 1.3j
+    img_s = oracle.image(inp.xy_m, inp.freq_hz, inp.gains.astype(complex) * s,
+                         inp.efield, 32)
+    assert np.allclose(img_s, abs(s) ** 2 * img, rtol=1e-13, atol=1e-9)
+    zero = np.zeros_like(inp.efield)
+    assert np.all(oracle.image(inp.xy_m, inp.freq_hz, inp.gains, zero, 32) == 0)
+    # single antenna: XX = sum_t |g e_t|^2 |B_a(k)|^2, B_a separable per axis
+    one = synth.random_problem(32, 32, 1, 1, 1, 3)
+    img1 = np.fft.ifftshift(oracle.image_from(one)[0, 0], axes=(-2, -1)).real
+    cell = oracle.C0 / one.freq_hz[0] * 0.5
+    X = one.xy_m[0, 0] / cell + 16
+    Y = one.xy_m[0, 1] / cell + 16
+    k = np.arange(32)
+
+    def axis_resp(x):
+        i0 = np.floor(x + 0.5)
+        return sum(np.exp(-2.0 * (i0 + d - x) ** 2) * np.exp(2j * np.pi * (i0 + d) * k / 32)
+                   for d in (-1, 0, 1))
+    e = oracle.unpack_ci4(one.efield[:, 0, 0, 0]) * complex(one.gains[0, 0, 0])
+    expect = np.sum(np.abs(e) ** 2) * np.outer(np.abs(axis_resp(Y)) ** 2, np.abs(axis_resp(X)) ** 2)
+    assert np.allclose(img1, expect, rtol=1e-12, atol=1e-12 * expect.max())
+
+
+# ------------------------------------------------------------------ P7, P9
+def test_p7_p9_symmetries_and_cauchy_schwarz():
+    inp = synth.random_problem(41, 32, 10, 2, 2, 5)
+    img = oracle.image_from(inp)
+    xx, xy, yx, yy = img[:, 0], img[:, 1], img[:, 2], img[:, 3]
+    assert np.all(xx.imag == 0) and np.all(yy.imag == 0)
+    assert np.all(xx.real >= 0) and np.all(yy.real >= 0)
+    assert np.array_equal(yx, np.conj(xy))
+    assert np.all(np.abs(xy) ** 2 <= xx.real * yy.real * (1 + 1e-12) + 1e-9)
+
+
+# ------------------------------------------------------------------ P8
+def test_p8_whole_cell_translation_invariance():
+    inp = synth.random_problem(51, 32, 10, 1, 2, 4, fill=0.35)
+    img = oracle.image_from(inp)
+    cell = oracle.C0 / inp.freq_hz[0] * 0.5
+    moved = inp.xy_m + np.array([3 * cell, -2 * cell])
+    img2 = oracle.image(moved, inp.freq_hz, inp.gains, inp.efield, 32)
+    assert np.linalg.norm(img2 - img) / np.linalg.norm(img) < 1e-12
+
+
+# ------------------------------------------------------------------ P12
+def test_p12_time_splitting():
+    inp = synth.random_problem(61, 32, 8, 2, 2, 9)
+    full = oracle.image_from(inp)
+    a = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield[:4], 32)
+    b = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield[4:], 32)
+    assert np.linalg.norm(a + b - full) / np.linalg.norm(full) < 1e-14
+
+
+# ------------------------------------------------------------------ P10, P11
+def _loss_setup(seed, N=32, A=8, C=2, P=2, T=3):
+    inp = synth.random_problem(seed, N, A, C, P, T, fill=0.4)
+    model = oracle.image_from(inp) * 0.0
+    rng = _rng(seed + 100)
+    model = model + rng.normal(size=model.shape) * 50.0      # any fixed M
+    g = inp.gains.astype(np.complex128)
+
+    def loss(gg):
+        return oracle.l2_loss(oracle.image(inp.xy_m, inp.freq_hz, gg, inp.efield, N), model)
+    return inp, model, g, loss
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_p10_gradient_matches_finite_differences(P):
+    inp, model, g, loss = _loss_setup(71 + P, P=P, A=6 if P == 2 else 8)
+    img = oracle.image(inp.xy_m, inp.freq_hz, g, inp.efield, 32)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(loss, g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_p10_gradient_of_cross_products_only():
+    """A loss on XY alone (XX, YY excluded) checks the h-terms of the chain."""
+    inp = synth.random_problem(81, 32, 5, 1, 2, 3, fill=0.4)
+    g = inp.gains.astype(np.complex128)
+    rng = _rng(5)
+    wxy = rng.normal(size=(1, 32, 32)) + 1j * rng.normal(size=(1, 32, 32))
+
+    def loss(gg):
+        im = oracle.image(inp.xy_m, inp.freq_hz, gg, inp.efield, 32)
+        return float(np.sum((np.conj(wxy) * im[:, 1]).real))
+    gam = np.zeros((1, 4, 32, 32), complex)
+    gam[:, 1] = wxy                     # dL/dRe(XY) + i dL/dIm(XY)
+    grad = oracle.grad_gains(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(loss, g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_p11_gradient_invariants():
+    inp, model, g, loss = _loss_setup(91, A=10)
+    img = oracle.image(inp.xy_m, inp.freq_hz, g, inp.efield, 32)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    # (i) a common phase per channel leaves every product unchanged
+    for c in range(g.shape[0]):
+        s = np.sum(np.conj(g[c]) * grad[c])
+        assert abs(s.imag) < 1e-10 * np.sum(np.abs(g[c] * grad[c]))
+    # (ii) degree-2 homogeneity: Re sum conj(g) grad = 2 sum Re(conj(Gamma) I)
+    lhs = np.sum(np.conj(g) * grad).real
+    rhs = 2.0 * np.sum((np.conj(gam) * img).real)
+    assert abs(lhs - rhs) / abs(rhs) < 1e-12
+
+
+# ------------------------------------------------------------------ generator
+def test_config2_generator_statistics():
+    inp = synth.config2(n_time=40, n_chan=3)
+    e = oracle.unpack_ci4(inp.efield)
+    clipped = np.mean((e.real == -8) | (e.real == 7) | (e.imag == -8) | (e.imag == 7))
+    assert clipped < 0.005
+    d = np.sqrt(((inp.xy_m[:, None] - inp.xy_m[None]) ** 2).sum(-1)) + np.eye(256) * 1e9
+    assert d.min() >= 4.5 - 1e-9
+    assert np.all(np.hypot(inp.xy_m[:, 0], inp.xy_m[:, 1]) <= 50.0)
+    oracle.kernel_taps(*oracle.antenna_cells(inp.xy_m, inp.freq_hz, 64), 64)   # on grid
+
+
+def test_cost_model_grid_scaling():
+    """n_g log2 n_g predicts x4.7 from 64^2 to 128^2 (paper §5.1)."""
+    r = (128 ** 2 * np.log2(128 ** 2)) / (64 ** 2 * np.log2(64 ** 2))
+    assert abs(r - 4.67) < 0.01
