@@ -1,0 +1,159 @@
+/*
+ * epic.h - C ABI of the MI355X (gfx950) MOFF direct imager.
+ *
+ * The library images channelised antenna E-fields the way the paper's EPIC
+ * imager does (Kent et al. 2019, "A Real-Time, All-Sky, High Time Resolution,
+ * Direct Imager for the Long Wavelength Array"):
+ *   - Sec. 3.2: 4+4-bit complex samples ordered [Time][Channel][Pol][Antenna]
+ *     are unpacked and multiplied by a per-antenna complex calibration factor
+ *     (cable delays appear as a phase of that factor);
+ *   - Sec. 2.1, Eq. (4)-(5): the calibrated point measurements are convolved
+ *     with an illumination kernel W and gridded on a regular aperture grid whose
+ *     spacing is a fixed fraction of the channel wavelength (half, Sec. 4.2);
+ *   - Sec. 2.1, Eq. (5) and Sec. 3.2: each gridded aperture is transformed with
+ *     an unnormalised 2-D DFT of positive exponent sign;
+ *   - Sec. 2.1 and Sec. 3.2: the instantaneous images are squared or cross
+ *     multiplied between polarisations (XX, XY, YX, YY) and summed over time.
+ *
+ * Conventions shared by every call
+ *   - Every pointer documented as "device" is memory on the context's GPU that
+ *     the caller owns; the library never frees or retains it after a call.
+ *     "host" pointers are read during the call only.
+ *   - complex64 = two interleaved float32 (re, im); complex128 = two
+ *     interleaved float64.
+ *   - Sample byte: high nibble = real part, low nibble = imaginary part, both
+ *     two's complement in [-8, 7] (0x7F = 7 - 1i, 0x80 = -8 + 0i).
+ *   - Grid: antenna a of channel c sits at cell coordinates
+ *     X = x_a / (lambda_c * cell_wavelengths) + N/2, same for Y with y_a;
+ *     lambda_c = 299792458 / freq_hz[c].  Its kernel taps are the K x K cells
+ *     centred on (floor(X + 1/2), floor(Y + 1/2)); the weight of tap (i, j) is
+ *     exp(-((i - X)^2 + (j - Y)^2) / (2 sigma^2)) (peak 1, not renormalised).
+ *   - Image: F[km][kl] = sum_{j,i} A[j][i] exp(+2 pi i (i kl + j km) / N),
+ *     A the gridded aperture (row j <-> y, column i <-> x).  Images are stored
+ *     fftshifted: pixel (row q_m, col q_l) holds k = (q - N/2) mod N, i.e.
+ *     direction l = (q_l - N/2) / (N * cell_wavelengths), same for m.
+ *   - Products: n_pol = 2 -> 4 products in the order XX, XY, YX, YY with
+ *     XY = F_X conj(F_Y), YX = F_Y conj(F_X); n_pol = 1 -> XX only.
+ *   - Calls are enqueued on the context's stream and return before the GPU has
+ *     finished; device faults surface at the caller's next synchronisation.
+ *     Arguments are validated before anything is enqueued: on any error the
+ *     outputs are untouched.  No call takes a lock; use one context per
+ *     stream or host thread.
+ *   - Results are deterministic: every reduction has a fixed order and no
+ *     floating-point atomics are used, so identical calls give identical bits.
+ */
+#ifndef EPIC_H
+#define EPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum epic_status {
+  EPIC_OK = 0,
+  EPIC_E_INVALID = 1,     /* null pointer, size out of range, non-finite geometry */
+  EPIC_E_DEVICE = 2,      /* the device is not gfx950, or a HIP runtime call failed */
+  EPIC_E_NOMEM = 3,       /* a device or host allocation failed */
+  EPIC_E_OFFGRID = 4,     /* a kernel tap of some antenna leaves the grid */
+  EPIC_E_STATE = 5,       /* antennas not set before an imaging call */
+  EPIC_E_LAUNCH = 6,      /* a kernel launch was rejected */
+  EPIC_E_UNSUPPORTED = 7  /* valid request outside what this build runs */
+} epic_status;
+
+/* epic_config.precision */
+enum { EPIC_FP32 = 0, EPIC_SPLIT_FP16 = 1, EPIC_SPLIT_BF16 = 2 };
+
+/* epic_config.flags */
+enum {
+  EPIC_FLAG_STAGED = 1,   /* one kernel per stage with FP32 intermediates in HBM
+                             (the plain comparator); default is the fused kernel */
+  EPIC_FLAG_TIMING = 2    /* record HIP events around the main kernel of each call */
+};
+
+typedef struct epic_config {
+  int32_t grid_n;              /* N: grid side; 32, 64 or 128 */
+  int32_t n_chan;              /* C >= 1 */
+  int32_t n_pol;               /* P: 1 or 2 */
+  int32_t n_ant;               /* A: 1 .. 4096 */
+  int32_t kernel_support;      /* K: odd, 1 .. 7 */
+  double kernel_sigma_cells;   /* Gaussian kernel width in cells, > 0 */
+  double cell_wavelengths;     /* grid spacing in wavelengths, > 0 (0.5 = lambda/2) */
+  int32_t precision;           /* EPIC_FP32, EPIC_SPLIT_FP16 or EPIC_SPLIT_BF16 */
+  int32_t flags;               /* EPIC_FLAG_* */
+} epic_config;
+
+typedef struct epic_ctx epic_ctx;
+
+/* Create a context on `device` (a HIP device ordinal).  All later work of the
+ * context is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream).
+ * The config is copied.  Allocates the library-owned tables and workspace.
+ * Errors: EPIC_E_INVALID (bad config or out == NULL), EPIC_E_DEVICE (not a
+ * gfx950 device), EPIC_E_NOMEM.  On error *out is set to NULL. */
+epic_status epic_init(const epic_config *cfg, int device, void *hip_stream,
+                      epic_ctx **out);
+
+/* Rebind the context to another stream (hipStream_t). */
+epic_status epic_set_stream(epic_ctx *ctx, void *hip_stream);
+
+/* Set the array geometry (Sec. 3.2 and Sec. 4.2: gridding at a fixed fraction
+ * of each channel's wavelength).  xy_m: host float64 [n_ant][2] (east, north)
+ * in metres; freq_hz: host float64 [n_chan].  Builds the per-channel kernel
+ * weights (in float64, rounded once to float32) and the gridding tables and
+ * uploads them before returning (synchronous).  May be called again.
+ * Errors: EPIC_E_INVALID (null, non-finite position, frequency not finite and
+ * positive), EPIC_E_OFFGRID (a tap outside [0, N) for some channel; the
+ * previous geometry, if any, stays in force), EPIC_E_NOMEM. */
+epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *freq_hz);
+
+/* Accumulate polarised images over n_time samples (Sec. 2.1 Eq. (5), Sec. 3.2).
+ *   efield: device uint8 [n_time][n_chan][n_pol][n_ant] (4+4-bit samples);
+ *   gains:  device complex64 [n_chan][n_pol][n_ant], e' = gain * e;
+ *   image:  device complex128 [n_chan][n_prod][N][N] (n_prod = 4 or 1),
+ *           fftshifted; reset != 0 overwrites it, reset == 0 adds to it, so an
+ *           integration can be split over several calls.
+ * XX and YY are written with a zero imaginary part (reset != 0) or have their
+ * imaginary part left unchanged (reset == 0).  Accumulation is float64;
+ * the per-sample transform is float32 (EPIC_FP32) or split float16 / bfloat16
+ * matrix products with float32 accumulation (EPIC_SPLIT_*).  Allocates nothing.
+ * Errors: EPIC_E_STATE (no antennas), EPIC_E_INVALID (null pointer,
+ * n_time <= 0), EPIC_E_UNSUPPORTED, EPIC_E_LAUNCH. */
+epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
+                                  const float *gains, double *image, int32_t reset);
+
+/* Gradient of a real loss L with respect to the gains, given the gradient of
+ * L with respect to the image accumulated by epic_image_accumulate(reset=1)
+ * over the same efield and gains.
+ *   grad_image: device complex128 like image, holding dL/dRe(I) + i dL/dIm(I);
+ *               the imaginary parts for XX and YY are ignored (those products
+ *               are real);
+ *   grad_gains: device complex64 [n_chan][n_pol][n_ant], overwritten with
+ *               dL/dRe(g) + i dL/dIm(g).
+ * The per-sample transforms are recomputed, not stored; the reduction over
+ * time is float64.  Allocates nothing.  Errors as epic_image_accumulate. */
+epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
+                                const float *gains, const double *grad_image,
+                                float *grad_gains);
+
+/* With EPIC_FLAG_TIMING: wait for the last imaging call and report the
+ * duration of its main kernel and of the whole call, in milliseconds, measured
+ * with HIP events on the context's stream.  Errors: EPIC_E_STATE (no timed
+ * call yet or flag not set). */
+epic_status epic_last_timing(epic_ctx *ctx, float *main_kernel_ms, float *call_ms);
+
+/* Name of the main kernel the last imaging call launched (static string). */
+const char *epic_last_kernel_name(const epic_ctx *ctx);
+
+/* Free the context and its library-owned memory (waits for its stream). */
+void epic_destroy(epic_ctx *ctx);
+
+/* Message of the last failed call on ctx, valid until the next call on ctx.
+ * With ctx == NULL: the message of the last failed epic_init in this thread. */
+const char *epic_last_error(const epic_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPIC_H */

@@ -1,0 +1,174 @@
+"""MI355X-native MOFF direct imager (Kent et al. 2019, the EPIC imager).
+
+Python binding of libepic.so: argument marshalling only.  Every step of the
+imaging path runs in the library's HIP kernels; PyTorch provides device
+memory and streams.  There is no CPU path: the calls raise if the library is
+not built or if a tensor is not on the GPU.
+
+    im = Imager(grid_n=64, n_chan=132, n_pol=2, n_ant=256)
+    im.set_antennas(xy_m, freq_hz)                     # host float64
+    img = im.accumulate(efield, gains)                 # uint8 [T,C,P,A], complex64 [C,P,A]
+    g = im.backward(efield, gains, grad_img)           # d loss / d gains
+    img = image(im, gains, efield)                     # autograd-aware
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import EpicError, EPIC_FP32, EPIC_SPLIT_FP16, EPIC_SPLIT_BF16  # noqa: F401
+
+_PRECISIONS = {"fp32": EPIC_FP32, "split_fp16": EPIC_SPLIT_FP16, "split_bf16": EPIC_SPLIT_BF16}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Imager:
+    """One library context: a fixed (N, C, P, A, kernel) configuration."""
+
+    def __init__(self, grid_n: int, n_chan: int, n_pol: int, n_ant: int,
+                 kernel_support: int = 3, kernel_sigma_cells: float = 0.5,
+                 cell_wavelengths: float = 0.5, precision: str = "fp32",
+                 staged: bool = False, timing: bool = False, device: Optional[int] = None):
+        torch = _torch()
+        self.L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the MOFF imager needs a GPU (no CPU path)")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        flags = (_lib.EPIC_FLAG_STAGED if staged else 0) | (_lib.EPIC_FLAG_TIMING if timing else 0)
+        self.cfg = _lib.EpicConfig(grid_n, n_chan, n_pol, n_ant, kernel_support,
+                                   kernel_sigma_cells, cell_wavelengths,
+                                   _PRECISIONS[precision], flags)
+        self.grid_n, self.n_chan, self.n_pol, self.n_ant = grid_n, n_chan, n_pol, n_ant
+        self.n_prod = 4 if n_pol == 2 else 1
+        ctx = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st = self.L.epic_init(ctypes.byref(self.cfg), self.device, ctypes.c_void_p(stream),
+                              ctypes.byref(ctx))
+        _lib.check(self.L, None, st)
+        self._ctx = ctx
+
+    # ------------------------------------------------------------------ setup
+    def set_antennas(self, xy_m, freq_hz) -> None:
+        xy = np.ascontiguousarray(np.asarray(xy_m, dtype=np.float64))
+        f = np.ascontiguousarray(np.asarray(freq_hz, dtype=np.float64))
+        if xy.shape != (self.n_ant, 2) or f.shape != (self.n_chan,):
+            raise ValueError(f"expected xy_m [{self.n_ant}, 2] and freq_hz [{self.n_chan}]")
+        dp = ctypes.POINTER(ctypes.c_double)
+        st = self.L.epic_set_antennas(self._ctx, xy.ctypes.data_as(dp), f.ctypes.data_as(dp))
+        _lib.check(self.L, self._ctx, st)
+
+    def _bind_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.L.epic_set_stream(self._ctx, ctypes.c_void_p(s))
+
+    def _check_inputs(self, efield, gains):
+        torch = _torch()
+        if efield.dtype != torch.uint8 or efield.dim() != 4 or \
+                tuple(efield.shape[1:]) != (self.n_chan, self.n_pol, self.n_ant):
+            raise ValueError(f"efield must be uint8 [T, {self.n_chan}, {self.n_pol}, {self.n_ant}]")
+        if gains.dtype != torch.complex64 or tuple(gains.shape) != (self.n_chan, self.n_pol, self.n_ant):
+            raise ValueError(f"gains must be complex64 [{self.n_chan}, {self.n_pol}, {self.n_ant}]")
+        for t in (efield, gains):
+            if not t.is_cuda or t.device.index != self.device:
+                raise ValueError("inputs must be on the imager's GPU")
+        return efield.contiguous(), gains.contiguous()
+
+    def image_shape(self):
+        return (self.n_chan, self.n_prod, self.grid_n, self.grid_n)
+
+    # ------------------------------------------------------------------ calls
+    def accumulate(self, efield, gains, image=None, reset: bool = True):
+        """Sum of polarised images over the samples of efield (complex128)."""
+        torch = _torch()
+        efield, gains = self._check_inputs(efield, gains)
+        if image is None:
+            image = torch.empty(self.image_shape(), dtype=torch.complex128,
+                                device=efield.device)
+        elif image.dtype != torch.complex128 or tuple(image.shape) != self.image_shape() or \
+                not image.is_contiguous() or not image.is_cuda:
+            raise ValueError("image must be a contiguous complex128 CUDA tensor "
+                             f"{self.image_shape()}")
+        self._bind_stream()
+        st = self.L.epic_image_accumulate(self._ctx, ctypes.c_void_p(efield.data_ptr()),
+                                          int(efield.shape[0]), ctypes.c_void_p(gains.data_ptr()),
+                                          ctypes.c_void_p(image.data_ptr()), 1 if reset else 0)
+        _lib.check(self.L, self._ctx, st)
+        return image
+
+    def backward(self, efield, gains, grad_image):
+        """d loss / d gains (dL/dRe + i dL/dIm, complex64 [C, P, A])."""
+        torch = _torch()
+        efield, gains = self._check_inputs(efield, gains)
+        grad_image = grad_image.to(torch.complex128).contiguous()
+        if tuple(grad_image.shape) != self.image_shape():
+            raise ValueError(f"grad_image must be {self.image_shape()}")
+        out = torch.empty((self.n_chan, self.n_pol, self.n_ant), dtype=torch.complex64,
+                          device=efield.device)
+        self._bind_stream()
+        st = self.L.epic_image_backward(self._ctx, ctypes.c_void_p(efield.data_ptr()),
+                                        int(efield.shape[0]), ctypes.c_void_p(gains.data_ptr()),
+                                        ctypes.c_void_p(grad_image.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()))
+        _lib.check(self.L, self._ctx, st)
+        return out
+
+    def last_timing(self):
+        """(main kernel ms, whole call ms) of the last call (timing=True)."""
+        m, c = ctypes.c_float(), ctypes.c_float()
+        st = self.L.epic_last_timing(self._ctx, ctypes.byref(m), ctypes.byref(c))
+        _lib.check(self.L, self._ctx, st)
+        return m.value, c.value
+
+    def last_kernel_name(self) -> str:
+        return self.L.epic_last_kernel_name(self._ctx).decode()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self.L.epic_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_image_fn():
+    torch = _torch()
+
+    class ImageFn(torch.autograd.Function):
+        """image = accumulate(efield, gains); backward gives d loss / d gains."""
+
+        @staticmethod
+        def forward(ctx, gains, efield, imager):
+            ctx.imager = imager
+            ctx.save_for_backward(gains, efield)
+            return imager.accumulate(efield, gains.contiguous())
+
+        @staticmethod
+        def backward(ctx, grad_image):
+            gains, efield = ctx.saved_tensors
+            g = ctx.imager.backward(efield, gains.contiguous(), grad_image)
+            return g, None, None
+
+    return ImageFn
+
+
+_IMAGE_FN = None
+
+
+def image(imager: Imager, gains, efield):
+    """Autograd-aware accumulated image (gains may be an expanded view)."""
+    global _IMAGE_FN
+    if _IMAGE_FN is None:
+        _IMAGE_FN = _make_image_fn()
+    return _IMAGE_FN.apply(gains, efield, imager)

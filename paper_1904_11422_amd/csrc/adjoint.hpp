@@ -1,0 +1,211 @@
+// Adjoint of the fused imaging kernel: gradient of a real loss with respect
+// to the per-antenna complex gains, given dL/dI for the accumulated image.
+//
+// Per sample (nothing is stored across samples, the forward is recomputed):
+//   F_p      = forward transform of the gridded aperture (as in the imager)
+//   G_X      = Re(Gxx) F_X + h F_Y,   G_Y = Re(Gyy) F_Y + conj(h) F_X,
+//              h = (Gxy + conj(Gyx)) / 2          (dL/dF_p*, Wirtinger calculus)
+//   H_p      = adjoint transform of G_p (negative exponent), columns then rows
+//   dL/dg*   += sum_taps w * conj(e[t,c,p,a]) * H_p[tap]
+// The per-antenna sums are float64, one slot per (workgroup, channel); a
+// second kernel adds the slots in workgroup order and returns 2 dL/dg*, i.e.
+// dL/dRe(g) + i dL/dIm(g).
+#pragma once
+#include "fused.hpp"
+
+namespace epic {
+
+struct AdjointArgs {
+  const uint8_t* efield;    // [T][C][P][A]
+  const float2* gains;      // [C][P][A]
+  const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
+  const uint2* prog;        // gridding programs, as the imager
+  const int4* chan;
+  const uint2* taps;        // [C][A][KK] {cell j*N+i, w bits}
+  const float2* twiddle;
+  double2* gpartial;        // [W + C - 1][P*A]
+  int64_t n_time, total;
+  int n_chan, n_ant, kk, L, W;
+};
+
+template <int N, int P, int GPT>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+adjoint_kernel(AdjointArgs a) {
+  using SH = FusedShape<N>;
+  constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, RS = SH::RS;
+  constexpr int NPROD = (P == 2) ? 4 : 1;
+  __shared__ float2 X[P * N * RS];
+  __shared__ float2 E[NT * GPT];
+
+  const Roles<N> r(threadIdx.x);
+  const int tid = r.tid;
+  const int64_t fb = range_begin(blockIdx.x, a.total, a.W);
+  const int64_t fe = range_begin(blockIdx.x + 1, a.total, a.W);
+  if (fb >= fe) return;
+
+  float2 tw[S];
+#pragma unroll
+  for (int k0 = 0; k0 < S; ++k0) tw[k0] = a.twiddle[(r.n0 * k0) % N];
+
+  const int PA = P * a.n_ant;
+  const int64_t row_bytes = (int64_t)a.n_chan * PA;
+
+  float ga[S], gb[S];                          // Re(Gxx), Re(Gyy) at owned pixels
+  float2 gh[S];                                // (Gxy + conj(Gyx)) / 2
+  double2 gacc[GPT];
+  float2 g[GPT];
+  uint32_t nxt[GPT];
+  int c = -1, j_lo = 0, nb = 0;
+  const uint2* prog = nullptr;
+
+  auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
+    const uint8_t* src = a.efield + tt * row_bytes + (int64_t)cc * PA;
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = tid + i * NT;
+      dst[i] = (k < PA) ? (uint32_t)src[k] : 0u;
+    }
+  };
+  auto flush = [&]() {
+    double2* out = a.gpartial + (int64_t)(blockIdx.x + c) * PA;
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = tid + i * NT;
+      if (k < PA) out[k] = gacc[i];
+    }
+  };
+
+  int cc = (int)(fb / a.n_time);
+  int64_t tt = fb - (int64_t)cc * a.n_time;
+  load_bytes(cc, tt, nxt);
+  for (int64_t left = fe - fb; left > 0; --left) {
+    if (cc != c) {
+      if (c >= 0) flush();
+      c = cc;
+      const int4 ci = a.chan[c];
+      j_lo = ci.x;
+      nb = ci.y;
+      prog = a.prog + (int64_t)c * a.L * NT + tid;
+#pragma unroll
+      for (int i = 0; i < GPT; ++i) {
+        const int k = tid + i * NT;
+        g[i] = (k < PA) ? a.gains[(int64_t)c * PA + k] : make_float2(0.f, 0.f);
+        gacc[i] = make_double2(0.0, 0.0);
+      }
+      const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) {
+          const int km = r.n0 * D + q + S * k1;
+          const int pix = ((km + N / 2) % N) * N + (r.kl + N / 2) % N;
+          const int i = q * R + k1;
+          ga[i] = (float)gi[pix].x;
+          if (P == 2) {
+            const double2 xy = gi[N * N + pix], yx = gi[2 * N * N + pix];
+            gb[i] = (float)gi[3 * N * N + pix].x;
+            gh[i] = make_float2((float)(0.5 * (xy.x + yx.x)), (float)(0.5 * (xy.y - yx.y)));
+          } else {
+            gb[i] = 0.f;
+            gh[i] = make_float2(0.f, 0.f);
+          }
+        }
+    }
+    uint32_t cur[GPT];
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) cur[i] = nxt[i];
+    ++tt;
+    if (tt == a.n_time) { tt = 0; ++cc; }
+    if (left > 1) load_bytes(cc, tt, nxt);
+
+    uint2 steps[kStepChunk];
+    load_steps<NT>(steps, prog, 0, a.L);
+    stage_samples<NT, GPT>(E, cur, g, tid, PA);
+    __syncthreads();
+    grid_band<N, P, NT, RS>(X, E, steps, prog, a.L, a.n_ant);
+    __syncthreads();
+    row_pass<N, P, +1>(X, r, tw, j_lo, nb);
+    __syncthreads();
+    float2 v[P][S];
+    column_pass_fwd<N, P>(v, X, r, tw, j_lo, nb);
+
+    // dL/dF* at the owned pixels
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const float2 fx = v[0][i];
+      if (P == 2) {
+        const float2 fy = v[P - 1][i];
+        const float2 hx = cmul(gh[i], fy);     // h F_Y
+        const float2 hy = cmulc(fx, gh[i]);    // conj(h) F_X
+        v[0][i] = make_float2(fmaf(ga[i], fx.x, hx.x), fmaf(ga[i], fx.y, hx.y));
+        v[P - 1][i] = make_float2(fmaf(gb[i], fy.x, hy.x), fmaf(gb[i], fy.y, hy.y));
+      } else {
+        v[0][i] = cscale(fx, ga[i]);
+      }
+    }
+    // adjoint column transforms, results to the band rows of each column
+    const int kl = r.kl;
+    line_transform_rev<N, -1, P>(v, tw, r.n0, X,
+                                 [kl](int p, int s) { return (p * N + s) * RS + kl; });
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int n1 = 0; n1 < S; ++n1) {
+        const int j = R * n1 + r.n0;
+        if ((unsigned)(j - j_lo) < (unsigned)nb) X[(p * N + j) * RS + kl] = v[p][n1];
+      }
+    __syncthreads();
+    row_pass<N, P, -1>(X, r, tw, j_lo, nb);
+    __syncthreads();
+
+    // degrid: dL/de'* at each antenna, times conj(e)
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = tid + i * NT;
+      if (k < PA) {
+        const int p = k / a.n_ant, ant = k - p * a.n_ant;
+        const uint2* tp = a.taps + ((int64_t)c * a.n_ant + ant) * a.kk;
+        float2 s = make_float2(0.f, 0.f);
+        for (int q = 0; q < a.kk; ++q) {
+          const uint2 t = tp[q];
+          const int cell = (int)t.x;
+          const float w = __uint_as_float(t.y);
+          const float2 h = X[(p * N + cell / N) * RS + cell % N];
+          s.x = fmaf(w, h.x, s.x);
+          s.y = fmaf(w, h.y, s.y);
+        }
+        const float2 e = unpack_ci4(cur[i]);
+        const float2 d = cmulc(s, e);           // s * conj(e)
+        gacc[i].x += (double)d.x;
+        gacc[i].y += (double)d.y;
+      }
+    }
+  }
+  flush();
+}
+
+struct GradReduceArgs {
+  const double2* gpartial;
+  float2* grad;             // [C][P*A]
+  int64_t n_time, total;
+  int n_chan, PA, W;
+};
+
+__global__ void __launch_bounds__(256) reduce_grad_kernel(GradReduceArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_chan * a.PA) return;
+  const int c = (int)(idx / a.PA);
+  const int k = (int)(idx % a.PA);
+  const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
+  const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
+  double sx = 0.0, sy = 0.0;
+  for (int64_t w = w_lo; w <= w_hi; ++w) {
+    if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
+    const double2 v = a.gpartial[(w + c) * a.PA + k];
+    sx += v.x;
+    sy += v.y;
+  }
+  a.grad[idx] = make_float2((float)(2.0 * sx), (float)(2.0 * sy));
+}
+
+}  // namespace epic

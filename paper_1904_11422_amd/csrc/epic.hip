@@ -1,0 +1,712 @@
+// Host side of the C ABI declared in include/epic.h: context, argument
+// validation, float64 geometry precompute, table upload and kernel launches.
+#include "epic.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <queue>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "dft.hpp"
+#include "fused.hpp"
+#include "staged.hpp"
+#include "adjoint.hpp"
+
+namespace {
+
+constexpr double kC0 = 299792458.0;
+thread_local std::string g_init_error;
+
+struct DevMem {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() { reset(); }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  bool alloc(size_t n) {
+    reset();
+    if (n == 0) n = 16;
+    if (hipMalloc(&p, n) != hipSuccess) { p = nullptr; return false; }
+    bytes = n;
+    return true;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Host-side per-channel geometry (float64 maths, float32 weights).
+struct Geometry {
+  int C = 0, A = 0, KK = 0;
+  std::vector<int> j_lo, nb;          // band of rows touched, per channel
+  std::vector<int> cell;              // [C][A][KK] j*N + i
+  std::vector<float> w;               // [C][A][KK]
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct epic_ctx {
+  epic_config cfg{};
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int nprod = 1, nacc = 1, PA = 0;
+  int n_cu = 0;
+
+  // path selection
+  bool fused = true;
+  int fused_gpt = 1;
+  int fused_w = 0;                    // persistent workgroups (upper bound)
+  int adj_w = 0;
+  const char* last_kernel = "none";
+
+  // tables
+  bool have_geom = false;
+  int L = 0;
+  DevMem prog, chan, twiddle, taps;
+  DevMem csr_off, csr_ent;
+  int nnz = 0;
+
+  // workspace
+  DevMem partial;                     // fused: [(W + C - 1)][nacc][N*N]
+  DevMem gpartial;                    // adjoint: [(W + C - 1)][P*A] complex f64
+  DevMem st_e, st_grid, st_acc;       // staged
+  int tb = 0;
+
+  // timing
+  bool timing = false, timed = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+
+  epic_status fail(epic_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+};
+
+namespace {
+
+epic_status check_config(const epic_config* c, std::string& m) {
+  if (!c) { m = "config is NULL"; return EPIC_E_INVALID; }
+  if (c->grid_n != 32 && c->grid_n != 64 && c->grid_n != 128) {
+    m = "grid_n must be 32, 64 or 128"; return EPIC_E_INVALID;
+  }
+  if (c->n_pol != 1 && c->n_pol != 2) { m = "n_pol must be 1 or 2"; return EPIC_E_INVALID; }
+  if (c->n_chan < 1 || c->n_chan > 65536) { m = "n_chan out of range"; return EPIC_E_INVALID; }
+  if (c->n_ant < 1 || c->n_ant > 4096) { m = "n_ant must be in 1..4096"; return EPIC_E_INVALID; }
+  if (c->kernel_support < 1 || c->kernel_support > 7 || c->kernel_support % 2 == 0) {
+    m = "kernel_support must be odd and in 1..7"; return EPIC_E_INVALID;
+  }
+  if (!(c->kernel_sigma_cells > 0) || !std::isfinite(c->kernel_sigma_cells)) {
+    m = "kernel_sigma_cells must be finite and positive"; return EPIC_E_INVALID;
+  }
+  if (!(c->cell_wavelengths > 0) || !std::isfinite(c->cell_wavelengths)) {
+    m = "cell_wavelengths must be finite and positive"; return EPIC_E_INVALID;
+  }
+  if (c->precision != EPIC_FP32 && c->precision != EPIC_SPLIT_FP16 &&
+      c->precision != EPIC_SPLIT_BF16) {
+    m = "unknown precision"; return EPIC_E_INVALID;
+  }
+  if (c->flags & ~(EPIC_FLAG_STAGED | EPIC_FLAG_TIMING)) { m = "unknown flag"; return EPIC_E_INVALID; }
+  return EPIC_OK;
+}
+
+// Kernel taps of every antenna for every channel (float64), with the grid
+// bounds check.  Tap order: dj outer, di inner.
+epic_status build_geometry(const epic_config& cfg, const double* xy, const double* freq,
+                           Geometry& g, std::string& m) {
+  const int N = cfg.grid_n, C = cfg.n_chan, A = cfg.n_ant, K = cfg.kernel_support;
+  const int h = K / 2;
+  g.C = C; g.A = A; g.KK = K * K;
+  g.j_lo.assign(C, 0); g.nb.assign(C, 0);
+  g.cell.assign((size_t)C * A * K * K, 0);
+  g.w.assign((size_t)C * A * K * K, 0.f);
+  for (int a = 0; a < A; ++a)
+    if (!std::isfinite(xy[2 * a]) || !std::isfinite(xy[2 * a + 1])) {
+      m = "antenna position is not finite"; return EPIC_E_INVALID;
+    }
+  for (int c = 0; c < C; ++c)
+    if (!std::isfinite(freq[c]) || !(freq[c] > 0)) {
+      m = "channel frequency must be finite and positive"; return EPIC_E_INVALID;
+    }
+  const double inv2s2 = 1.0 / (2.0 * cfg.kernel_sigma_cells * cfg.kernel_sigma_cells);
+  for (int c = 0; c < C; ++c) {
+    const double cell_m = kC0 / freq[c] * cfg.cell_wavelengths;
+    int jmin = N, jmax = -1;
+    for (int a = 0; a < A; ++a) {
+      const double X = xy[2 * a] / cell_m + N / 2.0;
+      const double Y = xy[2 * a + 1] / cell_m + N / 2.0;
+      const double i0 = std::floor(X + 0.5), j0 = std::floor(Y + 0.5);
+      if (i0 - h < 0 || j0 - h < 0 || i0 + h > N - 1 || j0 + h > N - 1) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "antenna %d leaves the %dx%d grid at channel %d "
+                      "(cell %.1f, %.1f)", a, N, N, c, X, Y);
+        m = buf;
+        return EPIC_E_OFFGRID;
+      }
+      int k = 0;
+      for (int dj = -h; dj <= h; ++dj)
+        for (int di = -h; di <= h; ++di, ++k) {
+          const double i = i0 + di, j = j0 + dj;
+          const double wt = std::exp(-((i - X) * (i - X) + (j - Y) * (j - Y)) * inv2s2);
+          const size_t o = ((size_t)c * A + a) * g.KK + k;
+          g.cell[o] = (int)j * N + (int)i;
+          g.w[o] = (float)wt;
+          jmin = std::min(jmin, (int)j);
+          jmax = std::max(jmax, (int)j);
+        }
+    }
+    g.j_lo[c] = jmin;
+    g.nb[c] = jmax - jmin + 1;
+  }
+  return EPIC_OK;
+}
+
+// Per-thread gather programs of the fused kernel.  Every band cell belongs to
+// exactly one thread; its entries (antenna ascending, then tap order) are summed
+// in that order and the cell is written once (zero cells get a write-only
+// step).  Cells are dealt longest-first to the least loaded thread.
+void build_programs(const epic_config& cfg, const Geometry& g, int NT,
+                    std::vector<uint32_t>& out, int& L) {
+  const int N = cfg.grid_n, C = g.C, A = g.A, KK = g.KK;
+  std::vector<std::vector<std::vector<uint32_t>>> per_chan(C);   // [c][thread] -> words
+  L = 1;
+  for (int c = 0; c < C; ++c) {
+    const int j_lo = g.j_lo[c], nb = g.nb[c];
+    const int ncell = nb * N;
+    std::vector<std::vector<std::pair<int, float>>> ent(ncell);
+    for (int a = 0; a < A; ++a)
+      for (int k = 0; k < KK; ++k) {
+        const size_t o = ((size_t)c * A + a) * KK + k;
+        ent[g.cell[o] - j_lo * N].push_back({a, g.w[o]});
+      }
+    std::vector<int> order(ncell);
+    for (int i = 0; i < ncell; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return std::max<size_t>(1, ent[x].size()) > std::max<size_t>(1, ent[y].size());
+    });
+    using Load = std::pair<int, int>;                  // (steps, thread)
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+    for (int t = 0; t < NT; ++t) pq.push({0, t});
+    auto& th = per_chan[c];
+    th.assign(NT, {});
+    for (int idx : order) {
+      Load ld = pq.top();
+      pq.pop();
+      const int cellabs = idx + j_lo * N;
+      auto& words = th[ld.second];
+      if (ent[idx].empty()) {
+        words.push_back((uint32_t)cellabs | epic::STEP_LAST);
+        words.push_back(0u);
+      } else {
+        for (size_t e = 0; e < ent[idx].size(); ++e) {
+          uint32_t code = (uint32_t)cellabs | epic::STEP_HAS |
+                          ((uint32_t)ent[idx][e].first << epic::STEP_ANT_SHIFT);
+          if (e + 1 == ent[idx].size()) code |= epic::STEP_LAST;
+          uint32_t wb;
+          std::memcpy(&wb, &ent[idx][e].second, 4);
+          words.push_back(code);
+          words.push_back(wb);
+        }
+      }
+      ld.first += (int)std::max<size_t>(1, ent[idx].size());
+      L = std::max(L, ld.first);
+      pq.push(ld);
+    }
+  }
+  out.assign((size_t)C * L * NT * 2, 0u);
+  for (int c = 0; c < C; ++c)
+    for (int t = 0; t < NT; ++t) {
+      const auto& words = per_chan[c][t];
+      for (size_t s = 0; s < words.size() / 2; ++s) {
+        const size_t o = (((size_t)c * L + s) * NT + t) * 2;
+        out[o] = words[2 * s];
+        out[o + 1] = words[2 * s + 1];
+      }
+    }
+}
+
+template <typename F>
+int occupancy_blocks(F kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess) nb = 1;
+  return std::max(1, nb);
+}
+
+template <int N, int P, int GPT>
+int fused_blocks_per_cu() {
+  return occupancy_blocks(epic::fused_image_kernel<N, P, GPT>, epic::FusedShape<N>::NT);
+}
+
+int fused_blocks_per_cu(int N, int P, int gpt) {
+#define EPIC_OCC(NN, PP, GG) if (N == NN && P == PP && gpt == GG) return fused_blocks_per_cu<NN, PP, GG>();
+  EPIC_OCC(32, 1, 1) EPIC_OCC(32, 1, 2) EPIC_OCC(32, 1, 4)
+  EPIC_OCC(32, 2, 1) EPIC_OCC(32, 2, 2) EPIC_OCC(32, 2, 4)
+  EPIC_OCC(64, 1, 1) EPIC_OCC(64, 1, 2) EPIC_OCC(64, 1, 4)
+  EPIC_OCC(64, 2, 1) EPIC_OCC(64, 2, 2) EPIC_OCC(64, 2, 4)
+#undef EPIC_OCC
+  return 1;
+}
+
+template <int N, int P>
+int adjoint_blocks_per_cu(int gpt) {
+  if (gpt == 1) return occupancy_blocks(epic::adjoint_kernel<N, P, 1>, epic::FusedShape<N>::NT);
+  if (gpt == 2) return occupancy_blocks(epic::adjoint_kernel<N, P, 2>, epic::FusedShape<N>::NT);
+  return occupancy_blocks(epic::adjoint_kernel<N, P, 4>, epic::FusedShape<N>::NT);
+}
+
+int adjoint_blocks_per_cu(int N, int P, int gpt) {
+  if (N == 32) return P == 1 ? adjoint_blocks_per_cu<32, 1>(gpt) : adjoint_blocks_per_cu<32, 2>(gpt);
+  return P == 1 ? adjoint_blocks_per_cu<64, 1>(gpt) : adjoint_blocks_per_cu<64, 2>(gpt);
+}
+
+int fused_threads(int N) { return N == 32 ? epic::FusedShape<32>::NT : epic::FusedShape<64>::NT; }
+
+bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
+  const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
+  const dim3 grid(a.W), block(fused_threads(N));
+#define EPIC_LF(NN, PP, GG)                                                          \
+  if (N == NN && P == PP && G == GG) {                                               \
+    hipLaunchKernelGGL((epic::fused_image_kernel<NN, PP, GG>), grid, block, 0, x->stream, a); \
+    return true;                                                                     \
+  }
+  EPIC_LF(32, 1, 1) EPIC_LF(32, 1, 2) EPIC_LF(32, 1, 4)
+  EPIC_LF(32, 2, 1) EPIC_LF(32, 2, 2) EPIC_LF(32, 2, 4)
+  EPIC_LF(64, 1, 1) EPIC_LF(64, 1, 2) EPIC_LF(64, 1, 4)
+  EPIC_LF(64, 2, 1) EPIC_LF(64, 2, 2) EPIC_LF(64, 2, 4)
+#undef EPIC_LF
+  return false;
+}
+
+bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a) {
+  const int N = x->cfg.grid_n, P = x->cfg.n_pol;
+  const int64_t n = (int64_t)x->cfg.n_chan * N * N;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+#define EPIC_LR(NN, PP)                                                                \
+  if (N == NN && P == PP) {                                                            \
+    hipLaunchKernelGGL((epic::reduce_image_kernel<NN, PP>), grid, block, 0, x->stream, a); \
+    return true;                                                                       \
+  }
+  EPIC_LR(32, 1) EPIC_LR(32, 2) EPIC_LR(64, 1) EPIC_LR(64, 2) EPIC_LR(128, 1) EPIC_LR(128, 2)
+#undef EPIC_LR
+  return false;
+}
+
+bool launch_adjoint(epic_ctx* x, const epic::AdjointArgs& a) {
+  const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
+  const dim3 grid(a.W), block(fused_threads(N));
+#define EPIC_LA(NN, PP, GG)                                                          \
+  if (N == NN && P == PP && G == GG) {                                               \
+    hipLaunchKernelGGL((epic::adjoint_kernel<NN, PP, GG>), grid, block, 0, x->stream, a); \
+    return true;                                                                     \
+  }
+  EPIC_LA(32, 1, 1) EPIC_LA(32, 1, 2) EPIC_LA(32, 1, 4)
+  EPIC_LA(32, 2, 1) EPIC_LA(32, 2, 2) EPIC_LA(32, 2, 4)
+  EPIC_LA(64, 1, 1) EPIC_LA(64, 1, 2) EPIC_LA(64, 1, 4)
+  EPIC_LA(64, 2, 1) EPIC_LA(64, 2, 2) EPIC_LA(64, 2, 4)
+#undef EPIC_LA
+  return false;
+}
+
+bool launch_staged_fft(epic_ctx* x, float2* grid, int64_t nimg) {
+  const int N = x->cfg.grid_n;
+  const float2* tw = x->twiddle.as<float2>();
+  if (N == 32) {
+    hipLaunchKernelGGL(epic::staged_fft_kernel<32>, dim3((unsigned)nimg),
+                       dim3(epic::StagedFftShape<32>::NT), 0, x->stream, grid, tw);
+  } else if (N == 64) {
+    hipLaunchKernelGGL(epic::staged_fft_kernel<64>, dim3((unsigned)nimg),
+                       dim3(epic::StagedFftShape<64>::NT), 0, x->stream, grid, tw);
+  } else {
+    hipLaunchKernelGGL(epic::staged_fft_kernel<128>, dim3((unsigned)nimg),
+                       dim3(epic::StagedFftShape<128>::NT), 0, x->stream, grid, tw);
+  }
+  return true;
+}
+
+unsigned grid_for(int64_t n, int64_t cap = 1 << 16) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 255) / 256));
+}
+
+}  // namespace
+
+extern "C" {
+
+epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic_ctx** out) {
+  g_init_error.clear();
+  if (!out) { g_init_error = "out is NULL"; return EPIC_E_INVALID; }
+  *out = nullptr;
+  std::string m;
+  epic_status s = check_config(cfg, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    g_init_error = "no such HIP device";
+    return EPIC_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_init_error = "hipGetDeviceProperties failed";
+    return EPIC_E_DEVICE;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_init_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+    return EPIC_E_DEVICE;
+  }
+  DeviceGuard guard(device);
+  epic_ctx* x = new (std::nothrow) epic_ctx();
+  if (!x) { g_init_error = "host allocation failed"; return EPIC_E_NOMEM; }
+  x->cfg = *cfg;
+  x->device = device;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  x->nprod = cfg->n_pol == 2 ? 4 : 1;
+  x->nacc = cfg->n_pol == 2 ? 4 : 1;
+  x->PA = cfg->n_pol * cfg->n_ant;
+  x->n_cu = prop.multiProcessorCount;
+  const int N = cfg->grid_n;
+
+  // twiddles exp(+2 pi i k / N), float64 then rounded once
+  std::vector<float2> tw(N);
+  for (int k = 0; k < N; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)N;
+    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  if (!x->twiddle.alloc(N * sizeof(float2)) ||
+      hipMemcpy(x->twiddle.p, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    g_init_error = "twiddle table allocation failed";
+    delete x;
+    return EPIC_E_NOMEM;
+  }
+
+  const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
+  x->fused = !want_staged && N <= 64;
+  if (x->fused) {
+    const int NT = fused_threads(N);
+    int gpt = (x->PA + NT - 1) / NT;
+    gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
+    if (gpt == 0) x->fused = false;
+    else x->fused_gpt = gpt;
+  }
+  if (x->fused) {
+    const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
+    x->fused_w = bpc * x->n_cu;
+    const size_t slots = (size_t)x->fused_w + cfg->n_chan - 1;
+    if (!x->partial.alloc(slots * x->nacc * N * N * sizeof(double))) {
+      g_init_error = "partial-image workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+    x->adj_w = adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
+    const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
+    if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double))) {
+      g_init_error = "gradient workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+  } else {
+    // staged: batches of tb samples, intermediates bounded to ~512 MiB
+    const size_t per_t = (size_t)cfg->n_chan * cfg->n_pol * ((size_t)N * N + cfg->n_ant) * sizeof(float2);
+    x->tb = (int)std::max<size_t>(1, std::min<size_t>(64, (512ull << 20) / per_t));
+    if (!x->st_e.alloc((size_t)x->tb * cfg->n_chan * x->PA * sizeof(float2)) ||
+        !x->st_grid.alloc((size_t)x->tb * cfg->n_chan * cfg->n_pol * N * N * sizeof(float2)) ||
+        !x->st_acc.alloc((size_t)cfg->n_chan * x->nacc * N * N * sizeof(double))) {
+      g_init_error = "staged workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+  }
+  if (cfg->flags & EPIC_FLAG_TIMING) {
+    x->timing = true;
+    for (auto& e : x->ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        g_init_error = "hipEventCreate failed";
+        epic_destroy(x);
+        return EPIC_E_DEVICE;
+      }
+  }
+  *out = x;
+  return EPIC_OK;
+}
+
+epic_status epic_set_stream(epic_ctx* x, void* hip_stream) {
+  if (!x) return EPIC_E_INVALID;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  return EPIC_OK;
+}
+
+epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* freq_hz) {
+  if (!x) return EPIC_E_INVALID;
+  if (!xy_m || !freq_hz) return x->fail(EPIC_E_INVALID, "xy_m or freq_hz is NULL");
+  Geometry g;
+  std::string m;
+  epic_status s = build_geometry(x->cfg, xy_m, freq_hz, g, m);
+  if (s != EPIC_OK) return x->fail(s, m);
+  DeviceGuard guard(x->device);
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant;
+  if (hipStreamSynchronize(x->stream) != hipSuccess)
+    return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
+  x->have_geom = false;
+
+  // adjoint / staged tables: taps [C][A][KK] {cell, w}
+  std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
+  for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
+    taps[2 * o] = (uint32_t)g.cell[o];
+    std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
+  }
+  if (!x->taps.alloc(taps.size() * 4) ||
+      hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return x->fail(EPIC_E_NOMEM, "tap table upload failed");
+
+  if (x->fused) {
+    std::vector<uint32_t> prog;
+    int L = 0;
+    build_programs(x->cfg, g, fused_threads(N), prog, L);
+    std::vector<int4> chan(C);
+    for (int c = 0; c < C; ++c) chan[c] = make_int4(g.j_lo[c], g.nb[c], L, 0);
+    if (!x->prog.alloc(prog.size() * 4) || !x->chan.alloc(C * sizeof(int4)) ||
+        hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x->chan.p, chan.data(), C * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
+    x->L = L;
+  } else {
+    // per-cell CSR over the whole grid, entries in (antenna, tap) order
+    const int npix = N * N, nnz = A * g.KK;
+    std::vector<int> off((size_t)C * (npix + 1));
+    std::vector<uint32_t> ent((size_t)C * nnz * 2);
+    for (int c = 0; c < C; ++c) {
+      std::vector<int> cnt(npix, 0);
+      for (int a = 0; a < A; ++a)
+        for (int k = 0; k < g.KK; ++k) cnt[g.cell[((size_t)c * A + a) * g.KK + k]]++;
+      int* o = &off[(size_t)c * (npix + 1)];
+      o[0] = 0;
+      for (int i = 0; i < npix; ++i) o[i + 1] = o[i] + cnt[i];
+      std::vector<int> fill(o, o + npix);
+      for (int a = 0; a < A; ++a)
+        for (int k = 0; k < g.KK; ++k) {
+          const size_t src = ((size_t)c * A + a) * g.KK + k;
+          const size_t dst = (size_t)c * nnz + fill[g.cell[src]]++;
+          ent[2 * dst] = (uint32_t)a;
+          std::memcpy(&ent[2 * dst + 1], &g.w[src], 4);
+        }
+    }
+    if (!x->csr_off.alloc(off.size() * 4) || !x->csr_ent.alloc(ent.size() * 4) ||
+        hipMemcpy(x->csr_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x->csr_ent.p, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
+    x->nnz = nnz;
+  }
+  x->have_geom = true;
+  return EPIC_OK;
+}
+
+epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_time,
+                                  const float* gains, double* image, int32_t reset) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!efield || !gains || !image) return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
+  if (x->cfg.precision != EPIC_FP32)
+    return x->fail(EPIC_E_UNSUPPORTED, "split-precision forms run through epic_split_* calls");
+  DeviceGuard guard(x->device);
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
+  const int64_t total = (int64_t)C * n_time;
+  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  (void)hipGetLastError();
+  if (x->fused) {
+    epic::FusedArgs a;
+    a.efield = efield;
+    a.gains = reinterpret_cast<const float2*>(gains);
+    a.prog = x->prog.as<uint2>();
+    a.chan = x->chan.as<int4>();
+    a.twiddle = x->twiddle.as<float2>();
+    a.partial = x->partial.as<double>();
+    a.n_time = n_time;
+    a.total = total;
+    a.n_chan = C;
+    a.n_ant = x->cfg.n_ant;
+    a.L = x->L;
+    a.W = (int)std::min<int64_t>(x->fused_w, total);
+    if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
+    x->last_kernel = "fused_image_kernel";
+    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    epic::ReduceArgs r;
+    r.partial = x->partial.as<double>();
+    r.image = image;
+    r.n_time = n_time;
+    r.total = total;
+    r.n_chan = C;
+    r.W = a.W;
+    r.reset = reset ? 1 : 0;
+    launch_reduce(x, r);
+  } else {
+    const int npix = N * N;
+    for (int64_t t0 = 0; t0 < n_time; t0 += x->tb) {
+      const int tb = (int)std::min<int64_t>(x->tb, n_time - t0);
+      epic::StagedUnpackArgs u;
+      u.efield = efield;
+      u.gains = reinterpret_cast<const float2*>(gains);
+      u.e = x->st_e.as<float2>();
+      u.t0 = t0;
+      u.per_t = (int64_t)C * x->PA;
+      u.count = tb * u.per_t;
+      u.PA = x->PA;
+      hipLaunchKernelGGL(epic::staged_unpack_kernel, dim3(grid_for(u.count)), dim3(256), 0,
+                         x->stream, u);
+      epic::StagedGridArgs gr;
+      gr.e = x->st_e.as<float2>();
+      gr.off = x->csr_off.as<int>();
+      gr.ent = x->csr_ent.as<uint2>();
+      gr.grid = x->st_grid.as<float2>();
+      gr.count = (int64_t)tb * C * P * npix;
+      gr.n_chan = C;
+      gr.n_pol = P;
+      gr.n_ant = x->cfg.n_ant;
+      gr.nnz = x->nnz;
+      gr.npix = npix;
+      hipLaunchKernelGGL(epic::staged_grid_kernel, dim3(grid_for(gr.count)), dim3(256), 0,
+                         x->stream, gr);
+      launch_staged_fft(x, x->st_grid.as<float2>(), (int64_t)tb * C * P);
+      epic::StagedAccumArgs ac;
+      ac.img = x->st_grid.as<float2>();
+      ac.acc = x->st_acc.as<double>();
+      ac.count = (int64_t)C * npix;
+      ac.n_chan = C;
+      ac.npix = npix;
+      ac.tb = tb;
+      ac.first = t0 == 0;
+      if (P == 2)
+        hipLaunchKernelGGL(epic::staged_accum_kernel<2>, dim3(grid_for(ac.count, 1 << 30)),
+                           dim3(256), 0, x->stream, ac);
+      else
+        hipLaunchKernelGGL(epic::staged_accum_kernel<1>, dim3(grid_for(ac.count, 1 << 30)),
+                           dim3(256), 0, x->stream, ac);
+    }
+    x->last_kernel = "staged_fft_kernel";
+    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    epic::ReduceArgs r;
+    r.partial = x->st_acc.as<double>();
+    r.image = image;
+    r.n_time = n_time;
+    r.total = total;
+    r.n_chan = C;
+    r.W = 1;
+    r.reset = reset ? 1 : 0;
+    launch_reduce(x, r);
+  }
+  if (x->timing) {
+    (void)hipEventRecord(x->ev[2], x->stream);
+    x->timed = true;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
+epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time,
+                                const float* gains, const double* grad_image, float* grad_gains) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!efield || !gains || !grad_image || !grad_gains)
+    return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
+  if (!x->fused || x->cfg.precision != EPIC_FP32)
+    return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path (N <= 64)");
+  DeviceGuard guard(x->device);
+  const int C = x->cfg.n_chan;
+  const int64_t total = (int64_t)C * n_time;
+  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  (void)hipGetLastError();
+  epic::AdjointArgs a;
+  a.efield = efield;
+  a.gains = reinterpret_cast<const float2*>(gains);
+  a.grad_image = reinterpret_cast<const double2*>(grad_image);
+  a.prog = x->prog.as<uint2>();
+  a.chan = x->chan.as<int4>();
+  a.taps = x->taps.as<uint2>();
+  a.twiddle = x->twiddle.as<float2>();
+  a.gpartial = x->gpartial.as<double2>();
+  a.n_time = n_time;
+  a.total = total;
+  a.n_chan = C;
+  a.n_ant = x->cfg.n_ant;
+  a.kk = x->cfg.kernel_support * x->cfg.kernel_support;
+  a.L = x->L;
+  a.W = (int)std::min<int64_t>(x->adj_w, total);
+  if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
+  x->last_kernel = "adjoint_kernel";
+  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  epic::GradReduceArgs r;
+  r.gpartial = x->gpartial.as<double2>();
+  r.grad = reinterpret_cast<float2*>(grad_gains);
+  r.n_time = n_time;
+  r.total = total;
+  r.n_chan = C;
+  r.PA = x->PA;
+  r.W = a.W;
+  const int64_t n = (int64_t)C * x->PA;
+  hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     x->stream, r);
+  if (x->timing) {
+    (void)hipEventRecord(x->ev[2], x->stream);
+    x->timed = true;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
+epic_status epic_last_timing(epic_ctx* x, float* main_ms, float* call_ms) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->timing || !x->timed) return x->fail(EPIC_E_STATE, "no timed call (EPIC_FLAG_TIMING)");
+  DeviceGuard guard(x->device);
+  if (hipEventSynchronize(x->ev[2]) != hipSuccess) return x->fail(EPIC_E_DEVICE, "event wait failed");
+  float m = 0.f, c = 0.f;
+  (void)hipEventElapsedTime(&m, x->ev[0], x->ev[1]);
+  (void)hipEventElapsedTime(&c, x->ev[0], x->ev[2]);
+  if (main_ms) *main_ms = m;
+  if (call_ms) *call_ms = c;
+  return EPIC_OK;
+}
+
+const char* epic_last_kernel_name(const epic_ctx* x) { return x ? x->last_kernel : "none"; }
+
+void epic_destroy(epic_ctx* x) {
+  if (!x) return;
+  {
+    DeviceGuard guard(x->device);
+    (void)hipStreamSynchronize(x->stream);
+    for (auto& e : x->ev)
+      if (e) (void)hipEventDestroy(e);
+    x->prog.reset(); x->chan.reset(); x->twiddle.reset(); x->taps.reset();
+    x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset();
+    x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
+  }
+  delete x;
+}
+
+const char* epic_last_error(const epic_ctx* x) {
+  return x ? x->err.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""Gain gradient of the HIP adjoint kernel against the FP64 oracle's analytic
+gradient (itself pinned to finite differences) and against central finite
+differences of the GPU forward image.
+
+Bar: relative L2 error of the gradient <= 1e-4 (the benchmark spec).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAD = 1e-4
+
+
+def _setup(inp):
+    import torch
+    from paper_1904_11422_amd import Imager
+    print(f"case {inp.name}: N={inp.grid_n} C={inp.n_chan} P={inp.n_pol} A={inp.n_ant} "
+          f"T={inp.n_time}", flush=True)
+    im = Imager(inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.kernel_support,
+                inp.kernel_sigma_cells, inp.cell_wavelengths)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    return im, ef, g
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("seed,N,A,C,P,T", [(201, 32, 16, 2, 2, 5), (202, 32, 16, 1, 1, 7),
+                                          (203, 64, 256, 3, 2, 11), (204, 64, 90, 2, 1, 4)])
+def test_grad_matches_oracle_l2_loss(seed, N, A, C, P, T):
+    import torch
+    inp = synth.random_problem(seed, N, A, C, P, T)
+    im, ef, g = _setup(inp)
+    img = im.accumulate(ef, g).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    model = img * (1 + 0.05 * rng.normal(size=img.shape))         # any fixed M
+    gam = oracle.l2_loss_grad_image(img, model)
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
+
+
+def test_grad_cross_products_only():
+    """Upstream gradient on XY and YX alone exercises the h terms."""
+    import torch
+    inp = synth.random_problem(205, 32, 24, 2, 2, 6)
+    im, ef, g = _setup(inp)
+    rng = np.random.default_rng(3)
+    gam = np.zeros((2, 4, 32, 32), complex)
+    gam[:, 1] = rng.normal(size=(2, 32, 32)) + 1j * rng.normal(size=(2, 32, 32))
+    gam[:, 2] = rng.normal(size=(2, 32, 32)) + 1j * rng.normal(size=(2, 32, 32))
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, gam)
+    assert _rel(got, ref) <= TOL_GRAD
+
+
+def test_grad_matches_finite_differences_of_gpu_forward():
+    """Central differences of the GPU image (float64 loss of float64 sums)."""
+    import torch
+    inp = synth.random_problem(206, 32, 8, 1, 2, 4)
+    im, ef, g = _setup(inp)
+    rng = np.random.default_rng(4)
+    w = rng.normal(size=(1, 4, 32, 32))
+
+    def loss(gg):
+        out = im.accumulate(ef, torch.from_numpy(gg.astype(np.complex64)).cuda()).cpu().numpy()
+        return float(np.sum(w * out.real))
+    gam = w.astype(complex)                                         # dL/dRe(I)
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    g0 = inp.gains.astype(np.complex128)
+    coords = [(0, 0, 1), (0, 1, 5), (0, 0, 7), (0, 1, 0)]
+    fd = oracle.fd_grad(loss, g0, coords, rel_step=2e-3)
+    an = np.array([got[c] for c in coords])
+    assert _rel(an, fd) <= 5e-3
+
+
+def test_config5_gradient_and_autograd():
+    """Calibration setup (model image from point sources, loss |I - M|^2) through
+    the autograd Function with gains shared over channels."""
+    import torch
+    from paper_1904_11422_amd import image
+    inp = synth.config5(n_time=40, n_chan=4, n_src=8)
+    im, ef, _ = _setup(inp)
+    src = inp.sources
+    model = oracle.model_image(inp.xy_m, inp.freq_hz, 64, inp.n_time, src["lm"],
+                               src["amp"] ** 2, src["noise_sigma"])
+    g_pa = torch.from_numpy(src["g_eval"]).cuda().requires_grad_(True)       # [P, A]
+    gains = g_pa[None].expand(inp.n_chan, 2, 256)
+    img = image(im, gains, ef)
+    m = torch.from_numpy(model).cuda()
+    loss = ((img - m).abs() ** 2).sum()
+    loss.backward()
+    got = g_pa.grad.cpu().numpy()
+    img_np = img.detach().cpu().numpy()
+    gam = oracle.l2_loss_grad_image(img_np, model)
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 64, gam).sum(0)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
+    ref_img = oracle.image_from(inp)
+    assert oracle.rel_errors(img_np, ref_img).max() <= 1e-5

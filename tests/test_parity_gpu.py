@@ -1,0 +1,162 @@
+"""Parity of the HIP imaging path with the FP64 oracle, element by element.
+
+Tolerance (spec bar for the float32 path): relative L2 error per
+(channel, product) <= 1e-5, with XY / YX scaled by sqrt(|XX| |YY|)
+(oracle.rel_errors).  The float32 transform of an int4 aperture carries an
+error of order eps32 * log2(n_g) ~ 1e-6; the time sums are float64.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+
+
+def _imager(inp, staged=False, timing=False):
+    from paper_1904_11422_amd import Imager
+    im = Imager(inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.kernel_support,
+                inp.kernel_sigma_cells, inp.cell_wavelengths, staged=staged, timing=timing)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    return im
+
+
+def _dev(inp):
+    import torch
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    return ef, g
+
+
+def _run(inp, staged=False):
+    import torch
+    print(f"case {inp.name}: N={inp.grid_n} C={inp.n_chan} P={inp.n_pol} A={inp.n_ant} "
+          f"T={inp.n_time} staged={staged}", flush=True)
+    im = _imager(inp, staged)
+    ef, g = _dev(inp)
+    out = im.accumulate(ef, g)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), im
+
+
+CASES = {
+    "cfg1": lambda: synth.config1(),
+    "n32_p2_ragged": lambda: synth.random_problem(101, 32, 64, 3, 2, 37),
+    "n64_p2": lambda: synth.random_problem(102, 64, 256, 5, 2, 23),
+    "n64_p1": lambda: synth.random_problem(103, 64, 100, 2, 1, 10),
+    "n64_p2_A300": lambda: synth.random_problem(104, 64, 300, 2, 2, 6, fill=0.48),
+    "n32_p2_A150": lambda: synth.random_problem(105, 32, 150, 2, 2, 5, fill=0.45),
+    "cfg2_small": lambda: synth.config2(n_time=40, n_chan=4),
+    "single_antenna": lambda: synth.random_problem(106, 64, 1, 2, 2, 9),
+    "one_sample": lambda: synth.random_problem(107, 64, 256, 3, 2, 1),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("staged", [False, True])
+def test_image_matches_oracle(name, staged):
+    inp = CASES[name]()
+    got, _ = _run(inp, staged)
+    ref = oracle.image_from(inp)
+    err = oracle.rel_errors(got, ref)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= TOL_FP32, f"max rel err {err.max():.3e}"
+    if inp.n_pol == 2:
+        assert np.array_equal(got[:, 2], np.conj(got[:, 1]))
+        assert np.all(got[:, 0].imag == 0) and np.all(got[:, 3].imag == 0)
+
+
+def test_grid128_staged_matches_oracle():
+    inp = synth.random_problem(108, 128, 400, 2, 2, 3, fill=0.45)
+    got, im = _run(inp, staged=False)          # 128^2 runs the staged kernels
+    assert im.last_kernel_name() == "staged_fft_kernel"
+    ref = oracle.image_from(inp)
+    assert oracle.rel_errors(got, ref).max() <= TOL_FP32
+
+
+def test_reset_zero_continues_integration():
+    import torch
+    inp = synth.random_problem(111, 64, 128, 3, 2, 17)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    img = im.accumulate(ef[:6], g)
+    im.accumulate(ef[6:], g, image=img, reset=False)
+    torch.cuda.synchronize()
+    ref = oracle.image_from(inp)
+    assert oracle.rel_errors(img.cpu().numpy(), ref).max() <= TOL_FP32
+
+
+def test_bitwise_deterministic():
+    import torch
+    inp = synth.random_problem(112, 64, 256, 4, 2, 31)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    a = im.accumulate(ef, g).clone()
+    b = im.accumulate(ef, g)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fewer_samples_than_workgroups():
+    """C*T below the persistent grid: every workgroup still owns >= 1 sample."""
+    inp = synth.random_problem(113, 64, 64, 2, 2, 3)
+    got, _ = _run(inp)
+    assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
+
+
+def test_fused_and_staged_agree():
+    inp = synth.random_problem(114, 64, 256, 3, 2, 20)
+    a, _ = _run(inp, staged=False)
+    b, _ = _run(inp, staged=True)
+    assert oracle.rel_errors(a, b).max() <= 2 * TOL_FP32
+
+
+def test_offgrid_geometry_is_rejected_and_previous_kept():
+    from paper_1904_11422_amd import EpicError
+    inp = synth.random_problem(115, 32, 16, 1, 1, 4)
+    im = _imager(inp)
+    far = inp.xy_m.copy()
+    far[0, 0] = 1e4
+    with pytest.raises(EpicError, match="OFFGRID"):
+        im.set_antennas(far, inp.freq_hz)
+    ef, g = _dev(inp)
+    got = im.accumulate(ef, g).cpu().numpy()
+    assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
+
+
+def test_invalid_calls_leave_output_untouched():
+    import torch
+    from paper_1904_11422_amd import EpicError, Imager
+    inp = synth.random_problem(116, 32, 16, 1, 1, 4)
+    im = Imager(32, 1, 1, 16)
+    ef, g = _dev(inp)
+    with pytest.raises(EpicError, match="STATE"):
+        im.accumulate(ef, g)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    out = torch.full((1, 1, 32, 32), 7.0, dtype=torch.complex128, device="cuda")
+    with pytest.raises(ValueError):
+        im.accumulate(ef[:, :, :, :8], g, image=out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+
+
+@pytest.mark.slow
+def test_config2_full_size_sampled_channels():
+    """The benchmark's launch (C=132, T=1000) checked on sampled channels, each
+    against the oracle over all 1000 samples."""
+    import torch
+    inp = synth.config2()
+    got, _ = _run(inp)
+    for c in (0, 65, 131):
+        sub = synth.Inputs(inp.grid_n, 1, inp.n_pol, inp.n_ant, 3, 0.5, 0.5, inp.xy_m,
+                           inp.freq_hz[c:c + 1], inp.gains[c:c + 1], inp.efield[:, c:c + 1])
+        ref = oracle.image_from(sub)
+        err = oracle.rel_errors(got[c:c + 1], ref)
+        assert err.max() <= TOL_FP32, f"channel {c}: {err.max():.3e}"
+    # properties that hold for every channel
+    assert np.all(got[:, 0].real >= 0) and np.all(got[:, 3].real >= 0)
+    assert np.all(np.abs(got[:, 1]) ** 2 <= got[:, 0].real * got[:, 3].real * (1 + 1e-5) + 1e-3)
+    del torch
