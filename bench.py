@@ -64,6 +64,20 @@ def cpu_baseline(inp, n_chan: int):
             "tc_images_per_s": n_chan * inp.n_time / dt}
 
 
+def copy_calibration(mib: int) -> int:
+    """A device-to-device copy of known size: its profiler counters read
+    mib MiB fetched and mib MiB written per dispatch when the counters are exact."""
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": mib, "bytes_read_per_copy": n * 4, "bytes_written_per_copy": n * 4}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,7 +87,12 @@ def main() -> int:
                     help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-staged", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (five times), to "
+                         "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(the imager shards by channel with no communication; see the design notes)",

@@ -145,6 +145,66 @@ epic_status epic_last_timing(epic_ctx *ctx, float *main_kernel_ms, float *call_m
 /* Name of the main kernel the last imaging call launched (static string). */
 const char *epic_last_kernel_name(const epic_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Heterogeneous batch: n_blocks independent configurations (different grid
+ * sizes, antenna and channel counts) imaged together.  Every block gets its
+ * own context and stream; a batch call forks from hip_stream to the block
+ * streams and joins back, so the blocks run concurrently.  All pointer-array
+ * arguments are host arrays of n_blocks device pointers, laid out per block
+ * exactly as for epic_image_accumulate; n_time is common to all blocks.
+ * ------------------------------------------------------------------------ */
+typedef struct epic_batch epic_batch;
+
+/* Create the batch and one context per block (configs copied).  Errors as
+ * epic_init; on error *out is NULL and epic_batch_last_error(NULL) says which
+ * block failed. */
+epic_status epic_batch_create(const epic_config *cfgs, int32_t n_blocks, int device,
+                              void *hip_stream, epic_batch **out);
+
+/* epic_set_antennas for one block. */
+epic_status epic_batch_set_antennas(epic_batch *b, int32_t block, const double *xy_m,
+                                    const double *freq_hz);
+
+/* epic_image_accumulate for every block, concurrently, ordered after earlier
+ * work on hip_stream; later work on hip_stream waits for all blocks. */
+epic_status epic_batch_accumulate(epic_batch *b, const uint8_t *const *efields, int64_t n_time,
+                                  const float *const *gains, double *const *images,
+                                  int32_t reset);
+
+/* Capture the same fork-join sequence into a HIP graph (replacing any earlier
+ * one).  Nothing runs until epic_batch_replay; every replay reads and writes
+ * the buffers given here.  The library's kernels clear their own workspace,
+ * so the graph contains kernel nodes only. */
+epic_status epic_batch_capture(epic_batch *b, const uint8_t *const *efields, int64_t n_time,
+                               const float *const *gains, double *const *images,
+                               int32_t reset);
+
+/* Launch the captured graph on hip_stream.  Errors: EPIC_E_STATE (none). */
+epic_status epic_batch_replay(epic_batch *b);
+
+/* Autotune the per-block launch shape (persistent grid size of the fused
+ * kernels, sample batch of the staged kernels) on these inputs: runs and
+ * times the blocks alone and the whole batch (overwriting images), or, when
+ * cache_path names a file holding a plan for the same device, block shapes
+ * and n_time, loads it.  A measured plan is appended to cache_path (if not
+ * NULL).  *measured = 1 when timings were taken, 0 when the cache was used.
+ * Synchronises hip_stream.  Call it before epic_batch_capture. */
+epic_status epic_batch_tune(epic_batch *b, const uint8_t *const *efields, int64_t n_time,
+                            const float *const *gains, double *const *images,
+                            const char *cache_path, int32_t *measured);
+
+/* The launch shape in force for a block: grid = persistent workgroups of the
+ * fused kernel (0 if the block runs the staged kernels), staged_batch =
+ * samples per staged pass (0 if fused). */
+epic_status epic_batch_plan(const epic_batch *b, int32_t block, int32_t *grid,
+                            int32_t *staged_batch);
+
+/* Free the batch, its graph, streams and contexts. */
+void epic_batch_destroy(epic_batch *b);
+
+/* Message of the last failed batch call (NULL: the last failed create). */
+const char *epic_batch_last_error(const epic_batch *b);
+
 /* Free the context and its library-owned memory (waits for its stream). */
 void epic_destroy(epic_ctx *ctx);
 

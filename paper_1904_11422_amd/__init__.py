@@ -172,3 +172,101 @@ def image(imager: Imager, gains, efield):
     if _IMAGE_FN is None:
         _IMAGE_FN = _make_image_fn()
     return _IMAGE_FN.apply(gains, efield, imager)
+
+
+class Batch:
+    """Several imaging configurations advanced together (one context and
+    stream per block, fork-join on the caller's stream), with optional HIP
+    graph capture/replay and an autotuned launch shape per block."""
+
+    def __init__(self, configs, device: Optional[int] = None):
+        """configs: list of dicts with the Imager keyword arguments."""
+        torch = _torch()
+        self.L = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the MOFF imager needs a GPU (no CPU path)")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        arr = (_lib.EpicConfig * len(configs))()
+        self.shapes = []
+        for i, c in enumerate(configs):
+            arr[i] = _lib.EpicConfig(c["grid_n"], c["n_chan"], c["n_pol"], c["n_ant"],
+                                     c.get("kernel_support", 3), c.get("kernel_sigma_cells", 0.5),
+                                     c.get("cell_wavelengths", 0.5),
+                                     _PRECISIONS[c.get("precision", "fp32")],
+                                     _lib.EPIC_FLAG_STAGED if c.get("staged") else 0)
+            self.shapes.append((c["n_chan"], 4 if c["n_pol"] == 2 else 1, c["grid_n"], c["grid_n"]))
+        self.n_blocks = len(configs)
+        b = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st = self.L.epic_batch_create(arr, len(configs), self.device, ctypes.c_void_p(stream),
+                                      ctypes.byref(b))
+        _lib.check_batch(self.L, None, st)
+        self._b = b
+
+    def set_antennas(self, block: int, xy_m, freq_hz):
+        xy = np.ascontiguousarray(np.asarray(xy_m, dtype=np.float64))
+        f = np.ascontiguousarray(np.asarray(freq_hz, dtype=np.float64))
+        dp = ctypes.POINTER(ctypes.c_double)
+        st = self.L.epic_batch_set_antennas(self._b, block, xy.ctypes.data_as(dp), f.ctypes.data_as(dp))
+        _lib.check_batch(self.L, self._b, st)
+
+    def _ptrs(self, tensors):
+        if len(tensors) != self.n_blocks:
+            raise ValueError(f"expected {self.n_blocks} tensors")
+        for t in tensors:
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError("batch tensors must be contiguous CUDA tensors")
+        return (ctypes.c_void_p * self.n_blocks)(*[t.data_ptr() for t in tensors])
+
+    def new_images(self):
+        torch = _torch()
+        return [torch.empty(s, dtype=torch.complex128, device=f"cuda:{self.device}")
+                for s in self.shapes]
+
+    def _args(self, efields, gains, images):
+        n_time = int(efields[0].shape[0])
+        if any(int(e.shape[0]) != n_time for e in efields):
+            raise ValueError("all blocks must have the same number of samples")
+        return self._ptrs(efields), n_time, self._ptrs(gains), self._ptrs(images)
+
+    def accumulate(self, efields, gains, images, reset: bool = True):
+        e, n, g, im = self._args(efields, gains, images)
+        st = self.L.epic_batch_accumulate(self._b, e, n, g, im, 1 if reset else 0)
+        _lib.check_batch(self.L, self._b, st)
+        return images
+
+    def capture(self, efields, gains, images, reset: bool = True):
+        self._keep = (efields, gains, images)          # the graph reads these buffers
+        e, n, g, im = self._args(efields, gains, images)
+        st = self.L.epic_batch_capture(self._b, e, n, g, im, 1 if reset else 0)
+        _lib.check_batch(self.L, self._b, st)
+
+    def replay(self):
+        _lib.check_batch(self.L, self._b, self.L.epic_batch_replay(self._b))
+
+    def tune(self, efields, gains, images, cache_path: Optional[str] = None) -> bool:
+        e, n, g, im = self._args(efields, gains, images)
+        measured = ctypes.c_int32()
+        path = cache_path.encode() if cache_path else None
+        st = self.L.epic_batch_tune(self._b, e, n, g, im, path, ctypes.byref(measured))
+        _lib.check_batch(self.L, self._b, st)
+        return bool(measured.value)
+
+    def plan(self):
+        out = []
+        for i in range(self.n_blocks):
+            gsz, tb = ctypes.c_int32(), ctypes.c_int32()
+            self.L.epic_batch_plan(self._b, i, ctypes.byref(gsz), ctypes.byref(tb))
+            out.append((gsz.value, tb.value))
+        return out
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self.L.epic_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

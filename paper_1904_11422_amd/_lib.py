@@ -18,7 +18,10 @@ EPIC_FLAG_STAGED, EPIC_FLAG_TIMING = 1, 2
 # Every function declared in include/epic.h, with its ctypes signature.
 EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_image_accumulate",
            "epic_image_backward", "epic_last_timing", "epic_last_kernel_name",
-           "epic_destroy", "epic_last_error")
+           "epic_destroy", "epic_last_error",
+           "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
+           "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
+           "epic_batch_destroy", "epic_batch_last_error")
 
 
 class EpicConfig(ctypes.Structure):
@@ -65,6 +68,25 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_destroy.restype = None
     L.epic_last_error.argtypes = [vp]
     L.epic_last_error.restype = ctypes.c_char_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    L.epic_batch_create.argtypes = [ctypes.POINTER(EpicConfig), i32, ctypes.c_int, vp,
+                                    ctypes.POINTER(vp)]
+    L.epic_batch_create.restype = ctypes.c_int
+    L.epic_batch_set_antennas.argtypes = [vp, i32, dp, dp]
+    L.epic_batch_set_antennas.restype = ctypes.c_int
+    for name in ("epic_batch_accumulate", "epic_batch_capture"):
+        getattr(L, name).argtypes = [vp, pp, i64, pp, pp, i32]
+        getattr(L, name).restype = ctypes.c_int
+    L.epic_batch_replay.argtypes = [vp]
+    L.epic_batch_replay.restype = ctypes.c_int
+    L.epic_batch_tune.argtypes = [vp, pp, i64, pp, pp, ctypes.c_char_p, ctypes.POINTER(i32)]
+    L.epic_batch_tune.restype = ctypes.c_int
+    L.epic_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.epic_batch_plan.restype = ctypes.c_int
+    L.epic_batch_destroy.argtypes = [vp]
+    L.epic_batch_destroy.restype = None
+    L.epic_batch_last_error.argtypes = [vp]
+    L.epic_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -72,4 +94,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 def check(L, ctx, status: int):
     if status != EPIC_OK:
         msg = L.epic_last_error(ctx)
+        raise EpicError(status, msg.decode() if msg else "")
+
+
+def check_batch(L, b, status: int):
+    if status != EPIC_OK:
+        msg = L.epic_batch_last_error(b)
         raise EpicError(status, msg.decode() if msg else "")

@@ -20,8 +20,7 @@ struct AdjointArgs {
   const float2* gains;      // [C][P][A]
   const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
   const uint2* prog;        // gridding programs, as the imager
-  const int4* chan;
-  const uint2* taps;        // [C][A][KK] {cell j*N+i, w bits}
+  const uint2* taps;        // [C][A][KK] {translated cell j*N+i, w bits}
   const float2* twiddle;
   double2* gpartial;        // [W + C - 1][P*A]
   int64_t n_time, total;
@@ -34,8 +33,12 @@ adjoint_kernel(AdjointArgs a) {
   using SH = FusedShape<N>;
   constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, RS = SH::RS;
   constexpr int NPROD = (P == 2) ? 4 : 1;
-  __shared__ float2 X[P * N * RS];
-  __shared__ float2 E[NT * GPT];
+  constexpr int ES = EStride<NT, GPT, P>::value;
+  constexpr int XBASE = P * ES * (int)sizeof(float2);
+  __shared__ float2 lds2[P * ES + P * N * RS]; // E'[p][a] (zero slot at a = A), then the grid
+  char* lds = reinterpret_cast<char*>(lds2);
+  float2* E = lds2;
+  float2* X = lds2 + P * ES;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -49,13 +52,15 @@ adjoint_kernel(AdjointArgs a) {
 
   const int PA = P * a.n_ant;
   const int64_t row_bytes = (int64_t)a.n_chan * PA;
+  int eidx[GPT];
+  init_stage<NT, GPT, ES>(E, eidx, tid, a.n_ant, P);
 
   float ga[S], gb[S];                          // Re(Gxx), Re(Gyy) at owned pixels
   float2 gh[S];                                // (Gxy + conj(Gyx)) / 2
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, j_lo = 0, nb = 0;
+  int c = -1;
   const uint2* prog = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
@@ -82,10 +87,7 @@ adjoint_kernel(AdjointArgs a) {
     if (cc != c) {
       if (c >= 0) flush();
       c = cc;
-      const int4 ci = a.chan[c];
-      j_lo = ci.x;
-      nb = ci.y;
-      prog = a.prog + (int64_t)c * a.L * NT + tid;
+      prog = a.prog + (int64_t)c * a.L * NT;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
         const int k = tid + i * NT;
@@ -118,16 +120,11 @@ adjoint_kernel(AdjointArgs a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    uint2 steps[kStepChunk];
-    load_steps<NT>(steps, prog, 0, a.L);
-    stage_samples<NT, GPT>(E, cur, g, tid, PA);
-    __syncthreads();
-    grid_band<N, P, NT, RS>(X, E, steps, prog, a.L, a.n_ant);
-    __syncthreads();
-    row_pass<N, P, +1>(X, r, tw, j_lo, nb);
+    stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
+    row_pass<N, P, +1>(X, r, tw);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P>(v, X, r, tw, j_lo, nb);
+    column_pass_fwd<N, P>(v, X, r, tw);
 
     // dL/dF* at the owned pixels
 #pragma unroll
@@ -150,12 +147,9 @@ adjoint_kernel(AdjointArgs a) {
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int n1 = 0; n1 < S; ++n1) {
-        const int j = R * n1 + r.n0;
-        if ((unsigned)(j - j_lo) < (unsigned)nb) X[(p * N + j) * RS + kl] = v[p][n1];
-      }
+      for (int n1 = 0; n1 < S / 2; ++n1) X[(p * N + R * n1 + r.n0) * RS + kl] = v[p][n1];
     __syncthreads();
-    row_pass<N, P, -1>(X, r, tw, j_lo, nb);
+    row_pass<N, P, -1>(X, r, tw);
     __syncthreads();
 
     // degrid: dL/de'* at each antenna, times conj(e)

@@ -100,6 +100,28 @@ template <int SG> __device__ __forceinline__ void dft16(float2* x) {
   }
 }
 
+// 8-point DFT whose inputs x[4..7] are zero (they are not read).
+template <int SG> __device__ __forceinline__ void dft8_half(float2* x) {
+  // 4-point DFTs of (a, b, 0, 0): a + b, a + SG i b, a - b, a - SG i b
+  const float2 ib0 = mul_i<SG>(x[2]), ib1 = mul_i<SG>(x[3]);
+  const float2 e0 = cadd(x[0], x[2]), e1 = cadd(x[0], ib0), e2 = csub(x[0], x[2]), e3 = csub(x[0], ib0);
+  const float2 o0 = cadd(x[1], x[3]), o1 = cadd(x[1], ib1), o2 = csub(x[1], x[3]), o3 = csub(x[1], ib1);
+  const float r = 0.70710678118654752440f;
+  float2 t1, t3;
+  if (SG > 0) {
+    t1 = make_float2((o1.x - o1.y) * r, (o1.x + o1.y) * r);
+    t3 = make_float2((-o3.x - o3.y) * r, (o3.x - o3.y) * r);
+  } else {
+    t1 = make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);
+    t3 = make_float2((o3.y - o3.x) * r, (-o3.x - o3.y) * r);
+  }
+  const float2 t2 = mul_i<SG>(o2);
+  x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+  x[1] = cadd(e1, t1); x[5] = csub(e1, t1);
+  x[2] = cadd(e2, t2); x[6] = csub(e2, t2);
+  x[3] = cadd(e3, t3); x[7] = csub(e3, t3);
+}
+
 template <int M, int SG> __device__ __forceinline__ void dft(float2* x) {
   if constexpr (M == 2) dft2<SG>(x[0], x[1]);
   else if constexpr (M == 4) dft4<SG>(x[0], x[1], x[2], x[3]);
@@ -133,13 +155,16 @@ template <> struct Line<128> { static constexpr int S = 16, R = 8, D = 2; };
 // tw[k0] = exp(+2 pi i n0 k0 / N) (conjugated here when SG < 0).
 // The exchange between the passes goes through the line's own slots, skewed
 // by k0 so that the lanes of the exchange hit different LDS banks.
-template <int N, int SG, int NP, typename SlotF>
+// HALFIN: the inputs with n1 >= S/2 are zero and are not read.
+template <int N, int SG, int NP, bool HALFIN = false, typename SlotF>
 __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], const float2* tw,
                                                int n0, float2* lds, SlotF slot) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
+  static_assert(!HALFIN || S == 8, "half-input pass implemented for radix 8");
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    dft<S, SG>(v[p]);
+    if constexpr (HALFIN) dft8_half<SG>(v[p]);
+    else dft<S, SG>(v[p]);
 #pragma unroll
     for (int k0 = 1; k0 < S; ++k0) v[p][k0] = twiddle_mul<SG>(v[p][k0], tw[k0]);
   }

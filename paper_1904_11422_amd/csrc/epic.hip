@@ -18,6 +18,7 @@
 #include "fused.hpp"
 #include "staged.hpp"
 #include "adjoint.hpp"
+#include "split.hpp"
 
 namespace {
 
@@ -49,9 +50,10 @@ struct DevMem {
 // Host-side per-channel geometry (float64 maths, float32 weights).
 struct Geometry {
   int C = 0, A = 0, KK = 0;
-  std::vector<int> j_lo, nb;          // band of rows touched, per channel
-  std::vector<int> cell;              // [C][A][KK] j*N + i
+  std::vector<int> cell;              // [C][A][KK] j*N + i on the centred grid
+  std::vector<int> tcell;             // [C][A][KK] the same taps translated to start at (0, 0)
   std::vector<float> w;               // [C][A][KK]
+  bool fits_half = true;              // every channel's taps fit an N/2 x N/2 block
 };
 
 struct DeviceGuard {
@@ -75,25 +77,31 @@ struct epic_ctx {
   int nprod = 1, nacc = 1, PA = 0;
   int n_cu = 0;
 
-  // path selection
-  bool fused = true;
+  // path selection: fused_ok = the configuration has fused kernels (decided at
+  // init); fused = the current geometry uses them (decided at set_antennas)
+  bool fused_ok = true, fused = false;
   int fused_gpt = 1;
   int fused_w = 0;                    // persistent workgroups (upper bound)
+  int w_override = 0;                 // tuned grid size (0: fused_w)
+  int tb_override = 0;                // tuned staged batch (0: tb)
   int adj_w = 0;
   const char* last_kernel = "none";
 
   // tables
   bool have_geom = false;
   int L = 0;
-  DevMem prog, chan, twiddle, taps;
+  DevMem prog, twiddle, taps;
   DevMem csr_off, csr_ent;
   int nnz = 0;
 
   // workspace
-  DevMem partial;                     // fused: [(W + C - 1)][nacc][N*N]
+  DevMem partial;                     // fused: [(W + C - 1)][nacc][N*N] thread-major
   DevMem gpartial;                    // adjoint: [(W + C - 1)][P*A] complex f64
   DevMem st_e, st_grid, st_acc;       // staged
   int tb = 0;
+  // split-precision matrix form
+  DevMem sp_beta, sp_betamax, sp_bmat, sp_scale, sp_partial;
+  int sp_apad = 0, sp_qb = 0, sp_max_chunks = 0;
 
   // timing
   bool timing = false, timed = false;
@@ -132,6 +140,23 @@ epic_status check_config(const epic_config* c, std::string& m) {
   return EPIC_OK;
 }
 
+// The split-precision matrix form keeps a 32-pixel tile of the matrix in
+// registers: A <= 32 antennas for one polarisation, A <= 16 for two, and the
+// float64 matrix of every channel (C * N^2 * A entries) within 2^24 entries.
+epic_status check_split(const epic_config* c, std::string& m) {
+  const int amax = c->n_pol == 1 ? 16 * epic::kSplitMaxBlocks : 16;
+  if (c->n_ant > amax) {
+    m = "split-precision forms take at most " + std::to_string(amax) + " antennas at n_pol = " +
+        std::to_string(c->n_pol);
+    return EPIC_E_UNSUPPORTED;
+  }
+  if ((double)c->n_chan * c->grid_n * c->grid_n * c->n_ant > (double)(1 << 24)) {
+    m = "split-precision forms: n_chan * N^2 * n_ant above 2^24";
+    return EPIC_E_UNSUPPORTED;
+  }
+  return EPIC_OK;
+}
+
 // Kernel taps of every antenna for every channel (float64), with the grid
 // bounds check.  Tap order: dj outer, di inner.
 epic_status build_geometry(const epic_config& cfg, const double* xy, const double* freq,
@@ -139,7 +164,6 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
   const int N = cfg.grid_n, C = cfg.n_chan, A = cfg.n_ant, K = cfg.kernel_support;
   const int h = K / 2;
   g.C = C; g.A = A; g.KK = K * K;
-  g.j_lo.assign(C, 0); g.nb.assign(C, 0);
   g.cell.assign((size_t)C * A * K * K, 0);
   g.w.assign((size_t)C * A * K * K, 0.f);
   for (int a = 0; a < A; ++a)
@@ -151,9 +175,11 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
       m = "channel frequency must be finite and positive"; return EPIC_E_INVALID;
     }
   const double inv2s2 = 1.0 / (2.0 * cfg.kernel_sigma_cells * cfg.kernel_sigma_cells);
+  g.tcell.assign((size_t)C * A * K * K, 0);
+  g.fits_half = true;
   for (int c = 0; c < C; ++c) {
     const double cell_m = kC0 / freq[c] * cfg.cell_wavelengths;
-    int jmin = N, jmax = -1;
+    int jmin = N, jmax = -1, imin = N, imax = -1;
     for (int a = 0; a < A; ++a) {
       const double X = xy[2 * a] / cell_m + N / 2.0;
       const double Y = xy[2 * a + 1] / cell_m + N / 2.0;
@@ -175,34 +201,51 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
           g.w[o] = (float)wt;
           jmin = std::min(jmin, (int)j);
           jmax = std::max(jmax, (int)j);
+          imin = std::min(imin, (int)i);
+          imax = std::max(imax, (int)i);
         }
     }
-    g.j_lo[c] = jmin;
-    g.nb[c] = jmax - jmin + 1;
+    if (jmax - jmin + 1 > N / 2 || imax - imin + 1 > N / 2) g.fits_half = false;
+    for (size_t o = (size_t)c * A * g.KK; o < (size_t)(c + 1) * A * g.KK; ++o)
+      g.tcell[o] = (g.cell[o] / N - jmin) * N + (g.cell[o] % N - imin);
   }
   return EPIC_OK;
 }
 
-// Per-thread gather programs of the fused kernel.  Every band cell belongs to
-// exactly one thread; its entries (antenna ascending, then tap order) are summed
-// in that order and the cell is written once (zero cells get a write-only
-// step).  Cells are dealt longest-first to the least loaded thread.
-void build_programs(const epic_config& cfg, const Geometry& g, int NT,
-                    std::vector<uint32_t>& out, int& L) {
-  const int N = cfg.grid_n, C = g.C, A = g.A, KK = g.KK;
+// Per-thread gather programs of the fused kernel over the N/2 x N/2 aperture
+// block (translated taps).  Every cell belongs to exactly one thread; its
+// entries (antenna ascending, then tap order) are summed in that order.  A
+// cell with no antenna gets one step that reads the zero slot of E'.  Cells
+// are dealt longest-first to the least loaded thread; lists are padded to a
+// common length L with steps that read the zero slot and write to a spare
+// column of the LDS grid (L above the kernel's fixed-length limit is rounded
+// up to a multiple of its step chunk).
+// Step: {cell byte offset << 16 | E' byte offset, weight bits with the sign
+// bit set on the last entry of a cell}.
+template <int N>
+void build_programs(const Geometry& g, std::vector<uint32_t>& out, int& L) {
+  constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
+  const int C = g.C, A = g.A, KK = g.KK;
   std::vector<std::vector<std::vector<uint32_t>>> per_chan(C);   // [c][thread] -> words
+  auto code = [](int cell_f2, int e) {
+    return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
+  };
+  auto wbits = [](float w, bool last) {
+    uint32_t b;
+    std::memcpy(&b, &w, 4);
+    return last ? (b | epic::STEP_LAST_BIT) : b;
+  };
   L = 1;
   for (int c = 0; c < C; ++c) {
-    const int j_lo = g.j_lo[c], nb = g.nb[c];
-    const int ncell = nb * N;
-    std::vector<std::vector<std::pair<int, float>>> ent(ncell);
+    std::vector<std::vector<std::pair<int, float>>> ent(H * H);
     for (int a = 0; a < A; ++a)
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
-        ent[g.cell[o] - j_lo * N].push_back({a, g.w[o]});
+        const int j = g.tcell[o] / N, i = g.tcell[o] % N;
+        ent[j * H + i].push_back({a, g.w[o]});
       }
-    std::vector<int> order(ncell);
-    for (int i = 0; i < ncell; ++i) order[i] = i;
+    std::vector<int> order(H * H);
+    for (int i = 0; i < H * H; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
       return std::max<size_t>(1, ent[x].size()) > std::max<size_t>(1, ent[y].size());
     });
@@ -214,20 +257,15 @@ void build_programs(const epic_config& cfg, const Geometry& g, int NT,
     for (int idx : order) {
       Load ld = pq.top();
       pq.pop();
-      const int cellabs = idx + j_lo * N;
+      const int cell = (idx / H) * RS + idx % H;
       auto& words = th[ld.second];
       if (ent[idx].empty()) {
-        words.push_back((uint32_t)cellabs | epic::STEP_LAST);
-        words.push_back(0u);
+        words.push_back(code(cell, A));
+        words.push_back(wbits(0.f, true));
       } else {
         for (size_t e = 0; e < ent[idx].size(); ++e) {
-          uint32_t code = (uint32_t)cellabs | epic::STEP_HAS |
-                          ((uint32_t)ent[idx][e].first << epic::STEP_ANT_SHIFT);
-          if (e + 1 == ent[idx].size()) code |= epic::STEP_LAST;
-          uint32_t wb;
-          std::memcpy(&wb, &ent[idx][e].second, 4);
-          words.push_back(code);
-          words.push_back(wb);
+          words.push_back(code(cell, ent[idx][e].first));
+          words.push_back(wbits(ent[idx][e].second, e + 1 == ent[idx].size()));
         }
       }
       ld.first += (int)std::max<size_t>(1, ent[idx].size());
@@ -235,14 +273,22 @@ void build_programs(const epic_config& cfg, const Geometry& g, int NT,
       pq.push(ld);
     }
   }
+  if (L > epic::kMaxFixedSteps) L = (L + epic::kStepChunk - 1) / epic::kStepChunk * epic::kStepChunk;
   out.assign((size_t)C * L * NT * 2, 0u);
   for (int c = 0; c < C; ++c)
     for (int t = 0; t < NT; ++t) {
       const auto& words = per_chan[c][t];
-      for (size_t s = 0; s < words.size() / 2; ++s) {
+      // padding: zero slot, spare column N + (t / N) % 4 of row t % N
+      const uint32_t pad = code((t % N) * RS + N + (t / N) % (RS - N), A);
+      for (int s = 0; s < L; ++s) {
         const size_t o = (((size_t)c * L + s) * NT + t) * 2;
-        out[o] = words[2 * s];
-        out[o + 1] = words[2 * s + 1];
+        if ((size_t)s < words.size() / 2) {
+          out[o] = words[2 * s];
+          out[o + 1] = words[2 * s + 1];
+        } else {
+          out[o] = pad;
+          out[o + 1] = wbits(0.f, true);
+        }
       }
     }
 }
@@ -299,16 +345,18 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   return false;
 }
 
-bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a) {
+bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol;
   const int64_t n = (int64_t)x->cfg.n_chan * N * N;
   const dim3 grid((unsigned)((n + 255) / 256)), block(256);
-#define EPIC_LR(NN, PP)                                                                \
-  if (N == NN && P == PP) {                                                            \
-    hipLaunchKernelGGL((epic::reduce_image_kernel<NN, PP>), grid, block, 0, x->stream, a); \
-    return true;                                                                       \
+#define EPIC_LR(NN, PP, TM)                                                                    \
+  if (N == NN && P == PP && thread_major == TM) {                                              \
+    hipLaunchKernelGGL((epic::reduce_image_kernel<NN, PP, TM>), grid, block, 0, x->stream, a); \
+    return true;                                                                               \
   }
-  EPIC_LR(32, 1) EPIC_LR(32, 2) EPIC_LR(64, 1) EPIC_LR(64, 2) EPIC_LR(128, 1) EPIC_LR(128, 2)
+  EPIC_LR(32, 1, true) EPIC_LR(32, 2, true) EPIC_LR(64, 1, true) EPIC_LR(64, 2, true)
+  EPIC_LR(32, 1, false) EPIC_LR(32, 2, false) EPIC_LR(64, 1, false) EPIC_LR(64, 2, false)
+  EPIC_LR(128, 1, false) EPIC_LR(128, 2, false)
 #undef EPIC_LR
   return false;
 }
@@ -345,6 +393,142 @@ bool launch_staged_fft(epic_ctx* x, float2* grid, int64_t nimg) {
   return true;
 }
 
+// Staged-path workspace: batches of tb samples, intermediates bounded to ~512 MiB.
+bool alloc_staged(epic_ctx* x) {
+  if (x->tb > 0) return true;
+  const epic_config& c = x->cfg;
+  const size_t N = (size_t)c.grid_n;
+  const size_t per_t = (size_t)c.n_chan * c.n_pol * (N * N + c.n_ant) * sizeof(float2);
+  const int tb = (int)std::max<size_t>(1, std::min<size_t>(64, (512ull << 20) / per_t));
+  if (!x->st_e.alloc((size_t)tb * c.n_chan * x->PA * sizeof(float2)) ||
+      !x->st_grid.alloc((size_t)tb * c.n_chan * c.n_pol * N * N * sizeof(float2)) ||
+      !x->st_acc.alloc((size_t)c.n_chan * x->nacc * N * N * sizeof(double)))
+    return false;
+  x->tb = tb;
+  return true;
+}
+
+// Split-precision tables: beta[c][pix][a] = sum_taps w exp(+2 pi i (i kl + j km)/N)
+// in float64 (pix = km*N + kl), its per-channel maximum modulus, and the
+// workspace of the matrix kernels.
+epic_status build_split_tables(epic_ctx* x, const Geometry& g) {
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
+  const int NG = N * N;
+  std::vector<double> cs(N * N), sn(N * N);            // exp(2 pi i u k / N) for u, k < N
+  for (int u = 0; u < N; ++u)
+    for (int k = 0; k < N; ++k) {
+      const double ang = 2.0 * M_PI * (double)((u * k) % N) / (double)N;
+      cs[u * N + k] = std::cos(ang);
+      sn[u * N + k] = std::sin(ang);
+    }
+  std::vector<double2> beta((size_t)C * NG * A);
+  std::vector<double> bmax(C, 0.0);
+  for (int c = 0; c < C; ++c)
+    for (int a = 0; a < A; ++a)
+      for (int km = 0; km < N; ++km)
+        for (int kl = 0; kl < N; ++kl) {
+          double re = 0.0, im = 0.0;
+          for (int k = 0; k < g.KK; ++k) {
+            const size_t o = ((size_t)c * A + a) * g.KK + k;
+            const int j = g.cell[o] / N, i = g.cell[o] % N;
+            const double w = g.w[o];
+            // exp(i (x + y)) with x = 2 pi i kl / N, y = 2 pi j km / N
+            const double cx = cs[i * N + kl], sx = sn[i * N + kl];
+            const double cy = cs[j * N + km], sy = sn[j * N + km];
+            re += w * (cx * cy - sx * sy);
+            im += w * (sx * cy + cx * sy);
+          }
+          beta[((size_t)c * NG + km * N + kl) * A + a] = make_double2(re, im);
+          bmax[c] = std::max(bmax[c], std::hypot(re, im));
+        }
+  const int qb = (A + 15) / 16;
+  const int apad = 16 * qb;
+  const int nacc = P == 2 ? 4 : 1;
+  const size_t per_chunk = (size_t)C * nacc * 2 * NG * sizeof(double);
+  const int max_chunks = (int)std::max<size_t>(1, std::min<size_t>(1024, (256ull << 20) / per_chunk));
+  if (!x->sp_beta.alloc(beta.size() * sizeof(double2)) || !x->sp_betamax.alloc(C * sizeof(double)) ||
+      !x->sp_bmat.alloc((size_t)C * P * epic::kSplitParts * 2 * NG * apad * sizeof(uint16_t)) ||
+      !x->sp_scale.alloc((size_t)C * P * sizeof(float)) ||
+      !x->sp_partial.alloc(per_chunk * max_chunks) ||
+      hipMemcpy(x->sp_beta.p, beta.data(), beta.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(x->sp_betamax.p, bmax.data(), C * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return x->fail(EPIC_E_NOMEM, "split-precision table allocation failed");
+  x->sp_apad = apad;
+  x->sp_qb = qb;
+  x->sp_max_chunks = max_chunks;
+  return EPIC_OK;
+}
+
+template <int P, bool BF, int QB>
+void launch_split_image(epic_ctx* x, const epic::SplitArgs& a, dim3 grid) {
+  hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB>), grid, dim3(256), 0, x->stream, a);
+}
+
+epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                      double* image, int32_t reset) {
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol, A = x->cfg.n_ant;
+  const int NG = N * N;
+  const bool bf = x->cfg.precision == EPIC_SPLIT_BF16;
+  epic::SplitPrepArgs pa;
+  pa.gains = reinterpret_cast<const float2*>(gains);
+  pa.beta = x->sp_beta.as<double2>();
+  pa.beta_max = x->sp_betamax.as<double>();
+  pa.bmat = x->sp_bmat.as<uint16_t>();
+  pa.scale = x->sp_scale.as<float>();
+  pa.n_chan = C;
+  pa.n_pol = P;
+  pa.n_ant = A;
+  pa.a_pad = x->sp_apad;
+  pa.ng = NG;
+  if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, dim3(C * P), dim3(256), 0, x->stream, pa);
+  else hipLaunchKernelGGL(epic::split_prep_kernel<false>, dim3(C * P), dim3(256), 0, x->stream, pa);
+  int64_t chunk = (n_time + x->sp_max_chunks - 1) / x->sp_max_chunks;
+  chunk = std::max<int64_t>(512, (chunk + 31) / 32 * 32);
+  const int n_chunks = (int)((n_time + chunk - 1) / chunk);
+  epic::SplitArgs sa;
+  sa.efield = efield;
+  sa.bmat = x->sp_bmat.as<uint16_t>();
+  sa.partial = x->sp_partial.as<double>();
+  sa.n_time = n_time;
+  sa.n_chan = C;
+  sa.n_ant = A;
+  sa.a_pad = x->sp_apad;
+  sa.ng = NG;
+  sa.chunk = (int)chunk;
+  sa.n_chunks = n_chunks;
+  const dim3 grid((unsigned)((NG / 32 + 3) / 4), (unsigned)n_chunks, (unsigned)C);
+  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  const int qb = x->sp_qb;
+  if (P == 1) {
+    if (bf) { if (qb == 1) launch_split_image<1, true, 1>(x, sa, grid); else launch_split_image<1, true, 2>(x, sa, grid); }
+    else    { if (qb == 1) launch_split_image<1, false, 1>(x, sa, grid); else launch_split_image<1, false, 2>(x, sa, grid); }
+  } else {
+    if (bf) launch_split_image<2, true, 1>(x, sa, grid);
+    else launch_split_image<2, false, 1>(x, sa, grid);
+  }
+  x->last_kernel = "split_image_kernel";
+  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  epic::SplitReduceArgs ra;
+  ra.partial = x->sp_partial.as<double>();
+  ra.scale = x->sp_scale.as<float>();
+  ra.image = image;
+  ra.n_chan = C;
+  ra.n_chunks = n_chunks;
+  ra.ng = NG;
+  ra.n = N;
+  ra.reset = reset ? 1 : 0;
+  const unsigned rg = (unsigned)(((int64_t)C * NG + 255) / 256);
+  if (P == 2) hipLaunchKernelGGL(epic::split_reduce_kernel<2>, dim3(rg), dim3(256), 0, x->stream, ra);
+  else hipLaunchKernelGGL(epic::split_reduce_kernel<1>, dim3(rg), dim3(256), 0, x->stream, ra);
+  if (x->timing) {
+    (void)hipEventRecord(x->ev[2], x->stream);
+    x->timed = true;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
 unsigned grid_for(int64_t n, int64_t cap = 1 << 16) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 255) / 256));
 }
@@ -359,6 +543,7 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   *out = nullptr;
   std::string m;
   epic_status s = check_config(cfg, m);
+  if (s == EPIC_OK && cfg->precision != EPIC_FP32) s = check_split(cfg, m);
   if (s != EPIC_OK) { g_init_error = m; return s; }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
@@ -400,15 +585,15 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   }
 
   const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
-  x->fused = !want_staged && N <= 64;
-  if (x->fused) {
+  x->fused_ok = !want_staged && N <= 64 && cfg->precision == EPIC_FP32;
+  if (x->fused_ok) {
     const int NT = fused_threads(N);
     int gpt = (x->PA + NT - 1) / NT;
     gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
-    if (gpt == 0) x->fused = false;
+    if (gpt == 0) x->fused_ok = false;
     else x->fused_gpt = gpt;
   }
-  if (x->fused) {
+  if (x->fused_ok) {
     const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
     x->fused_w = bpc * x->n_cu;
     const size_t slots = (size_t)x->fused_w + cfg->n_chan - 1;
@@ -421,17 +606,6 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
     if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double))) {
       g_init_error = "gradient workspace allocation failed";
-      delete x;
-      return EPIC_E_NOMEM;
-    }
-  } else {
-    // staged: batches of tb samples, intermediates bounded to ~512 MiB
-    const size_t per_t = (size_t)cfg->n_chan * cfg->n_pol * ((size_t)N * N + cfg->n_ant) * sizeof(float2);
-    x->tb = (int)std::max<size_t>(1, std::min<size_t>(64, (512ull << 20) / per_t));
-    if (!x->st_e.alloc((size_t)x->tb * cfg->n_chan * x->PA * sizeof(float2)) ||
-        !x->st_grid.alloc((size_t)x->tb * cfg->n_chan * cfg->n_pol * N * N * sizeof(float2)) ||
-        !x->st_acc.alloc((size_t)cfg->n_chan * x->nacc * N * N * sizeof(double))) {
-      g_init_error = "staged workspace allocation failed";
       delete x;
       return EPIC_E_NOMEM;
     }
@@ -467,29 +641,34 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
   if (hipStreamSynchronize(x->stream) != hipSuccess)
     return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
   x->have_geom = false;
-
-  // adjoint / staged tables: taps [C][A][KK] {cell, w}
-  std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
-  for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
-    taps[2 * o] = (uint32_t)g.cell[o];
-    std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
+  if (x->cfg.precision != EPIC_FP32) {
+    s = build_split_tables(x, g);
+    if (s != EPIC_OK) return s;
+    x->have_geom = true;
+    return EPIC_OK;
   }
-  if (!x->taps.alloc(taps.size() * 4) ||
-      hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-    return x->fail(EPIC_E_NOMEM, "tap table upload failed");
+  // The fused kernels need every channel's taps inside an N/2 x N/2 block;
+  // larger apertures (aliased images) run the staged kernels.
+  x->fused = x->fused_ok && g.fits_half;
 
   if (x->fused) {
+    // adjoint taps [C][A][KK] {translated cell, w}
+    std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
+    for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
+      taps[2 * o] = (uint32_t)g.tcell[o];
+      std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
+    }
     std::vector<uint32_t> prog;
     int L = 0;
-    build_programs(x->cfg, g, fused_threads(N), prog, L);
-    std::vector<int4> chan(C);
-    for (int c = 0; c < C; ++c) chan[c] = make_int4(g.j_lo[c], g.nb[c], L, 0);
-    if (!x->prog.alloc(prog.size() * 4) || !x->chan.alloc(C * sizeof(int4)) ||
-        hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(x->chan.p, chan.data(), C * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess)
+    if (N == 32) build_programs<32>(g, prog, L);
+    else build_programs<64>(g, prog, L);
+    if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
+        hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
       return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
     x->L = L;
   } else {
+    if (!alloc_staged(x)) return x->fail(EPIC_E_NOMEM, "staged workspace allocation failed");
     // per-cell CSR over the whole grid, entries in (antenna, tap) order
     const int npix = N * N, nnz = A * g.KK;
     std::vector<int> off((size_t)C * (npix + 1));
@@ -526,9 +705,11 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
   if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
   if (!efield || !gains || !image) return x->fail(EPIC_E_INVALID, "NULL device pointer");
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
-  if (x->cfg.precision != EPIC_FP32)
-    return x->fail(EPIC_E_UNSUPPORTED, "split-precision forms run through epic_split_* calls");
   DeviceGuard guard(x->device);
+  if (x->cfg.precision != EPIC_FP32) {
+    (void)hipGetLastError();
+    return run_split(x, efield, n_time, gains, image, reset);
+  }
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
@@ -538,7 +719,6 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     a.efield = efield;
     a.gains = reinterpret_cast<const float2*>(gains);
     a.prog = x->prog.as<uint2>();
-    a.chan = x->chan.as<int4>();
     a.twiddle = x->twiddle.as<float2>();
     a.partial = x->partial.as<double>();
     a.n_time = n_time;
@@ -546,7 +726,8 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    a.W = (int)std::min<int64_t>(x->fused_w, total);
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w;
+    a.W = (int)std::min<int64_t>(w_max, total);
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
@@ -558,11 +739,12 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     r.n_chan = C;
     r.W = a.W;
     r.reset = reset ? 1 : 0;
-    launch_reduce(x, r);
+    launch_reduce(x, r, true);
   } else {
     const int npix = N * N;
-    for (int64_t t0 = 0; t0 < n_time; t0 += x->tb) {
-      const int tb = (int)std::min<int64_t>(x->tb, n_time - t0);
+    const int tbu = x->tb_override > 0 ? std::min(x->tb_override, x->tb) : x->tb;
+    for (int64_t t0 = 0; t0 < n_time; t0 += tbu) {
+      const int tb = (int)std::min<int64_t>(tbu, n_time - t0);
       epic::StagedUnpackArgs u;
       u.efield = efield;
       u.gains = reinterpret_cast<const float2*>(gains);
@@ -612,7 +794,7 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     r.n_chan = C;
     r.W = 1;
     r.reset = reset ? 1 : 0;
-    launch_reduce(x, r);
+    launch_reduce(x, r, false);
   }
   if (x->timing) {
     (void)hipEventRecord(x->ev[2], x->stream);
@@ -631,7 +813,8 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
     return x->fail(EPIC_E_INVALID, "NULL device pointer");
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
   if (!x->fused || x->cfg.precision != EPIC_FP32)
-    return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path (N <= 64)");
+    return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path "
+                   "(N <= 64, aperture within N/2 x N/2 cells)");
   DeviceGuard guard(x->device);
   const int C = x->cfg.n_chan;
   const int64_t total = (int64_t)C * n_time;
@@ -642,7 +825,6 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.gains = reinterpret_cast<const float2*>(gains);
   a.grad_image = reinterpret_cast<const double2*>(grad_image);
   a.prog = x->prog.as<uint2>();
-  a.chan = x->chan.as<int4>();
   a.taps = x->taps.as<uint2>();
   a.twiddle = x->twiddle.as<float2>();
   a.gpartial = x->gpartial.as<double2>();
@@ -698,9 +880,11 @@ void epic_destroy(epic_ctx* x) {
     (void)hipStreamSynchronize(x->stream);
     for (auto& e : x->ev)
       if (e) (void)hipEventDestroy(e);
-    x->prog.reset(); x->chan.reset(); x->twiddle.reset(); x->taps.reset();
+    x->prog.reset(); x->twiddle.reset(); x->taps.reset();
     x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset();
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
+    x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
+    x->sp_partial.reset();
   }
   delete x;
 }
@@ -710,3 +894,5 @@ const char* epic_last_error(const epic_ctx* x) {
 }
 
 }  // extern "C"
+
+#include "batch.hpp"

@@ -5,44 +5,71 @@
 //   1. unpack the P*A 4+4-bit samples of (t, c) and multiply by the gains
 //      (paper Sec. 3.2), into LDS;
 //   2. grid them with the illumination kernel (Sec. 2.1, Eq. (4)-(5)) by a
-//      gather: every thread runs a precomputed list of (cell, antenna, weight)
-//      steps and writes whole cells, so no two threads touch the same cell and
-//      no atomics are needed; only the rows the aperture touches (the "band")
-//      are gridded and transformed along rows;
+//      gather: every thread runs a precomputed list of (cell, sample, weight)
+//      steps and owns whole cells, so no atomics are needed;
 //   3. transform rows then columns with the +i sign (Sec. 2.1, Eq. (5));
 //      the row transform works in place in each row's LDS storage, the column
-//      transform reads the band rows and keeps its results in registers;
+//      transform keeps its results in registers;
 //   4. form XX, YY and XY (YX = conj XY) for the pixels each thread owns and
-//      add them to float64 accumulators held in registers (Sec. 2.1, Sec. 3.2).
+//      add them to float32 block sums, flushed to float64 every KBLOCK samples
+//      (Sec. 2.1, Sec. 3.2: products accumulated over time).
 //
-// At a channel boundary (and at the end of its range) a workgroup writes its
-// float64 sums to its own partial-image slot; a second kernel adds the slots
+// Every channel's aperture is translated by whole cells so that its kernel
+// taps start at row 0 and column 0 (a common whole-cell shift multiplies both
+// polarisations' transforms by the same phase ramp, so every product is
+// unchanged).  The kernel requires the taps to fit the N/2 x N/2 corner of the
+// grid -- the condition for an unaliased image -- so only N/2 rows are
+// transformed along rows and the first radix stage of every line transform
+// has half of its inputs equal to zero.
+//
+// At a channel boundary (and at the end of its range) a workgroup adds its
+// sums into its own float64 partial-image slot; a second kernel adds the slots
 // of each channel in workgroup order.
 #pragma once
 #include "dft.hpp"
 
 namespace epic {
 
-// Gridding step encoding (one uint2 per step: {code, weight bits}).
-constexpr uint32_t STEP_CELL_MASK = 0x3FFFu;   // cell index j*N + i (N <= 128)
-constexpr uint32_t STEP_HAS = 1u << 14;        // accumulate w * E'[ant]
-constexpr uint32_t STEP_LAST = 1u << 15;       // write the cell, restart the sum
-constexpr int STEP_ANT_SHIFT = 16;             // antenna index in bits 16..31
+// Gridding step: {code, weight bits}.  code = LDS byte offset of the cell
+// (pol 0) << 16 | byte offset of E'[e] (pol 0); the weight's sign bit marks
+// the last entry of a cell (the weights themselves are >= 0).  Every step
+// reads E' of both polarisations, adds |w| * E' to the running sums, stores
+// them to the cell and restarts the sums after the last entry.  Cells with no
+// antenna read the zero slot of E'; padding steps write to a spare column.
+constexpr int STEP_CELL_SHIFT = 16;
+constexpr uint32_t STEP_E_MASK = 0xFFFFu;
+constexpr uint32_t STEP_LAST_BIT = 0x80000000u; // in the weight word
+constexpr int kMaxFixedSteps = 8;              // longer lists run in chunks of 4
+constexpr int kStepChunk = 4;
 
 template <int N> struct FusedShape {
   static constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
   static constexpr int NT = N * R;             // threads per workgroup
   static constexpr int CPW = 64 / R;           // columns (or rows) per wave
-  static constexpr int RS = N + 4;             // LDS row stride in float2
+  // LDS row stride in float2 (spare columns after N); with the lane roles
+  // below every access of the two line passes is free of LDS bank conflicts
+  // (32 banks of 4 bytes; paired 8-byte accesses by groups of 16 lanes)
+  static constexpr int RS = N == 32 ? N + 1 : N + 4;
+  static constexpr int H = N / 2;              // aperture block side
+  static constexpr int KBLOCK = 128;           // samples summed in float32 before a float64 flush
+  // waves per SIMD the register budget is sized for: two resident workgroups
+  // per CU (4 waves/SIMD, <= 128 VGPRs) at N = 64
+  static constexpr int MIN_WAVES_PER_EU = 4;
+};
+
+// E' stride between polarisations: the largest A a variant takes (NT*GPT/P)
+// plus a zero slot, rounded to 64 float2 so that both polarisations load with
+// one paired LDS read whose second offset is an immediate.
+template <int NT, int GPT, int P> struct EStride {
+  static constexpr int value = (NT * GPT) / P + 64;
 };
 
 struct FusedArgs {
   const uint8_t* efield;    // [T][C][P][A]
   const float2* gains;      // [C][P][A]
   const uint2* prog;        // [C][L][NT]
-  const int4* chan;         // [C] {j_lo, nb, L, 0}
   const float2* twiddle;    // [N] exp(+2 pi i k / N)
-  double* partial;          // [W + C - 1][NACC][N*N], pixel = km*N + kl
+  double* partial;          // [W + C - 1][NACC][S][NT] (thread-major)
   int64_t n_time;
   int64_t total;            // C * T
   int n_chan, n_ant, L, W;
@@ -53,18 +80,26 @@ __device__ __forceinline__ int64_t range_begin(int64_t w, int64_t total, int64_t
   return (w * total) / W;
 }
 
-// Lane roles shared by the row and column passes: the R lanes of a line are
-// n0-major inside a wave (lane = n0 * CPW + sub), so both passes use the same
-// twiddles.
+// Lane roles shared by the row and column passes (so both use the same
+// twiddles): n0 is the lane's index inside its line, sub the line of the
+// wave.  R = 8: each group of 16 lanes holds 4 n0 x 4 lines (lane = 16 G +
+// 4 a + b, n0 = 4 (G >> 1) + a, sub = 4 (G & 1) + b), which makes the row and
+// the column accesses the same 4 x 4 shape.  R = 4: lane = n0 * CPW + sub.
 template <int N> struct Roles {
   int tid, wave, n0, sub, kl;
-  __device__ __forceinline__ explicit Roles(int t) {
-    constexpr int CPW = FusedShape<N>::CPW;
+  __host__ __device__ __forceinline__ explicit Roles(int t) {
+    constexpr int R = FusedShape<N>::R, CPW = FusedShape<N>::CPW;
     tid = t;
     wave = t >> 6;
     const int lane = t & 63;
-    n0 = lane / CPW;
-    sub = lane % CPW;
+    if (R == 8) {
+      const int G = lane >> 4, a = (lane >> 2) & 3, b = lane & 3;
+      n0 = 4 * (G >> 1) + a;
+      sub = 4 * (G & 1) + b;
+    } else {
+      n0 = lane / CPW;
+      sub = lane % CPW;
+    }
     kl = wave * CPW + sub;
   }
 };
@@ -75,83 +110,143 @@ __device__ __forceinline__ float2 unpack_ci4(uint32_t b) {
                      (float)((v & 0xF) - ((v & 0x8) ? 16 : 0)));
 }
 
-// 1. E'[k] = g[k] * e[k] for the items k = tid + i*NT of this thread.
-template <int NT, int GPT>
-__device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[GPT],
-                                              const float2 (&g)[GPT], int tid, int PA) {
+// Slots of E' for this thread's items k = tid + i*NT (k = p*A + a), and the
+// zero slot (a = A) of each polarisation.
+template <int NT, int GPT, int ES>
+__device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid, int n_ant, int P) {
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
     const int k = tid + i * NT;
-    if (k < PA) {
-      const float2 e = unpack_ci4(cur[i]);
-      E[k] = cmul(g[i], e);
-    }
+    const int p = k >= n_ant ? 1 : 0;
+    eidx[i] = k + p * (ES - n_ant);
+  }
+  if (tid < P) E[tid * ES + n_ant] = make_float2(0.f, 0.f);
+}
+
+// 1. E'[p][a] = g * e.
+template <int NT, int GPT>
+__device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[GPT],
+                                              const float2 (&g)[GPT], const int (&eidx)[GPT],
+                                              int tid, int PA) {
+#pragma unroll
+  for (int i = 0; i < GPT; ++i) {
+    const int k = tid + i * NT;
+    if (k < PA) E[eidx[i]] = cmul(g[i], unpack_ci4(cur[i]));
   }
 }
 
-constexpr int kStepChunk = 16;
-
-template <int NT>
-__device__ __forceinline__ void load_steps(uint2 (&steps)[kStepChunk], const uint2* prog, int st0,
-                                           int L) {
-#pragma unroll
-  for (int st = 0; st < kStepChunk; ++st)
-    steps[st] = (st0 + st < L) ? prog[(int64_t)(st0 + st) * NT] : make_uint2(0u, 0u);
+// One gridding step on the running sums (s0, s1) of the current cell.
+// lds is the start of the shared buffer: E' at byte 0, the grid at xbase.
+template <int N, int P, int RS, int ES>
+__device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, float2 e0, float2 e1,
+                                          float2& s0, float2& s1) {
+  const float w = fabsf(__uint_as_float(step.y));
+  s0.x = fmaf(w, e0.x, s0.x);
+  s0.y = fmaf(w, e0.y, s0.y);
+  if (P == 2) {
+    s1.x = fmaf(w, e1.x, s1.x);
+    s1.y = fmaf(w, e1.y, s1.y);
+  }
+  float2* cell = reinterpret_cast<float2*>(lds + xbase + (step.x >> STEP_CELL_SHIFT));
+  cell[0] = s0;
+  if (P == 2) cell[N * RS] = s1;
+  const bool last = (int)step.y < 0;
+  s0 = last ? make_float2(0.f, 0.f) : s0;
+  s1 = last ? make_float2(0.f, 0.f) : s1;
 }
 
-// 2. Gather gridding of the band cells, both polarisations per step.  The
-// first chunk of steps has been loaded by the caller.
-template <int N, int P, int NT, int RS>
-__device__ __forceinline__ void grid_band(float2* X, const float2* E, uint2 (&steps)[kStepChunk],
-                                          const uint2* prog, int L, int n_ant) {
+template <int P, int ES>
+__device__ __forceinline__ void read_e(const char* lds, uint2 step, float2& e0, float2& e1) {
+  const float2* e = reinterpret_cast<const float2*>(lds + (step.x & STEP_E_MASK));
+  e0 = e[0];
+  if (P == 2) e1 = e[ES];
+}
+
+// 2. Gather gridding with exactly LS steps, already loaded into registers.
+template <int N, int P, int RS, int ES, int LS>
+__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[kMaxFixedSteps]) {
+  float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int st0 = 0; st0 < LS; st0 += kStepChunk) {      // E' reads in groups of 4
+    constexpr int G = kStepChunk;
+    float2 e0[G], e1[G];
+#pragma unroll
+    for (int st = 0; st < G; ++st)
+      if (st0 + st < LS) read_e<P, ES>(lds, steps[st0 + st], e0[st], e1[st]);
+#pragma unroll
+    for (int st = 0; st < G; ++st)
+      if (st0 + st < LS) grid_step<N, P, RS, ES>(lds, xbase, steps[st0 + st], e0[st], e1[st], s0, s1);
+  }
+}
+
+// 2'. Gather gridding of a long list (L a multiple of kStepChunk).
+template <int N, int P, int RS, int ES>
+__device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* prog, int stride, int L) {
   float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
   for (int st0 = 0; st0 < L; st0 += kStepChunk) {
-    if (st0 > 0) load_steps<NT>(steps, prog, st0, L);
+    uint2 steps[kStepChunk];
+    float2 e0[kStepChunk], e1[kStepChunk];
 #pragma unroll
-    for (int st = 0; st < kStepChunk; ++st) {
-      const uint32_t code = steps[st].x;
-      const float w = __uint_as_float(steps[st].y);
-      if (code & STEP_HAS) {
-        const int ant = (int)(code >> STEP_ANT_SHIFT);
-        const float2 e0 = E[ant];
-        s0.x = fmaf(w, e0.x, s0.x);
-        s0.y = fmaf(w, e0.y, s0.y);
-        if (P == 2) {
-          const float2 e1 = E[n_ant + ant];
-          s1.x = fmaf(w, e1.x, s1.x);
-          s1.y = fmaf(w, e1.y, s1.y);
-        }
-      }
-      if (code & STEP_LAST) {
-        const int cell = (int)(code & STEP_CELL_MASK);
-        const int j = cell / N, i = cell % N;
-        X[j * RS + i] = s0;
-        if (P == 2) X[(N + j) * RS + i] = s1;
-        s0 = make_float2(0.f, 0.f);
-        s1 = make_float2(0.f, 0.f);
-      }
-    }
+    for (int st = 0; st < kStepChunk; ++st) steps[st] = prog[(st0 + st) * stride];
+#pragma unroll
+    for (int st = 0; st < kStepChunk; ++st) read_e<P, ES>(lds, steps[st], e0[st], e1[st]);
+#pragma unroll
+    for (int st = 0; st < kStepChunk; ++st) grid_step<N, P, RS, ES>(lds, xbase, steps[st], e0[st], e1[st], s0, s1);
   }
 }
 
-// 3a. Row transforms of the P*nb band rows, in place (each row private to the
-// R lanes of one wave).
+// Steps 1-2 of one sample: load the gridding program (exactly L steps for
+// L <= kMaxFixedSteps), stage E', barrier, grid, barrier.  prog is the
+// channel's program [L][NT]; the switch on L is uniform over the workgroup.
+template <int N, int P, int NT, int RS, int ES, int GPT>
+__device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, const uint2* prog,
+                                               int L, const uint32_t (&cur)[GPT],
+                                               const float2 (&g)[GPT], const int (&eidx)[GPT],
+                                               int tid, int PA) {
+  if (L <= kMaxFixedSteps) {
+    uint2 steps[kMaxFixedSteps];
+#pragma unroll
+    for (int st = 0; st < kMaxFixedSteps; ++st)
+      if (st < L) steps[st] = prog[st * NT + tid];
+    stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
+    __syncthreads();
+    switch (L) {
+      case 1: grid_fixed<N, P, RS, ES, 1>(lds, xbase, steps); break;
+      case 2: grid_fixed<N, P, RS, ES, 2>(lds, xbase, steps); break;
+      case 3: grid_fixed<N, P, RS, ES, 3>(lds, xbase, steps); break;
+      case 4: grid_fixed<N, P, RS, ES, 4>(lds, xbase, steps); break;
+      case 5: grid_fixed<N, P, RS, ES, 5>(lds, xbase, steps); break;
+      case 6: grid_fixed<N, P, RS, ES, 6>(lds, xbase, steps); break;
+      case 7: grid_fixed<N, P, RS, ES, 7>(lds, xbase, steps); break;
+      default: grid_fixed<N, P, RS, ES, 8>(lds, xbase, steps); break;
+    }
+  } else {
+    stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
+    __syncthreads();
+    grid_chunked<N, P, RS, ES>(lds, xbase, prog + tid, NT, L);
+  }
+  __syncthreads();
+}
+
+// 3a. Row transforms of the H = N/2 aperture rows of each polarisation, in
+// place (each row private to the R lanes of one wave).  SG > 0: forward, the
+// row holds cells at columns < H.  SG < 0: adjoint, the row holds the forward
+// output layout and the columns < H of the result are written back.
 template <int N, int P, int SG>
-__device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw, int j_lo,
-                                         int nb) {
-  constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
+__device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw) {
+  constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D, H = N / 2;
   constexpr int NT = FusedShape<N>::NT, CPW = FusedShape<N>::CPW, RS = FusedShape<N>::RS;
-  for (int line0 = r.wave * CPW; line0 < P * nb; line0 += NT / R) {
+  for (int line0 = r.wave * CPW; line0 < P * H; line0 += NT / R) {
     const int line = line0 + r.sub;
-    if (line < P * nb) {
-      const int p = line / nb;
-      const int j = j_lo + (line - p * nb);
+    if (line < P * H) {
+      const int p = line / H;
+      const int j = line - p * H;
       float2* row = X + (p * N + j) * RS;
       float2 v[1][S];
       if (SG > 0) {
 #pragma unroll
-        for (int n1 = 0; n1 < S; ++n1) v[0][n1] = row[R * n1 + r.n0];
-        line_transform<N, +1, 1>(v, tw, r.n0, row, [](int, int s) { return s; });
+        for (int n1 = 0; n1 < S / 2; ++n1) v[0][n1] = row[R * n1 + r.n0];
+        line_transform<N, +1, 1, true>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
         for (int q = 0; q < D; ++q)
 #pragma unroll
@@ -163,39 +258,42 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
           for (int k1 = 0; k1 < R; ++k1) v[0][q * R + k1] = row[r.n0 * D + q + S * k1];
         line_transform_rev<N, -1, 1>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
-        for (int n1 = 0; n1 < S; ++n1) row[R * n1 + r.n0] = v[0][n1];
+        for (int n1 = 0; n1 < S / 2; ++n1) row[R * n1 + r.n0] = v[0][n1];
       }
     }
   }
 }
 
-// 3b. Forward column transforms of column r.kl for all polarisations; rows
-// outside the band are zero.  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
+// 3b. Forward column transforms of column r.kl for all polarisations; only
+// rows < H are nonzero.  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
 template <int N, int P>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
-                                                const Roles<N>& r, const float2* tw, int j_lo,
-                                                int nb) {
+                                                const Roles<N>& r, const float2* tw) {
   constexpr int S = Line<N>::S, R = Line<N>::R, RS = FusedShape<N>::RS;
   const int kl = r.kl;
 #pragma unroll
-  for (int p = 0; p < P; ++p)
+  for (int p = 0; p < P; ++p) {                 // one polarisation at a time
+    float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
 #pragma unroll
-    for (int n1 = 0; n1 < S; ++n1) {
-      const int j = R * n1 + r.n0;
-      v[p][n1] = ((unsigned)(j - j_lo) < (unsigned)nb) ? X[(p * N + j) * RS + kl]
-                                                       : make_float2(0.f, 0.f);
-    }
-  line_transform<N, +1, P>(v, tw, r.n0, X, [kl](int p, int s) { return (p * N + s) * RS + kl; });
+    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[(p * N + R * n1 + r.n0) * RS + kl];
+    line_transform<N, +1, 1, true>(vp, tw, r.n0, X + p * N * RS,
+                                   [kl](int, int s) { return s * RS + kl; });
+  }
 }
 
 template <int N, int P, int GPT>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_image_kernel(FusedArgs a) {
   using SH = FusedShape<N>;
-  constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, RS = SH::RS;
+  constexpr int S = SH::S, NT = SH::NT, RS = SH::RS, KB = SH::KBLOCK;
   constexpr int NACC = (P == 2) ? 4 : 1;
-  __shared__ float2 X[P * N * RS];             // gridded aperture / row transforms
-  __shared__ float2 E[NT * GPT];               // calibrated samples E'[p][a]
+  constexpr int ES = EStride<NT, GPT, P>::value;
+  constexpr int XBASE = P * ES * (int)sizeof(float2);
+  __shared__ float2 lds2[P * ES + P * N * RS]; // E'[p][a] (zero slot at a = A), then the grid
+  char* lds = reinterpret_cast<char*>(lds2);
+  float2* E = lds2;
+  float2* X = lds2 + P * ES;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -209,11 +307,13 @@ fused_image_kernel(FusedArgs a) {
 
   const int PA = P * a.n_ant;
   const int64_t row_bytes = (int64_t)a.n_chan * PA;   // bytes per time sample
+  int eidx[GPT];
+  init_stage<NT, GPT, ES>(E, eidx, tid, a.n_ant, P);
 
-  double acc[S][NACC];
+  float acc[S][NACC];                          // float32 sums over <= KB samples
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, j_lo = 0, nb = 0;
+  int c = -1, nblk = 0, nflush = 0;
   const uint2* prog = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
@@ -224,18 +324,19 @@ fused_image_kernel(FusedArgs a) {
       dst[i] = (k < PA) ? (uint32_t)src[k] : 0u;
     }
   };
-
+  // add the float32 block sums into this workgroup's float64 slot of channel c
   auto flush = [&]() {
-    double* out = a.partial + (int64_t)(blockIdx.x + c) * NACC * N * N;
+    double* out = a.partial + (int64_t)(blockIdx.x + c) * NACC * S * NT + tid;
 #pragma unroll
-    for (int q = 0; q < D; ++q)
+    for (int u = 0; u < NACC; ++u)
 #pragma unroll
-      for (int k1 = 0; k1 < R; ++k1) {
-        const int km = r.n0 * D + q + S * k1;
-#pragma unroll
-        for (int u = 0; u < NACC; ++u)
-          out[(int64_t)u * N * N + km * N + r.kl] = acc[q * R + k1][u];
+      for (int i = 0; i < S; ++i) {
+        double* o = out + (u * S + i) * NT;
+        *o = (nflush ? *o : 0.0) + (double)acc[i][u];
+        acc[i][u] = 0.f;
       }
+    ++nflush;
+    nblk = 0;
   };
 
   // current sample (cc, tt); one division per workgroup
@@ -246,19 +347,19 @@ fused_image_kernel(FusedArgs a) {
     if (cc != c) {                             // channel segment starts
       if (c >= 0) flush();
       c = cc;
-      const int4 ci = a.chan[c];
-      j_lo = ci.x;
-      nb = ci.y;
-      prog = a.prog + (int64_t)c * a.L * NT + tid;
+      nflush = 0;
+      prog = a.prog + (int64_t)c * a.L * NT;
 #pragma unroll
       for (int i = 0; i < S; ++i)
 #pragma unroll
-        for (int u = 0; u < NACC; ++u) acc[i][u] = 0.0;
+        for (int u = 0; u < NACC; ++u) acc[i][u] = 0.f;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
         const int k = tid + i * NT;
         g[i] = (k < PA) ? a.gains[(int64_t)c * PA + k] : make_float2(0.f, 0.f);
       }
+    } else if (nblk == KB) {
+      flush();
     }
     uint32_t cur[GPT];
 #pragma unroll
@@ -267,37 +368,35 @@ fused_image_kernel(FusedArgs a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    uint2 steps[kStepChunk];
-    load_steps<NT>(steps, prog, 0, a.L);       // latency overlaps the barrier below
-    stage_samples<NT, GPT>(E, cur, g, tid, PA);
-    __syncthreads();
-    grid_band<N, P, NT, RS>(X, E, steps, prog, a.L, a.n_ant);
-    __syncthreads();
-    row_pass<N, P, +1>(X, r, tw, j_lo, nb);
+    stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
+    row_pass<N, P, +1>(X, r, tw);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P>(v, X, r, tw, j_lo, nb);
+    column_pass_fwd<N, P>(v, X, r, tw);
 
-    // 4. polarisation products into float64 sums
+    // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
 #pragma unroll
     for (int i = 0; i < S; ++i) {
       const float2 fx = v[0][i];
-      acc[i][0] += (double)fmaf(fx.x, fx.x, fx.y * fx.y);
+      acc[i][0] = fmaf(fx.y, fx.y, fmaf(fx.x, fx.x, acc[i][0]));
       if (P == 2) {
         const float2 fy = v[P - 1][i];
-        acc[i][1 % NACC] += (double)fmaf(fy.x, fy.x, fy.y * fy.y);
-        acc[i][2 % NACC] += (double)fmaf(fx.x, fy.x, fx.y * fy.y);
-        acc[i][3 % NACC] += (double)fmaf(fx.y, fy.x, -fx.x * fy.y);
+        acc[i][1 % NACC] = fmaf(fy.y, fy.y, fmaf(fy.x, fy.x, acc[i][1 % NACC]));
+        acc[i][2 % NACC] = fmaf(fx.y, fy.y, fmaf(fx.x, fy.x, acc[i][2 % NACC]));
+        acc[i][3 % NACC] = fmaf(-fx.x, fy.y, fmaf(fx.y, fy.x, acc[i][3 % NACC]));
       }
     }
+    ++nblk;
   }
   flush();
 }
 
 // image[c][prod][qm][ql] (+)= sum over the workgroups covering channel c of
-// their partial slot, in workgroup order.  One thread per (c, pixel).
+// their partial slot, in workgroup order.  THREAD_MAJOR: slots are
+// [NACC][S][NT] as written by the fused kernel (value i of thread tid);
+// otherwise [NACC][N*N] in natural pixel order (staged path, W = 1).
 struct ReduceArgs {
-  const double* partial;    // [W + C - 1][NACC][N*N]
+  const double* partial;
   double* image;            // complex128 [C][NPROD][N][N]
   int64_t n_time, total;
   int n_chan, W, reset;
@@ -309,15 +408,31 @@ __device__ __forceinline__ int64_t owner_of(int64_t f, int64_t total, int64_t W)
   return ((f + 1) * W + total - 1) / total - 1;
 }
 
-template <int N, int P>
+// Pixel (km, kl) owned by value i of thread tid in the fused kernel.
+template <int N> __device__ __forceinline__ void owned_pixel(int tid, int i, int& km, int& kl) {
+  constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
+  const Roles<N> r(tid);
+  const int q = i / R, k1 = i % R;
+  kl = r.kl;
+  km = r.n0 * D + q + S * k1;
+}
+
+template <int N, int P, bool THREAD_MAJOR>
 __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int NPIX = N * N;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (idx >= (int64_t)a.n_chan * NPIX) return;
   const int c = (int)(idx / NPIX);
-  const int pix = (int)(idx % NPIX);
-  const int km = pix / N, kl = pix % N;
+  const int pix = (int)(idx % NPIX);         // THREAD_MAJOR: i * NT + tid
+  int km, kl;
+  if (THREAD_MAJOR) {
+    constexpr int NT = FusedShape<N>::NT;
+    owned_pixel<N>(pix % NT, pix / NT, km, kl);
+  } else {
+    km = pix / N;
+    kl = pix % N;
+  }
   const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
   const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
   double s[NACC];
@@ -335,10 +450,10 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   const int64_t base = (int64_t)c * NPROD * NPIX + qm * N + ql;
   double2 val[NPROD];
   if (P == 2) {
-    val[0] = make_double2(s[0], 0.0);          // XX
-    val[1 % NPROD] = make_double2(s[2], s[3]); // XY
-    val[2 % NPROD] = make_double2(s[2], -s[3]);// YX
-    val[3 % NPROD] = make_double2(s[1], 0.0);  // YY
+    val[0] = make_double2(s[0], 0.0);                          // XX
+    val[1 % NPROD] = make_double2(s[2 % NACC], s[3 % NACC]);   // XY
+    val[2 % NPROD] = make_double2(s[2 % NACC], -s[3 % NACC]);  // YX
+    val[3 % NPROD] = make_double2(s[1 % NACC], 0.0);           // YY
   } else {
     val[0] = make_double2(s[0], 0.0);
   }
@@ -348,7 +463,7 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
     if (a.reset) {
       *o = val[pr];
     } else {
-      double2 old = *o;
+      const double2 old = *o;
       *o = make_double2(old.x + val[pr].x, old.y + val[pr].y);
     }
   }

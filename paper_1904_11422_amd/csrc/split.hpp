@@ -1,0 +1,287 @@
+// Split-precision matrix form of gridding + transform (the operator view of
+// the imaging step, paper Sec. 3.3: gridding as a matrix product), on the
+// MFMA units.
+//
+// For one channel and polarisation the gridded-and-transformed field is
+// linear in the samples:  F[pix] = sum_a B[pix][a] e[a],  with
+//   B[pix][a] = g[a] * beta_a(pix),  beta_a(k) = sum_taps w exp(+2 pi i (i kl + j km)/N),
+// i.e. the transform of antenna a's kernel footprint times its gain.  beta is
+// computed once in float64 on the host; B is formed per call, scaled by a
+// power of two s (per channel and polarisation) and split as
+// B s = B_hi + B_lo with B_hi = rnd(B s), B_lo = rnd(B s - B_hi) in float16 or
+// bfloat16.  The samples are small integers, exact in both formats, so
+//   F s = B_hi e + B_lo e
+// with float32 accumulation.  In real form, over K' = 2A (re then im parts):
+//   Re(F s) = Br er - Bi ei,  Im(F s) = Bi er + Br ei.
+//
+// MFMA tiling (v_mfma_f32_32x32x16_{f16,bf16}): D[time][pixel] = E[time][k] B[k][pixel]
+// for 32 samples x 32 pixels, k over 16 antennas.  Lane l supplies
+// E[t = l%32][k = 8(l/32) .. +7] and B[k = 8(l/32) .. +7][pix = l%32]; it receives
+// D[8(r/4) + 4(l/32) + r%4][l%32] in register r, so every lane owns one pixel
+// and 16 of the 32 samples: |F|^2 (or F_X conj F_Y) is summed over time inside
+// the lane, in float64 per tile.  The matrix operands of one 32-pixel tile stay
+// in registers for the whole time range of the wave.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epic {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float16v_t __attribute__((ext_vector_type(16)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float x) {
+  const _Float16 h = (_Float16)x;
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t b) {
+  return (float)__builtin_bit_cast(_Float16, b);
+}
+
+constexpr int kSplitParts = 3;     // Br, Bi, -Bi
+constexpr int kSplitMaxBlocks = 2; // antenna blocks of 16 held in registers (A <= 32)
+
+struct SplitPrepArgs {
+  const float2* gains;      // [C][P][A]
+  const double2* beta;      // [C][NG][A]
+  const double* beta_max;   // [C] max |beta|
+  uint16_t* bmat;           // [C][P][part][hi/lo][NG][AP]
+  float* scale;             // [C][P]: s
+  int n_chan, n_pol, n_ant, a_pad, ng;
+};
+
+// One workgroup per (channel, polarisation).
+template <bool BF>
+__global__ void __launch_bounds__(256) split_prep_kernel(SplitPrepArgs a) {
+  const int cp = blockIdx.x;
+  const int c = cp / a.n_pol;
+  const float2* g = a.gains + (int64_t)cp * a.n_ant;
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < a.n_ant; i += 256) m = fmax(m, hypot((double)g[i].x, (double)g[i].y));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double bmax = red[0] * a.beta_max[c];
+  // scale so that |B s| < 2^14: the hi parts stay finite, the lo parts normal
+  const double sc = bmax > 0.0 ? ldexp(1.0, 13 - ilogb(bmax)) : 1.0;
+  if (threadIdx.x == 0) a.scale[cp] = (float)sc;
+  const int64_t plane = (int64_t)a.ng * a.a_pad;
+  uint16_t* out = a.bmat + (int64_t)cp * kSplitParts * 2 * plane;
+  const double2* beta = a.beta + (int64_t)c * a.ng * a.n_ant;
+  for (int64_t idx = threadIdx.x; idx < plane; idx += 256) {
+    const int pix = (int)(idx / a.a_pad), ant = (int)(idx % a.a_pad);
+    double br = 0.0, bi = 0.0;
+    if (ant < a.n_ant) {
+      const double2 b = beta[(int64_t)pix * a.n_ant + ant];
+      const double gr = g[ant].x, gi = g[ant].y;
+      br = (gr * b.x - gi * b.y) * sc;
+      bi = (gr * b.y + gi * b.x) * sc;
+    }
+    const double v[kSplitParts] = {br, bi, -bi};
+#pragma unroll
+    for (int part = 0; part < kSplitParts; ++part) {
+      const float x = (float)v[part];
+      uint16_t hi, lo;
+      if (BF) {
+        hi = f32_to_bf16_bits(x);
+        lo = f32_to_bf16_bits((float)(v[part] - (double)bf16_bits_to_f32(hi)));
+      } else {
+        hi = f32_to_f16_bits(x);
+        lo = f32_to_f16_bits((float)(v[part] - (double)f16_bits_to_f32(hi)));
+      }
+      out[(part * 2 + 0) * plane + idx] = hi;
+      out[(part * 2 + 1) * plane + idx] = lo;
+    }
+  }
+}
+
+struct SplitArgs {
+  const uint8_t* efield;    // [T][C][P][A]
+  const uint16_t* bmat;     // as written by split_prep_kernel
+  double* partial;          // [C][n_chunks][NACC][2][NG]
+  int64_t n_time;
+  int n_chan, n_ant, a_pad, ng, chunk, n_chunks;
+};
+
+template <bool BF> struct SplitOps;
+template <> struct SplitOps<false> {
+  using v8 = half8_t;
+  static __device__ __forceinline__ float16v_t mfma(v8 x, v8 y, float16v_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ v8 from_ints(const int (&q)[8]) {
+    v8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (_Float16)q[i];
+    return r;
+  }
+};
+template <> struct SplitOps<true> {
+  using v8 = bf16x8_t;
+  static __device__ __forceinline__ float16v_t mfma(v8 x, v8 y, float16v_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ v8 from_ints(const int (&q)[8]) {
+    v8 r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (__bf16)(float)q[i];   // small integers: exact
+    return r;
+  }
+};
+
+template <bool BF> __device__ __forceinline__ typename SplitOps<BF>::v8 load8(const uint16_t* p) {
+  const uint4 u = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(typename SplitOps<BF>::v8, u);
+}
+
+// One wave per (32-pixel tile, time chunk, channel); 4 waves per workgroup on
+// consecutive tiles.  QB antenna blocks of 16 (A <= 16 QB).
+template <int P, bool BF, int QB>
+__global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
+  using Ops = SplitOps<BF>;
+  using v8 = typename Ops::v8;
+  constexpr int NACC = (P == 2) ? 4 : 1;
+  const int lane = threadIdx.x & 63;
+  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int c = blockIdx.z;
+  const int chunk = blockIdx.y;
+  if (tile * 32 >= a.ng) return;
+  const int n = lane & 31, h = lane >> 5;
+  const int pix = tile * 32 + n;
+
+  // matrix operands of this tile: [pol][block][part][hi/lo]
+  v8 bm[P][QB][kSplitParts][2];
+  const int64_t plane = (int64_t)a.ng * a.a_pad;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const uint16_t* base = a.bmat + ((int64_t)c * P + p) * kSplitParts * 2 * plane +
+                           (int64_t)pix * a.a_pad + 8 * h;
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+#pragma unroll
+      for (int part = 0; part < kSplitParts; ++part)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) bm[p][q][part][hl] = load8<BF>(base + (part * 2 + hl) * plane + 16 * q);
+  }
+
+  double acc[NACC];
+#pragma unroll
+  for (int u = 0; u < NACC; ++u) acc[u] = 0.0;
+  const int64_t t_begin = (int64_t)chunk * a.chunk;
+  const int64_t t_end = t_begin + a.chunk < a.n_time ? t_begin + a.chunk : a.n_time;
+  const int64_t row_bytes = (int64_t)a.n_chan * P * a.n_ant;
+  for (int64_t t0 = t_begin; t0 < t_end; t0 += 32) {
+    const int64_t t = t0 + n;                  // this lane's sample row of E
+    float16v_t dre[P], dim[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      dre[p] = float16v_t{};
+      dim[p] = float16v_t{};
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        int re[8], im[8];
+        const uint8_t* src = a.efield + t * row_bytes + ((int64_t)c * P + p) * a.n_ant;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int ant = 16 * q + 8 * h + i;
+          const int b = (t < t_end && ant < a.n_ant) ? (int)src[ant] : 0;
+          re[i] = (b >> 4) - ((b & 0x80) ? 16 : 0);
+          im[i] = (b & 0xF) - ((b & 0x8) ? 16 : 0);
+        }
+        const v8 er = Ops::from_ints(re), ei = Ops::from_ints(im);
+        // Re(F s) = Br er - Bi ei ; Im(F s) = Bi er + Br ei   (hi and lo terms)
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+          dre[p] = Ops::mfma(er, bm[p][q][0][hl], dre[p]);
+          dre[p] = Ops::mfma(ei, bm[p][q][2][hl], dre[p]);
+          dim[p] = Ops::mfma(er, bm[p][q][1][hl], dim[p]);
+          dim[p] = Ops::mfma(ei, bm[p][q][0][hl], dim[p]);
+        }
+      }
+    }
+    // epilogue: products summed over the 16 samples of this lane
+    float s[NACC];
+#pragma unroll
+    for (int u = 0; u < NACC; ++u) s[u] = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float xr = dre[0][r], xi = dim[0][r];
+      s[0] = fmaf(xi, xi, fmaf(xr, xr, s[0]));
+      if (P == 2) {
+        const float yr = dre[P - 1][r], yi = dim[P - 1][r];
+        s[1 % NACC] = fmaf(yi, yi, fmaf(yr, yr, s[1 % NACC]));
+        s[2 % NACC] = fmaf(xi, yi, fmaf(xr, yr, s[2 % NACC]));
+        s[3 % NACC] = fmaf(-xr, yi, fmaf(xi, yr, s[3 % NACC]));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NACC; ++u) acc[u] += (double)s[u];
+  }
+  double* out = a.partial + (((int64_t)c * a.n_chunks + chunk) * NACC * 2) * a.ng;
+#pragma unroll
+  for (int u = 0; u < NACC; ++u) out[((int64_t)u * 2 + h) * a.ng + pix] = acc[u];
+}
+
+struct SplitReduceArgs {
+  const double* partial;    // [C][n_chunks][NACC][2][NG]
+  const float* scale;       // [C][P]
+  double* image;            // complex128 [C][NPROD][N][N]
+  int n_chan, n_chunks, ng, n, reset;
+};
+
+// image (+)= (sum over chunks, in order, and the two lane halves) / scales,
+// fftshifted and expanded to XX, XY, YX, YY.
+template <int P>
+__global__ void __launch_bounds__(256) split_reduce_kernel(SplitReduceArgs a) {
+  constexpr int NACC = (P == 2) ? 4 : 1;
+  constexpr int NPROD = (P == 2) ? 4 : 1;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_chan * a.ng) return;
+  const int c = (int)(idx / a.ng), pix = (int)(idx % a.ng);
+  double s[NACC];
+#pragma unroll
+  for (int u = 0; u < NACC; ++u) s[u] = 0.0;
+  for (int k = 0; k < a.n_chunks; ++k) {
+    const double* src = a.partial + (((int64_t)c * a.n_chunks + k) * NACC * 2) * a.ng + pix;
+#pragma unroll
+    for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)(2 * u) * a.ng] + src[(int64_t)(2 * u + 1) * a.ng];
+  }
+  const double sx = a.scale[c * P], sy = a.scale[c * P + P - 1];
+  const int N = a.n;
+  const int km = pix / N, kl = pix % N;
+  const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
+  double2* img = reinterpret_cast<double2*>(a.image) + (int64_t)c * NPROD * a.ng + qm * N + ql;
+  double2 val[NPROD];
+  val[0] = make_double2(s[0] / (sx * sx), 0.0);
+  if (P == 2) {
+    const double xy = 1.0 / (sx * sy);
+    val[1 % NPROD] = make_double2(s[2 % NACC] * xy, s[3 % NACC] * xy);
+    val[2 % NPROD] = make_double2(s[2 % NACC] * xy, -s[3 % NACC] * xy);
+    val[3 % NPROD] = make_double2(s[1 % NACC] / (sy * sy), 0.0);
+  }
+#pragma unroll
+  for (int pr = 0; pr < NPROD; ++pr) {
+    double2* o = img + (int64_t)pr * a.ng;
+    if (a.reset) {
+      *o = val[pr];
+    } else {
+      const double2 old = *o;
+      *o = make_double2(old.x + val[pr].x, old.y + val[pr].y);
+    }
+  }
+}
+
+}  // namespace epic

@@ -1,0 +1,81 @@
+"""Heterogeneous batch (grids of 32^2, 64^2, 128^2; 64, 256 and 1024
+antennas) advanced together: every block against the FP64 oracle, HIP graph
+replays against the eager batch, and the autotuner's cache."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# the heterogeneous shapes of the batched workload, fewer channels
+BLOCKS = ((32, 64, 12), (32, 64, 3), (64, 256, 6), (64, 256, 2), (128, 1024, 3), (128, 1024, 1))
+T = 24
+
+
+@pytest.fixture(scope="module")
+def batch_inputs():
+    return [synth.config4_block(b, n_time=T, blocks=BLOCKS) for b in range(len(BLOCKS))]
+
+
+def _batch(inputs):
+    import torch
+    from paper_1904_11422_amd import Batch
+    cfgs = [dict(grid_n=i.grid_n, n_chan=i.n_chan, n_pol=i.n_pol, n_ant=i.n_ant) for i in inputs]
+    b = Batch(cfgs)
+    for k, i in enumerate(inputs):
+        b.set_antennas(k, i.xy_m, i.freq_hz)
+    ef = [torch.from_numpy(np.ascontiguousarray(i.efield)).cuda() for i in inputs]
+    g = [torch.from_numpy(np.ascontiguousarray(i.gains)).cuda() for i in inputs]
+    return b, ef, g
+
+
+def test_batch_matches_oracle(batch_inputs):
+    import torch
+    b, ef, g = _batch(batch_inputs)
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    for k, inp in enumerate(batch_inputs):
+        print(f"block {k}: N={inp.grid_n} A={inp.n_ant} C={inp.n_chan}", flush=True)
+        err = oracle.rel_errors(imgs[k].cpu().numpy(), oracle.image_from(inp))
+        assert err.max() <= 1e-5, f"block {k}: {err.max():.3e}"
+
+
+def test_graph_replays_match_eager(batch_inputs):
+    import torch
+    b, ef, g = _batch(batch_inputs)
+    eager = [x.clone() for x in b.accumulate(ef, g, b.new_images())]
+    torch.cuda.synchronize()
+    out = b.new_images()
+    b.capture(ef, g, out)
+    for rep in range(3):
+        for x in out:
+            x.fill_(float("nan"))
+        b.replay()
+        torch.cuda.synchronize()
+        for k in range(len(out)):
+            assert torch.equal(out[k], eager[k]), f"replay {rep}, block {k}"
+        # eager work of the program between replays
+        scratch = b.accumulate(ef, g, b.new_images())
+        torch.cuda.synchronize()
+        assert torch.equal(scratch[0], eager[0])
+
+
+def test_tune_then_cache(batch_inputs, tmp_path):
+    import torch
+    cache = str(tmp_path / "plans.txt")
+    b, ef, g = _batch(batch_inputs)
+    imgs = b.new_images()
+    assert b.tune(ef, g, imgs, cache) is True
+    plan = b.plan()
+    b2, ef2, g2 = _batch(batch_inputs)
+    assert b2.tune(ef2, g2, b2.new_images(), cache) is False
+    assert b2.plan() == plan
+    for (grid, tb), inp in zip(plan, batch_inputs):
+        assert (grid > 0) == (inp.grid_n <= 64) and (tb > 0) == (inp.grid_n == 128)
+    out = b2.accumulate(ef2, g2, b2.new_images())
+    torch.cuda.synchronize()
+    for k, inp in enumerate(batch_inputs):
+        err = oracle.rel_errors(out[k].cpu().numpy(), oracle.image_from(inp))
+        assert err.max() <= 1e-5
