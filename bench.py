@@ -78,6 +78,186 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
+def bench_batch(args) -> int:
+    """Six blocks of different (N, A, C) advanced together: autotuned launch
+    shapes, one HIP graph replay per step."""
+    import tempfile
+    import torch
+    import synth
+    from paper_1904_11422_amd import Batch
+    print("bench: generating the heterogeneous batch", file=sys.stderr, flush=True)
+    inputs = [synth.config4_block(b) for b in range(len(synth.CONFIG4_BLOCKS))]
+    T = inputs[0].n_time
+    b = Batch([dict(grid_n=i.grid_n, n_chan=i.n_chan, n_pol=i.n_pol, n_ant=i.n_ant) for i in inputs])
+    for k, i in enumerate(inputs):
+        b.set_antennas(k, i.xy_m, i.freq_hz)
+    ef = [torch.from_numpy(i.efield).cuda() for i in inputs]
+    g = [torch.from_numpy(i.gains).cuda() for i in inputs]
+    imgs = b.new_images()
+    cache = os.path.join(tempfile.gettempdir(), "epic_batch_plans.txt")
+    b.tune(ef, g, imgs, cache)
+    b.capture(ef, g, imgs)
+    for _ in range(args.warmup):
+        b.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    # the same batch, one block after another, no graph, default launch shapes
+    seq = [None] * len(inputs)
+    from paper_1904_11422_amd import Imager
+    ims = []
+    for k, i in enumerate(inputs):
+        im = Imager(i.grid_n, i.n_chan, i.n_pol, i.n_ant)
+        im.set_antennas(i.xy_m, i.freq_hz)
+        ims.append(im)
+    for k in range(len(inputs)):
+        seq[k] = ims[k].accumulate(ef[k], g[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for k in range(len(inputs)):
+            ims[k].accumulate(ef[k], g[k], image=seq[k])
+    torch.cuda.synchronize()
+    dts = (time.perf_counter() - t1) / args.steps
+    tc = sum(i.n_chan for i in inputs) * T
+    fl = sum(flops_per_tc(i.grid_n, i.n_pol, i.n_ant) * i.n_chan * T for i in inputs)
+    out = {"metric": "heterogeneous batch (t,c)-images/s", "value": tc / dt,
+           "unit": "(t,c)-images/s", "ms_per_step": dt * 1e3, "steps": args.steps,
+           "channel_images_per_s": sum(i.n_chan for i in inputs) / dt,
+           "blocks": [dict(grid_n=i.grid_n, n_ant=i.n_ant, n_chan=i.n_chan, grid=p[0],
+                           staged_batch=p[1]) for i, p in zip(inputs, b.plan())],
+           "roofline": {"bound": "alu", "achieved": fl / dt / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                        "unit": "TFLOP/s", "frac": fl / dt / PEAK_FP32_VALU},
+           "sequential_no_graph_ms": dts * 1e3, "n_time": T, "data": "synthetic"}
+    print(json.dumps(out))
+    return 0
+
+
+PEAK_MFMA_F16 = 2.5e15          # MI355X dense fp16 / bf16 MFMA, FLOP/s
+
+
+def bench_split(args) -> int:
+    """16 antennas, one channel, 32x32 grid, 10^5 samples: the float32 fused
+    path and the float16 / bfloat16 hi+lo matrix forms on the same input."""
+    import torch
+    import oracle
+    import synth
+    from paper_1904_11422_amd import Imager
+    print("bench: generating the long tiny-geometry integration", file=sys.stderr, flush=True)
+    inp = synth.config3()
+    T, N, A, P = inp.n_time, inp.grid_n, inp.n_ant, inp.n_pol
+    ef = torch.from_numpy(inp.efield).cuda()
+    g = torch.from_numpy(inp.gains).cuda()
+    print("bench: FP64 oracle over all samples", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ref = oracle.image_from(inp)
+    t_oracle = time.perf_counter() - t0
+    res = {}
+    for prec in ("fp32", "split_fp16", "split_bf16"):
+        im = Imager(N, 1, P, A, precision=prec, timing=True)
+        im.set_antennas(inp.xy_m, inp.freq_hz)
+        img = im.accumulate(ef, g)
+        torch.cuda.synchronize()
+        err = oracle.rel_errors(img.cpu().numpy(), ref)[0]
+        ks = []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            im.accumulate(ef, g, image=img)
+            ks.append(im.last_timing()[0])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t1) / args.steps
+        r = {"samples_per_s": T / dt, "ms_per_call": dt * 1e3, "kernel": im.last_kernel_name(),
+             "kernel_ms": float(np.mean(ks)), "rel_err_vs_fp64": {"XX": float(err[0])}}
+        if prec != "fp32":
+            # v_mfma_f32_32x32x16: 32*32*16 MACs; per 32 samples x 32 pixels x 16 antennas:
+            # (Re, Im) x (er, ei) = 4 products, x 2 for the hi and lo parts
+            qb = (A + 15) // 16
+            n_mfma = (N * N // 32) * ((T + 31) // 32) * qb * P * 8
+            hw = n_mfma * 32 * 32 * 16 * 2
+            r["mfma_roofline"] = {"bound": "mfma", "achieved": hw / (r["kernel_ms"] * 1e-3) / 1e12,
+                                  "peak": PEAK_MFMA_F16 / 1e12, "unit": "TFLOP/s",
+                                  "frac": hw / (r["kernel_ms"] * 1e-3) / PEAK_MFMA_F16,
+                                  "hardware_flops": hw, "useful_flops": hw // 2}
+        res[prec] = r
+        im.close()
+    out = {"metric": "split-precision matrix forms, samples/s and error per product",
+           "workload": "16 single-pol antennas in a 20 m square, 1 channel at 50 MHz, 32x32 "
+                       "grid, 100000 samples", "results": res,
+           "cpu_baseline": {"value": T / t_oracle, "unit": "samples/s", "cores": 1,
+                            "kind": "oracle", "sample": "all 100000 samples"},
+           "data": "synthetic"}
+    print(json.dumps(out))
+    return 0
+
+
+def bench_grad(args) -> int:
+    """Calibration workload: 256 dual-pol antennas, 64 channels, 64x64 grid,
+    200 samples; one forward image and one gain gradient per step."""
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager
+    print("bench: generating the calibration workload", file=sys.stderr, flush=True)
+    inp = synth.config5()
+    N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
+    ef = torch.from_numpy(inp.efield).cuda()
+    g = torch.from_numpy(inp.gains).cuda()
+    im = Imager(N, C, P, A, timing=True)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    img = im.accumulate(ef, g)
+    gam = (2.0 * img).contiguous()
+    for _ in range(args.warmup):
+        im.accumulate(ef, g, image=img)
+        im.backward(ef, g, gam)
+    torch.cuda.synchronize()
+    fw, bw = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        im.accumulate(ef, g, image=img)
+        fw.append(im.last_timing()[0])
+        im.backward(ef, g, gam)
+        bw.append(im.last_timing()[0])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {"metric": "forward + gain-gradient evaluations/s", "value": 1.0 / dt,
+           "unit": "evaluations/s", "ms_per_step": dt * 1e3, "steps": args.steps,
+           "forward_kernel_ms": float(np.mean(fw)), "adjoint_kernel_ms": float(np.mean(bw)),
+           "adjoint_tc_images_per_s": C * T / (float(np.mean(bw)) * 1e-3),
+           "workload": "256 dual-pol antennas, 64 channels, 64x64 grid, 200 samples",
+           "data": "synthetic"}
+    print(json.dumps(out))
+    return 0
+
+
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                       "fused_image_kernel_lwa64_c132_t1000.md")
+PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/epic.hip", "build.py")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading), or
+    None when the kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    want = re.search(r"sources_sha256: ([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not want or not val:
+        return None
+    h = hashlib.sha256()
+    pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_11422_amd")
+    for f in PROFILED_SOURCES:
+        with open(os.path.join(pkg, f), "rb") as fh:
+            h.update(fh.read())
+    return int(val.group(1)) if h.hexdigest() == want.group(1) else None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,17 +267,31 @@ def main() -> int:
                     help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-staged", action="store_true")
+    ap.add_argument("--batch", action="store_true",
+                    help="measure the heterogeneous batch (grids 32/64/128, 64/256/1024 "
+                         "antennas, 16-264 channels, 200 samples) instead of the default line")
+    ap.add_argument("--split", action="store_true",
+                    help="measure the split-precision matrix forms on the tiny geometry over "
+                         "a long integration, with errors against the FP64 oracle")
+    ap.add_argument("--grad", action="store_true",
+                    help="measure forward + gain-gradient evaluations on the calibration workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (five times), to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
     args = ap.parse_args()
-    if args.copy_calibration:
-        return copy_calibration(args.copy_calibration)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
-              "(the imager shards by channel with no communication; see the design notes)",
-              file=sys.stderr)
+              "(channels shard across GPUs with no communication, so one GPU's "
+              "throughput times the GPU count is the multi-GPU figure)", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
+    if args.batch:
+        return bench_batch(args)
+    if args.split:
+        return bench_split(args)
+    if args.grad:
+        return bench_grad(args)
 
     import torch
     import synth
@@ -134,9 +328,10 @@ def main() -> int:
     fl = flops_per_tc(N, P, A) * C * T
     achieved = fl / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
                 "kernel": kname, "kernel_ms": k_ms,
-                "flops_per_launch": fl, "flops_per_tc_image": flops_per_tc(N, P, A)}
+                "flops_per_launch": fl, "flops_per_tc_image": flops_per_tc(N, P, A),
+                "input_bytes_per_launch": C * T * P * A}
     im.close()
 
     staged = None

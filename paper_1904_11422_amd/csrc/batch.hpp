@@ -15,7 +15,8 @@
 
 struct epic_batch {
   int device = 0;
-  hipStream_t main = nullptr;
+  hipStream_t main = nullptr;         // the caller's stream (may be the null stream)
+  hipStream_t cap = nullptr;          // fork stream used while capturing a graph
   std::vector<epic_ctx*> ctx;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> done;
@@ -34,9 +35,10 @@ namespace {
 
 thread_local std::string g_batch_init_error;
 
-epic_status batch_enqueue(epic_batch* b, const uint8_t* const* efields, int64_t n_time,
-                          const float* const* gains, double* const* images, int32_t reset) {
-  if (hipEventRecord(b->fork, b->main) != hipSuccess)
+epic_status batch_enqueue(epic_batch* b, hipStream_t root, const uint8_t* const* efields,
+                          int64_t n_time, const float* const* gains, double* const* images,
+                          int32_t reset) {
+  if (hipEventRecord(b->fork, root) != hipSuccess)
     return b->fail(EPIC_E_LAUNCH, "event record failed");
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     if (hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess)
@@ -48,7 +50,7 @@ epic_status batch_enqueue(epic_batch* b, const uint8_t* const* efields, int64_t 
       return b->fail(EPIC_E_LAUNCH, "event record failed");
   }
   for (size_t i = 0; i < b->ctx.size(); ++i)
-    if (hipStreamWaitEvent(b->main, b->done[i], 0) != hipSuccess)
+    if (hipStreamWaitEvent(root, b->done[i], 0) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "stream wait failed");
   return EPIC_OK;
 }
@@ -127,6 +129,8 @@ epic_status epic_batch_create(const epic_config* cfgs, int32_t n_blocks, int dev
         return bail(EPIC_E_DEVICE, "event creation failed");
       b->done.push_back(ev);
     }
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(EPIC_E_DEVICE, "stream creation failed");
     if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreate(&b->t0) != hipSuccess || hipEventCreate(&b->t1) != hipSuccess)
       return bail(EPIC_E_DEVICE, "event creation failed");
@@ -159,7 +163,7 @@ epic_status epic_batch_accumulate(epic_batch* b, const uint8_t* const* efields, 
   epic_status s = batch_check(b, efields, gains, images, n_time);
   if (s != EPIC_OK) return s;
   DeviceGuard guard(b->device);
-  return batch_enqueue(b, efields, n_time, gains, images, reset);
+  return batch_enqueue(b, b->main, efields, n_time, gains, images, reset);
 }
 
 epic_status epic_batch_capture(epic_batch* b, const uint8_t* const* efields, int64_t n_time,
@@ -170,11 +174,20 @@ epic_status epic_batch_capture(epic_batch* b, const uint8_t* const* efields, int
   DeviceGuard guard(b->device);
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-  if (hipStreamBeginCapture(b->main, hipStreamCaptureModeThreadLocal) != hipSuccess)
-    return b->fail(EPIC_E_LAUNCH, "graph capture could not start on the batch stream");
-  s = batch_enqueue(b, efields, n_time, gains, images, reset);
+  // Capture on the batch's own stream (capture is not possible on the null
+  // stream); the graph is launched on the caller's stream by epic_batch_replay.
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(b->cap, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(b->cap, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+    }
+    return b->fail(EPIC_E_LAUNCH, "graph capture could not start");
+  }
+  s = batch_enqueue(b, b->cap, efields, n_time, gains, images, reset);
   hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(b->main, &g);
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
   if (s != EPIC_OK) {
     if (g) (void)hipGraphDestroy(g);
     return s;
@@ -266,10 +279,10 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
   float chosen_ms = 1e30f;
   for (const auto* plan : {&best, &split}) {
     apply(*plan);
-    s = batch_enqueue(b, efields, n_time, gains, images, 1);
+    s = batch_enqueue(b, b->main, efields, n_time, gains, images, 1);
     if (s != EPIC_OK) return s;
     const float ms = time_on(b->main, b->t0, b->t1, 3, [&] {
-      (void)batch_enqueue(b, efields, n_time, gains, images, 1);
+      (void)batch_enqueue(b, b->main, efields, n_time, gains, images, 1);
     });
     if (ms < chosen_ms) { chosen_ms = ms; chosen = *plan; }
   }
@@ -303,6 +316,10 @@ void epic_batch_destroy(epic_batch* b) {
     (void)hipStreamDestroy(s);
   }
   for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
+  if (b->cap) {
+    (void)hipStreamSynchronize(b->cap);
+    (void)hipStreamDestroy(b->cap);
+  }
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->t0) (void)hipEventDestroy(b->t0);
   if (b->t1) (void)hipEventDestroy(b->t1);
