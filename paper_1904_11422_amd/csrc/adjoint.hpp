@@ -183,23 +183,31 @@ struct GradReduceArgs {
   float2* grad;             // [C][P*A]
   int64_t n_time, total;
   int n_chan, PA, W;
+  int sub;                  // sub-lanes per (c, p, a), as in reduce_image_kernel
 };
 
 __global__ void __launch_bounds__(256) reduce_grad_kernel(GradReduceArgs a) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)a.n_chan * a.PA) return;
-  const int c = (int)(idx / a.PA);
-  const int k = (int)(idx % a.PA);
-  const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
-  const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
-  double sx = 0.0, sy = 0.0;
-  for (int64_t w = w_lo; w <= w_hi; ++w) {
-    if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
-    const double2 v = a.gpartial[(w + c) * a.PA + k];
-    sx += v.x;
-    sy += v.y;
+  __shared__ double red[2 * 256];
+  const int ppb = 256 / a.sub;
+  const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
+  const int64_t idx = (int64_t)blockIdx.x * ppb + lp;
+  const bool valid = idx < (int64_t)a.n_chan * a.PA;
+  double s[2] = {0.0, 0.0};
+  if (valid) {
+    const int c = (int)(idx / a.PA);
+    const int k = (int)(idx % a.PA);
+    const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
+    const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
+#pragma unroll 4
+    for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
+      if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
+      const double2 v = a.gpartial[(w + c) * a.PA + k];
+      s[0] += v.x;
+      s[1] += v.y;
+    }
   }
-  a.grad[idx] = make_float2((float)(2.0 * sx), (float)(2.0 * sy));
+  combine_sublanes<2>(s, a.sub, ppb, j, lp, red);
+  if (valid && j == 0) a.grad[idx] = make_float2((float)(2.0 * s[0]), (float)(2.0 * s[1]));
 }
 
 }  // namespace epic

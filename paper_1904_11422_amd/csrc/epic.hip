@@ -222,11 +222,27 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 // up to a multiple of its step chunk).
 // Step: {cell byte offset << 16 | E' byte offset, weight bits with the sign
 // bit set on the last entry of a cell}.
+// Gridding programs of the fused kernels, one list of steps per thread and
+// channel, scheduled for the LDS banks.  LDS serves a 64-bit access 16 lanes
+// at a time from 32 four-byte banks, so 16 lanes of a quarter-wave hit
+// distinct banks when their float2 addresses differ modulo 16.
+//  * Cell writes: lane l of every quarter-wave only owns cells whose float2
+//    address is l modulo 16 (cells of one bank class are dealt longest-first
+//    to the least loaded of that class's lanes).
+//  * E' reads: the entries of a cell may be taken in any order; step by step,
+//    lanes whose cell has one entry left take it, then the others take the
+//    remaining entry whose bank the quarter-wave uses least.  Empty cells and
+//    padding read one of 16 zero slots of E' (slots A .. A+15), on the least
+//    used bank.
+//  * Padding steps write zero to a spare column (>= N/2, overwritten by the
+//    row transform) on the lane's own bank.
 template <int N>
-void build_programs(const Geometry& g, std::vector<uint32_t>& out, int& L) {
+void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L) {
   constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
+  constexpr int NQ = NT / 16;                          // quarter-waves per workgroup
   const int C = g.C, A = g.A, KK = g.KK;
-  std::vector<std::vector<std::vector<uint32_t>>> per_chan(C);   // [c][thread] -> words
+  const int ES = NT * gpt / P + 64;                    // EStride<NT, gpt, P>
+  const int XB = P * ES;                               // grid base, float2 units
   auto code = [](int cell_f2, int e) {
     return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
   };
@@ -235,62 +251,165 @@ void build_programs(const Geometry& g, std::vector<uint32_t>& out, int& L) {
     std::memcpy(&b, &w, 4);
     return last ? (b | epic::STEP_LAST_BIT) : b;
   };
+  struct Run {
+    int cell;
+    std::vector<std::pair<int, float>> ent;            // (antenna, weight)
+  };
+  std::vector<std::vector<uint32_t>> words((size_t)C * NT);   // [c][thread] -> step words
   L = 1;
   for (int c = 0; c < C; ++c) {
-    std::vector<std::vector<std::pair<int, float>>> ent(H * H);
+    std::vector<Run> cells(H * H);
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < H; ++i) cells[j * H + i].cell = j * RS + i;
     for (int a = 0; a < A; ++a)
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-        ent[j * H + i].push_back({a, g.w[o]});
+        cells[j * H + i].ent.push_back({a, g.w[o]});
       }
-    std::vector<int> order(H * H);
-    for (int i = 0; i < H * H; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-      return std::max<size_t>(1, ent[x].size()) > std::max<size_t>(1, ent[y].size());
-    });
-    using Load = std::pair<int, int>;                  // (steps, thread)
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-    for (int t = 0; t < NT; ++t) pq.push({0, t});
-    auto& th = per_chan[c];
-    th.assign(NT, {});
-    for (int idx : order) {
-      Load ld = pq.top();
-      pq.pop();
-      const int cell = (idx / H) * RS + idx % H;
-      auto& words = th[ld.second];
-      if (ent[idx].empty()) {
-        words.push_back(code(cell, A));
-        words.push_back(wbits(0.f, true));
-      } else {
-        for (size_t e = 0; e < ent[idx].size(); ++e) {
-          words.push_back(code(cell, ent[idx][e].first));
-          words.push_back(wbits(ent[idx][e].second, e + 1 == ent[idx].size()));
+    // bank classes, longest-first to the least loaded lane of the class
+    std::vector<std::vector<const Run*>> lane_runs(NT);
+    std::vector<int> load(NT, 0);
+    for (int b = 0; b < 16; ++b) {
+      std::vector<const Run*> cls;
+      for (const Run& r : cells)
+        if ((XB + r.cell) % 16 == b) cls.push_back(&r);
+      std::stable_sort(cls.begin(), cls.end(), [](const Run* x, const Run* y) {
+        return std::max<size_t>(1, x->ent.size()) > std::max<size_t>(1, y->ent.size());
+      });
+      using Load = std::pair<int, int>;                // (steps, quarter-wave)
+      std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+      for (int q = 0; q < NQ; ++q) pq.push({0, q});
+      for (const Run* r : cls) {
+        Load ld = pq.top();
+        pq.pop();
+        const int t = 16 * ld.second + b;
+        lane_runs[t].push_back(r);
+        ld.first += (int)std::max<size_t>(1, r->ent.size());
+        load[t] = ld.first;
+        pq.push(ld);
+      }
+    }
+    const int Lc = *std::max_element(load.begin(), load.end());
+    L = std::max(L, Lc);
+    // step-by-step choice of the E' entries, per quarter-wave
+    for (int q = 0; q < NQ; ++q) {
+      struct Lane {
+        size_t run = 0;
+        std::vector<std::pair<int, float>> left;       // entries of the current run not yet taken
+        bool started = false;
+      };
+      Lane st[16];
+      for (int step = 0; step < Lc; ++step) {
+        int used[16] = {0};
+        int pick_e[16], pick_cell[16];
+        float pick_w[16];
+        bool pick_last[16];
+        bool decided[16] = {false};
+        auto open = [&](int l) {                        // make the current run's list ready
+          Lane& s = st[l];
+          const auto& runs = lane_runs[16 * q + l];
+          if (!s.started && s.run < runs.size()) {
+            s.left = runs[s.run]->ent;
+            s.started = true;
+          }
+        };
+        // lanes with no choice: one entry left
+        for (int l = 0; l < 16; ++l) {
+          open(l);
+          Lane& s = st[l];
+          const auto& runs = lane_runs[16 * q + l];
+          if (s.run < runs.size() && s.left.size() == 1) {
+            pick_e[l] = s.left[0].first;
+            pick_w[l] = s.left[0].second;
+            pick_cell[l] = runs[s.run]->cell;
+            pick_last[l] = true;
+            used[pick_e[l] % 16]++;
+            decided[l] = true;
+          }
+        }
+        // lanes with several entries left
+        for (int l = 0; l < 16; ++l) {
+          if (decided[l]) continue;
+          Lane& s = st[l];
+          const auto& runs = lane_runs[16 * q + l];
+          if (s.run >= runs.size() || s.left.empty()) continue;
+          size_t best = 0;
+          for (size_t k = 1; k < s.left.size(); ++k)
+            if (used[s.left[k].first % 16] < used[s.left[best].first % 16]) best = k;
+          pick_e[l] = s.left[best].first;
+          pick_w[l] = s.left[best].second;
+          pick_cell[l] = runs[s.run]->cell;
+          pick_last[l] = false;
+          used[pick_e[l] % 16]++;
+          decided[l] = true;
+        }
+        // empty cells and padding: a zero slot on the least used bank
+        for (int l = 0; l < 16; ++l) {
+          if (decided[l]) continue;
+          int z = 0;
+          for (int k = 1; k < 16; ++k)
+            if (used[(A + k) % 16] < used[(A + z) % 16]) z = k;
+          used[(A + z) % 16]++;
+          pick_e[l] = A + z;
+          pick_w[l] = 0.f;
+          pick_last[l] = true;
+          Lane& s = st[l];
+          const auto& runs = lane_runs[16 * q + l];
+          if (s.run < runs.size()) {
+            pick_cell[l] = runs[s.run]->cell;          // empty cell
+          } else {                                     // padding: spare column, own bank
+            const int r = q % H;
+            int i = H;
+            while ((XB + r * RS + i) % 16 != l) ++i;
+            pick_cell[l] = r * RS + i;
+          }
+          decided[l] = true;
+        }
+        for (int l = 0; l < 16; ++l) {
+          auto& wv = words[(size_t)c * NT + 16 * q + l];
+          wv.push_back(code(pick_cell[l], pick_e[l]));
+          wv.push_back(wbits(pick_w[l], pick_last[l]));
+          Lane& s = st[l];
+          const auto& runs = lane_runs[16 * q + l];
+          if (s.run < runs.size()) {
+            for (size_t k = 0; k < s.left.size(); ++k)   // an antenna enters a cell once
+              if (s.left[k].first == pick_e[l]) {
+                s.left.erase(s.left.begin() + (long)k);
+                break;
+              }
+            if (s.left.empty()) {                      // run finished
+              ++s.run;
+              s.started = false;
+            }
+          }
         }
       }
-      ld.first += (int)std::max<size_t>(1, ent[idx].size());
-      L = std::max(L, ld.first);
-      pq.push(ld);
     }
   }
   if (L > epic::kMaxFixedSteps) L = (L + epic::kStepChunk - 1) / epic::kStepChunk * epic::kStepChunk;
   out.assign((size_t)C * L * NT * 2, 0u);
   for (int c = 0; c < C; ++c)
-    for (int t = 0; t < NT; ++t) {
-      const auto& words = per_chan[c][t];
-      // padding: zero slot, spare column N + (t / N) % 4 of row t % N
-      const uint32_t pad = code((t % N) * RS + N + (t / N) % (RS - N), A);
-      for (int s = 0; s < L; ++s) {
-        const size_t o = (((size_t)c * L + s) * NT + t) * 2;
-        if ((size_t)s < words.size() / 2) {
-          out[o] = words[2 * s];
-          out[o + 1] = words[2 * s + 1];
-        } else {
-          out[o] = pad;
-          out[o + 1] = wbits(0.f, true);
+    for (int q = 0; q < NQ; ++q)
+      for (int l = 0; l < 16; ++l) {
+        const int t = 16 * q + l;
+        const auto& wv = words[(size_t)c * NT + t];
+        // padding beyond this channel's steps: zero slot, spare column on the lane's bank
+        const int r = q % H;
+        int i = H;
+        while ((XB + r * RS + i) % 16 != l) ++i;
+        const uint32_t pad = code(r * RS + i, A + l);
+        for (int s2 = 0; s2 < L; ++s2) {
+          const size_t o = (((size_t)c * L + s2) * NT + t) * 2;
+          if ((size_t)s2 < wv.size() / 2) {
+            out[o] = wv[2 * s2];
+            out[o + 1] = wv[2 * s2 + 1];
+          } else {
+            out[o] = pad;
+            out[o + 1] = wbits(0.f, true);
+          }
         }
       }
-    }
 }
 
 template <typename F>
@@ -345,10 +464,23 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   return false;
 }
 
+// Sub-lanes per output value in the reduction kernels: enough that a channel
+// covered by many workgroup slots (or time chunks) is summed by several
+// threads with independent loads in flight.
+int reduce_sub(int64_t slots_per_value) {
+  return slots_per_value > 32 ? 16 : (slots_per_value > 4 ? 4 : 1);
+}
+
+// Upper bound on the workgroup slots covering one channel of a persistent launch.
+int64_t slots_per_channel(int64_t n_time, int64_t total, int64_t W) {
+  return (n_time * W + total - 1) / total + 1;
+}
+
 bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol;
   const int64_t n = (int64_t)x->cfg.n_chan * N * N;
-  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  const int64_t ppb = 256 / a.sub;
+  const dim3 grid((unsigned)((n + ppb - 1) / ppb)), block(256);
 #define EPIC_LR(NN, PP, TM)                                                                    \
   if (N == NN && P == PP && thread_major == TM) {                                              \
     hipLaunchKernelGGL((epic::reduce_image_kernel<NN, PP, TM>), grid, block, 0, x->stream, a); \
@@ -459,9 +591,10 @@ epic_status build_split_tables(epic_ctx* x, const Geometry& g) {
   return EPIC_OK;
 }
 
-template <int P, bool BF, int QB>
-void launch_split_image(epic_ctx* x, const epic::SplitArgs& a, dim3 grid) {
-  hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB>), grid, dim3(256), 0, x->stream, a);
+template <int P, bool BF, int QB, int TPW>
+void launch_split_image(epic_ctx* x, const epic::SplitArgs& a, dim3 grid, bool vec) {
+  if (vec) hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, true>), grid, dim3(256), 0, x->stream, a);
+  else hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, false>), grid, dim3(256), 0, x->stream, a);
 }
 
 epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
@@ -482,8 +615,18 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   pa.ng = NG;
   if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, dim3(C * P), dim3(256), 0, x->stream, pa);
   else hipLaunchKernelGGL(epic::split_prep_kernel<false>, dim3(C * P), dim3(256), 0, x->stream, pa);
-  int64_t chunk = (n_time + x->sp_max_chunks - 1) / x->sp_max_chunks;
-  chunk = std::max<int64_t>(512, (chunk + 31) / 32 * 32);
+  // tile groups of TPW 32-pixel tiles per wave (two while the operands of
+  // two tiles fit the registers); time chunks so that about three waves per
+  // SIMD are resident, each at least 256 samples long
+  const int qb = x->sp_qb;
+  const int tpw = (P == 1 && qb == 1) ? 2 : 1;
+  const int64_t groups = (int64_t)(NG / 32 / tpw) * C;
+  const int64_t want_waves = 3LL * 4 * x->n_cu;
+  int64_t n_ch = std::max<int64_t>(1, (want_waves + groups - 1) / groups);
+  int64_t chunk = (n_time + n_ch - 1) / n_ch;
+  chunk = std::max<int64_t>(256, (chunk + 31) / 32 * 32);
+  chunk = std::max<int64_t>(chunk, (n_time + x->sp_max_chunks - 1) / x->sp_max_chunks);
+  chunk = (chunk + 31) / 32 * 32;
   const int n_chunks = (int)((n_time + chunk - 1) / chunk);
   epic::SplitArgs sa;
   sa.efield = efield;
@@ -496,15 +639,16 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   sa.ng = NG;
   sa.chunk = (int)chunk;
   sa.n_chunks = n_chunks;
-  const dim3 grid((unsigned)((NG / 32 + 3) / 4), (unsigned)n_chunks, (unsigned)C);
+  const dim3 grid((unsigned)((NG / 32 / tpw + 3) / 4), (unsigned)n_chunks, (unsigned)C);
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
-  const int qb = x->sp_qb;
+  // 8-byte sample loads need A % 8 == 0 and an 8-byte aligned E-field
+  const bool vec = A % 8 == 0 && (reinterpret_cast<uintptr_t>(efield) & 7) == 0;
   if (P == 1) {
-    if (bf) { if (qb == 1) launch_split_image<1, true, 1>(x, sa, grid); else launch_split_image<1, true, 2>(x, sa, grid); }
-    else    { if (qb == 1) launch_split_image<1, false, 1>(x, sa, grid); else launch_split_image<1, false, 2>(x, sa, grid); }
+    if (bf) { if (qb == 1) launch_split_image<1, true, 1, 2>(x, sa, grid, vec); else launch_split_image<1, true, 2, 1>(x, sa, grid, vec); }
+    else    { if (qb == 1) launch_split_image<1, false, 1, 2>(x, sa, grid, vec); else launch_split_image<1, false, 2, 1>(x, sa, grid, vec); }
   } else {
-    if (bf) launch_split_image<2, true, 1>(x, sa, grid);
-    else launch_split_image<2, false, 1>(x, sa, grid);
+    if (bf) launch_split_image<2, true, 1, 1>(x, sa, grid, vec);
+    else launch_split_image<2, false, 1, 1>(x, sa, grid, vec);
   }
   x->last_kernel = "split_image_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
@@ -517,7 +661,9 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   ra.ng = NG;
   ra.n = N;
   ra.reset = reset ? 1 : 0;
-  const unsigned rg = (unsigned)(((int64_t)C * NG + 255) / 256);
+  ra.sub = reduce_sub(n_chunks);
+  const int64_t rppb = 256 / ra.sub;
+  const unsigned rg = (unsigned)(((int64_t)C * NG + rppb - 1) / rppb);
   if (P == 2) hipLaunchKernelGGL(epic::split_reduce_kernel<2>, dim3(rg), dim3(256), 0, x->stream, ra);
   else hipLaunchKernelGGL(epic::split_reduce_kernel<1>, dim3(rg), dim3(256), 0, x->stream, ra);
   if (x->timing) {
@@ -637,7 +783,7 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
   epic_status s = build_geometry(x->cfg, xy_m, freq_hz, g, m);
   if (s != EPIC_OK) return x->fail(s, m);
   DeviceGuard guard(x->device);
-  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant;
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
   if (hipStreamSynchronize(x->stream) != hipSuccess)
     return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
   x->have_geom = false;
@@ -660,8 +806,8 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
     }
     std::vector<uint32_t> prog;
     int L = 0;
-    if (N == 32) build_programs<32>(g, prog, L);
-    else build_programs<64>(g, prog, L);
+    if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L);
+    else build_programs<64>(g, P, x->fused_gpt, prog, L);
     if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
         hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
@@ -739,6 +885,7 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     r.n_chan = C;
     r.W = a.W;
     r.reset = reset ? 1 : 0;
+    r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
     launch_reduce(x, r, true);
   } else {
     const int npix = N * N;
@@ -794,6 +941,7 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     r.n_chan = C;
     r.W = 1;
     r.reset = reset ? 1 : 0;
+    r.sub = 1;
     launch_reduce(x, r, false);
   }
   if (x->timing) {
@@ -846,8 +994,9 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   r.n_chan = C;
   r.PA = x->PA;
   r.W = a.W;
-  const int64_t n = (int64_t)C * x->PA;
-  hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+  r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
+  const int64_t n = (int64_t)C * x->PA, gppb = 256 / r.sub;
+  hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + gppb - 1) / gppb)), dim3(256), 0,
                      x->stream, r);
   if (x->timing) {
     (void)hipEventRecord(x->ev[2], x->stream);

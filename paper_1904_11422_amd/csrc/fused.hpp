@@ -27,6 +27,7 @@
 // of each channel in workgroup order.
 #pragma once
 #include "dft.hpp"
+#include "reduce.hpp"
 
 namespace epic {
 
@@ -35,7 +36,9 @@ namespace epic {
 // the last entry of a cell (the weights themselves are >= 0).  Every step
 // reads E' of both polarisations, adds |w| * E' to the running sums, stores
 // them to the cell and restarts the sums after the last entry.  Cells with no
-// antenna read the zero slot of E'; padding steps write to a spare column.
+// antenna read a zero slot of E'; padding steps write to a spare column.  The
+// host orders the steps so that the lanes of a quarter-wave touch distinct
+// LDS banks.
 constexpr int STEP_CELL_SHIFT = 16;
 constexpr uint32_t STEP_E_MASK = 0xFFFFu;
 constexpr uint32_t STEP_LAST_BIT = 0x80000000u; // in the weight word
@@ -111,7 +114,7 @@ __device__ __forceinline__ float2 unpack_ci4(uint32_t b) {
 }
 
 // Slots of E' for this thread's items k = tid + i*NT (k = p*A + a), and the
-// zero slot (a = A) of each polarisation.
+// 16 zero slots (a = A .. A+15, one per LDS bank pair) of each polarisation.
 template <int NT, int GPT, int ES>
 __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid, int n_ant, int P) {
 #pragma unroll
@@ -120,7 +123,7 @@ __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid,
     const int p = k >= n_ant ? 1 : 0;
     eidx[i] = k + p * (ES - n_ant);
   }
-  if (tid < P) E[tid * ES + n_ant] = make_float2(0.f, 0.f);
+  if (tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
 }
 
 // 1. E'[p][a] = g * e.
@@ -392,14 +395,18 @@ fused_image_kernel(FusedArgs a) {
 }
 
 // image[c][prod][qm][ql] (+)= sum over the workgroups covering channel c of
-// their partial slot, in workgroup order.  THREAD_MAJOR: slots are
-// [NACC][S][NT] as written by the fused kernel (value i of thread tid);
-// otherwise [NACC][N*N] in natural pixel order (staged path, W = 1).
+// their partial slot.  THREAD_MAJOR: slots are [NACC][S][NT] as written by
+// the fused kernel (value i of thread tid); otherwise [NACC][N*N] in natural
+// pixel order (staged path, W = 1).  A block of 256 threads handles 256/sub
+// pixels; sub-lane j of a pixel sums the slots w_lo + j, w_lo + j + sub, ...
+// and the sub-lane sums are added in the order j = 0, 1, ...: a fixed order
+// for a given (W, C, T, sub), so the result is reproducible run to run.
 struct ReduceArgs {
   const double* partial;
   double* image;            // complex128 [C][NPROD][N][N]
   int64_t n_time, total;
   int n_chan, W, reset;
+  int sub;                  // 1, 4 or 16 sub-lanes per pixel
 };
 
 // Workgroup whose range contains flat index f: the largest w with
@@ -421,10 +428,29 @@ template <int N, int P, bool THREAD_MAJOR>
 __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int NPIX = N * N;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)a.n_chan * NPIX) return;
-  const int c = (int)(idx / NPIX);
+  __shared__ double red[NACC * 256];
+  const int ppb = 256 / a.sub;
+  const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
+  const int64_t idx = (int64_t)blockIdx.x * ppb + lp;
+  const bool valid = idx < (int64_t)a.n_chan * NPIX;
+  const int c = valid ? (int)(idx / NPIX) : 0;
   const int pix = (int)(idx % NPIX);         // THREAD_MAJOR: i * NT + tid
+  double s[NACC];
+#pragma unroll
+  for (int u = 0; u < NACC; ++u) s[u] = 0.0;
+  if (valid) {
+    const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
+    const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
+#pragma unroll 4
+    for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
+      if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
+      const double* src = a.partial + (w + c) * NACC * NPIX + pix;
+#pragma unroll
+      for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NPIX];
+    }
+  }
+  combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
+  if (!valid || j != 0) return;
   int km, kl;
   if (THREAD_MAJOR) {
     constexpr int NT = FusedShape<N>::NT;
@@ -432,17 +458,6 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   } else {
     km = pix / N;
     kl = pix % N;
-  }
-  const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
-  const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
-  double s[NACC];
-#pragma unroll
-  for (int u = 0; u < NACC; ++u) s[u] = 0.0;
-  for (int64_t w = w_lo; w <= w_hi; ++w) {
-    if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
-    const double* src = a.partial + (w + c) * NACC * NPIX + pix;
-#pragma unroll
-    for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NPIX];
   }
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
   double2* img = reinterpret_cast<double2*>(a.image);

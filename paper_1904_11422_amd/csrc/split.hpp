@@ -23,6 +23,8 @@
 // in registers for the whole time range of the wave.
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include "reduce.hpp"
 #include <stdint.h>
 
 namespace epic {
@@ -147,92 +149,145 @@ template <bool BF> __device__ __forceinline__ typename SplitOps<BF>::v8 load8(co
   return __builtin_bit_cast(typename SplitOps<BF>::v8, u);
 }
 
-// One wave per (32-pixel tile, time chunk, channel); 4 waves per workgroup on
-// consecutive tiles.  QB antenna blocks of 16 (A <= 16 QB).
-template <int P, bool BF, int QB>
+// The 8 bytes of antennas 16 q + 8 h .. + 7 of sample row t (zero past the
+// end of the chunk or of the antennas).  VEC: A is a multiple of 8, so the
+// 8 bytes are one aligned 8-byte load or all out of range.
+template <bool VEC>
+__device__ __forceinline__ uint2 load_e8(const uint8_t* row, int first_ant, int n_ant, bool in_time) {
+  if (VEC) {
+    if (!in_time || first_ant >= n_ant) return make_uint2(0u, 0u);
+    return *reinterpret_cast<const uint2*>(row + first_ant);
+  }
+  uint32_t w[2] = {0u, 0u};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int ant = first_ant + i;
+    const uint32_t b = (in_time && ant < n_ant) ? (uint32_t)row[ant] : 0u;
+    w[i >> 2] |= b << (8 * (i & 3));
+  }
+  return make_uint2(w[0], w[1]);
+}
+
+// One wave per (TPW 32-pixel tiles, time chunk, channel); 4 waves per
+// workgroup on consecutive tile groups.  QB antenna blocks of 16
+// (A <= 16 QB).  The samples of the next 32-row block are loaded while the
+// current one is on the matrix units.
+template <int P, bool BF, int QB, int TPW, bool VEC>
 __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
   using Ops = SplitOps<BF>;
   using v8 = typename Ops::v8;
   constexpr int NACC = (P == 2) ? 4 : 1;
   const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int tile0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * TPW;
   const int c = blockIdx.z;
   const int chunk = blockIdx.y;
-  if (tile * 32 >= a.ng) return;
+  if (tile0 * 32 >= a.ng) return;
   const int n = lane & 31, h = lane >> 5;
-  const int pix = tile * 32 + n;
 
-  // matrix operands of this tile: [pol][block][part][hi/lo]
-  v8 bm[P][QB][kSplitParts][2];
+  // matrix operands of the tiles: [tile][pol][block][part][hi/lo]
+  v8 bm[TPW][P][QB][kSplitParts][2];
   const int64_t plane = (int64_t)a.ng * a.a_pad;
 #pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const uint16_t* base = a.bmat + ((int64_t)c * P + p) * kSplitParts * 2 * plane +
-                           (int64_t)pix * a.a_pad + 8 * h;
+  for (int u = 0; u < TPW; ++u)
 #pragma unroll
-    for (int q = 0; q < QB; ++q)
+    for (int p = 0; p < P; ++p) {
+      const uint16_t* base = a.bmat + ((int64_t)c * P + p) * kSplitParts * 2 * plane +
+                             (int64_t)((tile0 + u) * 32 + n) * a.a_pad + 8 * h;
 #pragma unroll
-      for (int part = 0; part < kSplitParts; ++part)
+      for (int q = 0; q < QB; ++q)
 #pragma unroll
-        for (int hl = 0; hl < 2; ++hl) bm[p][q][part][hl] = load8<BF>(base + (part * 2 + hl) * plane + 16 * q);
-  }
+        for (int part = 0; part < kSplitParts; ++part)
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl)
+            bm[u][p][q][part][hl] = load8<BF>(base + (part * 2 + hl) * plane + 16 * q);
+    }
 
-  double acc[NACC];
+  double acc[TPW][NACC];
 #pragma unroll
-  for (int u = 0; u < NACC; ++u) acc[u] = 0.0;
+  for (int u = 0; u < TPW; ++u)
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[u][k] = 0.0;
   const int64_t t_begin = (int64_t)chunk * a.chunk;
   const int64_t t_end = t_begin + a.chunk < a.n_time ? t_begin + a.chunk : a.n_time;
   const int64_t row_bytes = (int64_t)a.n_chan * P * a.n_ant;
-  for (int64_t t0 = t_begin; t0 < t_end; t0 += 32) {
+  const uint8_t* chan = a.efield + (int64_t)c * P * a.n_ant;
+
+  uint2 nxt[P][QB];
+  auto load_block = [&](int64_t t0) {
     const int64_t t = t0 + n;                  // this lane's sample row of E
-    float16v_t dre[P], dim[P];
+    const uint8_t* row = chan + t * row_bytes;
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-      dre[p] = float16v_t{};
-      dim[p] = float16v_t{};
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < QB; ++q)
+        nxt[p][q] = load_e8<VEC>(row + p * a.n_ant, 16 * q + 8 * h, a.n_ant, t < t_end);
+  };
+  load_block(t_begin);
+  for (int64_t t0 = t_begin; t0 < t_end; t0 += 32) {
+    uint2 cur[P][QB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < QB; ++q) cur[p][q] = nxt[p][q];
+    if (t0 + 32 < t_end) load_block(t0 + 32);
+
+    float16v_t dre[TPW][P], dim[TPW][P];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u)
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        dre[u][p] = float16v_t{};
+        dim[u][p] = float16v_t{};
+      }
+#pragma unroll
+    for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         int re[8], im[8];
-        const uint8_t* src = a.efield + t * row_bytes + ((int64_t)c * P + p) * a.n_ant;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          const int ant = 16 * q + 8 * h + i;
-          const int b = (t < t_end && ant < a.n_ant) ? (int)src[ant] : 0;
-          re[i] = (b >> 4) - ((b & 0x80) ? 16 : 0);
-          im[i] = (b & 0xF) - ((b & 0x8) ? 16 : 0);
+          const uint32_t w = (i < 4) ? cur[p][q].x : cur[p][q].y;
+          re[i] = __builtin_amdgcn_sbfe((int)w, 8 * (i & 3) + 4, 4);   // high nibble
+          im[i] = __builtin_amdgcn_sbfe((int)w, 8 * (i & 3), 4);       // low nibble
         }
         const v8 er = Ops::from_ints(re), ei = Ops::from_ints(im);
         // Re(F s) = Br er - Bi ei ; Im(F s) = Bi er + Br ei   (hi and lo terms)
 #pragma unroll
-        for (int hl = 0; hl < 2; ++hl) {
-          dre[p] = Ops::mfma(er, bm[p][q][0][hl], dre[p]);
-          dre[p] = Ops::mfma(ei, bm[p][q][2][hl], dre[p]);
-          dim[p] = Ops::mfma(er, bm[p][q][1][hl], dim[p]);
-          dim[p] = Ops::mfma(ei, bm[p][q][0][hl], dim[p]);
+        for (int u = 0; u < TPW; ++u)
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) {
+            dre[u][p] = Ops::mfma(er, bm[u][p][q][0][hl], dre[u][p]);
+            dre[u][p] = Ops::mfma(ei, bm[u][p][q][2][hl], dre[u][p]);
+            dim[u][p] = Ops::mfma(er, bm[u][p][q][1][hl], dim[u][p]);
+            dim[u][p] = Ops::mfma(ei, bm[u][p][q][0][hl], dim[u][p]);
+          }
+      }
+    // epilogue: products summed over the 16 samples of this lane
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      float sm[NACC];
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) sm[k] = 0.f;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float xr = dre[u][0][r], xi = dim[u][0][r];
+        sm[0] = fmaf(xi, xi, fmaf(xr, xr, sm[0]));
+        if (P == 2) {
+          const float yr = dre[u][P - 1][r], yi = dim[u][P - 1][r];
+          sm[1 % NACC] = fmaf(yi, yi, fmaf(yr, yr, sm[1 % NACC]));
+          sm[2 % NACC] = fmaf(xi, yi, fmaf(xr, yr, sm[2 % NACC]));
+          sm[3 % NACC] = fmaf(-xr, yi, fmaf(xi, yr, sm[3 % NACC]));
         }
       }
+#pragma unroll
+      for (int k = 0; k < NACC; ++k) acc[u][k] += (double)sm[k];
     }
-    // epilogue: products summed over the 16 samples of this lane
-    float s[NACC];
-#pragma unroll
-    for (int u = 0; u < NACC; ++u) s[u] = 0.f;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float xr = dre[0][r], xi = dim[0][r];
-      s[0] = fmaf(xi, xi, fmaf(xr, xr, s[0]));
-      if (P == 2) {
-        const float yr = dre[P - 1][r], yi = dim[P - 1][r];
-        s[1 % NACC] = fmaf(yi, yi, fmaf(yr, yr, s[1 % NACC]));
-        s[2 % NACC] = fmaf(xi, yi, fmaf(xr, yr, s[2 % NACC]));
-        s[3 % NACC] = fmaf(-xr, yi, fmaf(xi, yr, s[3 % NACC]));
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < NACC; ++u) acc[u] += (double)s[u];
   }
   double* out = a.partial + (((int64_t)c * a.n_chunks + chunk) * NACC * 2) * a.ng;
 #pragma unroll
-  for (int u = 0; u < NACC; ++u) out[((int64_t)u * 2 + h) * a.ng + pix] = acc[u];
+  for (int u = 0; u < TPW; ++u)
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) out[((int64_t)k * 2 + h) * a.ng + (tile0 + u) * 32 + n] = acc[u][k];
 }
 
 struct SplitReduceArgs {
@@ -240,25 +295,36 @@ struct SplitReduceArgs {
   const float* scale;       // [C][P]
   double* image;            // complex128 [C][NPROD][N][N]
   int n_chan, n_chunks, ng, n, reset;
+  int sub;                  // sub-lanes per pixel, as in reduce_image_kernel
 };
 
-// image (+)= (sum over chunks, in order, and the two lane halves) / scales,
+// image (+)= (sum over chunks and the two lane halves, sub-lane j taking
+// chunks j, j + sub, ... and the sub-lanes added in order) / scales,
 // fftshifted and expanded to XX, XY, YX, YY.
 template <int P>
 __global__ void __launch_bounds__(256) split_reduce_kernel(SplitReduceArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int NPROD = (P == 2) ? 4 : 1;
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (int64_t)a.n_chan * a.ng) return;
-  const int c = (int)(idx / a.ng), pix = (int)(idx % a.ng);
+  __shared__ double red[NACC * 256];
+  const int ppb = 256 / a.sub;
+  const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
+  const int64_t idx = (int64_t)blockIdx.x * ppb + lp;
+  const bool valid = idx < (int64_t)a.n_chan * a.ng;
+  const int c = valid ? (int)(idx / a.ng) : 0, pix = (int)(idx % a.ng);
   double s[NACC];
 #pragma unroll
   for (int u = 0; u < NACC; ++u) s[u] = 0.0;
-  for (int k = 0; k < a.n_chunks; ++k) {
-    const double* src = a.partial + (((int64_t)c * a.n_chunks + k) * NACC * 2) * a.ng + pix;
+  if (valid) {
+#pragma unroll 4
+    for (int k = j; k < a.n_chunks; k += a.sub) {
+      const double* src = a.partial + (((int64_t)c * a.n_chunks + k) * NACC * 2) * a.ng + pix;
 #pragma unroll
-    for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)(2 * u) * a.ng] + src[(int64_t)(2 * u + 1) * a.ng];
+      for (int u = 0; u < NACC; ++u)
+        s[u] += src[(int64_t)(2 * u) * a.ng] + src[(int64_t)(2 * u + 1) * a.ng];
+    }
   }
+  combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
+  if (!valid || j != 0) return;
   const double sx = a.scale[c * P], sy = a.scale[c * P + P - 1];
   const int N = a.n;
   const int km = pix / N, kl = pix % N;
