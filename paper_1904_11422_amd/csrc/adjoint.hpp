@@ -19,7 +19,7 @@ struct AdjointArgs {
   const uint8_t* efield;    // [T][C][P][A]
   const float2* gains;      // [C][P][A]
   const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
-  const uint2* prog;        // gridding programs, as the imager
+  const uint2* prog;        // gridding programs and row-pass lines, as the imager
   const uint2* taps;        // [C][A][KK] {translated cell j*N+i, w bits}
   const float2* twiddle;
   double2* gpartial;        // [W + C - 1][P*A]
@@ -35,7 +35,9 @@ adjoint_kernel(AdjointArgs a) {
   constexpr int NPROD = (P == 2) ? 4 : 1;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
-  __shared__ float2 lds2[P * ES + P * N * RS]; // E'[p][a] (zero slot at a = A), then the grid
+  constexpr int PS = SH::PSTRIDE;
+  // E'[p][a] (zero slots at a = A .. A+15), then the grid
+  __shared__ float2 lds2[P * ES + (P - 1) * PS + N * RS];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
@@ -60,7 +62,7 @@ adjoint_kernel(AdjointArgs a) {
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1;
+  int c = -1, line = -1;
   const uint2* prog = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
@@ -87,7 +89,9 @@ adjoint_kernel(AdjointArgs a) {
     if (cc != c) {
       if (c >= 0) flush();
       c = cc;
-      prog = a.prog + (int64_t)c * a.L * NT;
+      prog = a.prog + (int64_t)c * (a.L + 1) * NT;
+      line = (int)prog[tid].x;
+      prog += NT;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
         const int k = tid + i * NT;
@@ -121,7 +125,7 @@ adjoint_kernel(AdjointArgs a) {
     if (left > 1) load_bytes(cc, tt, nxt);
 
     stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
-    row_pass<N, P, +1>(X, r, tw);
+    row_pass<N, P, +1>(X, r, tw, line);
     __syncthreads();
     float2 v[P][S];
     column_pass_fwd<N, P>(v, X, r, tw);
@@ -143,13 +147,13 @@ adjoint_kernel(AdjointArgs a) {
     // adjoint column transforms, results to the band rows of each column
     const int kl = r.kl;
     line_transform_rev<N, -1, P>(v, tw, r.n0, X,
-                                 [kl](int p, int s) { return (p * N + s) * RS + kl; });
+                                 [kl](int p, int s) { return p * PS + s * RS + kl; });
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int n1 = 0; n1 < S / 2; ++n1) X[(p * N + R * n1 + r.n0) * RS + kl] = v[p][n1];
+      for (int n1 = 0; n1 < S / 2; ++n1) X[p * PS + (R * n1 + r.n0) * RS + kl] = v[p][n1];
     __syncthreads();
-    row_pass<N, P, -1>(X, r, tw);
+    row_pass<N, P, -1>(X, r, tw, line);
     __syncthreads();
 
     // degrid: dL/de'* at each antenna, times conj(e)
@@ -164,7 +168,7 @@ adjoint_kernel(AdjointArgs a) {
           const uint2 t = tp[q];
           const int cell = (int)t.x;
           const float w = __uint_as_float(t.y);
-          const float2 h = X[(p * N + cell / N) * RS + cell % N];
+          const float2 h = X[p * PS + (cell / N) * RS + cell % N];
           s.x = fmaf(w, h.x, s.x);
           s.y = fmaf(w, h.y, s.y);
         }

@@ -222,27 +222,34 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 // up to a multiple of its step chunk).
 // Step: {cell byte offset << 16 | E' byte offset, weight bits with the sign
 // bit set on the last entry of a cell}.
-// Gridding programs of the fused kernels, one list of steps per thread and
-// channel, scheduled for the LDS banks.  LDS serves a 64-bit access 16 lanes
-// at a time from 32 four-byte banks, so 16 lanes of a quarter-wave hit
-// distinct banks when their float2 addresses differ modulo 16.
-//  * Cell writes: lane l of every quarter-wave only owns cells whose float2
-//    address is l modulo 16 (cells of one bank class are dealt longest-first
-//    to the least loaded of that class's lanes).
-//  * E' reads: the entries of a cell may be taken in any order; step by step,
-//    lanes whose cell has one entry left take it, then the others take the
-//    remaining entry whose bank the quarter-wave uses least.  Empty cells and
-//    padding read one of 16 zero slots of E' (slots A .. A+15), on the least
-//    used bank.
-//  * Padding steps write zero to a spare column (>= N/2, overwritten by the
-//    row transform) on the lane's own bank.
+// Gridding programs of the fused kernels, per channel: a header row with the
+// row-pass line of every thread (p << 16 | j, or -1), then L steps per thread.
+//  * Rows: each wave transforms CPW/P aperture rows of every polarisation and
+//    grids exactly those rows, so gridding and the row pass are separated by
+//    a wave-level fence only.  Row slot s of a wave takes a row j = s mod M
+//    (M = 4 at N = 64, 8 at N = 32 with P = 2, 16 with P = 1), which keeps the
+//    row pass free of bank conflicts; within that rule rows are dealt heaviest
+//    first to the least loaded wave.  A wave's cells are dealt longest first
+//    to the least loaded of its 64 threads.
+//  * Banks: LDS serves a 64-bit access 16 lanes at a time from 32 four-byte
+//    banks, so 16 lanes of a quarter-wave hit distinct banks when their float2
+//    addresses differ modulo 16.  A cell is written once, at its last entry,
+//    so few lanes of a quarter-wave write at the same step.  The entries of a
+//    cell may be taken in any order: step by step, lanes with one entry left
+//    take it, then the others take the remaining entry whose bank the
+//    quarter-wave uses least.  Empty cells read one of 16 zero slots of E'
+//    (slots A .. A+15) on the least used bank and write zero; padding steps
+//    add zero and write nothing.
 template <int N>
 void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L) {
   constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
-  constexpr int NQ = NT / 16;                          // quarter-waves per workgroup
+  constexpr int CPW = epic::FusedShape<N>::CPW, NWAVE = NT / 64;
   const int C = g.C, A = g.A, KK = g.KK;
   const int ES = NT * gpt / P + 64;                    // EStride<NT, gpt, P>
   const int XB = P * ES;                               // grid base, float2 units
+  const int SPW = CPW / P;                             // row slots per wave
+  const int M = N == 64 ? 4 : (P == 2 ? 8 : 16);       // residue rule of the slots
+  const int NWR = H / SPW;                             // waves that own rows
   auto code = [](int cell_f2, int e) {
     return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
   };
@@ -256,6 +263,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     std::vector<std::pair<int, float>> ent;            // (antenna, weight)
   };
   std::vector<std::vector<uint32_t>> words((size_t)C * NT);   // [c][thread] -> step words
+  std::vector<int32_t> header((size_t)C * NT, -1);
   L = 1;
   for (int c = 0; c < C; ++c) {
     std::vector<Run> cells(H * H);
@@ -267,33 +275,61 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
         cells[j * H + i].ent.push_back({a, g.w[o]});
       }
-    // bank classes, longest-first to the least loaded lane of the class
+    // rows to (wave, slot)
+    std::vector<int> row_load(H, 0);
+    for (int j = 0; j < H; ++j)
+      for (int i = 0; i < H; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * H + i].ent.size());
+    std::vector<int> wave_load(NWAVE, 0);
+    std::vector<std::vector<int>> row_of(NWAVE, std::vector<int>(SPW, -1));
+    for (int rho = 0; rho < M; ++rho) {
+      std::vector<int> rows;
+      for (int j = rho; j < H; j += M) rows.push_back(j);
+      std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
+      for (int j : rows) {
+        int bw = -1, bs = -1;
+        for (int w = 0; w < NWR; ++w)
+          for (int sl = rho; sl < SPW; sl += M)
+            if (row_of[w][sl] < 0 && (bw < 0 || wave_load[w] < wave_load[bw])) {
+              bw = w;
+              bs = sl;
+              break;
+            }
+        row_of[bw][bs] = j;
+        wave_load[bw] += row_load[j];
+      }
+    }
+    for (int t = 0; t < NT; ++t) {
+      const epic::Roles<N> ro(t);
+      if (ro.wave >= NWR) continue;
+      const int p = ro.sub / SPW, sl = ro.sub % SPW;
+      if (p < P) header[(size_t)c * NT + t] = (p << 16) | row_of[ro.wave][sl];
+    }
+    // cells of each wave's rows, longest first, to the least loaded lane of the wave
     std::vector<std::vector<const Run*>> lane_runs(NT);
     std::vector<int> load(NT, 0);
-    for (int b = 0; b < 16; ++b) {
-      std::vector<const Run*> cls;
-      for (const Run& r : cells)
-        if ((XB + r.cell) % 16 == b) cls.push_back(&r);
-      std::stable_sort(cls.begin(), cls.end(), [](const Run* x, const Run* y) {
+    for (int w = 0; w < NWR; ++w) {
+      std::vector<const Run*> wc;
+      for (int sl = 0; sl < SPW; ++sl)
+        for (int i = 0; i < H; ++i) wc.push_back(&cells[row_of[w][sl] * H + i]);
+      std::stable_sort(wc.begin(), wc.end(), [](const Run* x, const Run* y) {
         return std::max<size_t>(1, x->ent.size()) > std::max<size_t>(1, y->ent.size());
       });
-      using Load = std::pair<int, int>;                // (steps, quarter-wave)
+      using Load = std::pair<int, int>;                // (steps, thread)
       std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-      for (int q = 0; q < NQ; ++q) pq.push({0, q});
-      for (const Run* r : cls) {
+      for (int t = 64 * w; t < 64 * w + 64; ++t) pq.push({0, t});
+      for (const Run* r : wc) {
         Load ld = pq.top();
         pq.pop();
-        const int t = 16 * ld.second + b;
-        lane_runs[t].push_back(r);
+        lane_runs[ld.second].push_back(r);
         ld.first += (int)std::max<size_t>(1, r->ent.size());
-        load[t] = ld.first;
+        load[ld.second] = ld.first;
         pq.push(ld);
       }
     }
-    const int Lc = *std::max_element(load.begin(), load.end());
+    const int Lc = std::max(1, *std::max_element(load.begin(), load.end()));
     L = std::max(L, Lc);
     // step-by-step choice of the E' entries, per quarter-wave
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < NT / 16; ++q) {
       struct Lane {
         size_t run = 0;
         std::vector<std::pair<int, float>> left;       // entries of the current run not yet taken
@@ -306,17 +342,15 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
         float pick_w[16];
         bool pick_last[16];
         bool decided[16] = {false};
-        auto open = [&](int l) {                        // make the current run's list ready
+        for (int l = 0; l < 16; ++l) {                 // open the current run
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
           if (!s.started && s.run < runs.size()) {
             s.left = runs[s.run]->ent;
             s.started = true;
           }
-        };
-        // lanes with no choice: one entry left
-        for (int l = 0; l < 16; ++l) {
-          open(l);
+        }
+        for (int l = 0; l < 16; ++l) {                 // lanes with one entry left
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
           if (s.run < runs.size() && s.left.size() == 1) {
@@ -328,8 +362,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
             decided[l] = true;
           }
         }
-        // lanes with several entries left
-        for (int l = 0; l < 16; ++l) {
+        for (int l = 0; l < 16; ++l) {                 // lanes with several entries left
           if (decided[l]) continue;
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
@@ -344,8 +377,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
           used[pick_e[l] % 16]++;
           decided[l] = true;
         }
-        // empty cells and padding: a zero slot on the least used bank
-        for (int l = 0; l < 16; ++l) {
+        for (int l = 0; l < 16; ++l) {                 // empty cells and padding
           if (decided[l]) continue;
           int z = 0;
           for (int k = 1; k < 16; ++k)
@@ -353,17 +385,10 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
           used[(A + z) % 16]++;
           pick_e[l] = A + z;
           pick_w[l] = 0.f;
-          pick_last[l] = true;
-          Lane& s = st[l];
+          const Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
-          if (s.run < runs.size()) {
-            pick_cell[l] = runs[s.run]->cell;          // empty cell
-          } else {                                     // padding: spare column, own bank
-            const int r = q % H;
-            int i = H;
-            while ((XB + r * RS + i) % 16 != l) ++i;
-            pick_cell[l] = r * RS + i;
-          }
+          pick_last[l] = s.run < runs.size();          // empty cell: write zero; padding: no write
+          pick_cell[l] = s.run < runs.size() ? runs[s.run]->cell : 0;
           decided[l] = true;
         }
         for (int l = 0; l < 16; ++l) {
@@ -388,28 +413,25 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     }
   }
   if (L > epic::kMaxFixedSteps) L = (L + epic::kStepChunk - 1) / epic::kStepChunk * epic::kStepChunk;
-  out.assign((size_t)C * L * NT * 2, 0u);
+  out.assign((size_t)C * (L + 1) * NT * 2, 0u);
   for (int c = 0; c < C; ++c)
-    for (int q = 0; q < NQ; ++q)
-      for (int l = 0; l < 16; ++l) {
-        const int t = 16 * q + l;
-        const auto& wv = words[(size_t)c * NT + t];
-        // padding beyond this channel's steps: zero slot, spare column on the lane's bank
-        const int r = q % H;
-        int i = H;
-        while ((XB + r * RS + i) % 16 != l) ++i;
-        const uint32_t pad = code(r * RS + i, A + l);
-        for (int s2 = 0; s2 < L; ++s2) {
-          const size_t o = (((size_t)c * L + s2) * NT + t) * 2;
-          if ((size_t)s2 < wv.size() / 2) {
-            out[o] = wv[2 * s2];
-            out[o + 1] = wv[2 * s2 + 1];
-          } else {
-            out[o] = pad;
-            out[o + 1] = wbits(0.f, true);
-          }
+    for (int t = 0; t < NT; ++t) {
+      const size_t h = ((size_t)c * (L + 1) * NT + t) * 2;
+      out[h] = (uint32_t)header[(size_t)c * NT + t];
+      out[h + 1] = 0u;
+      const auto& wv = words[(size_t)c * NT + t];
+      const uint32_t pad = code(0, A + t % 16);
+      for (int s2 = 0; s2 < L; ++s2) {
+        const size_t o = (((size_t)c * (L + 1) + 1 + s2) * NT + t) * 2;
+        if ((size_t)s2 < wv.size() / 2) {
+          out[o] = wv[2 * s2];
+          out[o + 1] = wv[2 * s2 + 1];
+        } else {
+          out[o] = pad;
+          out[o + 1] = wbits(0.f, false);
         }
       }
+    }
 }
 
 template <typename F>

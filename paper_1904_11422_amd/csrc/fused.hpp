@@ -34,11 +34,11 @@ namespace epic {
 // Gridding step: {code, weight bits}.  code = LDS byte offset of the cell
 // (pol 0) << 16 | byte offset of E'[e] (pol 0); the weight's sign bit marks
 // the last entry of a cell (the weights themselves are >= 0).  Every step
-// reads E' of both polarisations, adds |w| * E' to the running sums, stores
-// them to the cell and restarts the sums after the last entry.  Cells with no
-// antenna read a zero slot of E'; padding steps write to a spare column.  The
-// host orders the steps so that the lanes of a quarter-wave touch distinct
-// LDS banks.
+// reads E' of both polarisations and adds |w| * E' to the running sums; the
+// last entry of a cell stores the sums to the cell and restarts them.  Cells
+// with no antenna read a zero slot of E'; padding steps add zero and store
+// nothing.  The host orders the steps so that the lanes of a quarter-wave
+// mostly touch distinct LDS banks.
 constexpr int STEP_CELL_SHIFT = 16;
 constexpr uint32_t STEP_E_MASK = 0xFFFFu;
 constexpr uint32_t STEP_LAST_BIT = 0x80000000u; // in the weight word
@@ -53,6 +53,10 @@ template <int N> struct FusedShape {
   // below every access of the two line passes is free of LDS bank conflicts
   // (32 banks of 4 bytes; paired 8-byte accesses by groups of 16 lanes)
   static constexpr int RS = N == 32 ? N + 1 : N + 4;
+  // polarisation stride of the grid in float2; at N = 32 the extra 8 puts the
+  // same row of the two polarisations on different banks (a wave transforms
+  // both in one row pass)
+  static constexpr int PSTRIDE = N * RS + (N == 32 ? 8 : 0);
   static constexpr int H = N / 2;              // aperture block side
   static constexpr int KBLOCK = 128;           // samples summed in float32 before a float64 flush
   // waves per SIMD the register budget is sized for: two resident workgroups
@@ -70,7 +74,7 @@ template <int NT, int GPT, int P> struct EStride {
 struct FusedArgs {
   const uint8_t* efield;    // [T][C][P][A]
   const float2* gains;      // [C][P][A]
-  const uint2* prog;        // [C][L][NT]
+  const uint2* prog;        // [C][1 + L][NT]: row-pass line of each thread, then L steps
   const float2* twiddle;    // [N] exp(+2 pi i k / N)
   double* partial;          // [W + C - 1][NACC][S][NT] (thread-major)
   int64_t n_time;
@@ -150,12 +154,13 @@ __device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, floa
     s1.x = fmaf(w, e1.x, s1.x);
     s1.y = fmaf(w, e1.y, s1.y);
   }
-  float2* cell = reinterpret_cast<float2*>(lds + xbase + (step.x >> STEP_CELL_SHIFT));
-  cell[0] = s0;
-  if (P == 2) cell[N * RS] = s1;
-  const bool last = (int)step.y < 0;
-  s0 = last ? make_float2(0.f, 0.f) : s0;
-  s1 = last ? make_float2(0.f, 0.f) : s1;
+  if ((int)step.y < 0) {                        // last entry of the cell
+    float2* cell = reinterpret_cast<float2*>(lds + xbase + (step.x >> STEP_CELL_SHIFT));
+    cell[0] = s0;
+    if (P == 2) cell[FusedShape<N>::PSTRIDE] = s1;
+    s0 = make_float2(0.f, 0.f);
+    s1 = make_float2(0.f, 0.f);
+  }
 }
 
 template <int P, int ES>
@@ -199,8 +204,10 @@ __device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* 
 }
 
 // Steps 1-2 of one sample: load the gridding program (exactly L steps for
-// L <= kMaxFixedSteps), stage E', barrier, grid, barrier.  prog is the
-// channel's program [L][NT]; the switch on L is uniform over the workgroup.
+// L <= kMaxFixedSteps), stage E', barrier, grid.  A thread grids only cells
+// of rows its own wave transforms next, so gridding ends with a wave-level
+// fence.  prog is the channel's step list [L][NT]; the switch on L is
+// uniform over the workgroup.
 template <int N, int P, int NT, int RS, int ES, int GPT>
 __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, const uint2* prog,
                                                int L, const uint32_t (&cur)[GPT],
@@ -228,41 +235,39 @@ __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, 
     __syncthreads();
     grid_chunked<N, P, RS, ES>(lds, xbase, prog + tid, NT, L);
   }
-  __syncthreads();
+  wave_lds_sync();
 }
 
 // 3a. Row transforms of the H = N/2 aperture rows of each polarisation, in
-// place (each row private to the R lanes of one wave).  SG > 0: forward, the
-// row holds cells at columns < H.  SG < 0: adjoint, the row holds the forward
-// output layout and the columns < H of the result are written back.
+// place.  line = p << 16 | j is the row this thread's R lanes transform (from
+// the channel's program; < 0: none); each wave transforms the rows it has
+// just gridded, so only a wave-level fence separates the two.  SG > 0:
+// forward, the row holds cells at columns < H.  SG < 0: adjoint, the row
+// holds the forward output layout and the columns < H of the result are
+// written back.
 template <int N, int P, int SG>
-__device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw) {
-  constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D, H = N / 2;
-  constexpr int NT = FusedShape<N>::NT, CPW = FusedShape<N>::CPW, RS = FusedShape<N>::RS;
-  for (int line0 = r.wave * CPW; line0 < P * H; line0 += NT / R) {
-    const int line = line0 + r.sub;
-    if (line < P * H) {
-      const int p = line / H;
-      const int j = line - p * H;
-      float2* row = X + (p * N + j) * RS;
-      float2 v[1][S];
-      if (SG > 0) {
+__device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw, int line) {
+  constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
+  constexpr int RS = FusedShape<N>::RS, PS = FusedShape<N>::PSTRIDE;
+  if (line >= 0) {
+    float2* row = X + (line >> 16) * PS + (line & 0xFFFF) * RS;
+    float2 v[1][S];
+    if (SG > 0) {
 #pragma unroll
-        for (int n1 = 0; n1 < S / 2; ++n1) v[0][n1] = row[R * n1 + r.n0];
-        line_transform<N, +1, 1, true>(v, tw, r.n0, row, [](int, int s) { return s; });
+      for (int n1 = 0; n1 < S / 2; ++n1) v[0][n1] = row[R * n1 + r.n0];
+      line_transform<N, +1, 1, true>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
-        for (int q = 0; q < D; ++q)
+      for (int q = 0; q < D; ++q)
 #pragma unroll
-          for (int k1 = 0; k1 < R; ++k1) row[r.n0 * D + q + S * k1] = v[0][q * R + k1];
-      } else {
+        for (int k1 = 0; k1 < R; ++k1) row[r.n0 * D + q + S * k1] = v[0][q * R + k1];
+    } else {
 #pragma unroll
-        for (int q = 0; q < D; ++q)
+      for (int q = 0; q < D; ++q)
 #pragma unroll
-          for (int k1 = 0; k1 < R; ++k1) v[0][q * R + k1] = row[r.n0 * D + q + S * k1];
-        line_transform_rev<N, -1, 1>(v, tw, r.n0, row, [](int, int s) { return s; });
+        for (int k1 = 0; k1 < R; ++k1) v[0][q * R + k1] = row[r.n0 * D + q + S * k1];
+      line_transform_rev<N, -1, 1>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
-        for (int n1 = 0; n1 < S / 2; ++n1) row[R * n1 + r.n0] = v[0][n1];
-      }
+      for (int n1 = 0; n1 < S / 2; ++n1) row[R * n1 + r.n0] = v[0][n1];
     }
   }
 }
@@ -273,13 +278,14 @@ template <int N, int P>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
                                                 const Roles<N>& r, const float2* tw) {
   constexpr int S = Line<N>::S, R = Line<N>::R, RS = FusedShape<N>::RS;
+  constexpr int PS = FusedShape<N>::PSTRIDE;
   const int kl = r.kl;
 #pragma unroll
   for (int p = 0; p < P; ++p) {                 // one polarisation at a time
     float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
 #pragma unroll
-    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[(p * N + R * n1 + r.n0) * RS + kl];
-    line_transform<N, +1, 1, true>(vp, tw, r.n0, X + p * N * RS,
+    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[p * PS + (R * n1 + r.n0) * RS + kl];
+    line_transform<N, +1, 1, true>(vp, tw, r.n0, X + p * PS,
                                    [kl](int, int s) { return s * RS + kl; });
   }
 }
@@ -293,7 +299,8 @@ fused_image_kernel(FusedArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
-  __shared__ float2 lds2[P * ES + P * N * RS]; // E'[p][a] (zero slot at a = A), then the grid
+  // E'[p][a] (zero slots at a = A .. A+15), then the grid
+  __shared__ float2 lds2[P * ES + (P - 1) * SH::PSTRIDE + N * RS];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
@@ -316,7 +323,7 @@ fused_image_kernel(FusedArgs a) {
   float acc[S][NACC];                          // float32 sums over <= KB samples
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, nblk = 0, nflush = 0;
+  int c = -1, nblk = 0, nflush = 0, line = -1;
   const uint2* prog = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
@@ -351,7 +358,9 @@ fused_image_kernel(FusedArgs a) {
       if (c >= 0) flush();
       c = cc;
       nflush = 0;
-      prog = a.prog + (int64_t)c * a.L * NT;
+      prog = a.prog + (int64_t)c * (a.L + 1) * NT;
+      line = (int)prog[tid].x;
+      prog += NT;
 #pragma unroll
       for (int i = 0; i < S; ++i)
 #pragma unroll
@@ -372,7 +381,7 @@ fused_image_kernel(FusedArgs a) {
     if (left > 1) load_bytes(cc, tt, nxt);
 
     stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
-    row_pass<N, P, +1>(X, r, tw);
+    row_pass<N, P, +1>(X, r, tw, line);
     __syncthreads();
     float2 v[P][S];
     column_pass_fwd<N, P>(v, X, r, tw);
