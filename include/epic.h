@@ -107,6 +107,28 @@ epic_status epic_set_stream(epic_ctx *ctx, void *hip_stream);
  * previous geometry, if any, stays in force), EPIC_E_NOMEM. */
 epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *freq_hz);
 
+/* Host-side view of the gridding programs the fused kernels run for a
+ * configuration and geometry (Sec. 2.1 Eq. (4): the kernel taps of every
+ * antenna, gathered per grid cell).  No device work: usable without a GPU, for
+ * verification tools.  cfg must select the fused float32 path (grid_n 32 or 64,
+ * EPIC_FP32, no EPIC_FLAG_STAGED).  out receives, as epic_set_antennas uploads it,
+ *   uint32 [n_chan][1 + L][NT][2]:
+ *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
+ *                    (int32 -1: none); word 1: 0;
+ *     rows 1..L:     steps {LDS byte offset of the cell, relative to the grid
+ *                    base, << 16 | LDS byte offset of E'[p = 0][a], float32
+ *                    weight bits with the sign bit set on a cell's last entry}.
+ * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
+ * layout: out, int32 [6] = {NT, L, row stride, polarisation stride, grid base,
+ * E' polarisation stride}, strides and base in float2 units.
+ * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
+ * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
+ * taps do not fit an N/2 x N/2 block), EPIC_E_NOMEM (capacity too small;
+ * *words holds the size).  Messages: epic_last_error(NULL). */
+epic_status epic_gridding_program(const epic_config *cfg, const double *xy_m,
+                                  const double *freq_hz, uint32_t *out, int64_t *words,
+                                  int32_t *layout);
+
 /* Accumulate polarised images over n_time samples (Sec. 2.1 Eq. (5), Sec. 3.2).
  *   efield: device uint8 [n_time][n_chan][n_pol][n_ant] (4+4-bit samples);
  *   gains:  device complex64 [n_chan][n_pol][n_ant], e' = gain * e;

@@ -212,16 +212,6 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
   return EPIC_OK;
 }
 
-// Per-thread gather programs of the fused kernel over the N/2 x N/2 aperture
-// block (translated taps).  Every cell belongs to exactly one thread; its
-// entries (antenna ascending, then tap order) are summed in that order.  A
-// cell with no antenna gets one step that reads the zero slot of E'.  Cells
-// are dealt longest-first to the least loaded thread; lists are padded to a
-// common length L with steps that read the zero slot and write to a spare
-// column of the LDS grid (L above the kernel's fixed-length limit is rounded
-// up to a multiple of its step chunk).
-// Step: {cell byte offset << 16 | E' byte offset, weight bits with the sign
-// bit set on the last entry of a cell}.
 // Gridding programs of the fused kernels, per channel: a header row with the
 // row-pass line of every thread (p << 16 | j, or -1), then L steps per thread.
 //  * Rows: each wave transforms CPW/P aperture rows of every polarisation and
@@ -794,6 +784,45 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
 epic_status epic_set_stream(epic_ctx* x, void* hip_stream) {
   if (!x) return EPIC_E_INVALID;
   x->stream = static_cast<hipStream_t>(hip_stream);
+  return EPIC_OK;
+}
+
+epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, const double* freq_hz,
+                                  uint32_t* out, int64_t* words, int32_t* layout) {
+  g_init_error.clear();
+  std::string m;
+  epic_status s = check_config(cfg, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  if (!xy_m || !freq_hz || !words || !layout) { g_init_error = "null pointer"; return EPIC_E_INVALID; }
+  const int N = cfg->grid_n, P = cfg->n_pol;
+  if (N > 64 || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
+    g_init_error = "the configuration has no fused kernel";
+    return EPIC_E_UNSUPPORTED;
+  }
+  const int NT = fused_threads(N);
+  int gpt = (P * cfg->n_ant + NT - 1) / NT;
+  gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
+  if (gpt == 0) { g_init_error = "too many antennas for the fused kernel"; return EPIC_E_UNSUPPORTED; }
+  Geometry g;
+  s = build_geometry(*cfg, xy_m, freq_hz, g, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  if (!g.fits_half) { g_init_error = "taps do not fit an N/2 x N/2 block"; return EPIC_E_UNSUPPORTED; }
+  std::vector<uint32_t> prog;
+  int L = 0;
+  if (N == 32) build_programs<32>(g, P, gpt, prog, L);
+  else build_programs<64>(g, P, gpt, prog, L);
+  const int64_t need = (int64_t)prog.size(), cap = *words;
+  *words = need;
+  const int ES = NT * gpt / P + 64;
+  layout[0] = NT;
+  layout[1] = L;
+  layout[2] = N == 32 ? epic::FusedShape<32>::RS : epic::FusedShape<64>::RS;
+  layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE : epic::FusedShape<64>::PSTRIDE;
+  layout[4] = P * ES;
+  layout[5] = ES;
+  if (cap == 0) return EPIC_OK;
+  if (!out || cap < need) { g_init_error = "output capacity too small"; return EPIC_E_NOMEM; }
+  std::memcpy(out, prog.data(), prog.size() * sizeof(uint32_t));
   return EPIC_OK;
 }
 

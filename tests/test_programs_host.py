@@ -1,0 +1,156 @@
+"""Host-side checks of the gridding programs the fused kernels run (built by
+the library without a GPU through epic_gridding_program): emulating the
+kernel's gather in float64 reproduces the oracle's gridding (paper Sec. 2.1
+Eq. (4)-(5)) of every channel; every aperture cell is stored exactly once, by
+a thread of the wave that transforms its row; every LDS offset stays inside
+its region; the row-pass lines cover each aperture row of each polarisation
+once, with a wave's rows distinct modulo 4 (N = 64) so the row transform stays
+free of bank conflicts."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1904_11422_amd import _lib
+
+pytestmark = pytest.mark.skipif(not __import__("os").path.exists(_lib.LIB_PATH),
+                                reason="libepic.so is not built")
+
+R_OF = {32: 4, 64: 8}
+
+
+def _program(inp, n_pol=None):
+    L = _lib.load()
+    P = inp.n_pol if n_pol is None else n_pol
+    cfg = _lib.EpicConfig(inp.grid_n, inp.n_chan, P, inp.n_ant, 3, 0.5, 0.5, _lib.EPIC_FP32, 0)
+    xy = np.ascontiguousarray(inp.xy_m, dtype=np.float64)
+    f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    words = ctypes.c_int64(0)
+    layout = (ctypes.c_int32 * 6)()
+    st = L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                 None, ctypes.byref(words), layout)
+    assert st == _lib.EPIC_OK, L.epic_last_error(None)
+    out = np.zeros(words.value, dtype=np.uint32)
+    st = L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                 ctypes.byref(words), layout)
+    assert st == _lib.EPIC_OK, L.epic_last_error(None)
+    NT, nsteps, RS, PS, XB, ES = list(layout)
+    return out.reshape(inp.n_chan, 1 + nsteps, NT, 2), dict(NT=NT, L=nsteps, RS=RS, PS=PS, XB=XB, ES=ES, P=P)
+
+
+CASES = {
+    "lwa_like_12ch": lambda: _subset(synth.config2(), 12),
+    "tiny_n32_p1": lambda: synth.config1(),
+    "n32_p2_a24": lambda: synth.random_problem(3, 32, 24, 2, 2, 2),
+    "n64_p2_a300_two_per_thread": lambda: synth.random_problem(5, 64, 300, 3, 2, 2),
+}
+
+
+def _subset(inp, n):
+    idx = np.linspace(0, inp.n_chan - 1, n).round().astype(int)
+    inp.freq_hz = np.asarray(inp.freq_hz)[idx]
+    inp.n_chan = n
+    return inp
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("one_pol", [False, True])
+def test_programs_reproduce_gridding(name, one_pol):
+    inp = CASES[name]()
+    P = 1 if one_pol else inp.n_pol
+    prog, g = _program(inp, P)
+    N, A, H = inp.grid_n, inp.n_ant, inp.grid_n // 2
+    NT, RS, PS, ES, nsteps = g["NT"], g["RS"], g["PS"], g["ES"], g["L"]
+    R = R_OF[N]
+    X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
+    ii, jj, w = oracle.kernel_taps(X, Y, N)
+    rng = np.random.default_rng(0)
+    for c in range(inp.n_chan):
+        # header: every (p, j < H) row owned by R lanes of one wave
+        hdr = prog[c, 0, :, 0].view(np.int32)
+        rows_of_wave = {}
+        seen = {}
+        for t in np.nonzero(hdr >= 0)[0]:
+            p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
+            assert p < P and j < H
+            seen.setdefault((p, j), []).append(t // 64)
+            rows_of_wave.setdefault(t // 64, set()).add(j)
+        assert sorted(seen) == [(p, j) for p in range(P) for j in range(H)]
+        for lanes in seen.values():
+            assert len(lanes) == R and len(set(lanes)) == 1
+        # first load of the row transform: the 16 lanes of a quarter-wave on
+        # distinct bank pairs (float2 address modulo 16)
+        for q in range(NT // 16):
+            banks = []
+            for t in range(16 * q, 16 * q + 16):
+                if hdr[t] < 0:
+                    continue
+                p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
+                lane = t % 64
+                n0 = 4 * ((lane >> 4) >> 1) + ((lane >> 2) & 3) if N == 64 else lane // 16
+                banks.append((g["XB"] + p * PS + j * RS + n0) % 16)
+            assert len(banks) == len(set(banks))
+        # emulate the gather (pol 0; the kernel applies the same step to pol 1)
+        code, wb = prog[c, 1:, :, 0], prog[c, 1:, :, 1]
+        cell = (code >> 16).astype(np.int64)
+        eoff = (code & 0xFFFF).astype(np.int64)
+        assert np.all(cell % 8 == 0) and np.all(eoff % 8 == 0)
+        cell //= 8
+        eoff //= 8
+        assert eoff.max() < A + 16 and A + 16 <= ES
+        last = (wb >> 31).astype(bool)
+        wt = (wb & 0x7FFFFFFF).view(np.float32).astype(np.float64)
+        assert np.all(cell < N * RS) and np.all(cell % RS < RS)
+        E = np.zeros(ES)
+        E[:A] = rng.standard_normal(A)
+        grid = np.full(N * RS, np.nan)
+        stores = np.zeros(N * RS, dtype=int)
+        s = np.zeros(NT)
+        for st in range(nsteps):
+            s += wt[st] * E[eoff[st]]
+            idx = np.nonzero(last[st])[0]
+            grid[cell[st, idx]] = s[idx]
+            np.add.at(stores, cell[st, idx], 1)
+            for t in idx:                       # stored by the wave owning the row
+                j, i = divmod(int(cell[st, t]), RS)
+                assert j < H and i < H and j in rows_of_wave[t // 64]
+            s[idx] = 0.0
+        ti = ii[c] - ii[c].min()
+        tj = jj[c] - jj[c].min()
+        ref = np.zeros((H, H))
+        np.add.at(ref, (tj, ti), w[c] * E[:A, None])
+        got = grid.reshape(N, RS)[:H, :H]
+        assert np.all(stores.reshape(N, RS)[:H, :H] == 1)
+        assert stores.sum() == H * H
+        assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_program_query_and_errors():
+    L = _lib.load()
+    inp = synth.config1()
+    dp = ctypes.POINTER(ctypes.c_double)
+    xy = np.ascontiguousarray(inp.xy_m, dtype=np.float64)
+    f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
+    layout = (ctypes.c_int32 * 6)()
+    words = ctypes.c_int64(0)
+    staged = _lib.EpicConfig(32, 1, 1, 16, 3, 0.5, 0.5, _lib.EPIC_FP32, _lib.EPIC_FLAG_STAGED)
+    assert L.epic_gridding_program(ctypes.byref(staged), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                   None, ctypes.byref(words), layout) == _lib.EPIC_E_UNSUPPORTED
+    cfg = _lib.EpicConfig(32, 1, 1, 16, 3, 0.5, 0.5, _lib.EPIC_FP32, 0)
+    assert L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                   None, ctypes.byref(words), layout) == _lib.EPIC_OK
+    need = words.value
+    small = np.zeros(max(need - 1, 1), dtype=np.uint32)
+    words = ctypes.c_int64(small.size)
+    assert L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                   small.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                   ctypes.byref(words), layout) == _lib.EPIC_E_NOMEM
+    assert words.value == need
+    far = np.array(xy) * 50.0                     # off the 32 x 32 grid
+    far = np.ascontiguousarray(far)
+    assert L.epic_gridding_program(ctypes.byref(cfg), far.ctypes.data_as(dp), f.ctypes.data_as(dp),
+                                   None, ctypes.byref(words), layout) == _lib.EPIC_E_OFFGRID
