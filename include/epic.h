@@ -119,8 +119,11 @@ epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *f
  *                    base, << 16 | LDS byte offset of E'[p = 0][a], float32
  *                    weight bits with the sign bit set on a cell's last entry}.
  * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
- * layout: out, int32 [6] = {NT, L, row stride, polarisation stride, grid base,
- * E' polarisation stride}, strides and base in float2 units.
+ * layout: out, int32 [7] = {NT, L, row stride, polarisation stride, grid base,
+ * E' polarisation stride, row order}, strides and base in float2 units; row
+ * order 1: aperture row j < N/2 is stored at physical row
+ * 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and cell offsets use
+ * physical rows), 0: at row j.
  * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
  * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
  * taps do not fit an N/2 x N/2 block), EPIC_E_NOMEM (capacity too small;

@@ -20,7 +20,7 @@ struct AdjointArgs {
   const float2* gains;      // [C][P][A]
   const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
   const uint2* prog;        // gridding programs and row-pass lines, as the imager
-  const uint2* taps;        // [C][A][KK] {translated cell j*N+i, w bits}
+  const uint2* taps;        // [C][A][KK] {physical translated cell j*N+i, w bits}
   const float2* twiddle;
   double2* gpartial;        // [W + C - 1][P*A]
   int64_t n_time, total;
@@ -144,14 +144,14 @@ adjoint_kernel(AdjointArgs a) {
         v[0][i] = cscale(fx, ga[i]);
       }
     }
-    // adjoint column transforms, results to the band rows of each column
+    // adjoint column transforms, results to the aperture rows of each column
     const int kl = r.kl;
     line_transform_rev<N, -1, P>(v, tw, r.n0, X,
                                  [kl](int p, int s) { return p * PS + s * RS + kl; });
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int n1 = 0; n1 < S / 2; ++n1) X[p * PS + (R * n1 + r.n0) * RS + kl] = v[p][n1];
+      for (int n1 = 0; n1 < S / 2; ++n1) X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl] = v[p][n1];
     __syncthreads();
     row_pass<N, P, -1>(X, r, tw, line);
     __syncthreads();

@@ -153,10 +153,11 @@ template <> struct Line<128> { static constexpr int S = 16, R = 8, D = 2; };
 //   in:  v[p][n1] = x_p[R n1 + n0]                      (n1 < S)
 //   out: v[p][q R + k1] = X_p[(n0 D + q) + S k1]        (q < D, k1 < R)
 // tw[k0] = exp(+2 pi i n0 k0 / N) (conjugated here when SG < 0).
-// The exchange between the passes goes through the line's own slots, skewed
-// by k0 so that the lanes of the exchange hit different LDS banks.
+// The exchange between the passes goes through the line's own slots: value k0
+// of lane n0 goes to slot k0 R + (n0 + SKEW k0) mod R, a skew chosen per
+// access pattern so that the lanes of the exchange hit different LDS banks.
 // HALFIN: the inputs with n1 >= S/2 are zero and are not read.
-template <int N, int SG, int NP, bool HALFIN = false, typename SlotF>
+template <int N, int SG, int NP, bool HALFIN = false, int SKEW = 1, typename SlotF>
 __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], const float2* tw,
                                                int n0, float2* lds, SlotF slot) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
@@ -172,7 +173,7 @@ __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], cons
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int k0 = 0; k0 < S; ++k0) lds[slot(p, k0 * R + ((n0 + k0) % R))] = v[p][k0];
+    for (int k0 = 0; k0 < S; ++k0) lds[slot(p, k0 * R + ((n0 + SKEW * k0) % R))] = v[p][k0];
   wave_lds_sync();
 #pragma unroll
   for (int p = 0; p < NP; ++p)
@@ -180,7 +181,7 @@ __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], cons
     for (int q = 0; q < D; ++q) {
       const int k0 = n0 * D + q;
 #pragma unroll
-      for (int m = 0; m < R; ++m) v[p][q * R + m] = lds[slot(p, k0 * R + ((m + k0) % R))];
+      for (int m = 0; m < R; ++m) v[p][q * R + m] = lds[slot(p, k0 * R + ((m + SKEW * k0) % R))];
     }
   wave_lds_sync();
 #pragma unroll
@@ -193,7 +194,7 @@ __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], cons
 // in the output layout of line_transform and returns v[p][n1] = y_p[R n1 + n0]
 // where y = sum_k X[k] exp(-2 pi i n k / N) (SG = -1) -- the adjoint of the
 // forward line transform when applied to the forward's output positions.
-template <int N, int SG, int NP, typename SlotF>
+template <int N, int SG, int NP, int SKEW = 1, typename SlotF>
 __device__ __forceinline__ void line_transform_rev(float2 (&v)[NP][Line<N>::S], const float2* tw,
                                                    int n0, float2* lds, SlotF slot) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
@@ -208,13 +209,13 @@ __device__ __forceinline__ void line_transform_rev(float2 (&v)[NP][Line<N>::S], 
     for (int q = 0; q < D; ++q) {
       const int k0 = n0 * D + q;
 #pragma unroll
-      for (int m = 0; m < R; ++m) lds[slot(p, k0 * R + ((m + k0) % R))] = v[p][q * R + m];
+      for (int m = 0; m < R; ++m) lds[slot(p, k0 * R + ((m + SKEW * k0) % R))] = v[p][q * R + m];
     }
   wave_lds_sync();
 #pragma unroll
   for (int p = 0; p < NP; ++p)
 #pragma unroll
-    for (int k0 = 0; k0 < S; ++k0) v[p][k0] = lds[slot(p, k0 * R + ((n0 + k0) % R))];
+    for (int k0 = 0; k0 < S; ++k0) v[p][k0] = lds[slot(p, k0 * R + ((n0 + SKEW * k0) % R))];
   wave_lds_sync();
 #pragma unroll
   for (int p = 0; p < NP; ++p) {

@@ -216,18 +216,18 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 // row-pass line of every thread (p << 16 | j, or -1), then L steps per thread.
 //  * Rows: each wave transforms CPW/P aperture rows of every polarisation and
 //    grids exactly those rows, so gridding and the row pass are separated by
-//    a wave-level fence only.  Row slot s of a wave takes a row j = s mod M
-//    (M = 4 at N = 64, 8 at N = 32 with P = 2, 16 with P = 1), which keeps the
-//    row pass free of bank conflicts; within that rule rows are dealt heaviest
-//    first to the least loaded wave.  A wave's cells are dealt longest first
-//    to the least loaded of its 64 threads.
-//  * Banks: LDS serves a 64-bit access 16 lanes at a time from 32 four-byte
-//    banks, so 16 lanes of a quarter-wave hit distinct banks when their float2
-//    addresses differ modulo 16.  A cell is written once, at its last entry,
+//    a wave-level fence only.  The row slots of a wave follow a residue rule
+//    (below) that keeps the row transform free of LDS bank conflicts; within
+//    it rows are dealt heaviest first to the least loaded wave.  Rows are
+//    stored at their physical rows (FusedShape::phys_row).  A wave's cells
+//    are dealt longest first to the least loaded of its 64 threads.
+//  * Banks: LDS serves 64-bit reads 32 lanes at a time from 64 four-byte
+//    banks and 64-bit writes 16 lanes at a time from 32 banks.  A cell is
+//    written once, at its last entry,
 //    so few lanes of a quarter-wave write at the same step.  The entries of a
 //    cell may be taken in any order: step by step, lanes with one entry left
-//    take it, then the others take the remaining entry whose bank the
-//    quarter-wave uses least.  Empty cells read one of 16 zero slots of E'
+//    take it, then the others take the remaining entry whose bank (float2
+//    address modulo 16) the quarter-wave uses least.  Empty cells read one of 16 zero slots of E'
 //    (slots A .. A+15) on the least used bank and write zero; padding steps
 //    add zero and write nothing.
 template <int N>
@@ -237,9 +237,21 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   const int C = g.C, A = g.A, KK = g.KK;
   const int ES = NT * gpt / P + 64;                    // EStride<NT, gpt, P>
   const int XB = P * ES;                               // grid base, float2 units
+  using SH = epic::FusedShape<N>;
   const int SPW = CPW / P;                             // row slots per wave
-  const int M = N == 64 ? 4 : (P == 2 ? 8 : 16);       // residue rule of the slots
   const int NWR = H / SPW;                             // waves that own rows
+  // residue rule (row j of slot s in a wave of group t has j mod M = residue):
+  // at N = 64 it puts the 4 (P = 2) or 8 (P = 1) rows a half-wave transforms
+  // on distinct bank ranges given the interleaved physical rows and the
+  // polarisation stride; at N = 32 rows of a wave are distinct modulo 8 / 16
+  const int M = N == 64 ? 8 : (P == 2 ? 8 : 16);
+  const int NGRP = (N == 64 && P == 2) ? 2 : 1;
+  auto residue = [&](int sl, int t) {
+    if (N == 32) return sl;
+    if (P == 1) return (sl >> 1) + 4 * (sl & 1);
+    static const int rho[4] = {0, 4, 1, 5};
+    return rho[sl] + 2 * t;
+  };
   auto code = [](int cell_f2, int e) {
     return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
   };
@@ -258,41 +270,41 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   for (int c = 0; c < C; ++c) {
     std::vector<Run> cells(H * H);
     for (int j = 0; j < H; ++j)
-      for (int i = 0; i < H; ++i) cells[j * H + i].cell = j * RS + i;
+      for (int i = 0; i < H; ++i) cells[j * H + i].cell = SH::phys_row(j) * RS + i;
     for (int a = 0; a < A; ++a)
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
         cells[j * H + i].ent.push_back({a, g.w[o]});
       }
-    // rows to (wave, slot)
+    // rows to (wave, slot): slot s of a wave in group t takes a row j with
+    // j mod M = residue(s, t); each residue class has exactly as many rows as
+    // the group has waves, dealt heaviest first to the least loaded wave
     std::vector<int> row_load(H, 0);
     for (int j = 0; j < H; ++j)
       for (int i = 0; i < H; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * H + i].ent.size());
     std::vector<int> wave_load(NWAVE, 0);
     std::vector<std::vector<int>> row_of(NWAVE, std::vector<int>(SPW, -1));
-    for (int rho = 0; rho < M; ++rho) {
-      std::vector<int> rows;
-      for (int j = rho; j < H; j += M) rows.push_back(j);
-      std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
-      for (int j : rows) {
-        int bw = -1, bs = -1;
-        for (int w = 0; w < NWR; ++w)
-          for (int sl = rho; sl < SPW; sl += M)
-            if (row_of[w][sl] < 0 && (bw < 0 || wave_load[w] < wave_load[bw])) {
-              bw = w;
-              bs = sl;
-              break;
-            }
-        row_of[bw][bs] = j;
-        wave_load[bw] += row_load[j];
+    const int WPG = NWR / NGRP;                        // waves per group
+    for (int t = 0; t < NGRP; ++t)
+      for (int sl = 0; sl < SPW; ++sl) {
+        const int rho = residue(sl, t);
+        std::vector<int> rows;
+        for (int j = rho; j < H; j += M) rows.push_back(j);
+        std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
+        for (int j : rows) {
+          int bw = -1;
+          for (int w = t * WPG; w < (t + 1) * WPG; ++w)
+            if (row_of[w][sl] < 0 && (bw < 0 || wave_load[w] < wave_load[bw])) bw = w;
+          row_of[bw][sl] = j;
+          wave_load[bw] += row_load[j];
+        }
       }
-    }
     for (int t = 0; t < NT; ++t) {
       const epic::Roles<N> ro(t);
       if (ro.wave >= NWR) continue;
       const int p = ro.sub / SPW, sl = ro.sub % SPW;
-      if (p < P) header[(size_t)c * NT + t] = (p << 16) | row_of[ro.wave][sl];
+      if (p < P) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
     }
     // cells of each wave's rows, longest first, to the least loaded lane of the wave
     std::vector<std::vector<const Run*>> lane_runs(NT);
@@ -820,6 +832,7 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE : epic::FusedShape<64>::PSTRIDE;
   layout[4] = P * ES;
   layout[5] = ES;
+  layout[6] = N == 64 ? 1 : 0;
   if (cap == 0) return EPIC_OK;
   if (!out || cap < need) { g_init_error = "output capacity too small"; return EPIC_E_NOMEM; }
   std::memcpy(out, prog.data(), prog.size() * sizeof(uint32_t));
@@ -852,7 +865,8 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
     // adjoint taps [C][A][KK] {translated cell, w}
     std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
     for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
-      taps[2 * o] = (uint32_t)g.tcell[o];
+      const int j = g.tcell[o] / N, i = g.tcell[o] % N;
+      taps[2 * o] = (uint32_t)((N == 32 ? epic::FusedShape<32>::phys_row(j) : epic::FusedShape<64>::phys_row(j)) * N + i);
       std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
     }
     std::vector<uint32_t> prog;

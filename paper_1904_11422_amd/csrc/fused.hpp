@@ -49,14 +49,22 @@ template <int N> struct FusedShape {
   static constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
   static constexpr int NT = N * R;             // threads per workgroup
   static constexpr int CPW = 64 / R;           // columns (or rows) per wave
-  // LDS row stride in float2 (spare columns after N); with the lane roles
-  // below every access of the two line passes is free of LDS bank conflicts
-  // (32 banks of 4 bytes; paired 8-byte accesses by groups of 16 lanes)
+  // LDS geometry in float2 units.  LDS serves 64-bit reads 32 lanes at a time
+  // from 64 four-byte banks (conflict-free when a half-wave's addresses differ
+  // modulo 32) and 64-bit writes 16 lanes at a time from 32 banks (a
+  // quarter-wave's addresses differing modulo 16).  With the lane roles below,
+  // the row stride RS, the polarisation stride PSTRIDE, the physical order of
+  // the aperture rows (phys_row), the exchange skews and the rule the host
+  // follows when it deals rows to waves, every access of the N = 64 row and
+  // column transforms is conflict-free under that model.
   static constexpr int RS = N == 32 ? N + 1 : N + 4;
-  // polarisation stride of the grid in float2; at N = 32 the extra 8 puts the
-  // same row of the two polarisations on different banks (a wave transforms
-  // both in one row pass)
-  static constexpr int PSTRIDE = N * RS + (N == 32 ? 8 : 0);
+  static constexpr int PSTRIDE = N * RS + (N == 32 ? 8 : 16);
+  static constexpr int COL_SKEW = N == 64 ? 2 : 1;   // exchange skew of the forward column pass
+  // physical row of aperture row j < N/2: at N = 64 rows are interleaved so
+  // that the 8 rows a column lane loads fall on distinct banks
+  static __host__ __device__ constexpr int phys_row(int j) {
+    return N == 64 ? 8 * (j >> 3) + 2 * (j & 3) + ((j >> 2) & 1) : j;
+  }
   static constexpr int H = N / 2;              // aperture block side
   static constexpr int KBLOCK = 128;           // samples summed in float32 before a float64 flush
   // waves per SIMD the register budget is sized for: two resident workgroups
@@ -273,19 +281,19 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 }
 
 // 3b. Forward column transforms of column r.kl for all polarisations; only
-// rows < H are nonzero.  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
+// rows < H are nonzero (stored at their physical rows).  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
 template <int N, int P>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
                                                 const Roles<N>& r, const float2* tw) {
-  constexpr int S = Line<N>::S, R = Line<N>::R, RS = FusedShape<N>::RS;
-  constexpr int PS = FusedShape<N>::PSTRIDE;
+  using SH = FusedShape<N>;
+  constexpr int S = Line<N>::S, R = Line<N>::R, RS = SH::RS, PS = SH::PSTRIDE;
   const int kl = r.kl;
 #pragma unroll
   for (int p = 0; p < P; ++p) {                 // one polarisation at a time
     float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
 #pragma unroll
-    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[p * PS + (R * n1 + r.n0) * RS + kl];
-    line_transform<N, +1, 1, true>(vp, tw, r.n0, X + p * PS,
+    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
+    line_transform<N, +1, 1, true, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
                                    [kl](int, int s) { return s * RS + kl; });
   }
 }

@@ -29,7 +29,7 @@ def _program(inp, n_pol=None):
     f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
     words = ctypes.c_int64(0)
-    layout = (ctypes.c_int32 * 6)()
+    layout = (ctypes.c_int32 * 7)()
     st = L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
                                  None, ctypes.byref(words), layout)
     assert st == _lib.EPIC_OK, L.epic_last_error(None)
@@ -38,8 +38,15 @@ def _program(inp, n_pol=None):
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                  ctypes.byref(words), layout)
     assert st == _lib.EPIC_OK, L.epic_last_error(None)
-    NT, nsteps, RS, PS, XB, ES = list(layout)
-    return out.reshape(inp.n_chan, 1 + nsteps, NT, 2), dict(NT=NT, L=nsteps, RS=RS, PS=PS, XB=XB, ES=ES, P=P)
+    NT, nsteps, RS, PS, XB, ES, order = list(layout)
+    return out.reshape(inp.n_chan, 1 + nsteps, NT, 2), dict(NT=NT, L=nsteps, RS=RS, PS=PS, XB=XB,
+                                                            ES=ES, P=P, order=order)
+
+
+def _phys(j, order):
+    """Physical row of aperture row j (the layout the library reports)."""
+    j = np.asarray(j)
+    return 8 * (j >> 3) + 2 * (j & 3) + ((j >> 2) & 1) if order else j
 
 
 CASES = {
@@ -69,8 +76,10 @@ def test_programs_reproduce_gridding(name, one_pol):
     X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
     ii, jj, w = oracle.kernel_taps(X, Y, N)
     rng = np.random.default_rng(0)
+    phys = _phys(np.arange(H), g["order"])
+    assert sorted(phys) == list(range(H))
     for c in range(inp.n_chan):
-        # header: every (p, j < H) row owned by R lanes of one wave
+        # header: every (p, physical row < H) owned by R lanes of one wave
         hdr = prog[c, 0, :, 0].view(np.int32)
         rows_of_wave = {}
         seen = {}
@@ -82,18 +91,20 @@ def test_programs_reproduce_gridding(name, one_pol):
         assert sorted(seen) == [(p, j) for p in range(P) for j in range(H)]
         for lanes in seen.values():
             assert len(lanes) == R and len(set(lanes)) == 1
-        # first load of the row transform: the 16 lanes of a quarter-wave on
-        # distinct bank pairs (float2 address modulo 16)
-        for q in range(NT // 16):
-            banks = []
-            for t in range(16 * q, 16 * q + 16):
-                if hdr[t] < 0:
-                    continue
-                p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
-                lane = t % 64
-                n0 = 4 * ((lane >> 4) >> 1) + ((lane >> 2) & 3) if N == 64 else lane // 16
-                banks.append((g["XB"] + p * PS + j * RS + n0) % 16)
-            assert len(banks) == len(set(banks))
+        # first load of the row transform (64-bit reads are served 32 lanes at
+        # a time from 64 banks): each half-wave's float2 addresses distinct
+        # modulo 32 (at N = 64, where the layout is chosen for it)
+        if N == 64:
+            for hw in range(NT // 32):
+                banks = []
+                for t in range(32 * hw, 32 * hw + 32):
+                    if hdr[t] < 0:
+                        continue
+                    p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
+                    lane = t % 64
+                    n0 = 4 * ((lane >> 4) >> 1) + ((lane >> 2) & 3)
+                    banks.append((g["XB"] + p * PS + j * RS + n0) % 32)
+                assert len(banks) == len(set(banks))
         # emulate the gather (pol 0; the kernel applies the same step to pol 1)
         code, wb = prog[c, 1:, :, 0], prog[c, 1:, :, 1]
         cell = (code >> 16).astype(np.int64)
@@ -123,7 +134,7 @@ def test_programs_reproduce_gridding(name, one_pol):
         tj = jj[c] - jj[c].min()
         ref = np.zeros((H, H))
         np.add.at(ref, (tj, ti), w[c] * E[:A, None])
-        got = grid.reshape(N, RS)[:H, :H]
+        got = grid.reshape(N, RS)[phys, :H]
         assert np.all(stores.reshape(N, RS)[:H, :H] == 1)
         assert stores.sum() == H * H
         assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
@@ -135,7 +146,7 @@ def test_program_query_and_errors():
     dp = ctypes.POINTER(ctypes.c_double)
     xy = np.ascontiguousarray(inp.xy_m, dtype=np.float64)
     f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
-    layout = (ctypes.c_int32 * 6)()
+    layout = (ctypes.c_int32 * 7)()
     words = ctypes.c_int64(0)
     staged = _lib.EpicConfig(32, 1, 1, 16, 3, 0.5, 0.5, _lib.EPIC_FP32, _lib.EPIC_FLAG_STAGED)
     assert L.epic_gridding_program(ctypes.byref(staged), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
