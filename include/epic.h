@@ -116,7 +116,7 @@ epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *f
  *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
  *                    (int32 -1: none); word 1: 0;
  *     rows 1..L:     steps {LDS byte offset of the cell, relative to the grid
- *                    base, << 16 | LDS byte offset of E'[p = 0][a], float32
+ *                    base, << 15 | LDS byte offset of E'[p = 0][a], float32
  *                    weight bits with the sign bit set on a cell's last entry}.
  * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
  * layout: out, int32 [7] = {NT, L, row stride, polarisation stride, grid base,

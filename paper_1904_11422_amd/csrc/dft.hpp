@@ -122,6 +122,40 @@ template <int SG> __device__ __forceinline__ void dft8_half(float2* x) {
   x[3] = cadd(e3, t3); x[7] = csub(e3, t3);
 }
 
+// 16-point DFT whose inputs x[8..15] are zero (they are not read): the 4 x 4
+// form of dft16 with a first stage of two-input 4-point DFTs.
+template <int SG> __device__ __forceinline__ void dft16_half(float2* x) {
+  const float c1 = 0.92387953251128675613f;  // cos(pi/8)
+  const float s1 = 0.38268343236508977173f;  // sin(pi/8)
+  const float r = 0.70710678118654752440f;   // cos(pi/4)
+  float2 y[16];
+#pragma unroll
+  for (int n0 = 0; n0 < 4; ++n0) {
+    const float2 a = x[n0], b = x[4 + n0], ib = mul_i<SG>(b);   // inputs 8 + n0, 12 + n0 are zero
+    y[n0] = cadd(a, b);
+    y[4 + n0] = cadd(a, ib);
+    y[8 + n0] = csub(a, b);
+    y[12 + n0] = csub(a, ib);
+  }
+  const float2 w1 = make_float2(c1, SG * s1), w2 = make_float2(r, SG * r), w3 = make_float2(s1, SG * c1);
+  const float2 w6 = make_float2(-r, SG * r), w9 = make_float2(-c1, -SG * s1);
+  y[4 * 1 + 1] = cmul(y[5], w1);
+  y[4 * 1 + 2] = cmul(y[6], w2);
+  y[4 * 1 + 3] = cmul(y[7], w3);
+  y[4 * 2 + 1] = cmul(y[9], w2);
+  y[4 * 2 + 2] = mul_i<SG>(y[10]);
+  y[4 * 2 + 3] = cmul(y[11], w6);
+  y[4 * 3 + 1] = cmul(y[13], w3);
+  y[4 * 3 + 2] = cmul(y[14], w6);
+  y[4 * 3 + 3] = cmul(y[15], w9);
+#pragma unroll
+  for (int k0 = 0; k0 < 4; ++k0) {
+    float2 a = y[4 * k0], b = y[4 * k0 + 1], c = y[4 * k0 + 2], d = y[4 * k0 + 3];
+    dft4<SG>(a, b, c, d);
+    x[k0] = a; x[k0 + 4] = b; x[k0 + 8] = c; x[k0 + 12] = d;
+  }
+}
+
 template <int M, int SG> __device__ __forceinline__ void dft(float2* x) {
   if constexpr (M == 2) dft2<SG>(x[0], x[1]);
   else if constexpr (M == 4) dft4<SG>(x[0], x[1], x[2], x[3]);
@@ -161,10 +195,11 @@ template <int N, int SG, int NP, bool HALFIN = false, int SKEW = 1, typename Slo
 __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], const float2* tw,
                                                int n0, float2* lds, SlotF slot) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
-  static_assert(!HALFIN || S == 8, "half-input pass implemented for radix 8");
+  static_assert(!HALFIN || S == 8 || S == 16, "half-input pass implemented for radix 8 and 16");
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    if constexpr (HALFIN) dft8_half<SG>(v[p]);
+    if constexpr (HALFIN && S == 8) dft8_half<SG>(v[p]);
+    else if constexpr (HALFIN) dft16_half<SG>(v[p]);
     else dft<S, SG>(v[p]);
 #pragma unroll
     for (int k0 = 1; k0 < S; ++k0) v[p][k0] = twiddle_mul<SG>(v[p][k0], tw[k0]);

@@ -19,6 +19,7 @@
 #include "staged.hpp"
 #include "adjoint.hpp"
 #include "split.hpp"
+#include "fused128.hpp"
 
 namespace {
 
@@ -223,13 +224,13 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 //    are dealt longest first to the least loaded of its 64 threads.
 //  * Banks: LDS serves 64-bit reads 32 lanes at a time from 64 four-byte
 //    banks and 64-bit writes 16 lanes at a time from 32 banks.  A cell is
-//    written once, at its last entry,
-//    so few lanes of a quarter-wave write at the same step.  The entries of a
-//    cell may be taken in any order: step by step, lanes with one entry left
-//    take it, then the others take the remaining entry whose bank (float2
-//    address modulo 16) the quarter-wave uses least.  Empty cells read one of 16 zero slots of E'
-//    (slots A .. A+15) on the least used bank and write zero; padding steps
-//    add zero and write nothing.
+//    written once, at its last entry, so few lanes of a quarter-wave write at
+//    the same step.  The entries of a cell may be taken in any order: step by
+//    step, lanes with one entry left take it, then the others take the
+//    remaining entry whose bank (float2 address modulo 16) the quarter-wave
+//    uses least.  Empty cells read one of 16 zero slots of E' (slots
+//    A .. A+15) on the least used bank and write zero; padding steps add zero
+//    and write nothing.
 template <int N>
 void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L) {
   constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
@@ -238,16 +239,19 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   const int ES = NT * gpt / P + 64;                    // EStride<NT, gpt, P>
   const int XB = P * ES;                               // grid base, float2 units
   using SH = epic::FusedShape<N>;
-  const int SPW = CPW / P;                             // row slots per wave
+  // row slots per wave: CPW / P lines of one polarisation each, or at N = 128
+  // CPW rows whose lane group takes both polarisations
+  const int SPW = N == 128 ? CPW : CPW / P;
   const int NWR = H / SPW;                             // waves that own rows
   // residue rule (row j of slot s in a wave of group t has j mod M = residue):
   // at N = 64 it puts the 4 (P = 2) or 8 (P = 1) rows a half-wave transforms
   // on distinct bank ranges given the interleaved physical rows and the
-  // polarisation stride; at N = 32 rows of a wave are distinct modulo 8 / 16
-  const int M = N == 64 ? 8 : (P == 2 ? 8 : 16);
+  // polarisation stride; at N = 32 rows of a wave are distinct modulo 8 / 16,
+  // at N = 128 (a lane group per row, both polarisations) modulo 8
+  const int M = N == 128 ? 8 : N == 64 ? 8 : (P == 2 ? 8 : 16);
   const int NGRP = (N == 64 && P == 2) ? 2 : 1;
   auto residue = [&](int sl, int t) {
-    if (N == 32) return sl;
+    if (N != 64) return sl;
     if (P == 1) return (sl >> 1) + 4 * (sl & 1);
     static const int rho[4] = {0, 4, 1, 5};
     return rho[sl] + 2 * t;
@@ -255,6 +259,14 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   auto code = [](int cell_f2, int e) {
     return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
   };
+  // the fields of a step word: cell byte offsets (the aperture rows of one
+  // polarisation) below 2^17, E' byte offsets (both polarisations) below 2^15
+  static_assert(H * SH::RS * 8 <= (1 << (32 - epic::STEP_CELL_SHIFT)), "cell offsets exceed the step field");
+  if ((int64_t)P * ES * 8 > (int64_t)epic::STEP_E_MASK + 1) {   // not reached by the shapes the kernels take
+    out.clear();
+    L = 0;
+    return;
+  }
   auto wbits = [](float w, bool last) {
     uint32_t b;
     std::memcpy(&b, &w, 4);
@@ -303,7 +315,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     for (int t = 0; t < NT; ++t) {
       const epic::Roles<N> ro(t);
       if (ro.wave >= NWR) continue;
-      const int p = ro.sub / SPW, sl = ro.sub % SPW;
+      const int p = ro.sub / SPW, sl = ro.sub % SPW;     // N = 128: p = 0, both polarisations
       if (p < P) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
     }
     // cells of each wave's rows, longest first, to the least loaded lane of the wave
@@ -330,7 +342,8 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     }
     const int Lc = std::max(1, *std::max_element(load.begin(), load.end()));
     L = std::max(L, Lc);
-    // step-by-step choice of the E' entries, per quarter-wave
+    // step-by-step choice of the E' entries, per quarter-wave (measured faster
+    // than choosing per half-wave for these paired reads)
     for (int q = 0; q < NT / 16; ++q) {
       struct Lane {
         size_t run = 0;
@@ -449,6 +462,12 @@ int fused_blocks_per_cu() {
 }
 
 int fused_blocks_per_cu(int N, int P, int gpt) {
+  if (N == 128) {
+    const int NT = epic::FusedShape<128>::NT;
+    if (gpt == 1) return occupancy_blocks(epic::fused_image128_kernel<1>, NT);
+    if (gpt == 2) return occupancy_blocks(epic::fused_image128_kernel<2>, NT);
+    return occupancy_blocks(epic::fused_image128_kernel<4>, NT);
+  }
 #define EPIC_OCC(NN, PP, GG) if (N == NN && P == PP && gpt == GG) return fused_blocks_per_cu<NN, PP, GG>();
   EPIC_OCC(32, 1, 1) EPIC_OCC(32, 1, 2) EPIC_OCC(32, 1, 4)
   EPIC_OCC(32, 2, 1) EPIC_OCC(32, 2, 2) EPIC_OCC(32, 2, 4)
@@ -470,7 +489,9 @@ int adjoint_blocks_per_cu(int N, int P, int gpt) {
   return P == 1 ? adjoint_blocks_per_cu<64, 1>(gpt) : adjoint_blocks_per_cu<64, 2>(gpt);
 }
 
-int fused_threads(int N) { return N == 32 ? epic::FusedShape<32>::NT : epic::FusedShape<64>::NT; }
+int fused_threads(int N) {
+  return N == 32 ? epic::FusedShape<32>::NT : N == 64 ? epic::FusedShape<64>::NT : epic::FusedShape<128>::NT;
+}
 
 bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
@@ -486,6 +507,16 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   EPIC_LF(64, 2, 1) EPIC_LF(64, 2, 2) EPIC_LF(64, 2, 4)
 #undef EPIC_LF
   return false;
+}
+
+bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
+  const dim3 grid(a.W), block(epic::FusedShape<128>::NT);
+  switch (x->fused_gpt) {
+    case 1: hipLaunchKernelGGL(epic::fused_image128_kernel<1>, grid, block, 0, x->stream, a); return true;
+    case 2: hipLaunchKernelGGL(epic::fused_image128_kernel<2>, grid, block, 0, x->stream, a); return true;
+    case 4: hipLaunchKernelGGL(epic::fused_image128_kernel<4>, grid, block, 0, x->stream, a); return true;
+    default: return false;
+  }
 }
 
 // Sub-lanes per output value in the reduction kernels: enough that a channel
@@ -755,7 +786,8 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   }
 
   const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
-  x->fused_ok = !want_staged && N <= 64 && cfg->precision == EPIC_FP32;
+  // fused kernels: N = 32 and 64 (one or two polarisations), N = 128 with two
+  x->fused_ok = !want_staged && cfg->precision == EPIC_FP32 && (N <= 64 || cfg->n_pol == 2);
   if (x->fused_ok) {
     const int NT = fused_threads(N);
     int gpt = (x->PA + NT - 1) / NT;
@@ -766,13 +798,16 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   if (x->fused_ok) {
     const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
     x->fused_w = bpc * x->n_cu;
-    const size_t slots = (size_t)x->fused_w + cfg->n_chan - 1;
-    if (!x->partial.alloc(slots * x->nacc * N * N * sizeof(double))) {
+    // N = 128: two accumulation segments (column halves) per channel
+    const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
+    const size_t slots = (size_t)x->fused_w + segs - 1;
+    const size_t per_slot = N == 128 ? (size_t)x->nacc * N * N / 2 : (size_t)x->nacc * N * N;
+    if (!x->partial.alloc(slots * per_slot * sizeof(double))) {
       g_init_error = "partial-image workspace allocation failed";
       delete x;
       return EPIC_E_NOMEM;
     }
-    x->adj_w = adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
+    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
     if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double))) {
       g_init_error = "gradient workspace allocation failed";
@@ -807,14 +842,17 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   if (s != EPIC_OK) { g_init_error = m; return s; }
   if (!xy_m || !freq_hz || !words || !layout) { g_init_error = "null pointer"; return EPIC_E_INVALID; }
   const int N = cfg->grid_n, P = cfg->n_pol;
-  if (N > 64 || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
+  if ((N > 64 && P != 2) || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
     g_init_error = "the configuration has no fused kernel";
     return EPIC_E_UNSUPPORTED;
   }
   const int NT = fused_threads(N);
   int gpt = (P * cfg->n_ant + NT - 1) / NT;
   gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
-  if (gpt == 0) { g_init_error = "too many antennas for the fused kernel"; return EPIC_E_UNSUPPORTED; }
+  if (gpt == 0) {
+    g_init_error = "too many antennas for the fused kernel";
+    return EPIC_E_UNSUPPORTED;
+  }
   Geometry g;
   s = build_geometry(*cfg, xy_m, freq_hz, g, m);
   if (s != EPIC_OK) { g_init_error = m; return s; }
@@ -822,14 +860,17 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   std::vector<uint32_t> prog;
   int L = 0;
   if (N == 32) build_programs<32>(g, P, gpt, prog, L);
-  else build_programs<64>(g, P, gpt, prog, L);
+  else if (N == 64) build_programs<64>(g, P, gpt, prog, L);
+  else build_programs<128>(g, P, gpt, prog, L);
+  if (L == 0) { g_init_error = "gridding program fields overflow"; return EPIC_E_UNSUPPORTED; }
   const int64_t need = (int64_t)prog.size(), cap = *words;
   *words = need;
   const int ES = NT * gpt / P + 64;
   layout[0] = NT;
   layout[1] = L;
-  layout[2] = N == 32 ? epic::FusedShape<32>::RS : epic::FusedShape<64>::RS;
-  layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE : epic::FusedShape<64>::PSTRIDE;
+  layout[2] = N == 32 ? epic::FusedShape<32>::RS : N == 64 ? epic::FusedShape<64>::RS : epic::FusedShape<128>::RS;
+  layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE
+            : N == 64 ? epic::FusedShape<64>::PSTRIDE : epic::FusedShape<128>::PSTRIDE;
   layout[4] = P * ES;
   layout[5] = ES;
   layout[6] = N == 64 ? 1 : 0;
@@ -866,13 +907,15 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
     std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
     for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
       const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-      taps[2 * o] = (uint32_t)((N == 32 ? epic::FusedShape<32>::phys_row(j) : epic::FusedShape<64>::phys_row(j)) * N + i);
+      taps[2 * o] = (uint32_t)((N == 64 ? epic::FusedShape<64>::phys_row(j) : j) * N + i);
       std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
     }
     std::vector<uint32_t> prog;
     int L = 0;
     if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L);
-    else build_programs<64>(g, P, x->fused_gpt, prog, L);
+    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L);
+    else build_programs<128>(g, P, x->fused_gpt, prog, L);
+    if (L == 0) return x->fail(EPIC_E_UNSUPPORTED, "gridding program fields overflow");
     if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
         hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
@@ -925,7 +968,36 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   (void)hipGetLastError();
-  if (x->fused) {
+  if (x->fused && N == 128) {
+    epic::Fused128Args a;
+    a.efield = efield;
+    a.gains = reinterpret_cast<const float2*>(gains);
+    a.prog = x->prog.as<uint2>();
+    a.twiddle = x->twiddle.as<float2>();
+    a.partial = x->partial.as<double>();
+    a.n_time = n_time;
+    a.total = 2 * total;
+    a.n_chan = C;
+    a.n_ant = x->cfg.n_ant;
+    a.L = x->L;
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w;
+    a.W = (int)std::min<int64_t>(w_max, a.total);
+    if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
+    x->last_kernel = "fused_image128_kernel";
+    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    epic::Reduce128Args r;
+    r.partial = x->partial.as<double>();
+    r.image = image;
+    r.n_time = n_time;
+    r.total = a.total;
+    r.n_chan = C;
+    r.W = a.W;
+    r.reset = reset ? 1 : 0;
+    r.sub = reduce_sub(slots_per_channel(n_time, a.total, a.W));
+    const int64_t n = (int64_t)C * N * N, ppb = 256 / r.sub;
+    hipLaunchKernelGGL(epic::reduce_image128_kernel, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
+                       x->stream, r);
+  } else if (x->fused) {
     epic::FusedArgs a;
     a.efield = efield;
     a.gains = reinterpret_cast<const float2*>(gains);
@@ -1025,7 +1097,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (!efield || !gains || !grad_image || !grad_gains)
     return x->fail(EPIC_E_INVALID, "NULL device pointer");
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
-  if (!x->fused || x->cfg.precision != EPIC_FP32)
+  if (!x->fused || x->cfg.precision != EPIC_FP32 || x->cfg.grid_n > 64)
     return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path "
                    "(N <= 64, aperture within N/2 x N/2 cells)");
   DeviceGuard guard(x->device);

@@ -32,22 +32,24 @@
 namespace epic {
 
 // Gridding step: {code, weight bits}.  code = LDS byte offset of the cell
-// (pol 0) << 16 | byte offset of E'[e] (pol 0); the weight's sign bit marks
+// (pol 0, relative to the grid base) << 15 | byte offset of E'[e] (pol 0); the weight's sign bit marks
 // the last entry of a cell (the weights themselves are >= 0).  Every step
 // reads E' of both polarisations and adds |w| * E' to the running sums; the
 // last entry of a cell stores the sums to the cell and restarts them.  Cells
 // with no antenna read a zero slot of E'; padding steps add zero and store
 // nothing.  The host orders the steps so that the lanes of a quarter-wave
 // mostly touch distinct LDS banks.
-constexpr int STEP_CELL_SHIFT = 16;
-constexpr uint32_t STEP_E_MASK = 0xFFFFu;
+constexpr int STEP_CELL_SHIFT = 15;            // cell byte offset < 128 KB
+constexpr uint32_t STEP_E_MASK = 0x7FFFu;      // E' byte offset < 32 KB
 constexpr uint32_t STEP_LAST_BIT = 0x80000000u; // in the weight word
 constexpr int kMaxFixedSteps = 8;              // longer lists run in chunks of 4
 constexpr int kStepChunk = 4;
 
 template <int N> struct FusedShape {
   static constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
-  static constexpr int NT = N * R;             // threads per workgroup
+  // threads per workgroup: one lane group per line; at N = 128 a lane group
+  // takes both polarisations of a row (and of a column), 512 threads
+  static constexpr int NT = N == 128 ? 512 : N * R;
   static constexpr int CPW = 64 / R;           // columns (or rows) per wave
   // LDS geometry in float2 units.  LDS serves 64-bit reads 32 lanes at a time
   // from 64 four-byte banks (conflict-free when a half-wave's addresses differ
@@ -58,7 +60,11 @@ template <int N> struct FusedShape {
   // follows when it deals rows to waves, every access of the N = 64 row and
   // column transforms is conflict-free under that model.
   static constexpr int RS = N == 32 ? N + 1 : N + 4;
-  static constexpr int PSTRIDE = N * RS + (N == 32 ? 8 : 16);
+  // rows of the LDS grid per polarisation: N (the column transforms exchange
+  // through all N rows of their column) or, at N = 128, N/2 (the aperture
+  // rows; columns exchange through their upper half instead)
+  static constexpr int XROWS = N == 128 ? N / 2 : N;
+  static constexpr int PSTRIDE = XROWS * RS + (N == 32 ? 8 : 16);
   static constexpr int COL_SKEW = N == 64 ? 2 : 1;   // exchange skew of the forward column pass
   // physical row of aperture row j < N/2: at N = 64 rows are interleaved so
   // that the 8 rows a column lane loads fall on distinct banks
@@ -73,8 +79,9 @@ template <int N> struct FusedShape {
 };
 
 // E' stride between polarisations: the largest A a variant takes (NT*GPT/P)
-// plus a zero slot, rounded to 64 float2 so that both polarisations load with
-// one paired LDS read whose second offset is an immediate.
+// plus 64 float2 (the 16 zero slots, and a multiple of 64 so that both
+// polarisations load with one paired LDS read whose second offset is an
+// immediate).
 template <int NT, int GPT, int P> struct EStride {
   static constexpr int value = (NT * GPT) / P + 64;
 };
@@ -126,7 +133,8 @@ __device__ __forceinline__ float2 unpack_ci4(uint32_t b) {
 }
 
 // Slots of E' for this thread's items k = tid + i*NT (k = p*A + a), and the
-// 16 zero slots (a = A .. A+15, one per LDS bank pair) of each polarisation.
+// 16 zero slots (a = A .. A+15, one per LDS bank pair of a quarter-wave) of
+// each polarisation.
 template <int NT, int GPT, int ES>
 __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid, int n_ant, int P) {
 #pragma unroll

@@ -52,6 +52,8 @@ CASES = {
     "cfg2_small": lambda: synth.config2(n_time=40, n_chan=4),
     "single_antenna": lambda: synth.random_problem(106, 64, 1, 2, 2, 9),
     "one_sample": lambda: synth.random_problem(107, 64, 256, 3, 2, 1),
+    "n128_p2_ragged": lambda: synth.random_problem(109, 128, 400, 2, 2, 7, fill=0.45),
+    "n128_p2_A1024": lambda: synth.random_problem(110, 128, 1024, 2, 2, 3, fill=0.47),
 }
 
 
@@ -69,12 +71,16 @@ def test_image_matches_oracle(name, staged):
         assert np.all(got[:, 0].imag == 0) and np.all(got[:, 3].imag == 0)
 
 
-def test_grid128_staged_matches_oracle():
+def test_grid128_routes():
+    """128^2: two polarisations run the fused kernel, one the staged kernels."""
     inp = synth.random_problem(108, 128, 400, 2, 2, 3, fill=0.45)
-    got, im = _run(inp, staged=False)          # 128^2 runs the staged kernels
-    assert im.last_kernel_name() == "staged_fft_kernel"
-    ref = oracle.image_from(inp)
-    assert oracle.rel_errors(got, ref).max() <= TOL_FP32
+    got, im = _run(inp, staged=False)
+    assert im.last_kernel_name() == "fused_image128_kernel"
+    assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
+    inp1 = synth.random_problem(112, 128, 300, 2, 1, 3, fill=0.45)
+    got1, im1 = _run(inp1, staged=False)
+    assert im1.last_kernel_name() == "staged_fft_kernel"
+    assert oracle.rel_errors(got1, oracle.image_from(inp1)).max() <= TOL_FP32
 
 
 def test_reset_zero_continues_integration():
