@@ -129,6 +129,7 @@ def bench_batch(args) -> int:
            "channel_images_per_s": sum(i.n_chan for i in inputs) / dt,
            "blocks": [dict(grid_n=i.grid_n, n_ant=i.n_ant, n_chan=i.n_chan, grid=p[0],
                            staged_batch=p[1]) for i, p in zip(inputs, b.plan())],
+           "serial": b.serial,
            "roofline": {"bound": "alu", "achieved": fl / dt / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                         "unit": "TFLOP/s", "frac": fl / dt / PEAK_FP32_VALU},
            "sequential_no_graph_ms": dts * 1e3, "n_time": T, "data": "synthetic"}

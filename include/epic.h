@@ -224,6 +224,15 @@ epic_status epic_batch_tune(epic_batch *b, const uint8_t *const *efields, int64_
 epic_status epic_batch_plan(const epic_batch *b, int32_t block, int32_t *grid,
                             int32_t *staged_batch);
 
+/* 1 if the blocks of b run one after another (each persistent launch with the
+ * whole GPU), 0 if they run concurrently on their own streams; set by
+ * epic_batch_tune (default 0) and applied to accumulate and capture. */
+int32_t epic_batch_serial(const epic_batch *b);
+
+/* Choose the mode by hand (serial != 0: one after another); applies to later
+ * accumulate and capture calls.  Errors: EPIC_E_INVALID (b NULL). */
+epic_status epic_batch_set_serial(epic_batch *b, int32_t serial);
+
 /* Free the batch, its graph, streams and contexts. */
 void epic_batch_destroy(epic_batch *b);
 

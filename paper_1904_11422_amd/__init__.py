@@ -260,6 +260,15 @@ class Batch:
             out.append((gsz.value, tb.value))
         return out
 
+    @property
+    def serial(self) -> bool:
+        """True if the blocks run one after another (the tuner's choice)."""
+        return bool(self.L.epic_batch_serial(self._b))
+
+    @serial.setter
+    def serial(self, value: bool):
+        _lib.check_batch(self.L, self._b, self.L.epic_batch_set_serial(self._b, 1 if value else 0))
+
     def close(self):
         if getattr(self, "_b", None):
             self.L.epic_batch_destroy(self._b)

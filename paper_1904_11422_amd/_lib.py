@@ -22,6 +22,7 @@ EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_gridding_p
            "epic_destroy", "epic_last_error",
            "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
            "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
+           "epic_batch_serial", "epic_batch_set_serial",
            "epic_batch_destroy", "epic_batch_last_error")
 
 
@@ -88,6 +89,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_batch_tune.restype = ctypes.c_int
     L.epic_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.epic_batch_plan.restype = ctypes.c_int
+    L.epic_batch_serial.argtypes = [vp]
+    L.epic_batch_serial.restype = i32
+    L.epic_batch_set_serial.argtypes = [vp, i32]
+    L.epic_batch_set_serial.restype = ctypes.c_int
     L.epic_batch_destroy.argtypes = [vp]
     L.epic_batch_destroy.restype = None
     L.epic_batch_last_error.argtypes = [vp]

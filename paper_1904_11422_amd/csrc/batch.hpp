@@ -4,10 +4,12 @@
 // streams and joins back, so independent blocks share the GPU.  The same
 // fork-join can be captured once into a HIP graph and replayed with one launch
 // per batch.  The autotuner measures, per block, the persistent-grid size
-// (fused path) or the sample batch (staged path), then picks between running
-// every block at its best standalone setting and a work-proportional split of
-// the GPU, by timing the whole batch; the choice is cached in a text file
-// keyed by the device and the block shapes.
+// (fused path) or the sample batch (staged path), then picks, by timing the
+// whole batch, between running every block at its best standalone setting
+// concurrently, a work-proportional split of the GPU between concurrent
+// blocks, and the blocks one after another (each persistent launch then has
+// the whole GPU); the choice is cached in a text file keyed by the device and
+// the block shapes.
 #pragma once
 
 #include <fstream>
@@ -23,6 +25,7 @@ struct epic_batch {
   hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool serial = false;                // blocks one after another instead of concurrently
   std::string err;
 
   epic_status fail(epic_status s, const std::string& m) {
@@ -41,7 +44,9 @@ epic_status batch_enqueue(epic_batch* b, hipStream_t root, const uint8_t* const*
   if (hipEventRecord(b->fork, root) != hipSuccess)
     return b->fail(EPIC_E_LAUNCH, "event record failed");
   for (size_t i = 0; i < b->ctx.size(); ++i) {
-    if (hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess)
+    // concurrent: every block waits for the fork; serial: for the block before
+    const hipEvent_t after = (b->serial && i > 0) ? b->done[i - 1] : b->fork;
+    if (hipStreamWaitEvent(b->streams[i], after, 0) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "stream wait failed");
     const epic_status s = epic_image_accumulate(b->ctx[i], efields[i], n_time, gains[i], images[i], reset);
     if (s != EPIC_OK)
@@ -49,7 +54,7 @@ epic_status batch_enqueue(epic_batch* b, hipStream_t root, const uint8_t* const*
     if (hipEventRecord(b->done[i], b->streams[i]) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "event record failed");
   }
-  for (size_t i = 0; i < b->ctx.size(); ++i)
+  for (size_t i = b->serial ? b->ctx.size() - 1 : 0; i < b->ctx.size(); ++i)
     if (hipStreamWaitEvent(root, b->done[i], 0) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "stream wait failed");
   return EPIC_OK;
@@ -87,7 +92,7 @@ float time_on(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, F fn) {
 
 std::string batch_key(const epic_batch* b, int64_t n_time) {
   std::ostringstream k;
-  k << "gfx950 T=" << n_time;
+  k << "gfx950 v3 T=" << n_time;
   for (const epic_ctx* x : b->ctx)
     k << " [N=" << x->cfg.grid_n << ",P=" << x->cfg.n_pol << ",A=" << x->cfg.n_ant << ",C="
       << x->cfg.n_chan << ",prec=" << x->cfg.precision << ",path=" << (x->fused ? "fused" : "staged")
@@ -233,11 +238,13 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
       if (sep == std::string::npos || line.compare(0, sep, key) != 0 || sep != key.size()) continue;
       std::vector<std::pair<int, int>> plan;
       std::istringstream vals(line.substr(sep + 4));
-      int w = 0, tb = 0;
+      int w = 0, tb = 0, serial = 0;
       char comma = 0;
+      if (!(vals >> serial)) continue;
       while (vals >> w >> comma >> tb) plan.push_back({w, tb});
       if (plan.size() == nb) {
         apply(plan);
+        b->serial = serial != 0;
         return EPIC_OK;
       }
     }
@@ -276,21 +283,45 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
     if (b->ctx[i]->fused && tot > 0)
       split[i].first = std::max(1, (int)std::lround(b->ctx[i]->fused_w * best_ms[i] / tot));
   std::vector<std::pair<int, int>> chosen = best;
+  bool chosen_serial = false;
   float chosen_ms = 1e30f;
-  for (const auto* plan : {&best, &split}) {
-    apply(*plan);
+  const std::pair<const std::vector<std::pair<int, int>>*, bool> trials[] = {
+      {&best, false}, {&split, false}, {&best, true}};
+  // each trial is timed as it will run: captured into a graph and replayed
+  // (concurrent persistent launches behave differently when launched eagerly)
+  for (const auto& tr : trials) {
+    apply(*tr.first);
+    b->serial = tr.second;
     s = batch_enqueue(b, b->main, efields, n_time, gains, images, 1);
     if (s != EPIC_OK) return s;
-    const float ms = time_on(b->main, b->t0, b->t1, 3, [&] {
-      (void)batch_enqueue(b, b->main, efields, n_time, gains, images, 1);
-    });
-    if (ms < chosen_ms) { chosen_ms = ms; chosen = *plan; }
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    bool graphed = false;
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const epic_status cs = batch_enqueue(b, b->cap, efields, n_time, gains, images, 1);
+      const hipError_t e = hipStreamEndCapture(b->cap, &g);
+      graphed = cs == EPIC_OK && e == hipSuccess && g &&
+                hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+    }
+    float ms;
+    if (graphed) {
+      (void)hipGraphLaunch(ge, b->main);
+      ms = time_on(b->main, b->t0, b->t1, 3, [&] { (void)hipGraphLaunch(ge, b->main); });
+    } else {
+      ms = time_on(b->main, b->t0, b->t1, 3, [&] {
+        (void)batch_enqueue(b, b->main, efields, n_time, gains, images, 1);
+      });
+    }
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    if (ms < chosen_ms) { chosen_ms = ms; chosen = *tr.first; chosen_serial = tr.second; }
   }
   apply(chosen);
+  b->serial = chosen_serial;
   if (measured) *measured = 1;
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
-    out << key << " =>";
+    out << key << " => " << (chosen_serial ? 1 : 0);
     for (const auto& p : chosen) out << " " << p.first << "," << p.second;
     out << "\n";
   }
@@ -302,6 +333,14 @@ epic_status epic_batch_plan(const epic_batch* b, int32_t block, int32_t* grid, i
   const epic_ctx* x = b->ctx[block];
   if (grid) *grid = x->fused ? (x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w) : 0;
   if (staged_batch) *staged_batch = x->fused ? 0 : (x->tb_override > 0 ? std::min(x->tb_override, x->tb) : x->tb);
+  return EPIC_OK;
+}
+
+int32_t epic_batch_serial(const epic_batch* b) { return b && b->serial ? 1 : 0; }
+
+epic_status epic_batch_set_serial(epic_batch* b, int32_t serial) {
+  if (!b) return EPIC_E_INVALID;
+  b->serial = serial != 0;
   return EPIC_OK;
 }
 

@@ -42,9 +42,12 @@ def test_batch_matches_oracle(batch_inputs):
         assert err.max() <= 1e-5, f"block {k}: {err.max():.3e}"
 
 
-def test_graph_replays_match_eager(batch_inputs):
+@pytest.mark.parametrize("serial", [False, True])
+def test_graph_replays_match_eager(batch_inputs, serial):
     import torch
     b, ef, g = _batch(batch_inputs)
+    b.serial = serial
+    assert b.serial is serial
     eager = [x.clone() for x in b.accumulate(ef, g, b.new_images())]
     torch.cuda.synchronize()
     out = b.new_images()
