@@ -234,7 +234,7 @@ def bench_grad(args) -> int:
 
 PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                        "fused_image_kernel_lwa64_c132_t1000.md")
-PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/epic.hip", "build.py")
+PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
 
 
 def measured_traffic():

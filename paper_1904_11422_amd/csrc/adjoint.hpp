@@ -204,7 +204,6 @@ __global__ void __launch_bounds__(256) reduce_grad_kernel(GradReduceArgs a) {
     const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
 #pragma unroll 4
     for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
-      if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
       const double2 v = a.gpartial[(w + c) * a.PA + k];
       s[0] += v.x;
       s[1] += v.y;

@@ -668,8 +668,11 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   pa.n_ant = A;
   pa.a_pad = x->sp_apad;
   pa.ng = NG;
-  if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, dim3(C * P), dim3(256), 0, x->stream, pa);
-  else hipLaunchKernelGGL(epic::split_prep_kernel<false>, dim3(C * P), dim3(256), 0, x->stream, pa);
+  // chunks of about 2048 matrix entries per workgroup
+  const unsigned pchunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)NG * x->sp_apad + 2047) / 2048));
+  const dim3 pgrid((unsigned)(C * P), pchunks);
+  if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, pgrid, dim3(256), 0, x->stream, pa);
+  else hipLaunchKernelGGL(epic::split_prep_kernel<false>, pgrid, dim3(256), 0, x->stream, pa);
   // tile groups of TPW 32-pixel tiles per wave (two while the operands of
   // two tiles fit the registers); time chunks so that about three waves per
   // SIMD are resident, each at least 256 samples long

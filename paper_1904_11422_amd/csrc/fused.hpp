@@ -435,7 +435,9 @@ struct ReduceArgs {
 };
 
 // Workgroup whose range contains flat index f: the largest w with
-// floor(w * total / W) <= f, i.e. ceil((f + 1) W / total) - 1.
+// floor(w * total / W) <= f, i.e. ceil((f + 1) W / total) - 1.  Launches take
+// W <= total, so every range is non-empty and every workgroup from the owner
+// of a segment's first index to the owner of its last one wrote a slot.
 __device__ __forceinline__ int64_t owner_of(int64_t f, int64_t total, int64_t W) {
   return ((f + 1) * W + total - 1) / total - 1;
 }
@@ -468,7 +470,6 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
     const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
 #pragma unroll 4
     for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
-      if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
       const double* src = a.partial + (w + c) * NACC * NPIX + pix;
 #pragma unroll
       for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NPIX];

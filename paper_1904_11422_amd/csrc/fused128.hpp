@@ -210,7 +210,6 @@ __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
     const int64_t w_hi = owner_of((int64_t)(sgm + 1) * a.n_time - 1, a.total, a.W);
 #pragma unroll 4
     for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
-      if (range_begin(w, a.total, a.W) == range_begin(w + 1, a.total, a.W)) continue;
       const double* src = a.partial + (w + sgm) * NACC * NLOC + pix;
 #pragma unroll
       for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NLOC];

@@ -61,7 +61,8 @@ struct SplitPrepArgs {
   int n_chan, n_pol, n_ant, a_pad, ng;
 };
 
-// One workgroup per (channel, polarisation).
+// Workgroups (channel and polarisation, chunk of the matrix); each computes
+// the scale of its (channel, polarisation) from the gains (A <= 32 values).
 template <bool BF>
 __global__ void __launch_bounds__(256) split_prep_kernel(SplitPrepArgs a) {
   const int cp = blockIdx.x;
@@ -79,11 +80,13 @@ __global__ void __launch_bounds__(256) split_prep_kernel(SplitPrepArgs a) {
   const double bmax = red[0] * a.beta_max[c];
   // scale so that |B s| < 2^14: the hi parts stay finite, the lo parts normal
   const double sc = bmax > 0.0 ? ldexp(1.0, 13 - ilogb(bmax)) : 1.0;
-  if (threadIdx.x == 0) a.scale[cp] = (float)sc;
+  if (threadIdx.x == 0 && blockIdx.y == 0) a.scale[cp] = (float)sc;
   const int64_t plane = (int64_t)a.ng * a.a_pad;
   uint16_t* out = a.bmat + (int64_t)cp * kSplitParts * 2 * plane;
   const double2* beta = a.beta + (int64_t)c * a.ng * a.n_ant;
-  for (int64_t idx = threadIdx.x; idx < plane; idx += 256) {
+  const int64_t per = (plane + gridDim.y - 1) / gridDim.y;
+  const int64_t end = plane < (int64_t)(blockIdx.y + 1) * per ? plane : (int64_t)(blockIdx.y + 1) * per;
+  for (int64_t idx = (int64_t)blockIdx.y * per + threadIdx.x; idx < end; idx += 256) {
     const int pix = (int)(idx / a.a_pad), ant = (int)(idx % a.a_pad);
     double br = 0.0, bi = 0.0;
     if (ant < a.n_ant) {
