@@ -82,3 +82,26 @@ def test_tune_then_cache(batch_inputs, tmp_path):
     for k, inp in enumerate(batch_inputs):
         err = oracle.rel_errors(out[k].cpu().numpy(), oracle.image_from(inp))
         assert err.max() <= 1e-5
+
+
+@pytest.mark.slow
+def test_full_batch_sampled_channels():
+    """The benchmark's batch (six blocks at their full channel counts, T = 200)
+    in the launch configuration bench.py times -- tuned plan, captured graph,
+    replayed -- checked on two sampled channels of every block against the
+    oracle over all 200 samples."""
+    import torch
+    inputs = [synth.config4_block(b) for b in range(len(synth.CONFIG4_BLOCKS))]
+    b, ef, g = _batch(inputs)
+    imgs = b.new_images()
+    b.tune(ef, g, imgs)
+    b.capture(ef, g, imgs)
+    b.replay()
+    torch.cuda.synchronize()
+    for k, inp in enumerate(inputs):
+        for c in (0, inp.n_chan - 1):
+            print(f"block {k}: N={inp.grid_n} A={inp.n_ant} channel {c}", flush=True)
+            sub = synth.Inputs(inp.grid_n, 1, inp.n_pol, inp.n_ant, 3, 0.5, 0.5, inp.xy_m,
+                               inp.freq_hz[c:c + 1], inp.gains[c:c + 1], inp.efield[:, c:c + 1])
+            err = oracle.rel_errors(imgs[k][c:c + 1].cpu().numpy(), oracle.image_from(sub))
+            assert err.max() <= 1e-5, f"block {k} channel {c}: {err.max():.3e}"

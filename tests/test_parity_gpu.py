@@ -95,6 +95,31 @@ def test_reset_zero_continues_integration():
     assert oracle.rel_errors(img.cpu().numpy(), ref).max() <= TOL_FP32
 
 
+def test_reset_zero_continues_integration_n128():
+    """128^2: reset=0 adds to the image, and the two column halves of a
+    sample land in their own pixels (split across calls and segments)."""
+    import torch
+    inp = synth.random_problem(117, 128, 512, 2, 2, 9, fill=0.45)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    img = im.accumulate(ef[:4], g)
+    im.accumulate(ef[4:], g, image=img, reset=False)
+    torch.cuda.synchronize()
+    assert im.last_kernel_name() == "fused_image128_kernel"
+    assert oracle.rel_errors(img.cpu().numpy(), oracle.image_from(inp)).max() <= TOL_FP32
+
+
+def test_bitwise_deterministic_n128():
+    import torch
+    inp = synth.random_problem(118, 128, 700, 2, 2, 11, fill=0.45)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    a = im.accumulate(ef, g).clone()
+    b = im.accumulate(ef, g)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
 def test_bitwise_deterministic():
     import torch
     inp = synth.random_problem(112, 64, 256, 4, 2, 31)
