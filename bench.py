@@ -222,10 +222,21 @@ def bench_grad(args) -> int:
         bw.append(im.last_timing()[0])
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # adjoint work per (t,c): the forward recompute without the products, dL/dF*
+    # (20 flop per pixel at P = 2), the adjoint transform, the degridding
+    # (K^2 taps, 4 flop each, and conj(e) h, 6 flop, per (p, a))
+    fl_fwd = flops_per_tc(N, P, A) - 16 * N * N
+    fl_adj = fl_fwd + 20 * N * N + P * 5 * N * N * int(math.log2(N * N)) + (4 * 9 + 6) * P * A
+    adj_ms = float(np.mean(bw))
     out = {"metric": "forward + gain-gradient evaluations/s", "value": 1.0 / dt,
            "unit": "evaluations/s", "ms_per_step": dt * 1e3, "steps": args.steps,
            "forward_kernel_ms": float(np.mean(fw)), "adjoint_kernel_ms": float(np.mean(bw)),
-           "adjoint_tc_images_per_s": C * T / (float(np.mean(bw)) * 1e-3),
+           "adjoint_tc_images_per_s": C * T / (adj_ms * 1e-3),
+           "roofline": {"bound": "alu", "kernel": "adjoint_kernel",
+                        "achieved": fl_adj * C * T / (adj_ms * 1e-3) / 1e12,
+                        "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                        "frac": fl_adj * C * T / (adj_ms * 1e-3) / PEAK_FP32_VALU,
+                        "flops_per_tc_image": fl_adj},
            "workload": "256 dual-pol antennas, 64 channels, 64x64 grid, 200 samples",
            "data": "synthetic"}
     print(json.dumps(out))

@@ -18,7 +18,7 @@ namespace epic {
 struct AdjointArgs {
   const uint8_t* efield;    // [T][C][P][A]
   const float2* gains;      // [C][P][A]
-  const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
+  const float4* gtab;       // [C][S][NT]: {Re Gxx, Re Gyy, Re h, Im h} at owned pixels
   const uint2* prog;        // gridding programs and row-pass lines, as the imager
   const uint2* taps;        // [C][A][KK] {physical translated cell j*N+i, w bits}
   const float2* twiddle;
@@ -27,12 +27,48 @@ struct AdjointArgs {
   int n_chan, n_ant, kk, L, W;
 };
 
+// The upstream gradient at the pixels each thread of the fused kernels owns,
+// as float32 {Re Gxx, Re Gyy, Re h, Im h} with h = (Gxy + conj(Gyx)) / 2:
+// gtab[c][i][tid] for value i of thread tid.  Read once per sample by the
+// adjoint kernel (L2-resident), so it need not occupy registers.
+struct GradTableArgs {
+  const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
+  float4* gtab;
+  int n_chan;
+};
+
+template <int N, int P>
+__global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
+  using SH = FusedShape<N>;
+  constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, NPROD = (P == 2) ? 4 : 1;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_chan * S * NT) return;
+  const int c = (int)(idx / (S * NT));
+  const int i = (int)((idx / NT) % S), tid = (int)(idx % NT);
+  const Roles<N> r(tid);
+  const int q = i / R, k1 = i % R;
+  const int km = r.n0 * D + q + S * k1;
+  const int pix = ((km + N / 2) % N) * N + (r.kl + N / 2) % N;
+  const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
+  float4 t;
+  t.x = (float)gi[pix].x;
+  if (P == 2) {
+    const double2 xy = gi[N * N + pix], yx = gi[2 * N * N + pix];
+    t.y = (float)gi[3 * N * N + pix].x;
+    t.z = (float)(0.5 * (xy.x + yx.x));
+    t.w = (float)(0.5 * (xy.y - yx.y));
+  } else {
+    t.y = t.z = t.w = 0.f;
+  }
+  a.gtab[idx] = t;
+}
+
 template <int N, int P, int GPT>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 adjoint_kernel(AdjointArgs a) {
   using SH = FusedShape<N>;
   constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, RS = SH::RS;
-  constexpr int NPROD = (P == 2) ? 4 : 1;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   constexpr int PS = SH::PSTRIDE;
@@ -57,8 +93,6 @@ adjoint_kernel(AdjointArgs a) {
   int eidx[GPT];
   init_stage<NT, GPT, ES>(E, eidx, tid, a.n_ant, P);
 
-  float ga[S], gb[S];                          // Re(Gxx), Re(Gyy) at owned pixels
-  float2 gh[S];                                // (Gxy + conj(Gyx)) / 2
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
@@ -98,24 +132,6 @@ adjoint_kernel(AdjointArgs a) {
         g[i] = (k < PA) ? a.gains[(int64_t)c * PA + k] : make_float2(0.f, 0.f);
         gacc[i] = make_double2(0.0, 0.0);
       }
-      const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
-#pragma unroll
-      for (int q = 0; q < D; ++q)
-#pragma unroll
-        for (int k1 = 0; k1 < R; ++k1) {
-          const int km = r.n0 * D + q + S * k1;
-          const int pix = ((km + N / 2) % N) * N + (r.kl + N / 2) % N;
-          const int i = q * R + k1;
-          ga[i] = (float)gi[pix].x;
-          if (P == 2) {
-            const double2 xy = gi[N * N + pix], yx = gi[2 * N * N + pix];
-            gb[i] = (float)gi[3 * N * N + pix].x;
-            gh[i] = make_float2((float)(0.5 * (xy.x + yx.x)), (float)(0.5 * (xy.y - yx.y)));
-          } else {
-            gb[i] = 0.f;
-            gh[i] = make_float2(0.f, 0.f);
-          }
-        }
     }
     uint32_t cur[GPT];
 #pragma unroll
@@ -131,17 +147,20 @@ adjoint_kernel(AdjointArgs a) {
     column_pass_fwd<N, P>(v, X, r, tw);
 
     // dL/dF* at the owned pixels
+    const float4* gt = a.gtab + (int64_t)c * S * NT + tid;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
+      const float4 t = gt[i * NT];
       const float2 fx = v[0][i];
       if (P == 2) {
         const float2 fy = v[P - 1][i];
-        const float2 hx = cmul(gh[i], fy);     // h F_Y
-        const float2 hy = cmulc(fx, gh[i]);    // conj(h) F_X
-        v[0][i] = make_float2(fmaf(ga[i], fx.x, hx.x), fmaf(ga[i], fx.y, hx.y));
-        v[P - 1][i] = make_float2(fmaf(gb[i], fy.x, hy.x), fmaf(gb[i], fy.y, hy.y));
+        const float2 gh = make_float2(t.z, t.w);
+        const float2 hx = cmul(gh, fy);         // h F_Y
+        const float2 hy = cmulc(fx, gh);        // conj(h) F_X
+        v[0][i] = make_float2(fmaf(t.x, fx.x, hx.x), fmaf(t.x, fx.y, hx.y));
+        v[P - 1][i] = make_float2(fmaf(t.y, fy.x, hy.x), fmaf(t.y, fy.y, hy.y));
       } else {
-        v[0][i] = cscale(fx, ga[i]);
+        v[0][i] = cscale(fx, t.x);
       }
     }
     // adjoint column transforms, results to the aperture rows of each column

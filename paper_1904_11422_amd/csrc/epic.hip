@@ -98,6 +98,7 @@ struct epic_ctx {
   // workspace
   DevMem partial;                     // fused: [(W + C - 1)][nacc][N*N] thread-major
   DevMem gpartial;                    // adjoint: [(W + C - 1)][P*A] complex f64
+  DevMem gtab;                        // adjoint: [C][S][NT] float4 upstream gradient at owned pixels
   DevMem st_e, st_grid, st_acc;       // staged
   int tb = 0;
   // split-precision matrix form
@@ -812,7 +813,8 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     }
     x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
-    if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double))) {
+    if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
+        (N <= 64 && !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4)))) {
       g_init_error = "gradient workspace allocation failed";
       delete x;
       return EPIC_E_NOMEM;
@@ -1106,12 +1108,24 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   DeviceGuard guard(x->device);
   const int C = x->cfg.n_chan;
   const int64_t total = (int64_t)C * n_time;
-  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   (void)hipGetLastError();
+  {
+    epic::GradTableArgs ta;
+    ta.grad_image = reinterpret_cast<const double2*>(grad_image);
+    ta.gtab = x->gtab.as<float4>();
+    ta.n_chan = C;
+    const int N = x->cfg.grid_n, P = x->cfg.n_pol;
+    const dim3 tg((unsigned)(((int64_t)C * N * N + 255) / 256));
+    if (N == 32 && P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<32, 1>), tg, dim3(256), 0, x->stream, ta);
+    else if (N == 32) hipLaunchKernelGGL((epic::grad_table_kernel<32, 2>), tg, dim3(256), 0, x->stream, ta);
+    else if (P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<64, 1>), tg, dim3(256), 0, x->stream, ta);
+    else hipLaunchKernelGGL((epic::grad_table_kernel<64, 2>), tg, dim3(256), 0, x->stream, ta);
+  }
+  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   epic::AdjointArgs a;
   a.efield = efield;
   a.gains = reinterpret_cast<const float2*>(gains);
-  a.grad_image = reinterpret_cast<const double2*>(grad_image);
+  a.gtab = x->gtab.as<float4>();
   a.prog = x->prog.as<uint2>();
   a.taps = x->taps.as<uint2>();
   a.twiddle = x->twiddle.as<float2>();
@@ -1170,7 +1184,7 @@ void epic_destroy(epic_ctx* x) {
     for (auto& e : x->ev)
       if (e) (void)hipEventDestroy(e);
     x->prog.reset(); x->twiddle.reset(); x->taps.reset();
-    x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset();
+    x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset(); x->gtab.reset();
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
     x->sp_partial.reset();
