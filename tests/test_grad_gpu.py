@@ -2,7 +2,7 @@
 gradient (itself pinned to finite differences) and against central finite
 differences of the GPU forward image.
 
-Bar: relative L2 error of the gradient <= 1e-4 (the benchmark spec).
+Bar: relative L2 error of the gradient <= 1e-4.
 """
 import numpy as np
 import pytest

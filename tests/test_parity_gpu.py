@@ -174,6 +174,19 @@ def test_invalid_calls_leave_output_untouched():
     assert torch.all(out == 7.0)
 
 
+def test_empty_integration_is_rejected_and_output_untouched():
+    import torch
+    from paper_1904_11422_amd import EpicError
+    inp = synth.random_problem(119, 64, 64, 2, 2, 3)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    out = torch.full(im.image_shape(), 3.0, dtype=torch.complex128, device="cuda")
+    with pytest.raises(EpicError, match="INVALID"):
+        im.accumulate(ef[:0], g, image=out)
+    torch.cuda.synchronize()
+    assert torch.all(out == 3.0)
+
+
 @pytest.mark.slow
 def test_config2_full_size_sampled_channels():
     """The benchmark's launch (C=132, T=1000) checked on sampled channels, each

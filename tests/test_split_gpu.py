@@ -1,6 +1,6 @@
 """Split-precision (float16 / bfloat16 hi+lo) MFMA form of gridding + transform
 against the FP64 oracle.  Bar: relative L2 error per (channel, product)
-<= 1e-3 (the benchmark spec); float16 hi+lo carries ~2^-22 relative per matrix entry,
+<= 1e-3; float16 hi+lo carries ~2^-22 relative per matrix entry,
 bfloat16 hi+lo ~2^-16, the products are summed in float64."""
 import numpy as np
 import pytest
