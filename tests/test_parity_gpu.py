@@ -1,6 +1,6 @@
 """Parity of the HIP imaging path with the FP64 oracle, element by element.
 
-Tolerance (spec bar for the float32 path): relative L2 error per
+Tolerance (the bar for the float32 path): relative L2 error per
 (channel, product) <= 1e-5, with XY / YX scaled by sqrt(|XX| |YY|)
 (oracle.rel_errors).  The float32 transform of an int4 aperture carries an
 error of order eps32 * log2(n_g) ~ 1e-6; the time sums are float64.
