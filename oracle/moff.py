@@ -232,6 +232,45 @@ def image_fx(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
     return np.fft.fftshift(out.reshape(C, V.shape[1], N, N), axes=(-2, -1))
 
 
+# ------------------------------------------- autocorrelation removal (§3.2)
+def auto_visibilities(gains, efield) -> np.ndarray:
+    """The antenna autocorrelations V_PQ[c, a, a] = sum_t e'_{P,a} conj(e'_{Q,a})
+    (the a = b entries of §2 Eq. (2)), complex128 [C, n_prod, A], products in
+    the order XX, XY, YX, YY."""
+    e = unpack_ci4(efield)                                           # [T, C, P, A]
+    ep = np.asarray(gains).astype(np.complex128)[None] * e
+    P = ep.shape[2]
+    pairs = [(0, 0)] if P == 1 else [(0, 0), (0, 1), (1, 0), (1, 1)]
+    return np.stack([np.sum(ep[:, :, p] * np.conj(ep[:, :, q]), axis=0) for p, q in pairs], axis=1)
+
+
+def autocorrelation_image(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
+                          kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+    """The zero-spacing part of the accumulated image that §3.2 optionally
+    removes: the a = b terms sum_a V_PQ[a, a] |b_a(k)|^2 of the visibility form
+    (fftshifted, like the image)."""
+    b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
+                          cell_wavelengths)                           # [C, A, N, N]
+    vd = auto_visibilities(gains, efield)                            # [C, n, A]
+    out = np.einsum("cka,cayx->ckyx", vd, np.abs(b) ** 2)
+    return np.fft.fftshift(out, axes=(-2, -1))
+
+
+def image_without_autos(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
+                        kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+    """The accumulated image with the antenna autocorrelations removed (§3.2):
+    image minus autocorrelation_image."""
+    full = image(xy_m, freq_hz, gains, efield, grid_n, kernel_support, kernel_sigma_cells,
+                 cell_wavelengths)
+    return full - autocorrelation_image(xy_m, freq_hz, gains, efield, grid_n, kernel_support,
+                                        kernel_sigma_cells, cell_wavelengths)
+
+
+def image_without_autos_from(inp) -> np.ndarray:
+    return image_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, inp.grid_n,
+                               inp.kernel_support, inp.kernel_sigma_cells, inp.cell_wavelengths)
+
+
 # ------------------------------------------------------------- O9 gradient
 def grad_gains(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
                kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128) -> np.ndarray:

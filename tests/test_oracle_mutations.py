@@ -11,6 +11,7 @@ _transform = moff.transform
 _products = moff.products
 _kernel_taps = moff.kernel_taps
 _grad = moff.grad_gains
+_auto_vis = moff.auto_visibilities
 
 
 def _wrong_sign(a):
@@ -50,6 +51,21 @@ def _grad_half(*a, **k):
     return 0.5 * _grad(*a, **k)
 
 
+def _autos_not_squared(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
+                       kernel_sigma_cells=0.5, cell_wavelengths=0.5):
+    b = moff.aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
+                               cell_wavelengths)
+    out = np.einsum("cka,cayx->ckyx", moff.auto_visibilities(gains, efield), np.abs(b))
+    return np.fft.fftshift(out, axes=(-2, -1))
+
+
+def _auto_vis_swapped(gains, efield):
+    v = _auto_vis(gains, efield)
+    if v.shape[1] == 4:
+        v = v[:, [0, 2, 1, 3]]
+    return v
+
+
 MUTATIONS = {
     "transform with the -i sign": ("transform", _wrong_sign,
                                    [pins.test_p1_transform_sign_single_cell]),
@@ -64,6 +80,10 @@ MUTATIONS = {
                                      [pins.test_p2_zenith_closed_form_off_cell]),
     "gradient without the factor 2": ("grad_gains", _grad_half,
                                       [lambda: pins.test_p10_gradient_matches_finite_differences(1)]),
+    "autocorrelations with |b| not squared": ("autocorrelation_image", _autos_not_squared,
+                                              [pins.test_p13_autos_removed_equals_fx_form_without_diagonal]),
+    "XY and YX autocorrelations swapped": ("auto_visibilities", _auto_vis_swapped,
+                                           [pins.test_p13_autos_removed_equals_fx_form_without_diagonal]),
 }
 
 

@@ -345,3 +345,53 @@ def test_cost_model_grid_scaling():
     """n_g log2 n_g predicts x4.7 from 64^2 to 128^2 (paper §5.1)."""
     r = (128 ** 2 * np.log2(128 ** 2)) / (64 ** 2 * np.log2(64 ** 2))
     assert abs(r - 4.67) < 0.01
+
+
+# ------------------------------------------------ autocorrelation removal
+def _small(seed, N=32, A=12, C=2, P=2, T=5):
+    return synth.random_problem(seed, N, A, C, P, T)
+
+
+def test_p13_autos_removed_equals_fx_form_without_diagonal():
+    """Image (gridding + FFT path) minus the autocorrelation image equals the
+    visibility form with the a = b entries removed (an independent route)."""
+    inp = _small(501)
+    got = oracle.image_without_autos_from(inp)
+    V = oracle.visibilities(inp.gains, inp.efield)
+    A = inp.n_ant
+    V[:, :, np.arange(A), np.arange(A)] = 0.0
+    ref = oracle.image_fx(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, inp.grid_n, vis=V)
+    scale = np.abs(oracle.image_from(inp)).max()
+    assert np.max(np.abs(got - ref)) <= 1e-11 * scale
+
+
+def test_p13_single_antenna_leaves_nothing():
+    inp = _small(502, A=1)
+    full = oracle.image_from(inp)
+    got = oracle.image_without_autos_from(inp)
+    assert np.max(np.abs(got)) <= 1e-12 * np.abs(full).max()
+
+
+def test_p13_zenith_autocorrelation_closed_form():
+    """At the zenith pixel |b_a(0)|^2 = (sum of the antenna's tap weights)^2."""
+    inp = _small(503, P=1)
+    N = inp.grid_n
+    auto = oracle.autocorrelation_image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N)
+    X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
+    _, _, w = oracle.kernel_taps(X, Y, N)
+    e = oracle.unpack_ci4(inp.efield)[:, :, 0]                        # [T, C, A]
+    g = inp.gains[:, 0].astype(np.complex128)                         # [C, A]
+    for c in range(inp.n_chan):
+        power = np.sum(np.abs(g[c][None] * e[:, c]) ** 2, axis=0)    # [A]
+        ref = np.sum(power * w[c].sum(axis=1) ** 2)
+        assert abs(auto[c, 0, N // 2, N // 2] - ref) <= 1e-12 * ref
+
+
+def test_p13_autocorrelations_split_over_time_and_conjugate():
+    inp = _small(504, T=7)
+    a = oracle.autocorrelation_image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, inp.grid_n)
+    a1 = oracle.autocorrelation_image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield[:3], inp.grid_n)
+    a2 = oracle.autocorrelation_image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield[3:], inp.grid_n)
+    assert np.max(np.abs(a - a1 - a2)) <= 1e-12 * np.abs(a).max()
+    assert np.max(np.abs(a[:, 2] - np.conj(a[:, 1]))) <= 1e-12 * np.abs(a).max()
+    assert np.all(a[:, 0].real >= 0) and np.max(np.abs(a[:, 0].imag)) <= 1e-12 * np.abs(a).max()
