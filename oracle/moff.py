@@ -311,6 +311,47 @@ def grad_gains(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=
     return 2.0 * out
 
 
+def grad_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
+               kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+    """The share of autocorrelation_image in the gain gradient: d/dg of
+    Re <grad_image, autocorrelation_image>, in the convention of grad_gains.
+
+    With B_a(k) = |b_a(k)|^2 (real), s_PQ[a] = sum_t e_P conj(e_Q) (no gains) and
+    U_PQ[a] = sum_k Gamma_PQ(k) B_a(k):
+      V_XX = |g_X|^2 s_XX           ->  2 Re(U_XX) s_XX g_X
+      V_XY = g_X conj(g_Y) s_XY, V_YX = conj(V_XY), H = U_XY + conj(U_YX)
+                                    ->  H conj(s_XY) g_Y  to X,  conj(H) s_XY g_X  to Y
+    (the imaginary parts of Gamma_XX, Gamma_YY are ignored, as in grad_gains)."""
+    b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
+                          cell_wavelengths)
+    B = np.abs(b) ** 2                                                # [C, A, N, N]
+    Gam = np.fft.ifftshift(np.asarray(grad_image).astype(np.complex128), axes=(-2, -1))
+    e = unpack_ci4(efield)                                            # [T, C, P, A]
+    g = np.asarray(gains).astype(np.complex128)
+    P = e.shape[2]
+    out = np.zeros(g.shape, dtype=np.complex128)
+    s_xx = np.sum(np.abs(e[:, :, 0]) ** 2, axis=0)                   # [C, A]
+    u_xx = np.einsum("cyx,cayx->ca", Gam[:, 0].real, B)
+    out[:, 0] = 2.0 * u_xx * s_xx * g[:, 0]
+    if P == 2:
+        s_yy = np.sum(np.abs(e[:, :, 1]) ** 2, axis=0)
+        s_xy = np.sum(e[:, :, 0] * np.conj(e[:, :, 1]), axis=0)
+        u_yy = np.einsum("cyx,cayx->ca", Gam[:, 3].real, B)
+        h = np.einsum("cyx,cayx->ca", Gam[:, 1] + np.conj(Gam[:, 2]), B)
+        out[:, 0] += h * np.conj(s_xy) * g[:, 1]
+        out[:, 1] = 2.0 * u_yy * s_yy * g[:, 1] + np.conj(h) * s_xy * g[:, 0]
+    return out
+
+
+def grad_gains_without_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image,
+                             kernel_support=3, kernel_sigma_cells=0.5,
+                             cell_wavelengths=0.5) -> np.ndarray:
+    """Gain gradient of a loss of image_without_autos: grad_gains minus grad_autos."""
+    args = (xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support,
+            kernel_sigma_cells, cell_wavelengths)
+    return grad_gains(*args) - grad_autos(*args)
+
+
 # ------------------------------------------------------------- losses, FD
 def l2_loss(img: np.ndarray, model: np.ndarray) -> float:
     """L = sum over channels, products and pixels of |I - M|^2."""

@@ -59,6 +59,28 @@ def _autos_not_squared(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
     return np.fft.fftshift(out, axes=(-2, -1))
 
 
+def _grad_autos_variant(conj_sxy=True, two=2.0):
+    """grad_autos with one planted slip (the cross term's conjugate, the factor 2)."""
+    def fn(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
+           kernel_sigma_cells=0.5, cell_wavelengths=0.5):
+        B = np.abs(moff.aperture_response(xy_m, freq_hz, grid_n, kernel_support,
+                                          kernel_sigma_cells, cell_wavelengths)) ** 2
+        gam = np.fft.ifftshift(np.asarray(grad_image).astype(complex), axes=(-2, -1))
+        e = moff.unpack_ci4(efield)
+        g = np.asarray(gains).astype(complex)
+        out = np.zeros(g.shape, complex)
+        out[:, 0] = two * np.einsum("cyx,cayx->ca", gam[:, 0].real, B) \
+            * np.sum(np.abs(e[:, :, 0]) ** 2, axis=0) * g[:, 0]
+        if g.shape[1] == 2:
+            s_xy = np.sum(e[:, :, 0] * np.conj(e[:, :, 1]), axis=0)
+            h = np.einsum("cyx,cayx->ca", gam[:, 1] + np.conj(gam[:, 2]), B)
+            out[:, 0] += h * (np.conj(s_xy) if conj_sxy else s_xy) * g[:, 1]
+            out[:, 1] = two * np.einsum("cyx,cayx->ca", gam[:, 3].real, B) \
+                * np.sum(np.abs(e[:, :, 1]) ** 2, axis=0) * g[:, 1] + np.conj(h) * s_xy * g[:, 0]
+        return out
+    return fn
+
+
 def _auto_vis_swapped(gains, efield):
     v = _auto_vis(gains, efield)
     if v.shape[1] == 4:
@@ -84,6 +106,14 @@ MUTATIONS = {
                                               [pins.test_p13_autos_removed_equals_fx_form_without_diagonal]),
     "XY and YX autocorrelations swapped": ("auto_visibilities", _auto_vis_swapped,
                                            [pins.test_p13_autos_removed_equals_fx_form_without_diagonal]),
+    "autocorrelation gradient with s_XY not conjugated": (
+        "grad_autos", _grad_autos_variant(conj_sxy=False),
+        [pins.test_p14_gradient_without_autos_cross_products_only,
+         lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(2)]),
+    "autocorrelation gradient without the factor 2": (
+        "grad_autos", _grad_autos_variant(two=1.0),
+        [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),
+         pins.test_p14_homogeneity_without_autos]),
 }
 
 

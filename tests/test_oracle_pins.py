@@ -395,3 +395,67 @@ def test_p13_autocorrelations_split_over_time_and_conjugate():
     assert np.max(np.abs(a - a1 - a2)) <= 1e-12 * np.abs(a).max()
     assert np.max(np.abs(a[:, 2] - np.conj(a[:, 1]))) <= 1e-12 * np.abs(a).max()
     assert np.all(a[:, 0].real >= 0) and np.max(np.abs(a[:, 0].imag)) <= 1e-12 * np.abs(a).max()
+
+
+# ------------------------------------------------ P14: gradient without autos
+def _loss_without_autos(inp, model):
+    def loss(gg):
+        return oracle.l2_loss(oracle.image_without_autos(inp.xy_m, inp.freq_hz, gg, inp.efield,
+                                                         inp.grid_n), model)
+    return loss
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_p14_gradient_without_autos_matches_finite_differences(P):
+    """Gradient of a loss on the image with the autocorrelations removed
+    (Sec. 3.2) against central differences of that loss."""
+    inp, model, g, _ = _loss_setup(171 + P, P=P, A=6 if P == 2 else 8)
+    img = oracle.image_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(_loss_without_autos(inp, model), g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_p14_gradient_without_autos_cross_products_only():
+    """A loss on XY and YX alone checks the cross-polarisation terms."""
+    inp = synth.random_problem(181, 32, 5, 1, 2, 3, fill=0.4)
+    g = inp.gains.astype(np.complex128)
+    rng = _rng(6)
+    wxy = rng.normal(size=(1, 32, 32)) + 1j * rng.normal(size=(1, 32, 32))
+    wyx = rng.normal(size=(1, 32, 32)) + 1j * rng.normal(size=(1, 32, 32))
+
+    def loss(gg):
+        im = oracle.image_without_autos(inp.xy_m, inp.freq_hz, gg, inp.efield, 32)
+        return float(np.sum((np.conj(wxy) * im[:, 1]).real + (np.conj(wyx) * im[:, 2]).real))
+    gam = np.zeros((1, 4, 32, 32), complex)
+    gam[:, 1], gam[:, 2] = wxy, wyx
+    grad = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(loss, g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_p14_single_antenna_gradient_vanishes():
+    """One antenna: the image without autocorrelations is zero for every gain,
+    so its gradient is zero whatever the upstream gradient."""
+    inp = synth.random_problem(182, 32, 1, 2, 2, 4)
+    rng = _rng(7)
+    gam = rng.normal(size=(2, 4, 32, 32)) + 1j * rng.normal(size=(2, 4, 32, 32))
+    full = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, gam)
+    grad = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, gam)
+    assert np.max(np.abs(grad)) <= 1e-12 * np.max(np.abs(full))
+
+
+def test_p14_homogeneity_without_autos():
+    """Degree-2 homogeneity in the gains holds for the removed image too."""
+    inp, model, g, _ = _loss_setup(191, A=10)
+    img = oracle.image_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam)
+    lhs = np.sum(np.conj(g) * grad).real
+    rhs = 2.0 * np.sum((np.conj(gam) * img).real)
+    assert abs(lhs - rhs) / abs(rhs) < 1e-12
