@@ -243,6 +243,57 @@ def bench_grad(args) -> int:
     return 0
 
 
+def bench_autos(args) -> int:
+    """The default workload with the antenna autocorrelations removed: one
+    imaging call per step, then the removal (a second pass over the E-field
+    for the exact per-antenna sums, a per-channel table, a pass over the image)."""
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager
+    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+    inp = synth.config2()
+    N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
+    ef = torch.from_numpy(inp.efield).cuda()
+    g = torch.from_numpy(inp.gains).cuda()
+    im = Imager(N, C, P, A, timing=True, remove_autos=True)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
+    for _ in range(args.warmup):
+        im.accumulate(ef, g, image=img)
+    torch.cuda.synchronize()
+    print("bench: timing imaging with autocorrelation removal", file=sys.stderr, flush=True)
+    main_ms, sum_ms, rem_ms = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        im.accumulate(ef, g, image=img)
+        main_ms.append(im.last_timing()[0])
+        s, r = im.last_autos_timing()
+        sum_ms.append(s)
+        rem_ms.append(r)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    nq = 4 if P == 2 else 1
+    # algorithmic bytes of the sum pass: every sample byte once, the exact
+    # per-antenna sums (nq int32) out once
+    alg = C * T * P * A + C * A * nq * 4
+    s_ms = float(np.mean(sum_ms))
+    out = {"metric": "channel-images/s with autocorrelations removed", "value": C / dt,
+           "unit": "channel-images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "LWA-like: 256 dual-pol antennas, 132 channels, 64x64 grid, "
+                                  "1000 samples, autocorrelations removed",
+                      "grid_n": N, "n_chan": C, "n_pol": P, "n_ant": A, "n_time": T},
+           "imager_kernel_ms": float(np.mean(main_ms)), "auto_sum_kernel_ms": s_ms,
+           "removal_ms": float(np.mean(rem_ms)),
+           "roofline": {"bound": "hbm", "kernel": "auto_sum_kernel",
+                        "achieved": alg / (s_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                        "unit": "GB/s", "frac": alg / (s_ms * 1e-3) / PEAK_HBM,
+                        "traffic": None, "bytes_per_launch": alg}}
+    print(json.dumps(out))
+    return 0
+
+
 PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                        "fused_image_kernel_lwa64_c132_t1000.md")
 PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
@@ -287,6 +338,8 @@ def main() -> int:
                          "a long integration, with errors against the FP64 oracle")
     ap.add_argument("--grad", action="store_true",
                     help="measure forward + gain-gradient evaluations on the calibration workload")
+    ap.add_argument("--autos", action="store_true",
+                    help="measure the default workload with the antenna autocorrelations removed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (five times), to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -304,6 +357,8 @@ def main() -> int:
         return bench_split(args)
     if args.grad:
         return bench_grad(args)
+    if args.autos:
+        return bench_autos(args)
 
     import torch
     import synth

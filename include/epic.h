@@ -69,7 +69,9 @@ enum { EPIC_FP32 = 0, EPIC_SPLIT_FP16 = 1, EPIC_SPLIT_BF16 = 2 };
 enum {
   EPIC_FLAG_STAGED = 1,   /* one kernel per stage with FP32 intermediates in HBM
                              (the plain comparator); default is the fused kernel */
-  EPIC_FLAG_TIMING = 2    /* record HIP events around the main kernel of each call */
+  EPIC_FLAG_TIMING = 2,   /* record HIP events around the main kernel of each call */
+  EPIC_FLAG_REMOVE_AUTOS = 4  /* subtract the antenna autocorrelations from the image
+                                 (see epic_image_accumulate) */
 };
 
 typedef struct epic_config {
@@ -142,6 +144,15 @@ epic_status epic_gridding_program(const epic_config *cfg, const double *xy_m,
  * imaginary part left unchanged (reset == 0).  Accumulation is float64;
  * the per-sample transform is float32 (EPIC_FP32) or split float16 / bfloat16
  * matrix products with float32 accumulation (EPIC_SPLIT_*).  Allocates nothing.
+ * With EPIC_FLAG_REMOVE_AUTOS (Sec. 3.2 and Fig. 2: the optional removal of
+ * the zero-spacing power, done after squaring and accumulation) the call then
+ * subtracts the a = b terms of the visibility form of the image,
+ *   sum_a V_PQ[a] |b_a(k)|^2,  V_PQ[a] = g_P conj(g_Q) sum_t e_P[t,a] conj(e_Q[t,a]),
+ * b_a(k) the transform of antenna a's kernel taps: the integer sums are exact
+ * and the rest is float64.  It adds two passes: one more read of efield and a
+ * read-modify-write of image.  Only the samples of this call are removed, so
+ * split integrations stay consistent; a call takes at most 2^24 - 1 samples
+ * with the flag (more: EPIC_E_UNSUPPORTED).
  * Errors: EPIC_E_STATE (no antennas), EPIC_E_INVALID (null pointer,
  * n_time <= 0), EPIC_E_UNSUPPORTED, EPIC_E_LAUNCH. */
 epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
@@ -156,7 +167,8 @@ epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t 
  *   grad_gains: device complex64 [n_chan][n_pol][n_ant], overwritten with
  *               dL/dRe(g) + i dL/dIm(g).
  * The per-sample transforms are recomputed, not stored; the reduction over
- * time is float64.  Allocates nothing.  Errors as epic_image_accumulate. */
+ * time is float64.  Allocates nothing.  Errors as epic_image_accumulate;
+ * EPIC_E_UNSUPPORTED for a context with EPIC_FLAG_REMOVE_AUTOS. */
 epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
                                 const float *gains, const double *grad_image,
                                 float *grad_gains);
@@ -166,6 +178,12 @@ epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_
  * with HIP events on the context's stream.  Errors: EPIC_E_STATE (no timed
  * call yet or flag not set). */
 epic_status epic_last_timing(epic_ctx *ctx, float *main_kernel_ms, float *call_ms);
+
+/* With EPIC_FLAG_TIMING and EPIC_FLAG_REMOVE_AUTOS: wait for the last imaging
+ * call and report the duration of its autocorrelation-sum kernel (the pass
+ * over efield) and of the whole removal (sums, table and subtraction), in
+ * milliseconds.  Errors: EPIC_E_STATE (no such call yet). */
+epic_status epic_last_autos_timing(epic_ctx *ctx, float *sum_kernel_ms, float *removal_ms);
 
 /* Name of the main kernel the last imaging call launched (static string). */
 const char *epic_last_kernel_name(const epic_ctx *ctx);

@@ -10,6 +10,7 @@ not built or if a tensor is not on the GPU.
     img = im.accumulate(efield, gains)                 # uint8 [T,C,P,A], complex64 [C,P,A]
     g = im.backward(efield, gains, grad_img)           # d loss / d gains
     img = image(im, gains, efield)                     # autograd-aware
+    im = Imager(..., remove_autos=True)                # images without the a = b terms
 """
 from __future__ import annotations
 
@@ -35,17 +36,20 @@ class Imager:
     def __init__(self, grid_n: int, n_chan: int, n_pol: int, n_ant: int,
                  kernel_support: int = 3, kernel_sigma_cells: float = 0.5,
                  cell_wavelengths: float = 0.5, precision: str = "fp32",
-                 staged: bool = False, timing: bool = False, device: Optional[int] = None):
+                 staged: bool = False, timing: bool = False, remove_autos: bool = False,
+                 device: Optional[int] = None):
         torch = _torch()
         self.L = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the MOFF imager needs a GPU (no CPU path)")
         self.device = torch.cuda.current_device() if device is None else int(device)
-        flags = (_lib.EPIC_FLAG_STAGED if staged else 0) | (_lib.EPIC_FLAG_TIMING if timing else 0)
+        flags = (_lib.EPIC_FLAG_STAGED if staged else 0) | (_lib.EPIC_FLAG_TIMING if timing else 0) \
+            | (_lib.EPIC_FLAG_REMOVE_AUTOS if remove_autos else 0)
         self.cfg = _lib.EpicConfig(grid_n, n_chan, n_pol, n_ant, kernel_support,
                                    kernel_sigma_cells, cell_wavelengths,
                                    _PRECISIONS[precision], flags)
         self.grid_n, self.n_chan, self.n_pol, self.n_ant = grid_n, n_chan, n_pol, n_ant
+        self.remove_autos = remove_autos
         self.n_prod = 4 if n_pol == 2 else 1
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -86,7 +90,8 @@ class Imager:
 
     # ------------------------------------------------------------------ calls
     def accumulate(self, efield, gains, image=None, reset: bool = True):
-        """Sum of polarised images over the samples of efield (complex128)."""
+        """Sum of polarised images over the samples of efield (complex128);
+        with remove_autos=True, less the antenna autocorrelations of these samples."""
         torch = _torch()
         efield, gains = self._check_inputs(efield, gains)
         if image is None:
@@ -126,6 +131,14 @@ class Imager:
         st = self.L.epic_last_timing(self._ctx, ctypes.byref(m), ctypes.byref(c))
         _lib.check(self.L, self._ctx, st)
         return m.value, c.value
+
+    def last_autos_timing(self):
+        """(autocorrelation-sum kernel ms, whole removal ms) of the last call
+        (timing=True, remove_autos=True)."""
+        m, r = ctypes.c_float(), ctypes.c_float()
+        st = self.L.epic_last_autos_timing(self._ctx, ctypes.byref(m), ctypes.byref(r))
+        _lib.check(self.L, self._ctx, st)
+        return m.value, r.value
 
     def last_kernel_name(self) -> str:
         return self.L.epic_last_kernel_name(self._ctx).decode()
@@ -193,7 +206,8 @@ class Batch:
                                      c.get("kernel_support", 3), c.get("kernel_sigma_cells", 0.5),
                                      c.get("cell_wavelengths", 0.5),
                                      _PRECISIONS[c.get("precision", "fp32")],
-                                     _lib.EPIC_FLAG_STAGED if c.get("staged") else 0)
+                                     (_lib.EPIC_FLAG_STAGED if c.get("staged") else 0)
+                                     | (_lib.EPIC_FLAG_REMOVE_AUTOS if c.get("remove_autos") else 0))
             self.shapes.append((c["n_chan"], 4 if c["n_pol"] == 2 else 1, c["grid_n"], c["grid_n"]))
         self.n_blocks = len(configs)
         b = ctypes.c_void_p()

@@ -13,12 +13,13 @@ STATUS_NAMES = {0: "EPIC_OK", 1: "EPIC_E_INVALID", 2: "EPIC_E_DEVICE", 3: "EPIC_
                 4: "EPIC_E_OFFGRID", 5: "EPIC_E_STATE", 6: "EPIC_E_LAUNCH",
                 7: "EPIC_E_UNSUPPORTED"}
 EPIC_FP32, EPIC_SPLIT_FP16, EPIC_SPLIT_BF16 = 0, 1, 2
-EPIC_FLAG_STAGED, EPIC_FLAG_TIMING = 1, 2
+EPIC_FLAG_STAGED, EPIC_FLAG_TIMING, EPIC_FLAG_REMOVE_AUTOS = 1, 2, 4
 
 # Every function declared in include/epic.h, with its ctypes signature.
 EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_gridding_program",
            "epic_image_accumulate",
-           "epic_image_backward", "epic_last_timing", "epic_last_kernel_name",
+           "epic_image_backward", "epic_last_timing", "epic_last_autos_timing",
+           "epic_last_kernel_name",
            "epic_destroy", "epic_last_error",
            "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
            "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_image_backward.restype = ctypes.c_int
     L.epic_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.epic_last_timing.restype = ctypes.c_int
+    L.epic_last_autos_timing.argtypes = L.epic_last_timing.argtypes
+    L.epic_last_autos_timing.restype = ctypes.c_int
     L.epic_last_kernel_name.argtypes = [vp]
     L.epic_last_kernel_name.restype = ctypes.c_char_p
     L.epic_destroy.argtypes = [vp]

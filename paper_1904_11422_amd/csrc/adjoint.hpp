@@ -207,6 +207,7 @@ struct GradReduceArgs {
   int64_t n_time, total;
   int n_chan, PA, W;
   int sub;                  // sub-lanes per (c, p, a), as in reduce_image_kernel
+  const double2* minus;     // [C][P*A] float64 term subtracted before rounding, or null
 };
 
 __global__ void __launch_bounds__(256) reduce_grad_kernel(GradReduceArgs a) {
@@ -229,7 +230,14 @@ __global__ void __launch_bounds__(256) reduce_grad_kernel(GradReduceArgs a) {
     }
   }
   combine_sublanes<2>(s, a.sub, ppb, j, lp, red);
-  if (valid && j == 0) a.grad[idx] = make_float2((float)(2.0 * s[0]), (float)(2.0 * s[1]));
+  if (valid && j == 0) {
+    double gr = 2.0 * s[0], gim = 2.0 * s[1];
+    if (a.minus) {
+      gr -= a.minus[idx].x;
+      gim -= a.minus[idx].y;
+    }
+    a.grad[idx] = make_float2((float)gr, (float)gim);
+  }
 }
 
 }  // namespace epic

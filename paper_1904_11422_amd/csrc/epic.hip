@@ -20,6 +20,7 @@
 #include "adjoint.hpp"
 #include "split.hpp"
 #include "fused128.hpp"
+#include "autos.hpp"
 
 namespace {
 
@@ -107,7 +108,18 @@ struct epic_ctx {
 
   // timing
   bool timing = false, timed = false;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool autos_timed = false;
+
+  // autocorrelation removal (EPIC_FLAG_REMOVE_AUTOS)
+  bool autos = false;
+  int au_nseg_cap = 0;
+  int au_bpc[2] = {1, 1};             // resident auto_sum_kernel workgroups per CU (VEC 1, 4)
+  DevMem au_part;                     // [nseg][C][A][NQ] int32 sums per time segment
+  DevMem au_tab;                      // [C][(2K-1)^2][NQ] float64
+  DevMem au_w;                        // [C][A][K*K] float32 tap weights
+  DevMem au_hat;                      // [C][(2K-1)^2][NQ] float64 upstream-gradient sums
+  DevMem au_gauto;                    // [C][P][A] complex float64 gradient of the removed term
 
   epic_status fail(epic_status s, const std::string& m) {
     err = m;
@@ -138,7 +150,9 @@ epic_status check_config(const epic_config* c, std::string& m) {
       c->precision != EPIC_SPLIT_BF16) {
     m = "unknown precision"; return EPIC_E_INVALID;
   }
-  if (c->flags & ~(EPIC_FLAG_STAGED | EPIC_FLAG_TIMING)) { m = "unknown flag"; return EPIC_E_INVALID; }
+  if (c->flags & ~(EPIC_FLAG_STAGED | EPIC_FLAG_TIMING | EPIC_FLAG_REMOVE_AUTOS)) {
+    m = "unknown flag"; return EPIC_E_INVALID;
+  }
   return EPIC_OK;
 }
 
@@ -725,12 +739,6 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   const unsigned rg = (unsigned)(((int64_t)C * NG + rppb - 1) / rppb);
   if (P == 2) hipLaunchKernelGGL(epic::split_reduce_kernel<2>, dim3(rg), dim3(256), 0, x->stream, ra);
   else hipLaunchKernelGGL(epic::split_reduce_kernel<1>, dim3(rg), dim3(256), 0, x->stream, ra);
-  if (x->timing) {
-    (void)hipEventRecord(x->ev[2], x->stream);
-    x->timed = true;
-  }
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   return EPIC_OK;
 }
 
@@ -738,241 +746,103 @@ unsigned grid_for(int64_t n, int64_t cap = 1 << 16) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, (n + 255) / 256));
 }
 
-}  // namespace
-
-extern "C" {
-
-epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic_ctx** out) {
-  g_init_error.clear();
-  if (!out) { g_init_error = "out is NULL"; return EPIC_E_INVALID; }
-  *out = nullptr;
-  std::string m;
-  epic_status s = check_config(cfg, m);
-  if (s == EPIC_OK && cfg->precision != EPIC_FP32) s = check_split(cfg, m);
-  if (s != EPIC_OK) { g_init_error = m; return s; }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
-    g_init_error = "no such HIP device";
-    return EPIC_E_DEVICE;
-  }
-  hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
-    g_init_error = "hipGetDeviceProperties failed";
-    return EPIC_E_DEVICE;
-  }
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
-    g_init_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
-    return EPIC_E_DEVICE;
-  }
-  DeviceGuard guard(device);
-  epic_ctx* x = new (std::nothrow) epic_ctx();
-  if (!x) { g_init_error = "host allocation failed"; return EPIC_E_NOMEM; }
-  x->cfg = *cfg;
-  x->device = device;
-  x->stream = static_cast<hipStream_t>(hip_stream);
-  x->nprod = cfg->n_pol == 2 ? 4 : 1;
-  x->nacc = cfg->n_pol == 2 ? 4 : 1;
-  x->PA = cfg->n_pol * cfg->n_ant;
-  x->n_cu = prop.multiProcessorCount;
-  const int N = cfg->grid_n;
-
-  // twiddles exp(+2 pi i k / N), float64 then rounded once
-  std::vector<float2> tw(N);
-  for (int k = 0; k < N; ++k) {
-    const double ang = 2.0 * M_PI * (double)k / (double)N;
-    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
-  if (!x->twiddle.alloc(N * sizeof(float2)) ||
-      hipMemcpy(x->twiddle.p, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
-    g_init_error = "twiddle table allocation failed";
-    delete x;
-    return EPIC_E_NOMEM;
-  }
-
-  const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
-  // fused kernels: N = 32 and 64 (one or two polarisations), N = 128 with two
-  x->fused_ok = !want_staged && cfg->precision == EPIC_FP32 && (N <= 64 || cfg->n_pol == 2);
-  if (x->fused_ok) {
-    const int NT = fused_threads(N);
-    int gpt = (x->PA + NT - 1) / NT;
-    gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
-    if (gpt == 0) x->fused_ok = false;
-    else x->fused_gpt = gpt;
-  }
-  if (x->fused_ok) {
-    const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
-    x->fused_w = bpc * x->n_cu;
-    // N = 128: two accumulation segments (column halves) per channel
-    const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
-    const size_t slots = (size_t)x->fused_w + segs - 1;
-    const size_t per_slot = N == 128 ? (size_t)x->nacc * N * N / 2 : (size_t)x->nacc * N * N;
-    if (!x->partial.alloc(slots * per_slot * sizeof(double))) {
-      g_init_error = "partial-image workspace allocation failed";
-      delete x;
-      return EPIC_E_NOMEM;
-    }
-    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
-    const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
-    if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
-        (N <= 64 && !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4)))) {
-      g_init_error = "gradient workspace allocation failed";
-      delete x;
-      return EPIC_E_NOMEM;
-    }
-  }
-  if (cfg->flags & EPIC_FLAG_TIMING) {
-    x->timing = true;
-    for (auto& e : x->ev)
-      if (hipEventCreate(&e) != hipSuccess) {
-        g_init_error = "hipEventCreate failed";
-        epic_destroy(x);
-        return EPIC_E_DEVICE;
-      }
-  }
-  *out = x;
-  return EPIC_OK;
-}
-
-epic_status epic_set_stream(epic_ctx* x, void* hip_stream) {
-  if (!x) return EPIC_E_INVALID;
-  x->stream = static_cast<hipStream_t>(hip_stream);
-  return EPIC_OK;
-}
-
-epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, const double* freq_hz,
-                                  uint32_t* out, int64_t* words, int32_t* layout) {
-  g_init_error.clear();
-  std::string m;
-  epic_status s = check_config(cfg, m);
-  if (s != EPIC_OK) { g_init_error = m; return s; }
-  if (!xy_m || !freq_hz || !words || !layout) { g_init_error = "null pointer"; return EPIC_E_INVALID; }
-  const int N = cfg->grid_n, P = cfg->n_pol;
-  if ((N > 64 && P != 2) || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
-    g_init_error = "the configuration has no fused kernel";
-    return EPIC_E_UNSUPPORTED;
-  }
-  const int NT = fused_threads(N);
-  int gpt = (P * cfg->n_ant + NT - 1) / NT;
-  gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
-  if (gpt == 0) {
-    g_init_error = "too many antennas for the fused kernel";
-    return EPIC_E_UNSUPPORTED;
-  }
-  Geometry g;
-  s = build_geometry(*cfg, xy_m, freq_hz, g, m);
-  if (s != EPIC_OK) { g_init_error = m; return s; }
-  if (!g.fits_half) { g_init_error = "taps do not fit an N/2 x N/2 block"; return EPIC_E_UNSUPPORTED; }
-  std::vector<uint32_t> prog;
-  int L = 0;
-  if (N == 32) build_programs<32>(g, P, gpt, prog, L);
-  else if (N == 64) build_programs<64>(g, P, gpt, prog, L);
-  else build_programs<128>(g, P, gpt, prog, L);
-  if (L == 0) { g_init_error = "gridding program fields overflow"; return EPIC_E_UNSUPPORTED; }
-  const int64_t need = (int64_t)prog.size(), cap = *words;
-  *words = need;
-  const int ES = NT * gpt / P + 64;
-  layout[0] = NT;
-  layout[1] = L;
-  layout[2] = N == 32 ? epic::FusedShape<32>::RS : N == 64 ? epic::FusedShape<64>::RS : epic::FusedShape<128>::RS;
-  layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE
-            : N == 64 ? epic::FusedShape<64>::PSTRIDE : epic::FusedShape<128>::PSTRIDE;
-  layout[4] = P * ES;
-  layout[5] = ES;
-  layout[6] = N == 64 ? 1 : 0;
-  if (cap == 0) return EPIC_OK;
-  if (!out || cap < need) { g_init_error = "output capacity too small"; return EPIC_E_NOMEM; }
-  std::memcpy(out, prog.data(), prog.size() * sizeof(uint32_t));
-  return EPIC_OK;
-}
-
-epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* freq_hz) {
-  if (!x) return EPIC_E_INVALID;
-  if (!xy_m || !freq_hz) return x->fail(EPIC_E_INVALID, "xy_m or freq_hz is NULL");
-  Geometry g;
-  std::string m;
-  epic_status s = build_geometry(x->cfg, xy_m, freq_hz, g, m);
-  if (s != EPIC_OK) return x->fail(s, m);
-  DeviceGuard guard(x->device);
-  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
-  if (hipStreamSynchronize(x->stream) != hipSuccess)
-    return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
-  x->have_geom = false;
-  if (x->cfg.precision != EPIC_FP32) {
-    s = build_split_tables(x, g);
-    if (s != EPIC_OK) return s;
-    x->have_geom = true;
-    return EPIC_OK;
-  }
-  // The fused kernels need every channel's taps inside an N/2 x N/2 block;
-  // larger apertures (aliased images) run the staged kernels.
-  x->fused = x->fused_ok && g.fits_half;
-
-  if (x->fused) {
-    // adjoint taps [C][A][KK] {translated cell, w}
-    std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
-    for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
-      const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-      taps[2 * o] = (uint32_t)((N == 64 ? epic::FusedShape<64>::phys_row(j) : j) * N + i);
-      std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
-    }
-    std::vector<uint32_t> prog;
-    int L = 0;
-    if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L);
-    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L);
-    else build_programs<128>(g, P, x->fused_gpt, prog, L);
-    if (L == 0) return x->fail(EPIC_E_UNSUPPORTED, "gridding program fields overflow");
-    if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
-        hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-      return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
-    x->L = L;
+// Exact per-antenna sums of e_P conj(e_Q) over the samples (auto_sum_kernel);
+// returns the number of time segments (partial sums) written.
+int launch_auto_sum(epic_ctx* x, const uint8_t* efield, int64_t n_time) {
+  const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
+  const bool vec4 = A % 4 == 0 && (reinterpret_cast<uintptr_t>(efield) & 3) == 0;
+  const int VEC = vec4 ? 4 : 1;
+  const int64_t gx = ((int64_t)C * (A / VEC) + epic::AUTO_LANES - 1) / epic::AUTO_LANES;
+  // as many time segments as keep every workgroup resident at once (one if
+  // the antennas alone fill the GPU), at least 64 samples per segment
+  int64_t nseg = std::max<int64_t>(1, (int64_t)x->n_cu * x->au_bpc[vec4 ? 1 : 0] / gx);
+  nseg = std::min<int64_t>(nseg, std::max<int64_t>(1, n_time / 64));
+  nseg = std::min<int64_t>(nseg, x->au_nseg_cap);
+  epic::AutoSumArgs sa;
+  sa.efield = efield;
+  sa.part = x->au_part.as<int32_t>();
+  sa.n_time = n_time;
+  sa.n_chan = C;
+  sa.n_ant = A;
+  sa.nseg = (int)nseg;
+  const dim3 sg((unsigned)gx, (unsigned)nseg), sb(epic::AUTO_LANES * epic::AUTO_TL);
+  if (P == 2) {
+    if (vec4) hipLaunchKernelGGL((epic::auto_sum_kernel<2, 4>), sg, sb, 0, x->stream, sa);
+    else hipLaunchKernelGGL((epic::auto_sum_kernel<2, 1>), sg, sb, 0, x->stream, sa);
   } else {
-    if (!alloc_staged(x)) return x->fail(EPIC_E_NOMEM, "staged workspace allocation failed");
-    // per-cell CSR over the whole grid, entries in (antenna, tap) order
-    const int npix = N * N, nnz = A * g.KK;
-    std::vector<int> off((size_t)C * (npix + 1));
-    std::vector<uint32_t> ent((size_t)C * nnz * 2);
-    for (int c = 0; c < C; ++c) {
-      std::vector<int> cnt(npix, 0);
-      for (int a = 0; a < A; ++a)
-        for (int k = 0; k < g.KK; ++k) cnt[g.cell[((size_t)c * A + a) * g.KK + k]]++;
-      int* o = &off[(size_t)c * (npix + 1)];
-      o[0] = 0;
-      for (int i = 0; i < npix; ++i) o[i + 1] = o[i] + cnt[i];
-      std::vector<int> fill(o, o + npix);
-      for (int a = 0; a < A; ++a)
-        for (int k = 0; k < g.KK; ++k) {
-          const size_t src = ((size_t)c * A + a) * g.KK + k;
-          const size_t dst = (size_t)c * nnz + fill[g.cell[src]]++;
-          ent[2 * dst] = (uint32_t)a;
-          std::memcpy(&ent[2 * dst + 1], &g.w[src], 4);
-        }
-    }
-    if (!x->csr_off.alloc(off.size() * 4) || !x->csr_ent.alloc(ent.size() * 4) ||
-        hipMemcpy(x->csr_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(x->csr_ent.p, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
-      return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
-    x->nnz = nnz;
+    if (vec4) hipLaunchKernelGGL((epic::auto_sum_kernel<1, 4>), sg, sb, 0, x->stream, sa);
+    else hipLaunchKernelGGL((epic::auto_sum_kernel<1, 1>), sg, sb, 0, x->stream, sa);
   }
-  x->have_geom = true;
-  return EPIC_OK;
+  return (int)nseg;
 }
 
-epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_time,
-                                  const float* gains, double* image, int32_t reset) {
-  if (!x) return EPIC_E_INVALID;
-  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
-  if (!efield || !gains || !image) return x->fail(EPIC_E_INVALID, "NULL device pointer");
-  if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
-  DeviceGuard guard(x->device);
-  if (x->cfg.precision != EPIC_FP32) {
-    (void)hipGetLastError();
-    return run_split(x, efield, n_time, gains, image, reset);
-  }
+// Autocorrelation sums, per-channel table and removal (after the image).
+void launch_autos(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                  double* image) {
+  const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol, N = x->cfg.grid_n;
+  const int K = x->cfg.kernel_support;
+  if (x->timing) (void)hipEventRecord(x->ev[3], x->stream);
+  const int nseg = launch_auto_sum(x, efield, n_time);
+  if (x->timing) (void)hipEventRecord(x->ev[4], x->stream);
+  epic::AutoTableArgs ta;
+  ta.part = x->au_part.as<int32_t>();
+  ta.gains = reinterpret_cast<const float2*>(gains);
+  ta.w = x->au_w.as<float>();
+  ta.table = x->au_tab.as<double>();
+  ta.n_chan = C;
+  ta.n_ant = A;
+  ta.nseg = nseg;
+  ta.K = K;
+  const dim3 tg((unsigned)((int64_t)8 * ((C + 7) / 8) * (2 * K - 1) * (2 * K - 1)));
+  if (P == 2) hipLaunchKernelGGL(epic::auto_table_kernel<2>, tg, dim3(256), 0, x->stream, ta);
+  else hipLaunchKernelGGL(epic::auto_table_kernel<1>, tg, dim3(256), 0, x->stream, ta);
+  epic::AutoRemoveArgs ra;
+  ra.table = x->au_tab.as<double>();
+  ra.image = reinterpret_cast<double2*>(image);
+  ra.n_chan = C;
+  ra.N = N;
+  ra.K = K;
+  const dim3 rg((unsigned)((int64_t)C * ((N * N + 255) / 256)));
+  if (P == 2) hipLaunchKernelGGL(epic::auto_remove_kernel<2>, rg, dim3(256), 0, x->stream, ra);
+  else hipLaunchKernelGGL(epic::auto_remove_kernel<1>, rg, dim3(256), 0, x->stream, ra);
+}
+
+// Gradient of the removed autocorrelation term into x->au_gauto.
+void launch_autos_grad(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                       const double* grad_image) {
+  const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol, N = x->cfg.grid_n;
+  const int K = x->cfg.kernel_support, D2 = (2 * K - 1) * (2 * K - 1);
+  const int nseg = launch_auto_sum(x, efield, n_time);
+  epic::AutoHatArgs ha;
+  ha.grad_image = reinterpret_cast<const double2*>(grad_image);
+  ha.hat = x->au_hat.as<double>();
+  ha.n_chan = C;
+  ha.N = N;
+  ha.K = K;
+  const dim3 hg((unsigned)((int64_t)8 * ((C + 7) / 8) * D2));
+  if (P == 2) hipLaunchKernelGGL(epic::auto_hat_kernel<2>, hg, dim3(256), 0, x->stream, ha);
+  else hipLaunchKernelGGL(epic::auto_hat_kernel<1>, hg, dim3(256), 0, x->stream, ha);
+  epic::AutoGradArgs ga;
+  ga.part = x->au_part.as<int32_t>();
+  ga.gains = reinterpret_cast<const float2*>(gains);
+  ga.w = x->au_w.as<float>();
+  ga.hat = x->au_hat.as<double>();
+  ga.gauto = x->au_gauto.as<double2>();
+  ga.n_chan = C;
+  ga.n_ant = A;
+  ga.nseg = nseg;
+  ga.K = K;
+  const dim3 gg((unsigned)(((int64_t)C * A + 255) / 256));
+  if (P == 2) hipLaunchKernelGGL(epic::auto_grad_kernel<2>, gg, dim3(256), 0, x->stream, ga);
+  else hipLaunchKernelGGL(epic::auto_grad_kernel<1>, gg, dim3(256), 0, x->stream, ga);
+}
+
+// The float32 paths: fused kernels, or the staged comparator.
+epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                     double* image, int32_t reset) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
-  (void)hipGetLastError();
   if (x->fused && N == 128) {
     epic::Fused128Args a;
     a.efield = efield;
@@ -1086,6 +956,268 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
     r.sub = 1;
     launch_reduce(x, r, false);
   }
+  return EPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic_ctx** out) {
+  g_init_error.clear();
+  if (!out) { g_init_error = "out is NULL"; return EPIC_E_INVALID; }
+  *out = nullptr;
+  std::string m;
+  epic_status s = check_config(cfg, m);
+  if (s == EPIC_OK && cfg->precision != EPIC_FP32) s = check_split(cfg, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    g_init_error = "no such HIP device";
+    return EPIC_E_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_init_error = "hipGetDeviceProperties failed";
+    return EPIC_E_DEVICE;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_init_error = std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950";
+    return EPIC_E_DEVICE;
+  }
+  DeviceGuard guard(device);
+  epic_ctx* x = new (std::nothrow) epic_ctx();
+  if (!x) { g_init_error = "host allocation failed"; return EPIC_E_NOMEM; }
+  x->cfg = *cfg;
+  x->device = device;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  x->nprod = cfg->n_pol == 2 ? 4 : 1;
+  x->nacc = cfg->n_pol == 2 ? 4 : 1;
+  x->PA = cfg->n_pol * cfg->n_ant;
+  x->n_cu = prop.multiProcessorCount;
+  const int N = cfg->grid_n;
+
+  // twiddles exp(+2 pi i k / N), float64 then rounded once
+  std::vector<float2> tw(N);
+  for (int k = 0; k < N; ++k) {
+    const double ang = 2.0 * M_PI * (double)k / (double)N;
+    tw[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  if (!x->twiddle.alloc(N * sizeof(float2)) ||
+      hipMemcpy(x->twiddle.p, tw.data(), N * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    g_init_error = "twiddle table allocation failed";
+    delete x;
+    return EPIC_E_NOMEM;
+  }
+
+  const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
+  // fused kernels: N = 32 and 64 (one or two polarisations), N = 128 with two
+  x->fused_ok = !want_staged && cfg->precision == EPIC_FP32 && (N <= 64 || cfg->n_pol == 2);
+  if (x->fused_ok) {
+    const int NT = fused_threads(N);
+    int gpt = (x->PA + NT - 1) / NT;
+    gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
+    if (gpt == 0) x->fused_ok = false;
+    else x->fused_gpt = gpt;
+  }
+  if (x->fused_ok) {
+    const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
+    x->fused_w = bpc * x->n_cu;
+    // N = 128: two accumulation segments (column halves) per channel
+    const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
+    const size_t slots = (size_t)x->fused_w + segs - 1;
+    const size_t per_slot = N == 128 ? (size_t)x->nacc * N * N / 2 : (size_t)x->nacc * N * N;
+    if (!x->partial.alloc(slots * per_slot * sizeof(double))) {
+      g_init_error = "partial-image workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
+    const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
+    if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
+        (N <= 64 && !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4)))) {
+      g_init_error = "gradient workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+  }
+  if (cfg->flags & EPIC_FLAG_REMOVE_AUTOS) {
+    const int NQ = cfg->n_pol == 2 ? 4 : 1, D = 2 * cfg->kernel_support - 1;
+    const size_t per_seg = (size_t)cfg->n_chan * cfg->n_ant * NQ * sizeof(int32_t);
+    x->autos = true;
+    const int st = epic::AUTO_LANES * epic::AUTO_TL;
+    x->au_bpc[0] = cfg->n_pol == 2 ? occupancy_blocks(epic::auto_sum_kernel<2, 1>, st)
+                                   : occupancy_blocks(epic::auto_sum_kernel<1, 1>, st);
+    x->au_bpc[1] = cfg->n_pol == 2 ? occupancy_blocks(epic::auto_sum_kernel<2, 4>, st)
+                                   : occupancy_blocks(epic::auto_sum_kernel<1, 4>, st);
+    x->au_nseg_cap = (int)std::max<size_t>(1, std::min<size_t>(epic::AUTO_MAX_SEG, (256u << 20) / per_seg));
+    if (!x->au_part.alloc(x->au_nseg_cap * per_seg) ||
+        !x->au_tab.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
+        !x->au_hat.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
+        !x->au_gauto.alloc((size_t)cfg->n_chan * x->PA * 2 * sizeof(double))) {
+      g_init_error = "autocorrelation workspace allocation failed";
+      delete x;
+      return EPIC_E_NOMEM;
+    }
+  }
+  if (cfg->flags & EPIC_FLAG_TIMING) {
+    x->timing = true;
+    for (auto& e : x->ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        g_init_error = "hipEventCreate failed";
+        epic_destroy(x);
+        return EPIC_E_DEVICE;
+      }
+  }
+  *out = x;
+  return EPIC_OK;
+}
+
+epic_status epic_set_stream(epic_ctx* x, void* hip_stream) {
+  if (!x) return EPIC_E_INVALID;
+  x->stream = static_cast<hipStream_t>(hip_stream);
+  return EPIC_OK;
+}
+
+epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, const double* freq_hz,
+                                  uint32_t* out, int64_t* words, int32_t* layout) {
+  g_init_error.clear();
+  std::string m;
+  epic_status s = check_config(cfg, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  if (!xy_m || !freq_hz || !words || !layout) { g_init_error = "null pointer"; return EPIC_E_INVALID; }
+  const int N = cfg->grid_n, P = cfg->n_pol;
+  if ((N > 64 && P != 2) || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
+    g_init_error = "the configuration has no fused kernel";
+    return EPIC_E_UNSUPPORTED;
+  }
+  const int NT = fused_threads(N);
+  int gpt = (P * cfg->n_ant + NT - 1) / NT;
+  gpt = gpt <= 1 ? 1 : gpt <= 2 ? 2 : gpt <= 4 ? 4 : 0;
+  if (gpt == 0) {
+    g_init_error = "too many antennas for the fused kernel";
+    return EPIC_E_UNSUPPORTED;
+  }
+  Geometry g;
+  s = build_geometry(*cfg, xy_m, freq_hz, g, m);
+  if (s != EPIC_OK) { g_init_error = m; return s; }
+  if (!g.fits_half) { g_init_error = "taps do not fit an N/2 x N/2 block"; return EPIC_E_UNSUPPORTED; }
+  std::vector<uint32_t> prog;
+  int L = 0;
+  if (N == 32) build_programs<32>(g, P, gpt, prog, L);
+  else if (N == 64) build_programs<64>(g, P, gpt, prog, L);
+  else build_programs<128>(g, P, gpt, prog, L);
+  if (L == 0) { g_init_error = "gridding program fields overflow"; return EPIC_E_UNSUPPORTED; }
+  const int64_t need = (int64_t)prog.size(), cap = *words;
+  *words = need;
+  const int ES = NT * gpt / P + 64;
+  layout[0] = NT;
+  layout[1] = L;
+  layout[2] = N == 32 ? epic::FusedShape<32>::RS : N == 64 ? epic::FusedShape<64>::RS : epic::FusedShape<128>::RS;
+  layout[3] = N == 32 ? epic::FusedShape<32>::PSTRIDE
+            : N == 64 ? epic::FusedShape<64>::PSTRIDE : epic::FusedShape<128>::PSTRIDE;
+  layout[4] = P * ES;
+  layout[5] = ES;
+  layout[6] = N == 64 ? 1 : 0;
+  if (cap == 0) return EPIC_OK;
+  if (!out || cap < need) { g_init_error = "output capacity too small"; return EPIC_E_NOMEM; }
+  std::memcpy(out, prog.data(), prog.size() * sizeof(uint32_t));
+  return EPIC_OK;
+}
+
+epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* freq_hz) {
+  if (!x) return EPIC_E_INVALID;
+  if (!xy_m || !freq_hz) return x->fail(EPIC_E_INVALID, "xy_m or freq_hz is NULL");
+  Geometry g;
+  std::string m;
+  epic_status s = build_geometry(x->cfg, xy_m, freq_hz, g, m);
+  if (s != EPIC_OK) return x->fail(s, m);
+  DeviceGuard guard(x->device);
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
+  if (hipStreamSynchronize(x->stream) != hipSuccess)
+    return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
+  x->have_geom = false;
+  if (x->autos &&
+      (!x->au_w.alloc(g.w.size() * sizeof(float)) ||
+       hipMemcpy(x->au_w.p, g.w.data(), g.w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess))
+    return x->fail(EPIC_E_NOMEM, "kernel weight upload failed");
+  if (x->cfg.precision != EPIC_FP32) {
+    s = build_split_tables(x, g);
+    if (s != EPIC_OK) return s;
+    x->have_geom = true;
+    return EPIC_OK;
+  }
+  // The fused kernels need every channel's taps inside an N/2 x N/2 block;
+  // larger apertures (aliased images) run the staged kernels.
+  x->fused = x->fused_ok && g.fits_half;
+
+  if (x->fused) {
+    // adjoint taps [C][A][KK] {translated cell, w}
+    std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
+    for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
+      const int j = g.tcell[o] / N, i = g.tcell[o] % N;
+      taps[2 * o] = (uint32_t)((N == 64 ? epic::FusedShape<64>::phys_row(j) : j) * N + i);
+      std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
+    }
+    std::vector<uint32_t> prog;
+    int L = 0;
+    if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L);
+    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L);
+    else build_programs<128>(g, P, x->fused_gpt, prog, L);
+    if (L == 0) return x->fail(EPIC_E_UNSUPPORTED, "gridding program fields overflow");
+    if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
+        hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
+    x->L = L;
+  } else {
+    if (!alloc_staged(x)) return x->fail(EPIC_E_NOMEM, "staged workspace allocation failed");
+    // per-cell CSR over the whole grid, entries in (antenna, tap) order
+    const int npix = N * N, nnz = A * g.KK;
+    std::vector<int> off((size_t)C * (npix + 1));
+    std::vector<uint32_t> ent((size_t)C * nnz * 2);
+    for (int c = 0; c < C; ++c) {
+      std::vector<int> cnt(npix, 0);
+      for (int a = 0; a < A; ++a)
+        for (int k = 0; k < g.KK; ++k) cnt[g.cell[((size_t)c * A + a) * g.KK + k]]++;
+      int* o = &off[(size_t)c * (npix + 1)];
+      o[0] = 0;
+      for (int i = 0; i < npix; ++i) o[i + 1] = o[i] + cnt[i];
+      std::vector<int> fill(o, o + npix);
+      for (int a = 0; a < A; ++a)
+        for (int k = 0; k < g.KK; ++k) {
+          const size_t src = ((size_t)c * A + a) * g.KK + k;
+          const size_t dst = (size_t)c * nnz + fill[g.cell[src]]++;
+          ent[2 * dst] = (uint32_t)a;
+          std::memcpy(&ent[2 * dst + 1], &g.w[src], 4);
+        }
+    }
+    if (!x->csr_off.alloc(off.size() * 4) || !x->csr_ent.alloc(ent.size() * 4) ||
+        hipMemcpy(x->csr_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(x->csr_ent.p, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
+    x->nnz = nnz;
+  }
+  x->have_geom = true;
+  return EPIC_OK;
+}
+
+epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_time,
+                                  const float* gains, double* image, int32_t reset) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!efield || !gains || !image) return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
+  if (x->autos && n_time > epic::AUTO_SEG_MAX_SAMPLES)
+    return x->fail(EPIC_E_UNSUPPORTED, "with EPIC_FLAG_REMOVE_AUTOS a call takes at most 2^24 - 1 samples");
+  DeviceGuard guard(x->device);
+  (void)hipGetLastError();
+  const epic_status s = x->cfg.precision != EPIC_FP32
+                            ? run_split(x, efield, n_time, gains, image, reset)
+                            : run_fp32(x, efield, n_time, gains, image, reset);
+  if (s != EPIC_OK) return s;
+  if (x->autos) launch_autos(x, efield, n_time, gains, image);
+  x->autos_timed = x->autos && x->timing;
   if (x->timing) {
     (void)hipEventRecord(x->ev[2], x->stream);
     x->timed = true;
@@ -1094,7 +1226,6 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
   if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   return EPIC_OK;
 }
-
 epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time,
                                 const float* gains, const double* grad_image, float* grad_gains) {
   if (!x) return EPIC_E_INVALID;
@@ -1102,6 +1233,8 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (!efield || !gains || !grad_image || !grad_gains)
     return x->fail(EPIC_E_INVALID, "NULL device pointer");
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
+  if (x->autos && n_time > epic::AUTO_SEG_MAX_SAMPLES)
+    return x->fail(EPIC_E_UNSUPPORTED, "with EPIC_FLAG_REMOVE_AUTOS a call takes at most 2^24 - 1 samples");
   if (!x->fused || x->cfg.precision != EPIC_FP32 || x->cfg.grid_n > 64)
     return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path "
                    "(N <= 64, aperture within N/2 x N/2 cells)");
@@ -1140,6 +1273,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
   x->last_kernel = "adjoint_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
   epic::GradReduceArgs r;
   r.gpartial = x->gpartial.as<double2>();
   r.grad = reinterpret_cast<float2*>(grad_gains);
@@ -1149,6 +1283,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   r.PA = x->PA;
   r.W = a.W;
   r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
+  r.minus = x->autos ? x->au_gauto.as<double2>() : nullptr;
   const int64_t n = (int64_t)C * x->PA, gppb = 256 / r.sub;
   hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + gppb - 1) / gppb)), dim3(256), 0,
                      x->stream, r);
@@ -1174,6 +1309,20 @@ epic_status epic_last_timing(epic_ctx* x, float* main_ms, float* call_ms) {
   return EPIC_OK;
 }
 
+epic_status epic_last_autos_timing(epic_ctx* x, float* sum_kernel_ms, float* removal_ms) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->timing || !x->timed || !x->autos_timed)
+    return x->fail(EPIC_E_STATE, "no timed call with EPIC_FLAG_REMOVE_AUTOS and EPIC_FLAG_TIMING");
+  DeviceGuard guard(x->device);
+  if (hipEventSynchronize(x->ev[2]) != hipSuccess) return x->fail(EPIC_E_DEVICE, "event wait failed");
+  float m = 0.f, r = 0.f;
+  (void)hipEventElapsedTime(&m, x->ev[3], x->ev[4]);
+  (void)hipEventElapsedTime(&r, x->ev[3], x->ev[2]);
+  if (sum_kernel_ms) *sum_kernel_ms = m;
+  if (removal_ms) *removal_ms = r;
+  return EPIC_OK;
+}
+
 const char* epic_last_kernel_name(const epic_ctx* x) { return x ? x->last_kernel : "none"; }
 
 void epic_destroy(epic_ctx* x) {
@@ -1188,6 +1337,8 @@ void epic_destroy(epic_ctx* x) {
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
     x->sp_partial.reset();
+    x->au_part.reset(); x->au_tab.reset(); x->au_w.reset(); x->au_hat.reset();
+    x->au_gauto.reset();
   }
   delete x;
 }
