@@ -289,24 +289,27 @@ def bench_autos(args) -> int:
            "roofline": {"bound": "hbm", "kernel": "auto_sum_kernel",
                         "achieved": alg / (s_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                         "unit": "GB/s", "frac": alg / (s_ms * 1e-3) / PEAK_HBM,
-                        "traffic": None, "bytes_per_launch": alg}}
+                        "traffic": measured_traffic(AUTOS_PROFILE, AUTOS_SOURCES),
+                        "bytes_per_launch": alg}}
     print(json.dumps(out))
     return 0
 
 
-PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                       "fused_image_kernel_lwa64_c132_t1000.md")
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+PROFILE = os.path.join(PROFILES, "fused_image_kernel_lwa64_c132_t1000.md")
 PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
+AUTOS_PROFILE = os.path.join(PROFILES, "auto_sum_kernel_lwa64_c132_t1000.md")
+AUTOS_SOURCES = ("csrc/autos.hpp", "build.py")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading), or
-    None when the kernel sources have changed since the counters were taken."""
+def measured_traffic(profile=PROFILE, sources=PROFILED_SOURCES):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's reading), or None
+    when the kernel sources have changed since the counters were taken."""
     import hashlib
     import re
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
     except OSError:
         return None
     want = re.search(r"sources_sha256: ([0-9a-f]{64})", text)
@@ -315,7 +318,7 @@ def measured_traffic():
         return None
     h = hashlib.sha256()
     pkg = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1904_11422_amd")
-    for f in PROFILED_SOURCES:
+    for f in sources:
         with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     return int(val.group(1)) if h.hexdigest() == want.group(1) else None

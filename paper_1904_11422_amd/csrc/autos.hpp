@@ -162,12 +162,50 @@ __global__ void __launch_bounds__(AUTO_LANES * AUTO_TL) auto_sum_kernel(AutoSumA
   }
 }
 
-struct AutoTableArgs {
+struct AutoFoldArgs {
   const int32_t* part;      // [nseg][C][A][NQ]
+  double* sums;             // [C][A][NQ], exact (integers below 2^31)
+  int64_t n;                // C * A
+  int nseg;
+};
+
+// The time segments' partial sums added up: one thread per (channel, antenna),
+// all segment loads issued together.
+template <int P>
+__global__ void __launch_bounds__(256) auto_fold_kernel(AutoFoldArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= a.n) return;
+  if constexpr (P == 2) {
+    const int4* p = reinterpret_cast<const int4*>(a.part) + idx;
+    int4 v[AUTO_MAX_SEG];
+#pragma unroll
+    for (int seg = 0; seg < AUTO_MAX_SEG; ++seg)
+      v[seg] = seg < a.nseg ? p[seg * a.n] : make_int4(0, 0, 0, 0);
+    int64_t m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+#pragma unroll
+    for (int seg = 0; seg < AUTO_MAX_SEG; ++seg) {
+      m0 += v[seg].x; m1 += v[seg].y; m2 += v[seg].z; m3 += v[seg].w;
+    }
+    double2* o = reinterpret_cast<double2*>(a.sums) + 2 * idx;
+    o[0] = make_double2((double)m0, (double)m1);
+    o[1] = make_double2((double)m2, (double)m3);
+  } else {
+    int v[AUTO_MAX_SEG];
+#pragma unroll
+    for (int seg = 0; seg < AUTO_MAX_SEG; ++seg) v[seg] = seg < a.nseg ? a.part[seg * a.n + idx] : 0;
+    int64_t m0 = 0;
+#pragma unroll
+    for (int seg = 0; seg < AUTO_MAX_SEG; ++seg) m0 += v[seg];
+    a.sums[idx] = (double)m0;
+  }
+}
+
+struct AutoTableArgs {
+  const double* sums;       // [C][A][NQ] from auto_fold_kernel
   const float2* gains;      // [C][P][A]
   const float* w;           // [C][A][K*K] tap weights, tap order dj outer, di inner
   double* table;            // [C][(2K-1)^2][NQ]: {XX, YY, Re XY, Im XY} or {XX}
-  int n_chan, n_ant, nseg, K;
+  int n_chan, n_ant;
 };
 
 // Sum of NV values over a 256-thread workgroup in a fixed order (halving
@@ -198,60 +236,101 @@ __device__ __forceinline__ void xcd_channel_offset(int D2, int& c, int& d) {
 }
 
 // R_a(d) = sum_u w(u) w(u - d) over the taps u with u and u - d in the K x K
-// footprint, in float64 from the float32 weights w[K*K].
-__device__ __forceinline__ double tap_autocorrelation(const float* w, int K, int dj, int di) {
-  const int uj0 = dj > 0 ? dj : 0, uj1 = dj < 0 ? K + dj : K;
-  const int ui0 = di > 0 ? di : 0, ui1 = di < 0 ? K + di : K;
+// footprint, in float64 from the float32 weights w[K*K] (in registers: K is a
+// template argument, every loop unrolls).
+template <int K>
+__device__ __forceinline__ double tap_autocorrelation(const float (&w)[K * K], int dj, int di) {
   double r = 0.0;
-  for (int uj = uj0; uj < uj1; ++uj)
-    for (int ui = ui0; ui < ui1; ++ui)
-      r = fma((double)w[uj * K + ui], (double)w[(uj - dj) * K + (ui - di)], r);
+#pragma unroll
+  for (int uj = 0; uj < K; ++uj)
+#pragma unroll
+    for (int ui = 0; ui < K; ++ui) {
+      const int vj = uj - dj, vi = ui - di;
+      if (vj >= 0 && vj < K && vi >= 0 && vi < K)
+        r = fma((double)w[uj * K + ui], (double)w[vj * K + vi], r);
+    }
   return r;
 }
 
-// S_PQ(d) for one (channel, tap offset) per workgroup; one antenna per thread
-// at a time.  d = (dj, di): dj = d / (2K-1) - (K-1), di = d % (2K-1) - (K-1).
-template <int P>
+template <int K>
+__device__ __forceinline__ void load_taps(const float* src, float (&w)[K * K]) {
+#pragma unroll
+  for (int i = 0; i < K * K; ++i) w[i] = src[i];
+}
+
+// S_PQ(d) for one (channel, tap offset) per wave, the wave's lanes taking
+// antennas lane, lane + 64, ...  Grid: 8 * ceil(C / 8) * ceil((2K-1)^2 / 4)
+// workgroups of four waves; workgroup b takes channel
+// (r / G) * 8 + b % 8 and offsets 4 (r % G) + wave, r = b / 8, G =
+// ceil((2K-1)^2 / 4), so the workgroups of a channel share one XCD.
+template <int P, int K>
 __global__ void __launch_bounds__(256) auto_table_kernel(AutoTableArgs a) {
   constexpr int NQ = AutoShape<P>::NQ;
-  __shared__ double red[NQ][4];
-  const int K = a.K, D = 2 * K - 1, D2 = D * D, KK = K * K;
-  int c, d;
-  xcd_channel_offset(D2, c, d);
-  if (c >= a.n_chan) return;
+  constexpr int D = 2 * K - 1, D2 = D * D, KK = K * K, G = (D2 + 3) / 4;
+  const int r = blockIdx.x / 8, wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int c = (r / G) * 8 + blockIdx.x % 8, d = (r % G) * 4 + wave;
+  if (c >= a.n_chan || d >= D2) return;
   const int dj = d / D - (K - 1), di = d % D - (K - 1);
-  const int64_t CA = (int64_t)a.n_chan * a.n_ant;
   double s[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) s[q] = 0.0;
-  for (int ant = threadIdx.x; ant < a.n_ant; ant += 256) {
+#pragma unroll 4
+  for (int ant = lane; ant < a.n_ant; ant += 64) {
     const int64_t ca = (int64_t)c * a.n_ant + ant;
-    int64_t m[NQ];
+    double m[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) m[q] = 0;
-    for (int seg = 0; seg < a.nseg; ++seg) {
-      const int32_t* p = a.part + ((int64_t)seg * CA + ca) * NQ;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) m[q] += p[q];
-    }
-    const double r = tap_autocorrelation(a.w + ca * KK, K, dj, di);
+    for (int q = 0; q < NQ; ++q) m[q] = a.sums[ca * NQ + q];
+    float w[KK];
+    load_taps<K>(a.w + ca * KK, w);
+    const double rr = tap_autocorrelation<K>(w, dj, di);
     const float2 gx = a.gains[(int64_t)c * P * a.n_ant + ant];
     const double gxr = gx.x, gxi = gx.y;
-    s[0] = fma((gxr * gxr + gxi * gxi) * (double)m[0], r, s[0]);
+    s[0] = fma((gxr * gxr + gxi * gxi) * m[0], rr, s[0]);
     if constexpr (P == 2) {
       const float2 gy = a.gains[((int64_t)c * P + 1) * a.n_ant + ant];
       const double gyr = gy.x, gyi = gy.y;
-      s[1] = fma((gyr * gyr + gyi * gyi) * (double)m[1], r, s[1]);
+      s[1] = fma((gyr * gyr + gyi * gyi) * m[1], rr, s[1]);
       // g_X conj(g_Y) (m2 + i m3)
       const double hr = gxr * gyr + gxi * gyi, hi = gxi * gyr - gxr * gyi;
-      s[2] = fma(hr * (double)m[2] - hi * (double)m[3], r, s[2]);
-      s[3] = fma(hr * (double)m[3] + hi * (double)m[2], r, s[3]);
+      s[2] = fma(hr * m[2] - hi * m[3], rr, s[2]);
+      s[3] = fma(hr * m[3] + hi * m[2], rr, s[3]);
     }
   }
-  block_sum256<NQ>(s, red);
-  if (threadIdx.x == 0)
+  // fixed-order sum over the wave
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
+  if (lane == 0)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) a.table[((int64_t)c * D2 + d) * NQ + q] = s[q];
+}
+
+// The removed term at unshifted pixel (km, kl) from a channel's table st
+// (in LDS, [(2K-1)^2][NQ]) and cs[m] = cos(2 pi m / N): v[q] = sum_d
+// st[d][q] cos(2 pi (di kl + dj km) / N).
+template <int NQ>
+__device__ __forceinline__ void autos_at(const double (*st)[NQ], const double* cs, int N, int K,
+                                         int km, int kl, double (&v)[NQ]) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int dj = -(K - 1), d = 0; dj <= K - 1; ++dj)
+    for (int di = -(K - 1); di <= K - 1; ++di, ++d) {
+      const double e = cs[(di * kl + dj * km) & (N - 1)];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[q] = fma(st[d][q], e, v[q]);
+    }
+}
+
+// Stage channel c's table and the cosine table into LDS (all threads of the
+// workgroup take part; a barrier follows).
+template <int NQ>
+__device__ __forceinline__ void stage_autos(const double* table, int c, int N, int K,
+                                            double (*st)[NQ], double* cs) {
+  const int D = 2 * K - 1;
+  for (int i = threadIdx.x; i < D * D * NQ; i += blockDim.x)
+    (&st[0][0])[i] = table[(int64_t)c * D * D * NQ + i];
+  for (int m = threadIdx.x; m < N; m += blockDim.x) cs[m] = cospi(2.0 * m / N);
+  __syncthreads();
 }
 
 struct AutoRemoveArgs {
@@ -266,25 +345,15 @@ __global__ void __launch_bounds__(256) auto_remove_kernel(AutoRemoveArgs a) {
   constexpr int NQ = AutoShape<P>::NQ;
   __shared__ double st[AUTO_MAX_D2][NQ];
   __shared__ double cs[128];
-  const int N = a.N, K = a.K, D = 2 * K - 1, tiles = (N * N + 255) / 256;
+  const int N = a.N, K = a.K, tiles = (N * N + 255) / 256;
   const int c = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-  for (int i = threadIdx.x; i < D * D * NQ; i += 256)
-    (&st[0][0])[i] = a.table[(int64_t)c * D * D * NQ + i];
-  for (int m = threadIdx.x; m < N; m += 256) cs[m] = cospi(2.0 * m / N);
-  __syncthreads();
+  stage_autos<NQ>(a.table, c, N, K, st, cs);
   const int pix = tile * 256 + threadIdx.x;
   if (pix >= N * N) return;
   // pixel (q_m, q_l) of the shifted image holds k = (q - N/2) mod N
   const int km = (pix / N + N / 2) & (N - 1), kl = (pix % N + N / 2) & (N - 1);
   double v[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
-  for (int dj = -(K - 1), d = 0; dj <= K - 1; ++dj)
-    for (int di = -(K - 1); di <= K - 1; ++di, ++d) {
-      const double e = cs[(di * kl + dj * km) & (N - 1)];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] = fma(st[d][q], e, v[q]);
-    }
+  autos_at<NQ>(st, cs, N, K, km, kl, v);
   constexpr int NPROD = P == 2 ? 4 : 1;
   double2* img = a.image + (int64_t)c * NPROD * N * N + pix;
   img[0].x -= v[0];
@@ -348,50 +417,47 @@ __global__ void __launch_bounds__(256) auto_hat_kernel(AutoHatArgs a) {
 }
 
 struct AutoGradArgs {
-  const int32_t* part;      // [nseg][C][A][NQ] integer sums
+  const double* sums;       // [C][A][NQ] from auto_fold_kernel
   const float2* gains;      // [C][P][A]
   const float* w;           // [C][A][K*K]
   const double* hat;        // [C][(2K-1)^2][NQ]
   double2* gauto;           // [C][P][A]: the removed term's gradient
-  int n_chan, n_ant, nseg, K;
+  int n_chan, n_ant;
 };
 
 // One thread per (channel, antenna).
-template <int P>
+template <int P, int K>
 __global__ void __launch_bounds__(256) auto_grad_kernel(AutoGradArgs a) {
-  constexpr int NQ = AutoShape<P>::NQ;
+  constexpr int NQ = AutoShape<P>::NQ, D = 2 * K - 1, KK = K * K;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t CA = (int64_t)a.n_chan * a.n_ant;
   if (idx >= CA) return;
   const int c = (int)(idx / a.n_ant), ant = (int)(idx % a.n_ant);
-  const int K = a.K, D = 2 * K - 1, KK = K * K;
-  const float* w = a.w + idx * KK;
+  float w[KK];
+  load_taps<K>(a.w + idx * KK, w);
   double u[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) u[q] = 0.0;
   const double* hc = a.hat + (int64_t)c * D * D * NQ;
   for (int dj = -(K - 1), d = 0; dj <= K - 1; ++dj)
     for (int di = -(K - 1); di <= K - 1; ++di, ++d) {
-      const double r = tap_autocorrelation(w, K, dj, di);
+      const double r = tap_autocorrelation<K>(w, dj, di);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) u[q] = fma(r, hc[d * NQ + q], u[q]);
     }
-  int64_t m[NQ];
+  double m[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) m[q] = 0;
-  for (int seg = 0; seg < a.nseg; ++seg)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) m[q] += a.part[((int64_t)seg * CA + idx) * NQ + q];
+  for (int q = 0; q < NQ; ++q) m[q] = a.sums[idx * NQ + q];
   const float2 gxf = a.gains[(int64_t)c * P * a.n_ant + ant];
   const double gxr = gxf.x, gxi = gxf.y;
-  const double fx = 2.0 * u[0] * (double)m[0];
+  const double fx = 2.0 * u[0] * m[0];
   double2 ox = make_double2(fx * gxr, fx * gxi);
   if constexpr (P == 2) {
     const float2 gyf = a.gains[((int64_t)c * P + 1) * a.n_ant + ant];
     const double gyr = gyf.x, gyi = gyf.y;
-    const double fy = 2.0 * u[1] * (double)m[1];
+    const double fy = 2.0 * u[1] * m[1];
     double2 oy = make_double2(fy * gyr, fy * gyi);
-    const double hr = u[2], hi = u[3], sr = (double)m[2], si = (double)m[3];
+    const double hr = u[2], hi = u[3], sr = m[2], si = m[3];
     // H conj(s) g_Y
     const double tr = hr * sr + hi * si, ti = hi * sr - hr * si;
     ox.x += tr * gyr - ti * gyi;

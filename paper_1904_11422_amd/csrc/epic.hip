@@ -117,6 +117,7 @@ struct epic_ctx {
   int au_bpc[2] = {1, 1};             // resident auto_sum_kernel workgroups per CU (VEC 1, 4)
   DevMem au_part;                     // [nseg][C][A][NQ] int32 sums per time segment
   DevMem au_tab;                      // [C][(2K-1)^2][NQ] float64
+  DevMem au_sums;                     // [C][A][NQ] float64 (exact integer sums)
   DevMem au_w;                        // [C][A][K*K] float32 tap weights
   DevMem au_hat;                      // [C][(2K-1)^2][NQ] float64 upstream-gradient sums
   DevMem au_gauto;                    // [C][P][A] complex float64 gradient of the removed term
@@ -776,26 +777,45 @@ int launch_auto_sum(epic_ctx* x, const uint8_t* efield, int64_t n_time) {
   return (int)nseg;
 }
 
-// Autocorrelation sums, per-channel table and removal (after the image).
-void launch_autos(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
-                  double* image) {
-  const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol, N = x->cfg.grid_n;
-  const int K = x->cfg.kernel_support;
+// The segments' partial sums added into x->au_sums.
+void launch_auto_fold(epic_ctx* x, int nseg) {
+  epic::AutoFoldArgs fa;
+  fa.part = x->au_part.as<int32_t>();
+  fa.sums = x->au_sums.as<double>();
+  fa.n = (int64_t)x->cfg.n_chan * x->cfg.n_ant;
+  fa.nseg = nseg;
+  const dim3 fg((unsigned)((fa.n + 255) / 256));
+  if (x->cfg.n_pol == 2) hipLaunchKernelGGL(epic::auto_fold_kernel<2>, fg, dim3(256), 0, x->stream, fa);
+  else hipLaunchKernelGGL(epic::auto_fold_kernel<1>, fg, dim3(256), 0, x->stream, fa);
+}
+
+// Autocorrelation sums and the per-channel table of the removed term.
+void launch_auto_table(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains) {
+  const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
+  const int K = x->cfg.kernel_support, D2 = (2 * K - 1) * (2 * K - 1);
   if (x->timing) (void)hipEventRecord(x->ev[3], x->stream);
   const int nseg = launch_auto_sum(x, efield, n_time);
   if (x->timing) (void)hipEventRecord(x->ev[4], x->stream);
+  launch_auto_fold(x, nseg);
   epic::AutoTableArgs ta;
-  ta.part = x->au_part.as<int32_t>();
+  ta.sums = x->au_sums.as<double>();
   ta.gains = reinterpret_cast<const float2*>(gains);
   ta.w = x->au_w.as<float>();
   ta.table = x->au_tab.as<double>();
   ta.n_chan = C;
   ta.n_ant = A;
-  ta.nseg = nseg;
-  ta.K = K;
-  const dim3 tg((unsigned)((int64_t)8 * ((C + 7) / 8) * (2 * K - 1) * (2 * K - 1)));
-  if (P == 2) hipLaunchKernelGGL(epic::auto_table_kernel<2>, tg, dim3(256), 0, x->stream, ta);
-  else hipLaunchKernelGGL(epic::auto_table_kernel<1>, tg, dim3(256), 0, x->stream, ta);
+  const dim3 tg((unsigned)((int64_t)8 * ((C + 7) / 8) * ((D2 + 3) / 4)));
+#define EPIC_AT(PP, KK_)                                                                      \
+  if (P == PP && K == KK_) hipLaunchKernelGGL((epic::auto_table_kernel<PP, KK_>), tg, dim3(256), 0, \
+                                              x->stream, ta);
+  EPIC_AT(1, 1) EPIC_AT(1, 3) EPIC_AT(1, 5) EPIC_AT(1, 7)
+  EPIC_AT(2, 1) EPIC_AT(2, 3) EPIC_AT(2, 5) EPIC_AT(2, 7)
+#undef EPIC_AT
+}
+
+// Subtract the removed term (table from launch_auto_table) from the image.
+void launch_auto_remove(epic_ctx* x, double* image) {
+  const int C = x->cfg.n_chan, P = x->cfg.n_pol, N = x->cfg.grid_n, K = x->cfg.kernel_support;
   epic::AutoRemoveArgs ra;
   ra.table = x->au_tab.as<double>();
   ra.image = reinterpret_cast<double2*>(image);
@@ -812,7 +832,7 @@ void launch_autos_grad(epic_ctx* x, const uint8_t* efield, int64_t n_time, const
                        const double* grad_image) {
   const int C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol, N = x->cfg.grid_n;
   const int K = x->cfg.kernel_support, D2 = (2 * K - 1) * (2 * K - 1);
-  const int nseg = launch_auto_sum(x, efield, n_time);
+  launch_auto_fold(x, launch_auto_sum(x, efield, n_time));
   epic::AutoHatArgs ha;
   ha.grad_image = reinterpret_cast<const double2*>(grad_image);
   ha.hat = x->au_hat.as<double>();
@@ -823,18 +843,20 @@ void launch_autos_grad(epic_ctx* x, const uint8_t* efield, int64_t n_time, const
   if (P == 2) hipLaunchKernelGGL(epic::auto_hat_kernel<2>, hg, dim3(256), 0, x->stream, ha);
   else hipLaunchKernelGGL(epic::auto_hat_kernel<1>, hg, dim3(256), 0, x->stream, ha);
   epic::AutoGradArgs ga;
-  ga.part = x->au_part.as<int32_t>();
+  ga.sums = x->au_sums.as<double>();
   ga.gains = reinterpret_cast<const float2*>(gains);
   ga.w = x->au_w.as<float>();
   ga.hat = x->au_hat.as<double>();
   ga.gauto = x->au_gauto.as<double2>();
   ga.n_chan = C;
   ga.n_ant = A;
-  ga.nseg = nseg;
-  ga.K = K;
   const dim3 gg((unsigned)(((int64_t)C * A + 255) / 256));
-  if (P == 2) hipLaunchKernelGGL(epic::auto_grad_kernel<2>, gg, dim3(256), 0, x->stream, ga);
-  else hipLaunchKernelGGL(epic::auto_grad_kernel<1>, gg, dim3(256), 0, x->stream, ga);
+#define EPIC_AG(PP, KK_)                                                                     \
+  if (P == PP && K == KK_) hipLaunchKernelGGL((epic::auto_grad_kernel<PP, KK_>), gg, dim3(256), 0, \
+                                              x->stream, ga);
+  EPIC_AG(1, 1) EPIC_AG(1, 3) EPIC_AG(1, 5) EPIC_AG(1, 7)
+  EPIC_AG(2, 1) EPIC_AG(2, 3) EPIC_AG(2, 5) EPIC_AG(2, 7)
+#undef EPIC_AG
 }
 
 // The float32 paths: fused kernels, or the staged comparator.
@@ -898,6 +920,12 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.W = a.W;
     r.reset = reset ? 1 : 0;
     r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
+    r.autos = nullptr;
+    r.K = x->cfg.kernel_support;
+    if (x->autos) {
+      launch_auto_table(x, efield, n_time, gains);
+      r.autos = x->au_tab.as<double>();
+    }
     launch_reduce(x, r, true);
   } else {
     const int npix = N * N;
@@ -954,6 +982,12 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.W = 1;
     r.reset = reset ? 1 : 0;
     r.sub = 1;
+    r.autos = nullptr;
+    r.K = x->cfg.kernel_support;
+    if (x->autos) {
+      launch_auto_table(x, efield, n_time, gains);
+      r.autos = x->au_tab.as<double>();
+    }
     launch_reduce(x, r, false);
   }
   return EPIC_OK;
@@ -1053,6 +1087,7 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     x->au_nseg_cap = (int)std::max<size_t>(1, std::min<size_t>(epic::AUTO_MAX_SEG, (256u << 20) / per_seg));
     if (!x->au_part.alloc(x->au_nseg_cap * per_seg) ||
         !x->au_tab.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
+        !x->au_sums.alloc((size_t)cfg->n_chan * cfg->n_ant * NQ * sizeof(double)) ||
         !x->au_hat.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
         !x->au_gauto.alloc((size_t)cfg->n_chan * x->PA * 2 * sizeof(double))) {
       g_init_error = "autocorrelation workspace allocation failed";
@@ -1216,7 +1251,11 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
                             ? run_split(x, efield, n_time, gains, image, reset)
                             : run_fp32(x, efield, n_time, gains, image, reset);
   if (s != EPIC_OK) return s;
-  if (x->autos) launch_autos(x, efield, n_time, gains, image);
+  // the N <= 64 reductions subtract the table themselves; the others need a pass
+  if (x->autos && (x->cfg.precision != EPIC_FP32 || (x->fused && x->cfg.grid_n == 128))) {
+    launch_auto_table(x, efield, n_time, gains);
+    launch_auto_remove(x, image);
+  }
   x->autos_timed = x->autos && x->timing;
   if (x->timing) {
     (void)hipEventRecord(x->ev[2], x->stream);
@@ -1337,7 +1376,7 @@ void epic_destroy(epic_ctx* x) {
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
     x->sp_partial.reset();
-    x->au_part.reset(); x->au_tab.reset(); x->au_w.reset(); x->au_hat.reset();
+    x->au_part.reset(); x->au_tab.reset(); x->au_sums.reset(); x->au_w.reset(); x->au_hat.reset();
     x->au_gauto.reset();
   }
   delete x;

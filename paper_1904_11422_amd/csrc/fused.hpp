@@ -26,6 +26,7 @@
 // sums into its own float64 partial-image slot; a second kernel adds the slots
 // of each channel in workgroup order.
 #pragma once
+#include "autos.hpp"
 #include "dft.hpp"
 #include "reduce.hpp"
 
@@ -432,6 +433,9 @@ struct ReduceArgs {
   int64_t n_time, total;
   int n_chan, W, reset;
   int sub;                  // 1, 4 or 16 sub-lanes per pixel
+  const double* autos;      // table of the antenna autocorrelations to subtract
+                            // ([C][(2K-1)^2][NACC], autos.hpp), or null
+  int K;
 };
 
 // Workgroup whose range contains flat index f: the largest w with
@@ -456,6 +460,8 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int NPIX = N * N;
   __shared__ double red[NACC * 256];
+  __shared__ double ast[AUTO_MAX_D2][NACC];
+  __shared__ double acs[128];
   const int ppb = 256 / a.sub;
   const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
   const int64_t idx = (int64_t)blockIdx.x * ppb + lp;
@@ -475,6 +481,8 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
       for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NPIX];
     }
   }
+  // a workgroup's pixels lie in one channel (N^2 is a multiple of 256 / sub)
+  if (a.autos) stage_autos<NACC>(a.autos, (int)((int64_t)blockIdx.x * ppb / NPIX), N, a.K, ast, acs);
   combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
   if (!valid || j != 0) return;
   int km, kl;
@@ -497,6 +505,18 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
     val[3 % NPROD] = make_double2(s[1 % NACC], 0.0);           // YY
   } else {
     val[0] = make_double2(s[0], 0.0);
+  }
+  if (a.autos) {
+    double v[NACC];
+    autos_at<NACC>(ast, acs, N, a.K, km, kl, v);
+    val[0].x -= v[0];
+    if (P == 2) {
+      val[3 % NPROD].x -= v[1 % NACC];
+      val[1 % NPROD].x -= v[2 % NACC];
+      val[1 % NPROD].y -= v[3 % NACC];
+      val[2 % NPROD].x -= v[2 % NACC];
+      val[2 % NPROD].y += v[3 % NACC];
+    }
   }
 #pragma unroll
   for (int pr = 0; pr < NPROD; ++pr) {
