@@ -9,4 +9,5 @@ from .moff import (C0, OffGridError, unpack_ci4, antenna_cells, kernel_taps,  # 
                    image_from, aperture_response, visibilities, image_fx, grad_gains,
                    l2_loss, l2_loss_grad_image, fd_grad, fd_directional, model_image,
                    rel_errors, auto_visibilities, autocorrelation_image, image_without_autos,
-                   image_without_autos_from, grad_autos, grad_gains_without_autos)
+                   image_without_autos_from, grad_autos, grad_gains_without_autos,
+                   decimate_transpose)

@@ -45,6 +45,20 @@ class OffGridError(ValueError):
     """A kernel tap of some antenna falls outside the grid for some channel."""
 
 
+# ------------------------------------------------------------ front end (§3.2)
+def decimate_transpose(raw: np.ndarray, n_chan: int, c0: int = 0, c_step: int = 1) -> np.ndarray:
+    """The front end before imaging (§3.2): channelised bytes arriving as
+    [Time, Channel, Antenna, Polarisation] are decimated in frequency (output
+    channel i is input channel c0 + i * c_step) and transposed to
+    [Time, Channel, Polarisation, Antenna].  Bytes are moved, never changed."""
+    raw = np.asarray(raw)
+    T, c_in, A, P = raw.shape
+    if c0 < 0 or c_step < 1 or n_chan < 1 or c0 + (n_chan - 1) * c_step >= c_in:
+        raise ValueError("channel selection outside the input")
+    sel = raw[:, c0:c0 + (n_chan - 1) * c_step + 1:c_step]           # [T, C, A, P]
+    return np.ascontiguousarray(np.transpose(sel, (0, 1, 3, 2)))
+
+
 # --------------------------------------------------------------------- O1
 def unpack_ci4(b: np.ndarray) -> np.ndarray:
     """4+4-bit complex integers -> complex128 (§3.2: "4+4-bit complex integer").

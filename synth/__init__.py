@@ -77,6 +77,12 @@ def random_bytes(rng: np.random.Generator, shape) -> np.ndarray:
     return rng.integers(0, 256, size=shape, dtype=np.uint8)
 
 
+def raw_gulp(seed: int, n_time: int, c_in: int, n_ant: int, n_pol: int) -> np.ndarray:
+    """Random 4+4-bit bytes in the order they arrive from the channeliser,
+    [Time, Channel, Antenna, Polarisation] (no imaging arithmetic: just bytes)."""
+    return random_bytes(np.random.default_rng(seed), (n_time, c_in, n_ant, n_pol))
+
+
 # ---------------------------------------------------------------- layouts
 def square_layout(rng: np.random.Generator, n_ant: int, side_m: float) -> np.ndarray:
     return rng.uniform(-side_m / 2, side_m / 2, size=(n_ant, 2))

@@ -12,6 +12,7 @@ _products = moff.products
 _kernel_taps = moff.kernel_taps
 _grad = moff.grad_gains
 _auto_vis = moff.auto_visibilities
+_front = moff.decimate_transpose
 
 
 def _wrong_sign(a):
@@ -81,6 +82,16 @@ def _grad_autos_variant(conj_sxy=True, two=2.0):
     return fn
 
 
+def _front_pol_antenna_swapped(raw, n_chan, c0=0, c_step=1):
+    out = _front(raw, n_chan, c0, c_step)
+    return np.ascontiguousarray(out.reshape(out.shape[0], out.shape[1], out.shape[3], out.shape[2])
+                                .transpose(0, 1, 3, 2)) if out.shape[2] != out.shape[3] else out
+
+
+def _front_step_ignored(raw, n_chan, c0=0, c_step=1):
+    return _front(raw, n_chan, c0, 1)
+
+
 def _auto_vis_swapped(gains, efield):
     v = _auto_vis(gains, efield)
     if v.shape[1] == 4:
@@ -110,6 +121,12 @@ MUTATIONS = {
         "grad_autos", _grad_autos_variant(conj_sxy=False),
         [pins.test_p14_gradient_without_autos_cross_products_only,
          lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(2)]),
+    "front end reading [A, P] as [P, A]": (
+        "decimate_transpose", _front_pol_antenna_swapped,
+        [lambda: pins.test_p15_decimate_transpose_by_loops(0, 1, 5, 2)]),
+    "front end ignoring the channel step": (
+        "decimate_transpose", _front_step_ignored,
+        [lambda: pins.test_p15_decimate_transpose_by_loops(1, 2, 3, 1)]),
     "autocorrelation gradient without the factor 2": (
         "grad_autos", _grad_autos_variant(two=1.0),
         [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),

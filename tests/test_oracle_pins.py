@@ -459,3 +459,44 @@ def test_p14_homogeneity_without_autos():
     lhs = np.sum(np.conj(g) * grad).real
     rhs = 2.0 * np.sum((np.conj(gam) * img).real)
     assert abs(lhs - rhs) / abs(rhs) < 1e-12
+
+
+# ------------------------------------------------------- P15: front end (§3.2)
+@pytest.mark.parametrize("c0,c_step,n_chan", [(0, 1, 5), (2, 1, 3), (1, 2, 3), (4, 3, 1), (0, 5, 2)])
+@pytest.mark.parametrize("P", [1, 2])
+def test_p15_decimate_transpose_by_loops(c0, c_step, n_chan, P):
+    """Decimation and transposition against explicit loops over every byte."""
+    raw = synth.raw_gulp(7, 3, 9, 5, P)
+    got = oracle.decimate_transpose(raw, n_chan, c0, c_step)
+    T, c_in, A, _ = raw.shape
+    assert got.shape == (T, n_chan, P, A)
+    for t in range(T):
+        for i in range(n_chan):
+            for p in range(P):
+                for a in range(A):
+                    assert got[t, i, p, a] == raw[t, c0 + i * c_step, a, p]
+
+
+def test_p15_front_end_rejects_selections_outside_the_input():
+    raw = synth.raw_gulp(8, 2, 6, 3, 2)
+    for c0, c_step, n in [(-1, 1, 2), (0, 0, 2), (5, 1, 2), (0, 3, 3), (0, 1, 0)]:
+        with pytest.raises(ValueError):
+            oracle.decimate_transpose(raw, n, c0, c_step)
+
+
+def test_p15_front_end_then_image_equals_image_of_the_selected_data():
+    """The image of a decimated, transposed gulp equals the image of the same
+    channels' data given directly in [T, C, P, A] order (built here by loops)."""
+    inp = synth.random_problem(151, 32, 12, 3, 2, 4)
+    c_in, c0, step = 8, 1, 3
+    raw = synth.raw_gulp(152, 4, c_in, 12, 2)
+    direct = np.empty((4, 3, 2, 12), np.uint8)
+    for t in range(4):
+        for i in range(3):
+            for p in range(2):
+                for a in range(12):
+                    direct[t, i, p, a] = raw[t, c0 + i * step, a, p]
+    ef = oracle.decimate_transpose(raw, 3, c0, step)
+    a = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, ef, 32)
+    b = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, direct, 32)
+    assert np.array_equal(a, b)
