@@ -295,6 +295,68 @@ def bench_autos(args) -> int:
     return 0
 
 
+def bench_stream(args) -> int:
+    """Streaming ingest: gulps of the LWA-like workload arriving as 264 channels
+    [T][C][A][P] in pinned host memory, the central 132 channels selected (a
+    contiguous sub-band, so only it crosses the host link), transposed and
+    imaged, the copy of each gulp overlapping the imaging of the one before."""
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager, Pipeline
+    print("bench: generating two raw gulps", file=sys.stderr, flush=True)
+    inp = synth.config2()
+    N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
+    c_in, c0 = 2 * C, C // 2
+    gulps = [torch.from_numpy(synth.raw_gulp(9000 + k, T, c_in, A, P)).pin_memory() for k in range(2)]
+    g = torch.from_numpy(inp.gains).cuda()
+    im = Imager(N, C, P, A)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
+    # the front end alone, timed with events around back-to-back launches
+    dev_raw = gulps[0].cuda()
+    ef = im.frontend(dev_raw, c0, 1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        im.frontend(dev_raw, c0, 1, out=ef)
+    e1.record()
+    torch.cuda.synchronize()
+    fe_ms = e0.elapsed_time(e1) / reps
+    fe_bytes = 2 * T * C * P * A
+    del dev_raw
+    pipe = Pipeline(im, T, c_in, c0, 1, sample_s=40e-6)
+    for k in range(args.warmup):
+        pipe.push(gulps[k % 2], g, img)
+    pipe.report()
+    pipe.close()
+    pipe = Pipeline(im, T, c_in, c0, 1, sample_s=40e-6)
+    print("bench: streaming", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pipe.push(gulps[k % 2], g, img)
+    st = pipe.report()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {"metric": "streamed channel-images/s (host gulps -> images)", "value": C / dt,
+           "unit": "channel-images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "LWA-like gulps: 264 channels arriving [T][C][A][P] in pinned "
+                                  "host memory, central 132 imaged (64x64, 256 dual-pol antennas), "
+                                  "1000 samples (40 ms) per gulp",
+                      "grid_n": N, "n_chan": C, "c_in": c_in, "n_pol": P, "n_ant": A, "n_time": T},
+           "pipeline": st,
+           "realtime_factor": st["gulp_ms"] / st["mean_ms"],
+           "host_copy_GBps": T * C * P * A / (st["mean_copy_ms"] * 1e-3) / 1e9,
+           "roofline": {"bound": "hbm", "kernel": "frontend_kernel",
+                        "achieved": fe_bytes / (fe_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                        "unit": "GB/s", "frac": fe_bytes / (fe_ms * 1e-3) / PEAK_HBM,
+                        "traffic": None, "kernel_ms": fe_ms, "bytes_per_launch": fe_bytes}}
+    print(json.dumps(out))
+    pipe.close()
+    return 0
+
+
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 PROFILE = os.path.join(PROFILES, "fused_image_kernel_lwa64_c132_t1000.md")
 PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
@@ -343,6 +405,9 @@ def main() -> int:
                     help="measure forward + gain-gradient evaluations on the calibration workload")
     ap.add_argument("--autos", action="store_true",
                     help="measure the default workload with the antenna autocorrelations removed")
+    ap.add_argument("--stream", action="store_true",
+                    help="measure the double-buffered streaming ingest (host gulps in arrival "
+                         "order, decimated, transposed and imaged)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (five times), to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -362,6 +427,8 @@ def main() -> int:
         return bench_grad(args)
     if args.autos:
         return bench_autos(args)
+    if args.stream:
+        return bench_stream(args)
 
     import torch
     import synth

@@ -189,6 +189,74 @@ epic_status epic_last_autos_timing(epic_ctx *ctx, float *sum_kernel_ms, float *r
 const char *epic_last_kernel_name(const epic_ctx *ctx);
 
 /* ------------------------------------------------------------------------
+ * Front end and streaming ingest (Sec. 3.2 and Fig. 2: the channelised
+ * samples are decimated in frequency, then transposed from [Time, Channel,
+ * Antenna, Polarisation] to [Time, Channel, Polarisation, Antenna]; Sec. 5.1:
+ * a gulp must be processed within about 90 % of the time it spans).
+ * ------------------------------------------------------------------------ */
+
+/* Decimate and transpose one gulp on the context's stream (bytes moved, not
+ * changed):
+ *   raw:    device uint8 [n_time][c_in][n_ant][n_pol], as it arrives;
+ *   efield: device uint8 [n_time][n_chan][n_pol][n_ant] (the layout of
+ *           epic_image_accumulate), overwritten;
+ *   output channel i = input channel c0 + i * c_step, i < n_chan (the
+ *   context's channel count).
+ * Allocates nothing.  Errors: EPIC_E_INVALID (null pointer, n_time <= 0, a
+ * selected channel outside [0, c_in)), EPIC_E_LAUNCH. */
+epic_status epic_frontend(epic_ctx *ctx, const uint8_t *raw, int64_t n_time, int32_t c_in,
+                          int32_t c0, int32_t c_step, uint8_t *efield);
+
+typedef struct epic_pipeline epic_pipeline;
+
+/* Statistics of the gulps a pipeline has completed (all times in ms). */
+typedef struct epic_pipeline_stats {
+  int64_t gulps;            /* gulps completed and measured */
+  int64_t over_budget;      /* gulps whose processing time exceeded 0.9 * gulp_ms */
+  double gulp_ms;           /* time one gulp spans: n_time * sample_s */
+  double mean_ms, max_ms;   /* processing time per gulp: from the later of its copy
+                               start and the previous gulp's end, to its end */
+  double mean_copy_ms;      /* host-to-device copy of one gulp */
+  double mean_compute_ms;   /* front end + imaging of one gulp (incl. waiting for
+                               the previous gulp) */
+} epic_pipeline_stats;
+
+/* Create a double-buffered ingest for ctx: gulps of n_time samples with c_in
+ * channels in arrival order, channels c0 + i * c_step imaged (i < n_chan).
+ * Allocates two device gulp buffers and one transposed buffer, a copy stream
+ * (default priority) and events; sample_s is the duration of one sample in
+ * seconds (40e-6 for 25 kHz channels).  With c_step == 1 only the selected
+ * sub-band is copied from the host.  The pipeline uses ctx (its stream,
+ * tables, flags): destroy the pipeline before the context.
+ * Errors: EPIC_E_INVALID (null, n_time <= 0, sample_s not positive, a channel
+ * outside [0, c_in)), EPIC_E_NOMEM, EPIC_E_DEVICE; *out is NULL on error and
+ * epic_pipeline_last_error(NULL) says why. */
+epic_status epic_pipeline_create(epic_ctx *ctx, int64_t n_time, int32_t c_in, int32_t c0,
+                                 int32_t c_step, double sample_s, epic_pipeline **out);
+
+/* Enqueue one gulp and return: the copy of host_raw (host uint8
+ * [n_time][c_in][n_ant][n_pol]; pinned memory, e.g. from hipHostMalloc, lets
+ * the copy overlap the imaging of the previous gulp) starts once the buffer it
+ * fills is free, then the front end and epic_image_accumulate(gains, image,
+ * reset) run on the context's stream.  host_raw must stay valid and unchanged
+ * until the gulp's copy has finished (at the latest when epic_pipeline_report
+ * or epic_pipeline_destroy returns).  After kRing = 64 gulps a push waits for
+ * the gulp 63 places earlier to finish (bounded run-ahead).
+ * Errors: EPIC_E_INVALID, EPIC_E_STATE (no antennas), EPIC_E_UNSUPPORTED /
+ * EPIC_E_LAUNCH from the imaging call, EPIC_E_DEVICE. */
+epic_status epic_pipeline_push(epic_pipeline *p, const uint8_t *host_raw, const float *gains,
+                               double *image, int32_t reset);
+
+/* Wait for every pushed gulp and report the statistics. */
+epic_status epic_pipeline_report(epic_pipeline *p, epic_pipeline_stats *out);
+
+/* Wait for the pipeline's work and free it (not the context). */
+void epic_pipeline_destroy(epic_pipeline *p);
+
+/* Message of the last failed call on p (NULL: of the last failed create). */
+const char *epic_pipeline_last_error(const epic_pipeline *p);
+
+/* ------------------------------------------------------------------------
  * Heterogeneous batch: n_blocks independent configurations (different grid
  * sizes, antenna and channel counts) imaged together.  Every block gets its
  * own context and stream; a batch call forks from hip_stream to the block

@@ -108,6 +108,26 @@ class Imager:
         _lib.check(self.L, self._ctx, st)
         return image
 
+    def frontend(self, raw, c0: int = 0, c_step: int = 1, out=None):
+        """Decimate and transpose a gulp in arrival order, uint8 [T, c_in, A, P]
+        on the GPU, into the imaging layout [T, C, P, A] (channel i = c0 + i c_step)."""
+        torch = _torch()
+        if raw.dtype != torch.uint8 or raw.dim() != 4 or \
+                tuple(raw.shape[2:]) != (self.n_ant, self.n_pol) or not raw.is_cuda:
+            raise ValueError(f"raw must be a CUDA uint8 tensor [T, c_in, {self.n_ant}, {self.n_pol}]")
+        raw = raw.contiguous()
+        shape = (raw.shape[0], self.n_chan, self.n_pol, self.n_ant)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.uint8, device=raw.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.uint8 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous uint8 tensor {shape}")
+        self._bind_stream()
+        st = self.L.epic_frontend(self._ctx, ctypes.c_void_p(raw.data_ptr()), int(raw.shape[0]),
+                                  int(raw.shape[1]), int(c0), int(c_step),
+                                  ctypes.c_void_p(out.data_ptr()))
+        _lib.check(self.L, self._ctx, st)
+        return out
+
     def backward(self, efield, gains, grad_image):
         """d loss / d gains (dL/dRe + i dL/dIm, complex64 [C, P, A])."""
         torch = _torch()
@@ -147,6 +167,66 @@ class Imager:
         if getattr(self, "_ctx", None):
             self.L.epic_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """Double-buffered streaming of gulps from pinned host memory into an
+    Imager: copy of gulp i overlaps the front end and imaging of gulp i - 1."""
+
+    def __init__(self, imager: Imager, n_time: int, c_in: int, c0: int = 0, c_step: int = 1,
+                 sample_s: float = 40e-6):
+        self.imager, self.L = imager, imager.L
+        self.n_time, self.c_in = int(n_time), int(c_in)
+        imager._bind_stream()
+        p = ctypes.c_void_p()
+        st = self.L.epic_pipeline_create(imager._ctx, self.n_time, self.c_in, int(c0), int(c_step),
+                                         float(sample_s), ctypes.byref(p))
+        _lib.check_pipeline(self.L, None, st)
+        self._p = p
+        self._held = []          # host gulps whose copies may still be pending
+
+    def push(self, host_raw, gains, image, reset: bool = True):
+        """host_raw: CPU uint8 [n_time, c_in, A, P] (pinned for overlap); gains and
+        image on the GPU as for Imager.accumulate."""
+        torch = _torch()
+        im = self.imager
+        if host_raw.dtype != torch.uint8 or host_raw.is_cuda or not host_raw.is_contiguous() or \
+                tuple(host_raw.shape) != (self.n_time, self.c_in, im.n_ant, im.n_pol):
+            raise ValueError("host_raw must be a contiguous CPU uint8 tensor "
+                             f"[{self.n_time}, {self.c_in}, {im.n_ant}, {im.n_pol}]")
+        if gains.dtype != torch.complex64 or tuple(gains.shape) != (im.n_chan, im.n_pol, im.n_ant) \
+                or not gains.is_cuda:
+            raise ValueError("gains must be a CUDA complex64 tensor [C, P, A]")
+        if image.dtype != torch.complex128 or tuple(image.shape) != im.image_shape() or \
+                not image.is_contiguous() or not image.is_cuda:
+            raise ValueError(f"image must be a contiguous CUDA complex128 tensor {im.image_shape()}")
+        gains = gains.contiguous()
+        self._held.append((host_raw, gains))
+        if len(self._held) > 2 * 64:
+            self._held = self._held[-64:]        # the library waits for older gulps
+        st = self.L.epic_pipeline_push(self._p, ctypes.c_void_p(host_raw.data_ptr()),
+                                       ctypes.c_void_p(gains.data_ptr()),
+                                       ctypes.c_void_p(image.data_ptr()), 1 if reset else 0)
+        _lib.check_pipeline(self.L, self._p, st)
+
+    def report(self) -> dict:
+        """Wait for every pushed gulp; statistics (ms) and the real-time check."""
+        s = _lib.PipelineStats()
+        _lib.check_pipeline(self.L, self._p, self.L.epic_pipeline_report(self._p, ctypes.byref(s)))
+        self._held = []
+        return {k: getattr(s, k) for k, _ in _lib.PipelineStats._fields_}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            self.L.epic_pipeline_destroy(self._p)
+            self._p = None
+            self._held = []
 
     def __del__(self):
         try:

@@ -24,7 +24,9 @@ EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_gridding_p
            "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
            "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
            "epic_batch_serial", "epic_batch_set_serial",
-           "epic_batch_destroy", "epic_batch_last_error")
+           "epic_batch_destroy", "epic_batch_last_error",
+           "epic_frontend", "epic_pipeline_create", "epic_pipeline_push", "epic_pipeline_report",
+           "epic_pipeline_destroy", "epic_pipeline_last_error")
 
 
 class EpicConfig(ctypes.Structure):
@@ -33,6 +35,13 @@ class EpicConfig(ctypes.Structure):
                 ("kernel_support", ctypes.c_int32), ("kernel_sigma_cells", ctypes.c_double),
                 ("cell_wavelengths", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_int32)]
+
+
+class PipelineStats(ctypes.Structure):
+    _fields_ = [("gulps", ctypes.c_int64), ("over_budget", ctypes.c_int64),
+                ("gulp_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("mean_copy_ms", ctypes.c_double),
+                ("mean_compute_ms", ctypes.c_double)]
 
 
 class EpicError(RuntimeError):
@@ -100,6 +109,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_batch_destroy.restype = None
     L.epic_batch_last_error.argtypes = [vp]
     L.epic_batch_last_error.restype = ctypes.c_char_p
+    L.epic_frontend.argtypes = [vp, vp, i64, i32, i32, i32, vp]
+    L.epic_frontend.restype = ctypes.c_int
+    L.epic_pipeline_create.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.POINTER(vp)]
+    L.epic_pipeline_create.restype = ctypes.c_int
+    L.epic_pipeline_push.argtypes = [vp, vp, vp, vp, i32]
+    L.epic_pipeline_push.restype = ctypes.c_int
+    L.epic_pipeline_report.argtypes = [vp, ctypes.POINTER(PipelineStats)]
+    L.epic_pipeline_report.restype = ctypes.c_int
+    L.epic_pipeline_destroy.argtypes = [vp]
+    L.epic_pipeline_destroy.restype = None
+    L.epic_pipeline_last_error.argtypes = [vp]
+    L.epic_pipeline_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -107,6 +128,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
 def check(L, ctx, status: int):
     if status != EPIC_OK:
         msg = L.epic_last_error(ctx)
+        raise EpicError(status, msg.decode() if msg else "")
+
+
+def check_pipeline(L, p, status: int):
+    if status != EPIC_OK:
+        msg = L.epic_pipeline_last_error(p)
         raise EpicError(status, msg.decode() if msg else "")
 
 

@@ -21,6 +21,7 @@
 #include "split.hpp"
 #include "fused128.hpp"
 #include "autos.hpp"
+#include "frontend.hpp"
 
 namespace {
 
@@ -1389,3 +1390,4 @@ const char* epic_last_error(const epic_ctx* x) {
 }  // extern "C"
 
 #include "batch.hpp"
+#include "pipeline.hpp"
