@@ -92,13 +92,18 @@ def antenna_cells(xy_m: np.ndarray, freq_hz: np.ndarray, grid_n: int,
 
 
 def kernel_taps(X: np.ndarray, Y: np.ndarray, grid_n: int, support: int = 3,
-                sigma_cells: float = 0.5):
+                sigma_cells: float = 0.5, kernels=None):
     """Cells and weights of the illumination kernel W around each antenna
-    (§2.1 Eq. (4): E = W * E').  Returns ii, jj (int) and w (float64), each of
-    shape [C, A, K*K], tap order (dj outer, di inner)."""
+    (§2.1 Eq. (4): E = W * E').  Returns ii, jj (int) and w, each of shape
+    [C, A, K*K], tap order (dj outer, di inner).
+
+    kernels None: w = the Gaussian of width sigma_cells at each tap's offset
+    (float64).  Otherwise kernels [C, A, K, K] (complex) gives each channel's
+    and antenna's own kernel on the same K x K cells (§3.3: any kernel per
+    antenna, e.g. its illumination pattern for A-projection); w = kernels."""
     if support < 1 or support % 2 == 0:
         raise ValueError("kernel support must be odd and positive")
-    if not sigma_cells > 0:
+    if kernels is None and not sigma_cells > 0:
         raise ValueError("kernel width must be positive")
     h = support // 2
     i0 = np.floor(X + 0.5).astype(np.int64)
@@ -109,8 +114,14 @@ def kernel_taps(X: np.ndarray, Y: np.ndarray, grid_n: int, support: int = 3,
     dj = dj.reshape(-1)
     ii = i0[..., None] + di
     jj = j0[..., None] + dj
-    w = np.exp(-((ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2)
-               / (2.0 * sigma_cells ** 2))
+    if kernels is None:
+        w = np.exp(-((ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2)
+                   / (2.0 * sigma_cells ** 2))
+    else:
+        kern = np.asarray(kernels)
+        if kern.shape != X.shape + (support, support):
+            raise ValueError(f"kernels must be [C, A, {support}, {support}]")
+        w = kern.astype(np.complex128).reshape(X.shape + (support * support,))
     if ii.min() < 0 or jj.min() < 0 or ii.max() >= grid_n or jj.max() >= grid_n:
         raise OffGridError("a kernel tap falls outside the grid")
     return ii, jj, w
@@ -173,7 +184,7 @@ def n_products(n_pol: int) -> int:
 
 # ------------------------------------------------------------ O1..O8 chained
 def image(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
-          kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128) -> np.ndarray:
+          kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128, kernels=None) -> np.ndarray:
     """Accumulated polarised images, complex128 [C, n_prod, N, N], fftshifted.
 
     gains [C, P, A] complex (promoted exactly to complex128);
@@ -181,7 +192,7 @@ def image(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
     efield = np.asarray(efield)
     T, C, P, Aant = efield.shape
     X, Y = antenna_cells(xy_m, freq_hz, grid_n, cell_wavelengths)
-    ii, jj, w = kernel_taps(X, Y, grid_n, kernel_support, kernel_sigma_cells)
+    ii, jj, w = kernel_taps(X, Y, grid_n, kernel_support, kernel_sigma_cells, kernels)
     g = np.asarray(gains).astype(np.complex128)
     out = np.zeros((C, n_products(P), grid_n, grid_n), dtype=np.complex128)
     for c in range(C):
@@ -199,17 +210,18 @@ def image(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
 
 def image_from(inp, **kw) -> np.ndarray:
     """image() on a synth.Inputs-like object (anything with the same fields)."""
+    kw.setdefault("kernels", getattr(inp, "kernels", None))
     return image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, inp.grid_n,
                  inp.kernel_support, inp.kernel_sigma_cells, inp.cell_wavelengths, **kw)
 
 
 # --------------------------------------------------------------- FX form (P5)
 def aperture_response(xy_m, freq_hz, grid_n, kernel_support=3, kernel_sigma_cells=0.5,
-                      cell_wavelengths=0.5) -> np.ndarray:
+                      cell_wavelengths=0.5, kernels=None) -> np.ndarray:
     """b[c, a, km, kl] = sum_taps w e^{+2 pi i (i kl + j km)/N}: the transform of
     one antenna's kernel footprint (unshifted pixel order)."""
     X, Y = antenna_cells(xy_m, freq_hz, grid_n, cell_wavelengths)
-    ii, jj, w = kernel_taps(X, Y, grid_n, kernel_support, kernel_sigma_cells)
+    ii, jj, w = kernel_taps(X, Y, grid_n, kernel_support, kernel_sigma_cells, kernels)
     N = grid_n
     k = np.arange(N)
     C, Aant, KK = w.shape
@@ -233,11 +245,11 @@ def visibilities(gains, efield) -> np.ndarray:
 
 
 def image_fx(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
-             kernel_sigma_cells=0.5, cell_wavelengths=0.5, vis=None) -> np.ndarray:
+             kernel_sigma_cells=0.5, cell_wavelengths=0.5, vis=None, kernels=None) -> np.ndarray:
     """The same accumulated image from visibilities (the FX route, §2 Eq. (1)-(2)):
     I_PQ(k) = sum_{a,b} V_PQ[a,b] b_a(k) conj(b_b(k)).  No gridding, no FFT."""
     b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
-                          cell_wavelengths)                           # [C, A, N, N]
+                          cell_wavelengths, kernels)                  # [C, A, N, N]
     V = visibilities(gains, efield) if vis is None else vis          # [C, n, A, A]
     C = b.shape[0]
     N = grid_n
@@ -259,49 +271,51 @@ def auto_visibilities(gains, efield) -> np.ndarray:
 
 
 def autocorrelation_image(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
-                          kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+                          kernel_sigma_cells=0.5, cell_wavelengths=0.5, kernels=None) -> np.ndarray:
     """The zero-spacing part of the accumulated image that §3.2 optionally
     removes: the a = b terms sum_a V_PQ[a, a] |b_a(k)|^2 of the visibility form
     (fftshifted, like the image)."""
     b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
-                          cell_wavelengths)                           # [C, A, N, N]
+                          cell_wavelengths, kernels)                  # [C, A, N, N]
     vd = auto_visibilities(gains, efield)                            # [C, n, A]
     out = np.einsum("cka,cayx->ckyx", vd, np.abs(b) ** 2)
     return np.fft.fftshift(out, axes=(-2, -1))
 
 
 def image_without_autos(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
-                        kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+                        kernel_sigma_cells=0.5, cell_wavelengths=0.5, kernels=None) -> np.ndarray:
     """The accumulated image with the antenna autocorrelations removed (§3.2):
     image minus autocorrelation_image."""
     full = image(xy_m, freq_hz, gains, efield, grid_n, kernel_support, kernel_sigma_cells,
-                 cell_wavelengths)
+                 cell_wavelengths, kernels=kernels)
     return full - autocorrelation_image(xy_m, freq_hz, gains, efield, grid_n, kernel_support,
-                                        kernel_sigma_cells, cell_wavelengths)
+                                        kernel_sigma_cells, cell_wavelengths, kernels)
 
 
 def image_without_autos_from(inp) -> np.ndarray:
     return image_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, inp.grid_n,
-                               inp.kernel_support, inp.kernel_sigma_cells, inp.cell_wavelengths)
+                               inp.kernel_support, inp.kernel_sigma_cells, inp.cell_wavelengths,
+                               getattr(inp, "kernels", None))
 
 
 # ------------------------------------------------------------- O9 gradient
 def grad_gains(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
-               kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128) -> np.ndarray:
+               kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128, kernels=None) -> np.ndarray:
     """d(loss)/d(gain) in the PyTorch complex convention (dL/dRe + i dL/dIm),
     given grad_image = dL/dRe(I) + i dL/dIm(I) in the image layout.
 
-    Wirtinger chain (F = Phi A with Phi the +i DFT; A linear in g with real w):
+    Wirtinger chain (F = Phi A with Phi the +i DFT; A = sum w e' is holomorphic
+    in g, so the kernel enters conjugated):
       dL/dF_X* = Re(G_XX) F_X + h F_Y,  dL/dF_Y* = Re(G_YY) F_Y + conj(h) F_X,
       h = (G_XY + conj(G_YX)) / 2;  dL/dA* = Phi^H dL/dF*  (the -i transform);
-      dL/dg*[c,p,a] = sum_t sum_taps w conj(e[t,c,p,a]) (dL/dA*)[tap];
+      dL/dg*[c,p,a] = sum_t sum_taps conj(w) conj(e[t,c,p,a]) (dL/dA*)[tap];
       returned gradient = 2 dL/dg*.
     The imaginary parts of G_XX, G_YY are ignored: those products are real."""
     efield = np.asarray(efield)
     T, C, P, Aant = efield.shape
     N = grid_n
     X, Y = antenna_cells(xy_m, freq_hz, N, cell_wavelengths)
-    ii, jj, w = kernel_taps(X, Y, N, kernel_support, kernel_sigma_cells)
+    ii, jj, w = kernel_taps(X, Y, N, kernel_support, kernel_sigma_cells, kernels)
     g = np.asarray(gains).astype(np.complex128)
     Gam = np.fft.ifftshift(np.asarray(grad_image).astype(np.complex128), axes=(-2, -1))
     out = np.zeros((C, P, Aant), dtype=np.complex128)
@@ -321,12 +335,12 @@ def grad_gains(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=
                 G = np.stack([gx, gy], axis=1)
             H = np.fft.fft2(G, axes=(-2, -1))                          # Phi^H, unnormalised
             Htap = H[:, :, jj[c], ii[c]]                                # [t, P, A, K*K]
-            out[c] += np.einsum("ak,tpak,tpa->pa", w[c], Htap, np.conj(e))
+            out[c] += np.einsum("ak,tpak,tpa->pa", np.conj(w[c]), Htap, np.conj(e))
     return 2.0 * out
 
 
 def grad_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
-               kernel_sigma_cells=0.5, cell_wavelengths=0.5) -> np.ndarray:
+               kernel_sigma_cells=0.5, cell_wavelengths=0.5, kernels=None) -> np.ndarray:
     """The share of autocorrelation_image in the gain gradient: d/dg of
     Re <grad_image, autocorrelation_image>, in the convention of grad_gains.
 
@@ -337,7 +351,7 @@ def grad_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=
                                     ->  H conj(s_XY) g_Y  to X,  conj(H) s_XY g_X  to Y
     (the imaginary parts of Gamma_XX, Gamma_YY are ignored, as in grad_gains)."""
     b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
-                          cell_wavelengths)
+                          cell_wavelengths, kernels)
     B = np.abs(b) ** 2                                                # [C, A, N, N]
     Gam = np.fft.ifftshift(np.asarray(grad_image).astype(np.complex128), axes=(-2, -1))
     e = unpack_ci4(efield)                                            # [T, C, P, A]
@@ -359,11 +373,11 @@ def grad_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=
 
 def grad_gains_without_autos(xy_m, freq_hz, gains, efield, grid_n, grad_image,
                              kernel_support=3, kernel_sigma_cells=0.5,
-                             cell_wavelengths=0.5) -> np.ndarray:
+                             cell_wavelengths=0.5, kernels=None) -> np.ndarray:
     """Gain gradient of a loss of image_without_autos: grad_gains minus grad_autos."""
     args = (xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support,
             kernel_sigma_cells, cell_wavelengths)
-    return grad_gains(*args) - grad_autos(*args)
+    return grad_gains(*args, kernels=kernels) - grad_autos(*args, kernels=kernels)
 
 
 # ------------------------------------------------------------- losses, FD

@@ -49,6 +49,7 @@ class Inputs:
     efield: np.ndarray          # uint8 [T, C, P, A]
     sources: Optional[dict] = None
     name: str = ""
+    kernels: Optional[np.ndarray] = None   # complex64 [C, A, K, K] user kernels, or None
 
     @property
     def n_time(self) -> int:
@@ -75,6 +76,31 @@ def pack_ci4(re: np.ndarray, im: np.ndarray) -> np.ndarray:
 def random_bytes(rng: np.random.Generator, shape) -> np.ndarray:
     """Uniformly random ci4 bytes (every nibble value equally likely)."""
     return rng.integers(0, 256, size=shape, dtype=np.uint8)
+
+
+def complex_kernels(seed: int, n_chan: int, n_ant: int, support: int,
+                    width_cells: float = 1.5) -> np.ndarray:
+    """Seeded complex gridding kernels [C, A, K, K] (complex64) with the shape of
+    per-antenna illumination patterns: a smooth envelope of the given width in
+    cells, a per-antenna amplitude in [0.7, 1.3], and a per-(channel, antenna)
+    phase offset and linear phase gradient across the footprint."""
+    rng = np.random.default_rng(seed)
+    h = support // 2
+    d = np.arange(-h, h + 1, dtype=np.float64)
+    env = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * width_cells ** 2))   # [dj, di]
+    amp = rng.uniform(0.7, 1.3, size=(1, n_ant, 1, 1))
+    ph0 = rng.uniform(0, 2 * np.pi, size=(n_chan, n_ant, 1, 1))
+    gj = rng.uniform(-0.6, 0.6, size=(n_chan, n_ant, 1, 1))
+    gi = rng.uniform(-0.6, 0.6, size=(n_chan, n_ant, 1, 1))
+    phase = ph0 + gj * d[None, None, :, None] + gi * d[None, None, None, :]
+    return (amp * env[None, None] * np.exp(1j * phase)).astype(np.complex64)
+
+
+def with_kernels(inp: "Inputs", support: int, seed: int, width_cells: float = 1.5) -> "Inputs":
+    """The same problem gridded with seeded complex kernels of the given support."""
+    k = complex_kernels(seed, inp.n_chan, inp.n_ant, support, width_cells)
+    return dataclasses.replace(inp, kernel_support=support, kernels=k,
+                               name=f"{inp.name}_k{support}c")
 
 
 def raw_gulp(seed: int, n_time: int, c_in: int, n_ant: int, n_pol: int) -> np.ndarray:

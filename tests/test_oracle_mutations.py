@@ -35,13 +35,13 @@ def _xy_without_conj(F):
     return out
 
 
-def _sigma_not_squared(X, Y, grid_n, support=3, sigma_cells=0.5):
+def _sigma_not_squared(X, Y, grid_n, support=3, sigma_cells=0.5, kernels=None):
     ii, jj, w = _kernel_taps(X, Y, grid_n, support, sigma_cells)
     d2 = (ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2
     return ii, jj, np.exp(-d2 / (2.0 * sigma_cells))
 
 
-def _taps_rounded_down(X, Y, grid_n, support=3, sigma_cells=0.5):
+def _taps_rounded_down(X, Y, grid_n, support=3, sigma_cells=0.5, kernels=None):
     """Nearest cell taken as floor(X) instead of floor(X + 1/2)."""
     ii, jj, _ = _kernel_taps(X - 0.5, Y - 0.5, grid_n, support, sigma_cells)
     d2 = (ii - X[..., None]) ** 2 + (jj - Y[..., None]) ** 2
@@ -53,9 +53,9 @@ def _grad_half(*a, **k):
 
 
 def _autos_not_squared(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
-                       kernel_sigma_cells=0.5, cell_wavelengths=0.5):
+                       kernel_sigma_cells=0.5, cell_wavelengths=0.5, kernels=None):
     b = moff.aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
-                               cell_wavelengths)
+                               cell_wavelengths, kernels)
     out = np.einsum("cka,cayx->ckyx", moff.auto_visibilities(gains, efield), np.abs(b))
     return np.fft.fftshift(out, axes=(-2, -1))
 
@@ -63,9 +63,9 @@ def _autos_not_squared(xy_m, freq_hz, gains, efield, grid_n, kernel_support=3,
 def _grad_autos_variant(conj_sxy=True, two=2.0):
     """grad_autos with one planted slip (the cross term's conjugate, the factor 2)."""
     def fn(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
-           kernel_sigma_cells=0.5, cell_wavelengths=0.5):
+           kernel_sigma_cells=0.5, cell_wavelengths=0.5, kernels=None):
         B = np.abs(moff.aperture_response(xy_m, freq_hz, grid_n, kernel_support,
-                                          kernel_sigma_cells, cell_wavelengths)) ** 2
+                                          kernel_sigma_cells, cell_wavelengths, kernels)) ** 2
         gam = np.fft.ifftshift(np.asarray(grad_image).astype(complex), axes=(-2, -1))
         e = moff.unpack_ci4(efield)
         g = np.asarray(gains).astype(complex)
@@ -90,6 +90,38 @@ def _front_pol_antenna_swapped(raw, n_chan, c0=0, c_step=1):
 
 def _front_step_ignored(raw, n_chan, c0=0, c_step=1):
     return _front(raw, n_chan, c0, 1)
+
+
+def _kernels_conjugated(X, Y, grid_n, support=3, sigma_cells=0.5, kernels=None):
+    ii, jj, w = _kernel_taps(X, Y, grid_n, support, sigma_cells, kernels)
+    return ii, jj, np.conj(w)
+
+
+def _grad_kernel_unconjugated(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support=3,
+                              kernel_sigma_cells=0.5, cell_wavelengths=0.5, chunk=128,
+                              kernels=None):
+    if kernels is None:
+        return _grad(xy_m, freq_hz, gains, efield, grid_n, grad_image, kernel_support,
+                     kernel_sigma_cells, cell_wavelengths, chunk, kernels)
+    X, Y = moff.antenna_cells(xy_m, freq_hz, grid_n, cell_wavelengths)
+    ii, jj, w = _kernel_taps(X, Y, grid_n, kernel_support, kernel_sigma_cells, kernels)
+    # recompute with the kernel left unconjugated in the degridding
+    e_all = moff.unpack_ci4(np.asarray(efield))
+    gg = np.asarray(gains).astype(complex)
+    Gam = np.fft.ifftshift(np.asarray(grad_image).astype(complex), axes=(-2, -1))
+    out = np.zeros(gg.shape, complex)
+    for c in range(gg.shape[0]):
+        e = e_all[:, c]
+        F = moff.transform(moff.grid_efield(gg[c][None] * e, ii[c], jj[c], w[c], grid_n))
+        if gg.shape[1] == 1:
+            G = (Gam[c, 0].real * F[:, 0])[:, None]
+        else:
+            h = 0.5 * (Gam[c, 1] + np.conj(Gam[c, 2]))
+            G = np.stack([Gam[c, 0].real * F[:, 0] + h * F[:, 1],
+                          Gam[c, 3].real * F[:, 1] + np.conj(h) * F[:, 0]], axis=1)
+        H = np.fft.fft2(G, axes=(-2, -1))
+        out[c] = np.einsum("ak,tpak,tpa->pa", w[c], H[:, :, jj[c], ii[c]], np.conj(e))
+    return 2.0 * out
 
 
 def _auto_vis_swapped(gains, efield):
@@ -127,6 +159,11 @@ MUTATIONS = {
     "front end ignoring the channel step": (
         "decimate_transpose", _front_step_ignored,
         [lambda: pins.test_p15_decimate_transpose_by_loops(1, 2, 3, 1)]),
+    "user kernels conjugated in the gridding": (
+        "kernel_taps", _kernels_conjugated, [pins.test_p16_kernel_phase_moves_into_the_gain]),
+    "gradient degridding with the kernel unconjugated": (
+        "grad_gains", _grad_kernel_unconjugated,
+        [lambda: pins.test_p16_gradient_with_complex_kernels_matches_finite_differences(2)]),
     "autocorrelation gradient without the factor 2": (
         "grad_autos", _grad_autos_variant(two=1.0),
         [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),

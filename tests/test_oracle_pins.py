@@ -500,3 +500,77 @@ def test_p15_front_end_then_image_equals_image_of_the_selected_data():
     a = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, ef, 32)
     b = oracle.image(inp.xy_m, inp.freq_hz, inp.gains, direct, 32)
     assert np.array_equal(a, b)
+
+
+# ------------------------------------------- P16: user (complex) kernels (§3.3)
+def _kinp(seed, K, A=9, C=2, P=2, T=3, N=32, fill=0.3):
+    return synth.with_kernels(synth.random_problem(seed, N, A, C, P, T, fill=fill), K, seed + 1)
+
+
+@pytest.mark.parametrize("K", [3, 5, 9])
+def test_p16_fx_form_with_complex_kernels(K):
+    """The visibility form with each antenna's own complex kernel equals the
+    MOFF image gridded with those kernels (§2.1 Eq. (1) <-> Eq. (5))."""
+    inp = _kinp(160 + K, K)
+    a = oracle.image_from(inp)
+    b = oracle.image_fx(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, K, 0.5, 0.5,
+                        kernels=inp.kernels)
+    assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
+
+
+def test_p16_kernel_phase_moves_into_the_gain():
+    """A kernel multiplies the calibrated sample like a gain does: a unit phase
+    per antenna taken off the gains and put on the kernels leaves every product
+    unchanged (catches a conjugated kernel in the gridding)."""
+    inp = _kinp(170, 5)
+    phase = np.exp(1j * np.random.default_rng(171).uniform(0, 2 * np.pi, size=(2, 1, 9)))
+    g2 = inp.gains.astype(complex) * phase
+    k2 = inp.kernels.astype(complex) * np.conj(phase[:, 0, :, None, None])
+    a = oracle.image_from(inp)
+    b = oracle.image(inp.xy_m, inp.freq_hz, g2, inp.efield, 32, 5, 0.5, 0.5, kernels=k2)
+    assert np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(a))
+
+
+def test_p16_single_antenna_closed_form_complex_kernel():
+    """One antenna: XX(k) = sum_t |g e_t|^2 |sum_taps w e^{+2 pi i (i kl + j km)/N}|^2,
+    the kernel's own transform evaluated here by a direct sum over its taps."""
+    inp = _kinp(180, 7, A=1, C=1, P=1, T=5)
+    N, K, h = 32, 7, 3
+    got = np.fft.ifftshift(oracle.image_from(inp)[0, 0], axes=(-2, -1)).real
+    X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
+    i0, j0 = int(np.floor(X[0, 0] + 0.5)), int(np.floor(Y[0, 0] + 0.5))
+    k = np.arange(N)
+    b = np.zeros((N, N), complex)
+    for dj in range(-h, h + 1):
+        for di in range(-h, h + 1):
+            w = complex(inp.kernels[0, 0, dj + h, di + h])
+            b += w * np.exp(2j * np.pi * ((j0 + dj) * k[:, None] + (i0 + di) * k[None, :]) / N)
+    e = oracle.unpack_ci4(inp.efield[:, 0, 0, 0])
+    power = np.sum(np.abs(complex(inp.gains[0, 0, 0]) * e) ** 2)
+    assert np.max(np.abs(got - power * np.abs(b) ** 2)) <= 1e-11 * np.max(got)
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_p16_gradient_with_complex_kernels_matches_finite_differences(P):
+    inp = _kinp(190 + P, 5, A=6, P=P)
+    rng = _rng(192)
+    model = rng.normal(size=oracle.image_from(inp).shape) * 50.0
+    g = inp.gains.astype(np.complex128)
+
+    def loss(gg):
+        return oracle.l2_loss(oracle.image(inp.xy_m, inp.freq_hz, gg, inp.efield, 32, 5,
+                                           kernels=inp.kernels), model)
+    img = oracle.image(inp.xy_m, inp.freq_hz, g, inp.efield, 32, 5, kernels=inp.kernels)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam, 5,
+                             kernels=inp.kernels)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(loss, g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+def test_p16_kernels_shape_checked():
+    inp = _kinp(195, 3)
+    with pytest.raises(ValueError):
+        oracle.image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, 5, kernels=inp.kernels)
