@@ -79,7 +79,7 @@ typedef struct epic_config {
   int32_t n_chan;              /* C >= 1 */
   int32_t n_pol;               /* P: 1 or 2 */
   int32_t n_ant;               /* A: 1 .. 4096 */
-  int32_t kernel_support;      /* K: odd, 1 .. 7 */
+  int32_t kernel_support;      /* K: odd, 1 .. 15 (EPIC_FLAG_REMOVE_AUTOS: 1 .. 7) */
   double kernel_sigma_cells;   /* Gaussian kernel width in cells, > 0 */
   double cell_wavelengths;     /* grid spacing in wavelengths, > 0 (0.5 = lambda/2) */
   int32_t precision;           /* EPIC_FP32, EPIC_SPLIT_FP16 or EPIC_SPLIT_BF16 */
@@ -109,6 +109,19 @@ epic_status epic_set_stream(epic_ctx *ctx, void *hip_stream);
  * previous geometry, if any, stays in force), EPIC_E_NOMEM. */
 epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *freq_hz);
 
+/* epic_set_antennas with the caller's own gridding kernels in place of the
+ * Gaussian (Sec. 3.3: the gridding convolution takes any kernel per antenna,
+ * e.g. its illumination pattern for A-projection).  kernels: host complex64
+ * [n_chan][n_ant][K][K] (K = kernel_support, up to 15; row dj outer, column
+ * di inner), the weight of antenna a at cell (i0 + di - K/2, j0 + dj - K/2)
+ * of channel c, where (i0, j0) is the cell nearest to the antenna (as for
+ * the Gaussian).  Copied; kernels == NULL is epic_set_antennas.  Works on
+ * every path (fused, staged, split) and in epic_image_backward.
+ * Errors: as epic_set_antennas; EPIC_E_INVALID (a non-finite kernel value),
+ * EPIC_E_UNSUPPORTED (context created with EPIC_FLAG_REMOVE_AUTOS). */
+epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const double *freq_hz,
+                                      const float *kernels);
+
 /* Host-side view of the gridding programs the fused kernels run for a
  * configuration and geometry (Sec. 2.1 Eq. (4): the kernel taps of every
  * antenna, gathered per grid cell).  No device work: usable without a GPU, for
@@ -118,8 +131,8 @@ epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *f
  *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
  *                    (int32 -1: none); word 1: 0;
  *     rows 1..L:     steps {LDS byte offset of the cell, relative to the grid
- *                    base, << 15 | LDS byte offset of E'[p = 0][a], float32
- *                    weight bits with the sign bit set on a cell's last entry}.
+ *                    base, << 15 | LDS byte offset of E'[p = 0][a] (a multiple
+ *                    of 8), bit 0 set on a cell's last entry; float32 weight}.
  * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
  * layout: out, int32 [7] = {NT, L, row stride, polarisation stride, grid base,
  * E' polarisation stride, row order}, strides and base in float2 units; row

@@ -50,6 +50,7 @@ class Imager:
                                    _PRECISIONS[precision], flags)
         self.grid_n, self.n_chan, self.n_pol, self.n_ant = grid_n, n_chan, n_pol, n_ant
         self.remove_autos = remove_autos
+        self.kernel_support = kernel_support
         self.n_prod = 4 if n_pol == 2 else 1
         ctx = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -59,13 +60,23 @@ class Imager:
         self._ctx = ctx
 
     # ------------------------------------------------------------------ setup
-    def set_antennas(self, xy_m, freq_hz) -> None:
+    def set_antennas(self, xy_m, freq_hz, kernels=None) -> None:
+        """Geometry (metres, Hz); kernels: optional complex [C, A, K, K] gridding
+        kernels per channel and antenna in place of the Gaussian."""
         xy = np.ascontiguousarray(np.asarray(xy_m, dtype=np.float64))
         f = np.ascontiguousarray(np.asarray(freq_hz, dtype=np.float64))
         if xy.shape != (self.n_ant, 2) or f.shape != (self.n_chan,):
             raise ValueError(f"expected xy_m [{self.n_ant}, 2] and freq_hz [{self.n_chan}]")
         dp = ctypes.POINTER(ctypes.c_double)
-        st = self.L.epic_set_antennas(self._ctx, xy.ctypes.data_as(dp), f.ctypes.data_as(dp))
+        if kernels is None:
+            st = self.L.epic_set_antennas(self._ctx, xy.ctypes.data_as(dp), f.ctypes.data_as(dp))
+        else:
+            K = self.kernel_support
+            k = np.ascontiguousarray(np.asarray(kernels, dtype=np.complex64))
+            if k.shape != (self.n_chan, self.n_ant, K, K):
+                raise ValueError(f"kernels must be [{self.n_chan}, {self.n_ant}, {K}, {K}]")
+            st = self.L.epic_set_antennas_kernels(self._ctx, xy.ctypes.data_as(dp),
+                                                  f.ctypes.data_as(dp), ctypes.c_void_p(k.ctypes.data))
         _lib.check(self.L, self._ctx, st)
 
     def _bind_stream(self):

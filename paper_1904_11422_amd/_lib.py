@@ -16,7 +16,8 @@ EPIC_FP32, EPIC_SPLIT_FP16, EPIC_SPLIT_BF16 = 0, 1, 2
 EPIC_FLAG_STAGED, EPIC_FLAG_TIMING, EPIC_FLAG_REMOVE_AUTOS = 1, 2, 4
 
 # Every function declared in include/epic.h, with its ctypes signature.
-EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_gridding_program",
+EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_set_antennas_kernels",
+           "epic_gridding_program",
            "epic_image_accumulate",
            "epic_image_backward", "epic_last_timing", "epic_last_autos_timing",
            "epic_last_kernel_name",
@@ -68,6 +69,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_set_stream.restype = ctypes.c_int
     L.epic_set_antennas.argtypes = [vp, dp, dp]
     L.epic_set_antennas.restype = ctypes.c_int
+    L.epic_set_antennas_kernels.argtypes = [vp, dp, dp, vp]
+    L.epic_set_antennas_kernels.restype = ctypes.c_int
     L.epic_gridding_program.argtypes = [ctypes.POINTER(EpicConfig), dp, dp,
                                         ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(i64),
                                         ctypes.POINTER(i32)]

@@ -6,7 +6,7 @@
 //   G_X      = Re(Gxx) F_X + h F_Y,   G_Y = Re(Gyy) F_Y + conj(h) F_X,
 //              h = (Gxy + conj(Gyx)) / 2          (dL/dF_p*, Wirtinger calculus)
 //   H_p      = adjoint transform of G_p (negative exponent), columns then rows
-//   dL/dg*   += sum_taps w * conj(e[t,c,p,a]) * H_p[tap]
+//   dL/dg*   += sum_taps conj(w) * conj(e[t,c,p,a]) * H_p[tap]
 // The per-antenna sums are float64, one slot per (workgroup, channel); a
 // second kernel adds the slots in workgroup order and returns 2 dL/dg*, i.e.
 // dL/dRe(g) + i dL/dIm(g).
@@ -20,6 +20,8 @@ struct AdjointArgs {
   const float2* gains;      // [C][P][A]
   const float4* gtab;       // [C][S][NT]: {Re Gxx, Re Gyy, Re h, Im h} at owned pixels
   const uint2* prog;        // gridding programs and row-pass lines, as the imager
+  const float* wim;         // imaginary step weights (complex kernels), or null
+  const float* tapim;       // [C][A][KK] imaginary tap weights (complex kernels), or null
   const uint2* taps;        // [C][A][KK] {physical translated cell j*N+i, w bits}
   const float2* twiddle;
   double2* gpartial;        // [W + C - 1][P*A]
@@ -63,7 +65,7 @@ __global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
   a.gtab[idx] = t;
 }
 
-template <int N, int P, int GPT>
+template <int N, int P, int GPT, bool CPX>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 adjoint_kernel(AdjointArgs a) {
@@ -98,6 +100,7 @@ adjoint_kernel(AdjointArgs a) {
   uint32_t nxt[GPT];
   int c = -1, line = -1;
   const uint2* prog = nullptr;
+  const float* wim = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
     const uint8_t* src = a.efield + tt * row_bytes + (int64_t)cc * PA;
@@ -124,6 +127,7 @@ adjoint_kernel(AdjointArgs a) {
       if (c >= 0) flush();
       c = cc;
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
+      if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
       prog += NT;
 #pragma unroll
@@ -140,7 +144,7 @@ adjoint_kernel(AdjointArgs a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
     row_pass<N, P, +1>(X, r, tw, line);
     __syncthreads();
     float2 v[P][S];
@@ -181,15 +185,21 @@ adjoint_kernel(AdjointArgs a) {
       const int k = tid + i * NT;
       if (k < PA) {
         const int p = k / a.n_ant, ant = k - p * a.n_ant;
-        const uint2* tp = a.taps + ((int64_t)c * a.n_ant + ant) * a.kk;
+        const int64_t tbase = ((int64_t)c * a.n_ant + ant) * a.kk;
+        const uint2* tp = a.taps + tbase;
         float2 s = make_float2(0.f, 0.f);
-        for (int q = 0; q < a.kk; ++q) {
+        for (int q = 0; q < a.kk; ++q) {       // sum_taps conj(w) h
           const uint2 t = tp[q];
           const int cell = (int)t.x;
           const float w = __uint_as_float(t.y);
           const float2 h = X[p * PS + (cell / N) * RS + cell % N];
           s.x = fmaf(w, h.x, s.x);
           s.y = fmaf(w, h.y, s.y);
+          if (CPX) {
+            const float wi = a.tapim[tbase + q];
+            s.x = fmaf(wi, h.y, s.x);
+            s.y = fmaf(-wi, h.x, s.y);
+          }
         }
         const float2 e = unpack_ci4(cur[i]);
         const float2 d = cmulc(s, e);           // s * conj(e)

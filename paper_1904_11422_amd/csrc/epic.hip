@@ -55,7 +55,8 @@ struct Geometry {
   int C = 0, A = 0, KK = 0;
   std::vector<int> cell;              // [C][A][KK] j*N + i on the centred grid
   std::vector<int> tcell;             // [C][A][KK] the same taps translated to start at (0, 0)
-  std::vector<float> w;               // [C][A][KK]
+  std::vector<float> w;               // [C][A][KK] (real parts for complex kernels)
+  std::vector<float> wi;              // [C][A][KK] imaginary parts, empty for real kernels
   bool fits_half = true;              // every channel's taps fit an N/2 x N/2 block
 };
 
@@ -94,7 +95,10 @@ struct epic_ctx {
   bool have_geom = false;
   int L = 0;
   DevMem prog, twiddle, taps;
-  DevMem csr_off, csr_ent;
+  DevMem prog_im, taps_im;            // imaginary weights of programs and taps (complex kernels)
+  bool cpx = false;                   // the geometry carries complex kernels
+  int fused_w_cpx = 0, adj_w_cpx = 0; // persistent grids of the complex-kernel variants
+  DevMem csr_off, csr_ent, csr_im;
   int nnz = 0;
 
   // workspace
@@ -139,8 +143,8 @@ epic_status check_config(const epic_config* c, std::string& m) {
   if (c->n_pol != 1 && c->n_pol != 2) { m = "n_pol must be 1 or 2"; return EPIC_E_INVALID; }
   if (c->n_chan < 1 || c->n_chan > 65536) { m = "n_chan out of range"; return EPIC_E_INVALID; }
   if (c->n_ant < 1 || c->n_ant > 4096) { m = "n_ant must be in 1..4096"; return EPIC_E_INVALID; }
-  if (c->kernel_support < 1 || c->kernel_support > 7 || c->kernel_support % 2 == 0) {
-    m = "kernel_support must be odd and in 1..7"; return EPIC_E_INVALID;
+  if (c->kernel_support < 1 || c->kernel_support > 15 || c->kernel_support % 2 == 0) {
+    m = "kernel_support must be odd and in 1..15"; return EPIC_E_INVALID;
   }
   if (!(c->kernel_sigma_cells > 0) || !std::isfinite(c->kernel_sigma_cells)) {
     m = "kernel_sigma_cells must be finite and positive"; return EPIC_E_INVALID;
@@ -175,10 +179,12 @@ epic_status check_split(const epic_config* c, std::string& m) {
   return EPIC_OK;
 }
 
-// Kernel taps of every antenna for every channel (float64), with the grid
-// bounds check.  Tap order: dj outer, di inner.
+// Kernel taps of every antenna for every channel, with the grid bounds check.
+// Tap order: dj outer, di inner.  kernels == NULL: the Gaussian evaluated in
+// float64 at each tap's offset, rounded once; else the caller's complex
+// kernels [C][A][K][K] (interleaved float32 re, im) on the same cells.
 epic_status build_geometry(const epic_config& cfg, const double* xy, const double* freq,
-                           Geometry& g, std::string& m) {
+                           const float* kernels, Geometry& g, std::string& m) {
   const int N = cfg.grid_n, C = cfg.n_chan, A = cfg.n_ant, K = cfg.kernel_support;
   const int h = K / 2;
   g.C = C; g.A = A; g.KK = K * K;
@@ -194,6 +200,11 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
     }
   const double inv2s2 = 1.0 / (2.0 * cfg.kernel_sigma_cells * cfg.kernel_sigma_cells);
   g.tcell.assign((size_t)C * A * K * K, 0);
+  if (kernels) {
+    g.wi.assign((size_t)C * A * K * K, 0.f);
+    for (size_t o = 0; o < 2 * (size_t)C * A * K * K; ++o)
+      if (!std::isfinite(kernels[o])) { m = "kernel value is not finite"; return EPIC_E_INVALID; }
+  }
   g.fits_half = true;
   for (int c = 0; c < C; ++c) {
     const double cell_m = kC0 / freq[c] * cfg.cell_wavelengths;
@@ -213,10 +224,14 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
       for (int dj = -h; dj <= h; ++dj)
         for (int di = -h; di <= h; ++di, ++k) {
           const double i = i0 + di, j = j0 + dj;
-          const double wt = std::exp(-((i - X) * (i - X) + (j - Y) * (j - Y)) * inv2s2);
           const size_t o = ((size_t)c * A + a) * g.KK + k;
           g.cell[o] = (int)j * N + (int)i;
-          g.w[o] = (float)wt;
+          if (kernels) {
+            g.w[o] = kernels[2 * o];
+            g.wi[o] = kernels[2 * o + 1];
+          } else {
+            g.w[o] = (float)std::exp(-((i - X) * (i - X) + (j - Y) * (j - Y)) * inv2s2);
+          }
           jmin = std::min(jmin, (int)j);
           jmax = std::max(jmax, (int)j);
           imin = std::min(imin, (int)i);
@@ -249,7 +264,8 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 //    A .. A+15) on the least used bank and write zero; padding steps add zero
 //    and write nothing.
 template <int N>
-void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L) {
+void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L,
+                    std::vector<float>* out_im = nullptr) {
   constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
   constexpr int CPW = epic::FusedShape<N>::CPW, NWAVE = NT / 64;
   const int C = g.C, A = g.A, KK = g.KK;
@@ -273,27 +289,31 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     static const int rho[4] = {0, 4, 1, 5};
     return rho[sl] + 2 * t;
   };
-  auto code = [](int cell_f2, int e) {
-    return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8);
+  auto code = [](int cell_f2, int e, bool last) {
+    return ((uint32_t)(cell_f2 * 8) << epic::STEP_CELL_SHIFT) | (uint32_t)(e * 8) |
+           (last ? epic::STEP_LAST_BIT : 0u);
   };
   // the fields of a step word: cell byte offsets (the aperture rows of one
   // polarisation) below 2^17, E' byte offsets (both polarisations) below 2^15
   static_assert(H * SH::RS * 8 <= (1 << (32 - epic::STEP_CELL_SHIFT)), "cell offsets exceed the step field");
-  if ((int64_t)P * ES * 8 > (int64_t)epic::STEP_E_MASK + 1) {   // not reached by the shapes the kernels take
+  if ((int64_t)P * ES * 8 > (int64_t)epic::STEP_E_MASK + 8) {   // not reached by the shapes the kernels take
     out.clear();
     L = 0;
     return;
   }
-  auto wbits = [](float w, bool last) {
+  auto wbits = [](float w) {
     uint32_t b;
     std::memcpy(&b, &w, 4);
-    return last ? (b | epic::STEP_LAST_BIT) : b;
+    return b;
   };
+  const bool cpx = !g.wi.empty() && out_im;
+  constexpr size_t kNoTap = ~(size_t)0;
   struct Run {
     int cell;
-    std::vector<std::pair<int, float>> ent;            // (antenna, weight)
+    std::vector<std::pair<int, size_t>> ent;           // (antenna, tap index)
   };
   std::vector<std::vector<uint32_t>> words((size_t)C * NT);   // [c][thread] -> step words
+  std::vector<std::vector<float>> wims(cpx ? (size_t)C * NT : 0);
   std::vector<int32_t> header((size_t)C * NT, -1);
   L = 1;
   for (int c = 0; c < C; ++c) {
@@ -304,7 +324,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-        cells[j * H + i].ent.push_back({a, g.w[o]});
+        cells[j * H + i].ent.push_back({a, o});
       }
     // rows to (wave, slot): slot s of a wave in group t takes a row j with
     // j mod M = residue(s, t); each residue class has exactly as many rows as
@@ -364,14 +384,14 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     for (int q = 0; q < NT / 16; ++q) {
       struct Lane {
         size_t run = 0;
-        std::vector<std::pair<int, float>> left;       // entries of the current run not yet taken
+        std::vector<std::pair<int, size_t>> left;      // entries of the current run not yet taken
         bool started = false;
       };
       Lane st[16];
       for (int step = 0; step < Lc; ++step) {
         int used[16] = {0};
         int pick_e[16], pick_cell[16];
-        float pick_w[16];
+        size_t pick_w[16];                             // tap index, or kNoTap
         bool pick_last[16];
         bool decided[16] = {false};
         for (int l = 0; l < 16; ++l) {                 // open the current run
@@ -416,7 +436,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
             if (used[(A + k) % 16] < used[(A + z) % 16]) z = k;
           used[(A + z) % 16]++;
           pick_e[l] = A + z;
-          pick_w[l] = 0.f;
+          pick_w[l] = kNoTap;
           const Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
           pick_last[l] = s.run < runs.size();          // empty cell: write zero; padding: no write
@@ -425,8 +445,9 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
         }
         for (int l = 0; l < 16; ++l) {
           auto& wv = words[(size_t)c * NT + 16 * q + l];
-          wv.push_back(code(pick_cell[l], pick_e[l]));
-          wv.push_back(wbits(pick_w[l], pick_last[l]));
+          wv.push_back(code(pick_cell[l], pick_e[l], pick_last[l]));
+          wv.push_back(wbits(pick_w[l] == kNoTap ? 0.f : g.w[pick_w[l]]));
+          if (cpx) wims[(size_t)c * NT + 16 * q + l].push_back(pick_w[l] == kNoTap ? 0.f : g.wi[pick_w[l]]);
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
           if (s.run < runs.size()) {
@@ -446,21 +467,23 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   }
   if (L > epic::kMaxFixedSteps) L = (L + epic::kStepChunk - 1) / epic::kStepChunk * epic::kStepChunk;
   out.assign((size_t)C * (L + 1) * NT * 2, 0u);
+  if (cpx) out_im->assign((size_t)C * (L + 1) * NT, 0.f);
   for (int c = 0; c < C; ++c)
     for (int t = 0; t < NT; ++t) {
       const size_t h = ((size_t)c * (L + 1) * NT + t) * 2;
       out[h] = (uint32_t)header[(size_t)c * NT + t];
       out[h + 1] = 0u;
       const auto& wv = words[(size_t)c * NT + t];
-      const uint32_t pad = code(0, A + t % 16);
+      const uint32_t pad = code(0, A + t % 16, false);
       for (int s2 = 0; s2 < L; ++s2) {
         const size_t o = (((size_t)c * (L + 1) + 1 + s2) * NT + t) * 2;
         if ((size_t)s2 < wv.size() / 2) {
           out[o] = wv[2 * s2];
           out[o + 1] = wv[2 * s2 + 1];
+          if (cpx) (*out_im)[o / 2] = wims[(size_t)c * NT + t][s2];
         } else {
           out[o] = pad;
-          out[o + 1] = wbits(0.f, false);
+          out[o + 1] = wbits(0.f);
         }
       }
     }
@@ -474,18 +497,22 @@ int occupancy_blocks(F kernel, int threads) {
 }
 
 template <int N, int P, int GPT>
-int fused_blocks_per_cu() {
-  return occupancy_blocks(epic::fused_image_kernel<N, P, GPT>, epic::FusedShape<N>::NT);
+int fused_blocks_per_cu(bool cpx) {
+  return cpx ? occupancy_blocks(epic::fused_image_kernel<N, P, GPT, true>, epic::FusedShape<N>::NT)
+             : occupancy_blocks(epic::fused_image_kernel<N, P, GPT, false>, epic::FusedShape<N>::NT);
 }
 
-int fused_blocks_per_cu(int N, int P, int gpt) {
+int fused_blocks_per_cu(int N, int P, int gpt, bool cpx) {
   if (N == 128) {
     const int NT = epic::FusedShape<128>::NT;
-    if (gpt == 1) return occupancy_blocks(epic::fused_image128_kernel<1>, NT);
-    if (gpt == 2) return occupancy_blocks(epic::fused_image128_kernel<2>, NT);
-    return occupancy_blocks(epic::fused_image128_kernel<4>, NT);
+    if (gpt == 1) return cpx ? occupancy_blocks(epic::fused_image128_kernel<1, true>, NT)
+                             : occupancy_blocks(epic::fused_image128_kernel<1, false>, NT);
+    if (gpt == 2) return cpx ? occupancy_blocks(epic::fused_image128_kernel<2, true>, NT)
+                             : occupancy_blocks(epic::fused_image128_kernel<2, false>, NT);
+    return cpx ? occupancy_blocks(epic::fused_image128_kernel<4, true>, NT)
+               : occupancy_blocks(epic::fused_image128_kernel<4, false>, NT);
   }
-#define EPIC_OCC(NN, PP, GG) if (N == NN && P == PP && gpt == GG) return fused_blocks_per_cu<NN, PP, GG>();
+#define EPIC_OCC(NN, PP, GG) if (N == NN && P == PP && gpt == GG) return fused_blocks_per_cu<NN, PP, GG>(cpx);
   EPIC_OCC(32, 1, 1) EPIC_OCC(32, 1, 2) EPIC_OCC(32, 1, 4)
   EPIC_OCC(32, 2, 1) EPIC_OCC(32, 2, 2) EPIC_OCC(32, 2, 4)
   EPIC_OCC(64, 1, 1) EPIC_OCC(64, 1, 2) EPIC_OCC(64, 1, 4)
@@ -494,16 +521,20 @@ int fused_blocks_per_cu(int N, int P, int gpt) {
   return 1;
 }
 
-template <int N, int P>
+template <int N, int P, bool CPX>
 int adjoint_blocks_per_cu(int gpt) {
-  if (gpt == 1) return occupancy_blocks(epic::adjoint_kernel<N, P, 1>, epic::FusedShape<N>::NT);
-  if (gpt == 2) return occupancy_blocks(epic::adjoint_kernel<N, P, 2>, epic::FusedShape<N>::NT);
-  return occupancy_blocks(epic::adjoint_kernel<N, P, 4>, epic::FusedShape<N>::NT);
+  if (gpt == 1) return occupancy_blocks(epic::adjoint_kernel<N, P, 1, CPX>, epic::FusedShape<N>::NT);
+  if (gpt == 2) return occupancy_blocks(epic::adjoint_kernel<N, P, 2, CPX>, epic::FusedShape<N>::NT);
+  return occupancy_blocks(epic::adjoint_kernel<N, P, 4, CPX>, epic::FusedShape<N>::NT);
 }
 
-int adjoint_blocks_per_cu(int N, int P, int gpt) {
-  if (N == 32) return P == 1 ? adjoint_blocks_per_cu<32, 1>(gpt) : adjoint_blocks_per_cu<32, 2>(gpt);
-  return P == 1 ? adjoint_blocks_per_cu<64, 1>(gpt) : adjoint_blocks_per_cu<64, 2>(gpt);
+int adjoint_blocks_per_cu(int N, int P, int gpt, bool cpx) {
+  if (cpx) {
+    if (N == 32) return P == 1 ? adjoint_blocks_per_cu<32, 1, true>(gpt) : adjoint_blocks_per_cu<32, 2, true>(gpt);
+    return P == 1 ? adjoint_blocks_per_cu<64, 1, true>(gpt) : adjoint_blocks_per_cu<64, 2, true>(gpt);
+  }
+  if (N == 32) return P == 1 ? adjoint_blocks_per_cu<32, 1, false>(gpt) : adjoint_blocks_per_cu<32, 2, false>(gpt);
+  return P == 1 ? adjoint_blocks_per_cu<64, 1, false>(gpt) : adjoint_blocks_per_cu<64, 2, false>(gpt);
 }
 
 int fused_threads(int N) {
@@ -513,10 +544,13 @@ int fused_threads(int N) {
 bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
   const dim3 grid(a.W), block(fused_threads(N));
-#define EPIC_LF(NN, PP, GG)                                                          \
-  if (N == NN && P == PP && G == GG) {                                               \
-    hipLaunchKernelGGL((epic::fused_image_kernel<NN, PP, GG>), grid, block, 0, x->stream, a); \
-    return true;                                                                     \
+#define EPIC_LF(NN, PP, GG)                                                                 \
+  if (N == NN && P == PP && G == GG) {                                                      \
+    if (x->cpx) hipLaunchKernelGGL((epic::fused_image_kernel<NN, PP, GG, true>), grid, block, 0, \
+                                   x->stream, a);                                           \
+    else hipLaunchKernelGGL((epic::fused_image_kernel<NN, PP, GG, false>), grid, block, 0,   \
+                            x->stream, a);                                                  \
+    return true;                                                                            \
   }
   EPIC_LF(32, 1, 1) EPIC_LF(32, 1, 2) EPIC_LF(32, 1, 4)
   EPIC_LF(32, 2, 1) EPIC_LF(32, 2, 2) EPIC_LF(32, 2, 4)
@@ -528,10 +562,18 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
 
 bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
   const dim3 grid(a.W), block(epic::FusedShape<128>::NT);
+  if (x->cpx) {
+    switch (x->fused_gpt) {
+      case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<1, true>), grid, block, 0, x->stream, a); return true;
+      case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<2, true>), grid, block, 0, x->stream, a); return true;
+      case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<4, true>), grid, block, 0, x->stream, a); return true;
+      default: return false;
+    }
+  }
   switch (x->fused_gpt) {
-    case 1: hipLaunchKernelGGL(epic::fused_image128_kernel<1>, grid, block, 0, x->stream, a); return true;
-    case 2: hipLaunchKernelGGL(epic::fused_image128_kernel<2>, grid, block, 0, x->stream, a); return true;
-    case 4: hipLaunchKernelGGL(epic::fused_image128_kernel<4>, grid, block, 0, x->stream, a); return true;
+    case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<1, false>), grid, block, 0, x->stream, a); return true;
+    case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<2, false>), grid, block, 0, x->stream, a); return true;
+    case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<4, false>), grid, block, 0, x->stream, a); return true;
     default: return false;
   }
 }
@@ -568,10 +610,13 @@ bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {
 bool launch_adjoint(epic_ctx* x, const epic::AdjointArgs& a) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
   const dim3 grid(a.W), block(fused_threads(N));
-#define EPIC_LA(NN, PP, GG)                                                          \
-  if (N == NN && P == PP && G == GG) {                                               \
-    hipLaunchKernelGGL((epic::adjoint_kernel<NN, PP, GG>), grid, block, 0, x->stream, a); \
-    return true;                                                                     \
+#define EPIC_LA(NN, PP, GG)                                                                  \
+  if (N == NN && P == PP && G == GG) {                                                       \
+    if (x->cpx) hipLaunchKernelGGL((epic::adjoint_kernel<NN, PP, GG, true>), grid, block, 0,  \
+                                   x->stream, a);                                            \
+    else hipLaunchKernelGGL((epic::adjoint_kernel<NN, PP, GG, false>), grid, block, 0,        \
+                            x->stream, a);                                                   \
+    return true;                                                                             \
   }
   EPIC_LA(32, 1, 1) EPIC_LA(32, 1, 2) EPIC_LA(32, 1, 4)
   EPIC_LA(32, 2, 1) EPIC_LA(32, 2, 2) EPIC_LA(32, 2, 4)
@@ -635,12 +680,13 @@ epic_status build_split_tables(epic_ctx* x, const Geometry& g) {
           for (int k = 0; k < g.KK; ++k) {
             const size_t o = ((size_t)c * A + a) * g.KK + k;
             const int j = g.cell[o] / N, i = g.cell[o] % N;
-            const double w = g.w[o];
-            // exp(i (x + y)) with x = 2 pi i kl / N, y = 2 pi j km / N
+            const double w = g.w[o], wi = g.wi.empty() ? 0.0 : g.wi[o];
+            // (w + i wi) exp(i (x + y)) with x = 2 pi i kl / N, y = 2 pi j km / N
             const double cx = cs[i * N + kl], sx = sn[i * N + kl];
             const double cy = cs[j * N + km], sy = sn[j * N + km];
-            re += w * (cx * cy - sx * sy);
-            im += w * (sx * cy + cx * sy);
+            const double er = cx * cy - sx * sy, ei = sx * cy + cx * sy;
+            re += w * er - wi * ei;
+            im += w * ei + wi * er;
           }
           beta[((size_t)c * NG + km * N + kl) * A + a] = make_double2(re, im);
           bmax[c] = std::max(bmax[c], std::hypot(re, im));
@@ -871,6 +917,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.efield = efield;
     a.gains = reinterpret_cast<const float2*>(gains);
     a.prog = x->prog.as<uint2>();
+    a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
     a.twiddle = x->twiddle.as<float2>();
     a.partial = x->partial.as<double>();
     a.n_time = n_time;
@@ -878,7 +925,8 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w;
+    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
     a.W = (int)std::min<int64_t>(w_max, a.total);
     if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image128_kernel";
@@ -900,6 +948,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.efield = efield;
     a.gains = reinterpret_cast<const float2*>(gains);
     a.prog = x->prog.as<uint2>();
+    a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
     a.twiddle = x->twiddle.as<float2>();
     a.partial = x->partial.as<double>();
     a.n_time = n_time;
@@ -907,7 +956,8 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w;
+    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
     a.W = (int)std::min<int64_t>(w_max, total);
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image_kernel";
@@ -947,6 +997,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
       gr.e = x->st_e.as<float2>();
       gr.off = x->csr_off.as<int>();
       gr.ent = x->csr_ent.as<uint2>();
+      gr.ent_im = x->cpx ? x->csr_im.as<float>() : nullptr;
       gr.grid = x->st_grid.as<float2>();
       gr.count = (int64_t)tb * C * P * npix;
       gr.n_chan = C;
@@ -1056,8 +1107,10 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     else x->fused_gpt = gpt;
   }
   if (x->fused_ok) {
-    const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt);
+    const int bpc = fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, false);
     x->fused_w = bpc * x->n_cu;
+    // complex-kernel variants: never more workgroups than the slots allow
+    x->fused_w_cpx = std::min(x->fused_w, fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
     // N = 128: two accumulation segments (column halves) per channel
     const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
     const size_t slots = (size_t)x->fused_w + segs - 1;
@@ -1067,7 +1120,8 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
       delete x;
       return EPIC_E_NOMEM;
     }
-    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt) * x->n_cu;
+    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, false) * x->n_cu;
+    x->adj_w_cpx = N == 128 ? 1 : std::min(x->adj_w, adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
     if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
         (N <= 64 && !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4)))) {
@@ -1075,6 +1129,11 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
       delete x;
       return EPIC_E_NOMEM;
     }
+  }
+  if ((cfg->flags & EPIC_FLAG_REMOVE_AUTOS) && cfg->kernel_support > epic::AUTO_MAX_K) {
+    g_init_error = "EPIC_FLAG_REMOVE_AUTOS takes kernel_support <= 7";
+    delete x;
+    return EPIC_E_UNSUPPORTED;
   }
   if (cfg->flags & EPIC_FLAG_REMOVE_AUTOS) {
     const int NQ = cfg->n_pol == 2 ? 4 : 1, D = 2 * cfg->kernel_support - 1;
@@ -1135,7 +1194,7 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
     return EPIC_E_UNSUPPORTED;
   }
   Geometry g;
-  s = build_geometry(*cfg, xy_m, freq_hz, g, m);
+  s = build_geometry(*cfg, xy_m, freq_hz, nullptr, g, m);
   if (s != EPIC_OK) { g_init_error = m; return s; }
   if (!g.fits_half) { g_init_error = "taps do not fit an N/2 x N/2 block"; return EPIC_E_UNSUPPORTED; }
   std::vector<uint32_t> prog;
@@ -1162,17 +1221,25 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
 }
 
 epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* freq_hz) {
+  return epic_set_antennas_kernels(x, xy_m, freq_hz, nullptr);
+}
+
+epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const double* freq_hz,
+                                      const float* kernels) {
   if (!x) return EPIC_E_INVALID;
   if (!xy_m || !freq_hz) return x->fail(EPIC_E_INVALID, "xy_m or freq_hz is NULL");
+  if (kernels && x->autos)
+    return x->fail(EPIC_E_UNSUPPORTED, "EPIC_FLAG_REMOVE_AUTOS takes the Gaussian kernel only");
   Geometry g;
   std::string m;
-  epic_status s = build_geometry(x->cfg, xy_m, freq_hz, g, m);
+  epic_status s = build_geometry(x->cfg, xy_m, freq_hz, kernels, g, m);
   if (s != EPIC_OK) return x->fail(s, m);
   DeviceGuard guard(x->device);
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
   if (hipStreamSynchronize(x->stream) != hipSuccess)
     return x->fail(EPIC_E_DEVICE, "stream synchronisation failed");
   x->have_geom = false;
+  x->cpx = kernels != nullptr;
   if (x->autos &&
       (!x->au_w.alloc(g.w.size() * sizeof(float)) ||
        hipMemcpy(x->au_w.p, g.w.data(), g.w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess))
@@ -1196,14 +1263,20 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
       std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
     }
     std::vector<uint32_t> prog;
+    std::vector<float> prog_im;
     int L = 0;
-    if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L);
-    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L);
-    else build_programs<128>(g, P, x->fused_gpt, prog, L);
+    if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L, &prog_im);
+    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L, &prog_im);
+    else build_programs<128>(g, P, x->fused_gpt, prog, L, &prog_im);
     if (L == 0) return x->fail(EPIC_E_UNSUPPORTED, "gridding program fields overflow");
     if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
         hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(x->prog.p, prog.data(), prog.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
+    if (x->cpx &&
+        (!x->prog_im.alloc(prog_im.size() * 4) || !x->taps_im.alloc(g.wi.size() * 4) ||
+         hipMemcpy(x->prog_im.p, prog_im.data(), prog_im.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+         hipMemcpy(x->taps_im.p, g.wi.data(), g.wi.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
     x->L = L;
   } else {
@@ -1212,6 +1285,7 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
     const int npix = N * N, nnz = A * g.KK;
     std::vector<int> off((size_t)C * (npix + 1));
     std::vector<uint32_t> ent((size_t)C * nnz * 2);
+    std::vector<float> ent_im(x->cpx ? (size_t)C * nnz : 0);
     for (int c = 0; c < C; ++c) {
       std::vector<int> cnt(npix, 0);
       for (int a = 0; a < A; ++a)
@@ -1226,11 +1300,15 @@ epic_status epic_set_antennas(epic_ctx* x, const double* xy_m, const double* fre
           const size_t dst = (size_t)c * nnz + fill[g.cell[src]]++;
           ent[2 * dst] = (uint32_t)a;
           std::memcpy(&ent[2 * dst + 1], &g.w[src], 4);
+          if (x->cpx) ent_im[dst] = g.wi[src];
         }
     }
     if (!x->csr_off.alloc(off.size() * 4) || !x->csr_ent.alloc(ent.size() * 4) ||
         hipMemcpy(x->csr_off.p, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(x->csr_ent.p, ent.data(), ent.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
+    if (x->cpx && (!x->csr_im.alloc(ent_im.size() * 4) ||
+                   hipMemcpy(x->csr_im.p, ent_im.data(), ent_im.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
     x->nnz = nnz;
   }
@@ -1300,7 +1378,9 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.gains = reinterpret_cast<const float2*>(gains);
   a.gtab = x->gtab.as<float4>();
   a.prog = x->prog.as<uint2>();
+  a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
   a.taps = x->taps.as<uint2>();
+  a.tapim = x->cpx ? x->taps_im.as<float>() : nullptr;
   a.twiddle = x->twiddle.as<float2>();
   a.gpartial = x->gpartial.as<double2>();
   a.n_time = n_time;
@@ -1309,7 +1389,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.n_ant = x->cfg.n_ant;
   a.kk = x->cfg.kernel_support * x->cfg.kernel_support;
   a.L = x->L;
-  a.W = (int)std::min<int64_t>(x->adj_w, total);
+  a.W = (int)std::min<int64_t>(x->cpx ? x->adj_w_cpx : x->adj_w, total);
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
   x->last_kernel = "adjoint_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
@@ -1372,7 +1452,8 @@ void epic_destroy(epic_ctx* x) {
     (void)hipStreamSynchronize(x->stream);
     for (auto& e : x->ev)
       if (e) (void)hipEventDestroy(e);
-    x->prog.reset(); x->twiddle.reset(); x->taps.reset();
+    x->prog.reset(); x->twiddle.reset(); x->taps.reset(); x->prog_im.reset(); x->taps_im.reset();
+    x->csr_im.reset();
     x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset(); x->gtab.reset();
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();

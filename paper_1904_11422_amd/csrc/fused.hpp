@@ -33,16 +33,17 @@
 namespace epic {
 
 // Gridding step: {code, weight bits}.  code = LDS byte offset of the cell
-// (pol 0, relative to the grid base) << 15 | byte offset of E'[e] (pol 0); the weight's sign bit marks
-// the last entry of a cell (the weights themselves are >= 0).  Every step
-// reads E' of both polarisations and adds |w| * E' to the running sums; the
+// (pol 0, relative to the grid base) << 15 | byte offset of E'[e] (pol 0, a
+// multiple of 8), with bit 0 set on the last entry of a cell.  Every step
+// reads E' of both polarisations and adds w * E' to the running sums; the
 // last entry of a cell stores the sums to the cell and restarts them.  Cells
 // with no antenna read a zero slot of E'; padding steps add zero and store
-// nothing.  The host orders the steps so that the lanes of a quarter-wave
-// mostly touch distinct LDS banks.
+// nothing.  With complex kernels (CPX) a parallel array holds each step's
+// imaginary weight.  The host orders the steps so that the lanes of a
+// quarter-wave mostly touch distinct LDS banks.
 constexpr int STEP_CELL_SHIFT = 15;            // cell byte offset < 128 KB
-constexpr uint32_t STEP_E_MASK = 0x7FFFu;      // E' byte offset < 32 KB
-constexpr uint32_t STEP_LAST_BIT = 0x80000000u; // in the weight word
+constexpr uint32_t STEP_E_MASK = 0x7FF8u;      // E' byte offset < 32 KB, 8-byte aligned
+constexpr uint32_t STEP_LAST_BIT = 1u;         // in the code word
 constexpr int kMaxFixedSteps = 8;              // longer lists run in chunks of 4
 constexpr int kStepChunk = 4;
 
@@ -91,6 +92,7 @@ struct FusedArgs {
   const uint8_t* efield;    // [T][C][P][A]
   const float2* gains;      // [C][P][A]
   const uint2* prog;        // [C][1 + L][NT]: row-pass line of each thread, then L steps
+  const float* wim;         // [C][1 + L][NT] imaginary step weights (complex kernels), or null
   const float2* twiddle;    // [N] exp(+2 pi i k / N)
   double* partial;          // [W + C - 1][NACC][S][NT] (thread-major)
   int64_t n_time;
@@ -161,17 +163,26 @@ __device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[G
 
 // One gridding step on the running sums (s0, s1) of the current cell.
 // lds is the start of the shared buffer: E' at byte 0, the grid at xbase.
-template <int N, int P, int RS, int ES>
-__device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, float2 e0, float2 e1,
-                                          float2& s0, float2& s1) {
-  const float w = fabsf(__uint_as_float(step.y));
+// CPX: the weight is w + i wi.
+template <int N, int P, int RS, int ES, bool CPX>
+__device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, float wi, float2 e0,
+                                          float2 e1, float2& s0, float2& s1) {
+  const float w = __uint_as_float(step.y);
   s0.x = fmaf(w, e0.x, s0.x);
   s0.y = fmaf(w, e0.y, s0.y);
+  if (CPX) {
+    s0.x = fmaf(-wi, e0.y, s0.x);
+    s0.y = fmaf(wi, e0.x, s0.y);
+  }
   if (P == 2) {
     s1.x = fmaf(w, e1.x, s1.x);
     s1.y = fmaf(w, e1.y, s1.y);
+    if (CPX) {
+      s1.x = fmaf(-wi, e1.y, s1.x);
+      s1.y = fmaf(wi, e1.x, s1.y);
+    }
   }
-  if ((int)step.y < 0) {                        // last entry of the cell
+  if (step.x & STEP_LAST_BIT) {                 // last entry of the cell
     float2* cell = reinterpret_cast<float2*>(lds + xbase + (step.x >> STEP_CELL_SHIFT));
     cell[0] = s0;
     if (P == 2) cell[FusedShape<N>::PSTRIDE] = s1;
@@ -187,9 +198,11 @@ __device__ __forceinline__ void read_e(const char* lds, uint2 step, float2& e0, 
   if (P == 2) e1 = e[ES];
 }
 
-// 2. Gather gridding with exactly LS steps, already loaded into registers.
-template <int N, int P, int RS, int ES, int LS>
-__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[kMaxFixedSteps]) {
+// 2. Gather gridding with exactly LS steps, already loaded into registers
+// (wis: the imaginary weights, read only when CPX).
+template <int N, int P, int RS, int ES, int LS, bool CPX>
+__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[kMaxFixedSteps],
+                                           const float (&wis)[kMaxFixedSteps]) {
   float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
 #pragma unroll
   for (int st0 = 0; st0 < LS; st0 += kStepChunk) {      // E' reads in groups of 4
@@ -200,57 +213,67 @@ __device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&s
       if (st0 + st < LS) read_e<P, ES>(lds, steps[st0 + st], e0[st], e1[st]);
 #pragma unroll
     for (int st = 0; st < G; ++st)
-      if (st0 + st < LS) grid_step<N, P, RS, ES>(lds, xbase, steps[st0 + st], e0[st], e1[st], s0, s1);
+      if (st0 + st < LS)
+        grid_step<N, P, RS, ES, CPX>(lds, xbase, steps[st0 + st], wis[st0 + st], e0[st], e1[st], s0, s1);
   }
 }
 
 // 2'. Gather gridding of a long list (L a multiple of kStepChunk).
-template <int N, int P, int RS, int ES>
-__device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* prog, int stride, int L) {
+template <int N, int P, int RS, int ES, bool CPX>
+__device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* prog, const float* wim,
+                                             int stride, int L) {
   float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
   for (int st0 = 0; st0 < L; st0 += kStepChunk) {
     uint2 steps[kStepChunk];
+    float wis[kStepChunk];
     float2 e0[kStepChunk], e1[kStepChunk];
 #pragma unroll
-    for (int st = 0; st < kStepChunk; ++st) steps[st] = prog[(st0 + st) * stride];
+    for (int st = 0; st < kStepChunk; ++st) {
+      steps[st] = prog[(st0 + st) * stride];
+      wis[st] = CPX ? wim[(st0 + st) * stride] : 0.f;
+    }
 #pragma unroll
     for (int st = 0; st < kStepChunk; ++st) read_e<P, ES>(lds, steps[st], e0[st], e1[st]);
 #pragma unroll
-    for (int st = 0; st < kStepChunk; ++st) grid_step<N, P, RS, ES>(lds, xbase, steps[st], e0[st], e1[st], s0, s1);
+    for (int st = 0; st < kStepChunk; ++st)
+      grid_step<N, P, RS, ES, CPX>(lds, xbase, steps[st], wis[st], e0[st], e1[st], s0, s1);
   }
 }
 
 // Steps 1-2 of one sample: load the gridding program (exactly L steps for
 // L <= kMaxFixedSteps), stage E', barrier, grid.  A thread grids only cells
 // of rows its own wave transforms next, so gridding ends with a wave-level
-// fence.  prog is the channel's step list [L][NT]; the switch on L is
-// uniform over the workgroup.
-template <int N, int P, int NT, int RS, int ES, int GPT>
+// fence.  prog is the channel's step list [L][NT] (wim: its imaginary
+// weights when CPX); the switch on L is uniform over the workgroup.
+template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX>
 __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, const uint2* prog,
-                                               int L, const uint32_t (&cur)[GPT],
+                                               const float* wim, int L, const uint32_t (&cur)[GPT],
                                                const float2 (&g)[GPT], const int (&eidx)[GPT],
                                                int tid, int PA) {
   if (L <= kMaxFixedSteps) {
     uint2 steps[kMaxFixedSteps];
+    float wis[kMaxFixedSteps];
 #pragma unroll
-    for (int st = 0; st < kMaxFixedSteps; ++st)
+    for (int st = 0; st < kMaxFixedSteps; ++st) {
       if (st < L) steps[st] = prog[st * NT + tid];
+      wis[st] = (CPX && st < L) ? wim[st * NT + tid] : 0.f;
+    }
     stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
     __syncthreads();
     switch (L) {
-      case 1: grid_fixed<N, P, RS, ES, 1>(lds, xbase, steps); break;
-      case 2: grid_fixed<N, P, RS, ES, 2>(lds, xbase, steps); break;
-      case 3: grid_fixed<N, P, RS, ES, 3>(lds, xbase, steps); break;
-      case 4: grid_fixed<N, P, RS, ES, 4>(lds, xbase, steps); break;
-      case 5: grid_fixed<N, P, RS, ES, 5>(lds, xbase, steps); break;
-      case 6: grid_fixed<N, P, RS, ES, 6>(lds, xbase, steps); break;
-      case 7: grid_fixed<N, P, RS, ES, 7>(lds, xbase, steps); break;
-      default: grid_fixed<N, P, RS, ES, 8>(lds, xbase, steps); break;
+      case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, steps, wis); break;
+      case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, steps, wis); break;
+      case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, steps, wis); break;
+      case 4: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, steps, wis); break;
+      case 5: grid_fixed<N, P, RS, ES, 5, CPX>(lds, xbase, steps, wis); break;
+      case 6: grid_fixed<N, P, RS, ES, 6, CPX>(lds, xbase, steps, wis); break;
+      case 7: grid_fixed<N, P, RS, ES, 7, CPX>(lds, xbase, steps, wis); break;
+      default: grid_fixed<N, P, RS, ES, 8, CPX>(lds, xbase, steps, wis); break;
     }
   } else {
     stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
     __syncthreads();
-    grid_chunked<N, P, RS, ES>(lds, xbase, prog + tid, NT, L);
+    grid_chunked<N, P, RS, ES, CPX>(lds, xbase, prog + tid, CPX ? wim + tid : nullptr, NT, L);
   }
   wave_lds_sync();
 }
@@ -307,7 +330,7 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
   }
 }
 
-template <int N, int P, int GPT>
+template <int N, int P, int GPT, bool CPX>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_image_kernel(FusedArgs a) {
@@ -342,6 +365,7 @@ fused_image_kernel(FusedArgs a) {
   uint32_t nxt[GPT];
   int c = -1, nblk = 0, nflush = 0, line = -1;
   const uint2* prog = nullptr;
+  const float* wim = nullptr;
 
   auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
     const uint8_t* src = a.efield + tt * row_bytes + (int64_t)cc * PA;
@@ -376,6 +400,7 @@ fused_image_kernel(FusedArgs a) {
       c = cc;
       nflush = 0;
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
+      if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
       prog += NT;
 #pragma unroll
@@ -397,7 +422,7 @@ fused_image_kernel(FusedArgs a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
     row_pass<N, P, +1>(X, r, tw, line);
     __syncthreads();
     float2 v[P][S];

@@ -29,6 +29,7 @@ struct Fused128Args {
   const uint8_t* efield;    // [T][C][2][A]
   const float2* gains;      // [C][2][A]
   const uint2* prog;        // [C][1 + L][NT], as fused_image_kernel
+  const float* wim;         // [C][1 + L][NT] imaginary step weights (complex kernels), or null
   const float2* twiddle;    // [128] exp(+2 pi i k / 128)
   double* partial;          // [W + 2 C - 1][4][16][NT] (thread-major)
   int64_t n_time;
@@ -42,7 +43,7 @@ __host__ __device__ __forceinline__ int km128(int n0, int i) {
   return 2 * n0 + (i >> 3) + 16 * (i & 7);
 }
 
-template <int GPT>
+template <int GPT, bool CPX>
 __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
   using SH = FusedShape<128>;
   constexpr int N = 128, S = SH::S, R = SH::R, NT = SH::NT, RS = SH::RS, PS = SH::PSTRIDE;
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
   uint32_t nxt[GPT];
   int seg = -1, nblk = 0, nflush = 0, line = -1, h = 0;
   const uint2* prog = nullptr;
+  const float* wim = nullptr;
 
   auto load_bytes = [&](int64_t sg, int64_t tt, uint32_t (&dst)[GPT]) {
     const uint8_t* src = a.efield + tt * row_bytes + (sg >> 1) * PA;
@@ -118,6 +120,7 @@ __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
         for (int u = 0; u < NACC; ++u) acc[i][u] = 0.f;
       if (c != c_old) {
         prog = a.prog + (int64_t)c * (a.L + 1) * NT;
+        if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
         line = (int)prog[tid].x;
         prog += NT;
 #pragma unroll
@@ -137,7 +140,7 @@ __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
     if (left > 1) load_bytes(sg, tt, nxt);
 
     // 1. stage and grid the aperture (both halves grid the whole aperture)
-    stage_and_grid<N, P, NT, RS, ES, GPT>(lds, XBASE, E, prog, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
 
     // 2. row transforms of row `line` of both polarisations; keep half h
     if (line >= 0) {

@@ -42,6 +42,7 @@ struct StagedGridArgs {
   float2* grid;             // [Tb][C][P][N*N]
   int64_t count;            // Tb * C * P * N*N
   int n_chan, n_pol, n_ant, nnz, npix;
+  const float* ent_im;      // [C][nnz] imaginary weights (complex kernels), or null
 };
 
 __global__ void __launch_bounds__(256) staged_grid_kernel(StagedGridArgs a) {
@@ -54,6 +55,7 @@ __global__ void __launch_bounds__(256) staged_grid_kernel(StagedGridArgs a) {
     const int c = (int)(tc % a.n_chan);
     const int* off = a.off + (int64_t)c * (a.npix + 1);
     const uint2* ent = a.ent + (int64_t)c * a.nnz;
+    const float* eim = a.ent_im ? a.ent_im + (int64_t)c * a.nnz : nullptr;
     const float2* e = a.e + (tc * a.n_pol + p) * a.n_ant;
     float2 s = make_float2(0.f, 0.f);
     for (int k = off[cell]; k < off[cell + 1]; ++k) {
@@ -62,6 +64,11 @@ __global__ void __launch_bounds__(256) staged_grid_kernel(StagedGridArgs a) {
       const float2 v = e[en.x];
       s.x = fmaf(w, v.x, s.x);
       s.y = fmaf(w, v.y, s.y);
+      if (eim) {                                  // complex kernel: + i wi v
+        const float wi = eim[k];
+        s.x = fmaf(-wi, v.y, s.x);
+        s.y = fmaf(wi, v.x, s.y);
+      }
     }
     a.grid[i] = s;
   }

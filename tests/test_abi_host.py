@@ -43,7 +43,7 @@ def _init(cfg):
 
 @pytest.mark.parametrize("field,value", [("grid_n", 48), ("grid_n", 256), ("n_pol", 3),
                                          ("n_ant", 0), ("n_chan", 0), ("kernel_support", 4),
-                                         ("kernel_support", 9), ("kernel_sigma_cells", 0.0),
+                                         ("kernel_support", 17), ("kernel_sigma_cells", 0.0),
                                          ("cell_wavelengths", -0.5), ("precision", 5),
                                          ("flags", 64)])
 def test_init_rejects_bad_config(field, value):

@@ -113,13 +113,14 @@ def test_programs_reproduce_gridding(name, one_pol):
         # emulate the gather (pol 0; the kernel applies the same step to pol 1)
         code, wb = prog[c, 1:, :, 0], prog[c, 1:, :, 1]
         cell = (code >> 15).astype(np.int64)
-        eoff = (code & 0x7FFF).astype(np.int64)
-        assert np.all(cell % 8 == 0) and np.all(eoff % 8 == 0)
+        eoff = (code & 0x7FF8).astype(np.int64)
+        last = (code & 1).astype(bool)
+        assert np.all(code & 0x6 == 0)           # E' offsets are 8-byte multiples
+        assert np.all(cell % 8 == 0)
         cell //= 8
         eoff //= 8
         assert eoff.max() < A + 16 and A + 16 <= ES
-        last = (wb >> 31).astype(bool)
-        wt = (wb & 0x7FFFFFFF).view(np.float32).astype(np.float64)
+        wt = wb.view(np.float32).astype(np.float64)
         assert np.all(cell < N * RS) and np.all(cell % RS < RS)
         E = np.zeros(ES)
         E[:A] = rng.standard_normal(A)
