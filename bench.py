@@ -30,18 +30,19 @@ PEAK_FP32_VALU = 157.3e12       # MI355X fp32 vector, FLOP/s
 PEAK_HBM = 8.0e12               # MI355X HBM3E, B/s
 
 
-def flops_per_tc(N: int, P: int, A: int, K: int = 3) -> int:
+def flops_per_tc(N: int, P: int, A: int, K: int = 3, complex_kernel: bool = False) -> int:
     """Algorithmic float work of one (time, channel) image.
 
     transform: 5 n_g log2 n_g per polarisation (radix-2 count of a complex FFT)
-    gridding:  4 flops (complex x real weight, add) per tap per antenna per pol
+    gridding:  4 flops (complex x real weight, add) per tap per antenna per pol,
+               8 with a complex kernel (complex multiply-add)
     gain:      6 flops per complex multiply per antenna per pol
     products:  XX 3, YY 3, XY 6 and 4 accumulating adds per pixel (P = 2);
                XX 3 + 1 add (P = 1)
     """
     ng = N * N
     fft = P * 5 * ng * int(round(math.log2(ng)))
-    grid = 4 * K * K * P * A
+    grid = (8 if complex_kernel else 4) * K * K * P * A
     gain = 6 * P * A
     prod = 16 * ng if P == 2 else 4 * ng
     return fft + grid + gain + prod
@@ -357,6 +358,60 @@ def bench_stream(args) -> int:
     return 0
 
 
+def bench_kernels(args) -> int:
+    """The LWA-like workload gridded with seeded complex kernels per channel and
+    antenna (A-projection-like): 5 x 5 on the 64 x 64 grid (the largest support
+    whose taps keep this aperture inside N/2 cells, so the fused kernel runs),
+    and 15 x 15 on a 128 x 128 grid (same array, same channels)."""
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager
+    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+    base = synth.config2()
+    ef = torch.from_numpy(base.efield).cuda()
+    g = torch.from_numpy(base.gains).cuda()
+    out = {}
+    for N, K in ((64, 5), (128, 15)):
+        inp = synth.with_kernels(base, K, 7000 + K)
+        C, P, A, T = inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
+        im = Imager(N, C, P, A, kernel_support=K, timing=True)
+        im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
+        img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
+        for _ in range(args.warmup):
+            im.accumulate(ef, g, image=img)
+        torch.cuda.synchronize()
+        ks = []
+        steps = args.steps if N == 64 else max(3, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            im.accumulate(ef, g, image=img)
+            ks.append(im.last_timing()[0])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        k_ms = float(np.mean(ks))
+        fl = flops_per_tc(N, P, A, K, complex_kernel=True)
+        out[f"n{N}_k{K}"] = {
+            "value": C / dt, "unit": "channel-images/s", "ms_per_step": dt * 1e3, "steps": steps,
+            "kernel": im.last_kernel_name(), "kernel_ms": k_ms,
+            "roofline": {"bound": "alu", "achieved": fl * C * T / (k_ms * 1e-3) / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": fl * C * T / (k_ms * 1e-3) / PEAK_FP32_VALU,
+                         "traffic": None, "flops_per_tc_image": fl}}
+        im.close()
+    main = out["n64_k5"]
+    line = {"metric": "channel-images/s with complex per-antenna kernels", "value": main["value"],
+            "unit": "channel-images/s", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
+            "ms_per_step": main["ms_per_step"], "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "LWA-like (256 dual-pol antennas, 132 channels, 1000 samples) "
+                                   "gridded with seeded complex 5x5 kernels per channel and "
+                                   "antenna on 64x64; also 15x15 on 128x128",
+                       "grid_n": 64, "kernel_support": 5},
+            "roofline": main["roofline"], "results": out}
+    print(json.dumps(line))
+    return 0
+
+
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 PROFILE = os.path.join(PROFILES, "fused_image_kernel_lwa64_c132_t1000.md")
 PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
@@ -408,6 +463,9 @@ def main() -> int:
     ap.add_argument("--stream", action="store_true",
                     help="measure the double-buffered streaming ingest (host gulps in arrival "
                          "order, decimated, transposed and imaged)")
+    ap.add_argument("--kernels", action="store_true",
+                    help="measure imaging with complex per-antenna gridding kernels (5x5 on 64x64, "
+                         "15x15 on 128x128)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (five times), to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -429,6 +487,8 @@ def main() -> int:
         return bench_autos(args)
     if args.stream:
         return bench_stream(args)
+    if args.kernels:
+        return bench_kernels(args)
 
     import torch
     import synth
