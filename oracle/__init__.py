@@ -10,4 +10,4 @@ from .moff import (C0, OffGridError, unpack_ci4, antenna_cells, kernel_taps,  # 
                    l2_loss, l2_loss_grad_image, fd_grad, fd_directional, model_image,
                    rel_errors, auto_visibilities, autocorrelation_image, image_without_autos,
                    image_without_autos_from, grad_autos, grad_gains_without_autos,
-                   decimate_transpose)
+                   decimate_transpose, pseudo_stokes, kernel_taper, taper_corrected)

@@ -448,6 +448,43 @@ def model_image(xy_m, freq_hz, grid_n, n_time, src_lm, src_power, noise_sigma,
     return np.fft.fftshift(out, axes=(-2, -1))
 
 
+# ------------------------------------------------ post-processing (§3.2, §4.3)
+def pseudo_stokes(img: np.ndarray) -> np.ndarray:
+    """Pseudo-Stokes images from the accumulated products (§4.3: linear
+    combinations of the linear-polarisation coherencies, leakage not removed):
+    I = XX + YY, Q = XX - YY, U = XY + YX, V = -i (XY - YX), all real.
+    img [C, 4, N, N] (XX, XY, YX, YY) -> float64 [C, 4, N, N] (I, Q, U, V);
+    one polarisation: [C, 1, N, N] -> XX (real)."""
+    img = np.asarray(img)
+    if img.shape[1] == 1:
+        return img.real.copy()
+    xx, xy, yx, yy = img[:, 0], img[:, 1], img[:, 2], img[:, 3]
+    return np.stack([(xx + yy).real, (xx - yy).real, (xy + yx).real, (-1j * (xy - yx)).real],
+                    axis=1)
+
+
+def kernel_taper(xy_m, freq_hz, grid_n, kernel_support=3, kernel_sigma_cells=0.5,
+                 cell_wavelengths=0.5, kernels=None) -> np.ndarray:
+    """The imprint of the gridding kernels on a power image (§3.2: known in
+    advance, removable after the fact): the antennas' mean kernel power
+    pattern T[c, k] = mean_a |b_a(k)|^2, fftshifted like the image.  When every
+    antenna has the same kernel up to a whole-cell shift, each product is the
+    product of a point-kernel image and exactly this T."""
+    b = aperture_response(xy_m, freq_hz, grid_n, kernel_support, kernel_sigma_cells,
+                          cell_wavelengths, kernels)
+    return np.fft.fftshift(np.mean(np.abs(b) ** 2, axis=1), axes=(-2, -1))
+
+
+def taper_corrected(planes: np.ndarray, taper: np.ndarray, floor: float) -> np.ndarray:
+    """planes [C, n, N, N] divided by taper [C, N, N] where the taper is at
+    least floor times its channel's maximum, zero elsewhere."""
+    t = np.asarray(taper, dtype=np.float64)
+    keep = t >= floor * t.reshape(t.shape[0], -1).max(axis=1)[:, None, None]
+    out = np.zeros(np.shape(planes), dtype=np.float64)
+    np.divide(planes, t[:, None], out=out, where=np.broadcast_to(keep[:, None], out.shape))
+    return out
+
+
 # -------------------------------------------------------- error metric
 def rel_errors(img: np.ndarray, ref: np.ndarray) -> np.ndarray:
     """Per (channel, product) relative L2 error.  XX, YY: ||dI|| / ||I_ref||.

@@ -13,6 +13,8 @@ _kernel_taps = moff.kernel_taps
 _grad = moff.grad_gains
 _auto_vis = moff.auto_visibilities
 _front = moff.decimate_transpose
+_stokes = moff.pseudo_stokes
+_taper = moff.kernel_taper
 
 
 def _wrong_sign(a):
@@ -124,6 +126,17 @@ def _grad_kernel_unconjugated(xy_m, freq_hz, gains, efield, grid_n, grad_image, 
     return 2.0 * out
 
 
+def _stokes_v_flipped(img):
+    out = _stokes(img)
+    if out.shape[1] == 4:
+        out[:, 3] *= -1
+    return out
+
+
+def _taper_not_squared(*a, **k):
+    return np.sqrt(_taper(*a, **k))
+
+
 def _auto_vis_swapped(gains, efield):
     v = _auto_vis(gains, efield)
     if v.shape[1] == 4:
@@ -164,6 +177,12 @@ MUTATIONS = {
     "gradient degridding with the kernel unconjugated": (
         "grad_gains", _grad_kernel_unconjugated,
         [lambda: pins.test_p16_gradient_with_complex_kernels_matches_finite_differences(2)]),
+    "Stokes V with the opposite sign": (
+        "pseudo_stokes", _stokes_v_flipped,
+        [lambda: pins.test_p17_pseudo_stokes_of_pure_polarisation_states(4, 4j, 0, 0, -1)]),
+    "kernel taper not squared": (
+        "kernel_taper", _taper_not_squared,
+        [pins.test_p17_taper_correction_is_exact_for_identical_kernels]),
     "autocorrelation gradient without the factor 2": (
         "grad_autos", _grad_autos_variant(two=1.0),
         [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),

@@ -574,3 +574,57 @@ def test_p16_kernels_shape_checked():
     inp = _kinp(195, 3)
     with pytest.raises(ValueError):
         oracle.image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, 5, kernels=inp.kernels)
+
+
+# ------------------------------------------------- P17: post-processing (§3.2, §4.3)
+def _one_antenna_pol(ex, ey, T=6, N=32):
+    """One antenna, unit gain, every sample E_X = ex, E_Y = ey (int4 complex)."""
+    inp = synth.random_problem(200, N, 1, 1, 2, T)
+    byte = lambda z: ((int(z.real) & 0xF) << 4) | (int(z.imag) & 0xF)
+    ef = np.empty((T, 1, 2, 1), np.uint8)
+    ef[:, 0, 0, 0] = byte(ex)
+    ef[:, 0, 1, 0] = byte(ey)
+    gains = np.ones((1, 2, 1), np.complex64)
+    return oracle.image(inp.xy_m, inp.freq_hz, gains, ef, N)
+
+
+@pytest.mark.parametrize("ex,ey,q,u,v", [(4, 0, 1, 0, 0), (0, 4, -1, 0, 0), (3, 3, 0, 1, 0),
+                                         (3, -3, 0, -1, 0), (4, 4j, 0, 0, -1), (4, -4j, 0, 0, 1)])
+def test_p17_pseudo_stokes_of_pure_polarisation_states(ex, ey, q, u, v):
+    """Textbook states: X only (Q = I), Y only (Q = -I), +-45 deg linear (U = +-I),
+    E_Y = +-i E_X (V = -+I), at every pixel of a one-antenna image."""
+    st = oracle.pseudo_stokes(_one_antenna_pol(complex(ex), complex(ey)))
+    I = st[0, 0]
+    assert np.all(I > 0)
+    for plane, want in ((1, q), (2, u), (3, v)):
+        assert np.max(np.abs(st[0, plane] - want * I)) <= 1e-12 * I.max()
+
+
+def test_p17_taper_correction_is_exact_for_identical_kernels():
+    """Antennas on whole cells all have the same Gaussian kernel, so each product
+    is the point-kernel image times T = |kernel transform|^2: dividing by
+    kernel_taper recovers the image gridded with a unit 1 x 1 kernel."""
+    N, A, T = 32, 7, 4
+    inp = synth.random_problem(201, N, A, 1, 2, T)
+    cell_m = oracle.C0 / inp.freq_hz[0] * 0.5
+    rng = np.random.default_rng(202)
+    cells = rng.choice(np.arange(-6, 7), size=(A, 2))
+    xy = cells * cell_m
+    img = oracle.image(xy, inp.freq_hz, inp.gains, inp.efield, N, 3, 0.5)
+    ones = np.ones((1, A, 1, 1), complex)
+    point = oracle.image(xy, inp.freq_hz, inp.gains, inp.efield, N, 1, 0.5, kernels=ones)
+    taper = oracle.kernel_taper(xy, inp.freq_hz, N, 3, 0.5)
+    floor = 1e-3
+    got = oracle.taper_corrected(oracle.pseudo_stokes(img), taper, floor)
+    want = oracle.pseudo_stokes(point)
+    keep = taper[0] >= floor * taper.max()
+    assert keep.sum() > N * N // 2
+    assert np.max(np.abs(got[0][:, keep] - want[0][:, keep])) <= 1e-9 * np.abs(want).max()
+    assert np.all(got[0][:, ~keep] == 0)
+
+
+def test_p17_taper_of_a_unit_point_kernel_is_one():
+    inp = synth.random_problem(203, 32, 5, 2, 1, 1)
+    ones = np.ones((2, 5, 1, 1), complex)
+    t = oracle.kernel_taper(inp.xy_m, inp.freq_hz, 32, 1, 0.5, kernels=ones)
+    assert np.max(np.abs(t - 1.0)) <= 1e-12
