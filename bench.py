@@ -412,6 +412,52 @@ def bench_kernels(args) -> int:
     return 0
 
 
+def bench_post(args) -> int:
+    """Post-processing of the LWA-like image (132 channels, 64 x 64, 4 products):
+    pseudo-Stokes I, Q, U, V with the kernel taper divided out, then FITS export."""
+    import tempfile
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager, fits
+    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+    inp = synth.config2()
+    N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
+    im = Imager(N, C, P, A)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    img = im.accumulate(torch.from_numpy(inp.efield).cuda(), torch.from_numpy(inp.gains).cuda())
+    out = im.postprocess(img, 1e-3)
+    for _ in range(args.warmup):
+        im.postprocess(img, 1e-3, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        im.postprocess(img, 1e-3, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    k_ms = e0.elapsed_time(e1) / args.steps
+    # algorithmic bytes: the four complex128 products in, the taper, four float64 planes out
+    alg = C * N * N * (4 * 16 + 8 + 4 * 8)
+    with tempfile.TemporaryDirectory() as d:
+        t0 = time.perf_counter()
+        fits.write(os.path.join(d, "cube.fits"), out, N, inp.cell_wavelengths, inp.freq_hz,
+                   n_time=T, sample_s=40e-6)
+        fits_s = time.perf_counter() - t0
+    line = {"metric": "post-processed channel images/s (pseudo-Stokes, taper-corrected)",
+            "value": C / (k_ms * 1e-3), "unit": "channel-images/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": k_ms,
+            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "LWA-like image: 132 channels, 4 products, 64x64, "
+                                   "taper floor 1e-3", "grid_n": N, "n_chan": C},
+            "roofline": {"bound": "hbm", "kernel": "postprocess_kernel",
+                         "achieved": alg / (k_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
+                         "unit": "GB/s", "frac": alg / (k_ms * 1e-3) / PEAK_HBM,
+                         "traffic": None, "bytes_per_launch": alg, "kernel_ms": k_ms},
+            "fits_write_s": fits_s, "fits_bytes": C * 4 * N * N * 4}
+    print(json.dumps(line))
+    return 0
+
+
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 PROFILE = os.path.join(PROFILES, "fused_image_kernel_lwa64_c132_t1000.md")
 PROFILED_SOURCES = ("csrc/fused.hpp", "csrc/dft.hpp", "csrc/reduce.hpp", "build.py")
@@ -466,6 +512,9 @@ def main() -> int:
     ap.add_argument("--kernels", action="store_true",
                     help="measure imaging with complex per-antenna gridding kernels (5x5 on 64x64, "
                          "15x15 on 128x128)")
+    ap.add_argument("--post", action="store_true",
+                    help="measure post-processing (pseudo-Stokes with kernel-taper correction) "
+                         "and FITS export of the LWA-like image")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (five times), to "
                          "scale the FETCH_SIZE / WRITE_SIZE counters of a profiler run")
@@ -489,6 +538,8 @@ def main() -> int:
         return bench_stream(args)
     if args.kernels:
         return bench_kernels(args)
+    if args.post:
+        return bench_post(args)
 
     import torch
     import synth

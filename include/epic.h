@@ -186,6 +186,32 @@ epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_
                                 const float *gains, const double *grad_image,
                                 float *grad_gains);
 
+/* Post-processing of an accumulated image (Sec. 3.2: the imprint of the
+ * gridding kernels is known in advance and removed after the fact; Sec. 4.3:
+ * pseudo-Stokes images, linear combinations of the linear-polarisation
+ * products without leakage correction).
+ *   image: device complex128 [n_chan][n_prod][N][N] from epic_image_accumulate;
+ *   out:   device float64 [n_chan][4][N][N] = I = XX + YY, Q = XX - YY,
+ *          U = XY + YX, V = -i (XY - YX) for n_pol = 2; [n_chan][1][N][N] = XX
+ *          for n_pol = 1;
+ *   taper_floor < 0: no correction; 0 <= taper_floor <= 1: each plane is
+ *          divided by the kernel taper T (epic_kernel_taper) at pixels where T is
+ *          at least taper_floor times the channel's maximum, and set to 0 elsewhere.
+ * Exact when all antennas share one kernel up to a whole-cell shift (then
+ * every product is the point-kernel image times T); otherwise it divides by
+ * the antennas' mean kernel power pattern.  Allocates nothing; enqueued on the
+ * context's stream.  Errors: EPIC_E_STATE (no antennas), EPIC_E_INVALID (null,
+ * taper_floor NaN or above 1), EPIC_E_LAUNCH. */
+epic_status epic_postprocess(epic_ctx *ctx, const double *image, double taper_floor, double *out);
+
+/* The kernel taper of the current geometry, T_c(k) = mean over antennas of
+ * |b_a(k)|^2 (b_a the transform of antenna a's kernel taps, positive exponent),
+ * fftshifted like the image, float64 computed from the kernel weights the
+ * imager uses; built by epic_set_antennas.  taper: device float64
+ * [n_chan][N][N], overwritten (asynchronously, on the context's stream).
+ * Errors: EPIC_E_STATE, EPIC_E_INVALID, EPIC_E_LAUNCH. */
+epic_status epic_kernel_taper(epic_ctx *ctx, double *taper);
+
 /* With EPIC_FLAG_TIMING: wait for the last imaging call and report the
  * duration of its main kernel and of the whole call, in milliseconds, measured
  * with HIP events on the context's stream.  Errors: EPIC_E_STATE (no timed

@@ -119,6 +119,35 @@ class Imager:
         _lib.check(self.L, self._ctx, st)
         return image
 
+    def postprocess(self, image, taper_floor: Optional[float] = None, out=None):
+        """Pseudo-Stokes planes I, Q, U, V (XX for one polarisation), float64
+        [C, 4 or 1, N, N]; with taper_floor (0..1) divided by the kernel taper
+        where it is at least taper_floor times the channel's maximum."""
+        torch = _torch()
+        if image.dtype != torch.complex128 or tuple(image.shape) != self.image_shape() or \
+                not image.is_contiguous() or not image.is_cuda:
+            raise ValueError(f"image must be a contiguous CUDA complex128 tensor {self.image_shape()}")
+        shape = (self.n_chan, self.n_prod, self.grid_n, self.grid_n)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=image.device)
+        elif tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous float64 tensor {shape}")
+        self._bind_stream()
+        st = self.L.epic_postprocess(self._ctx, ctypes.c_void_p(image.data_ptr()),
+                                     -1.0 if taper_floor is None else float(taper_floor),
+                                     ctypes.c_void_p(out.data_ptr()))
+        _lib.check(self.L, self._ctx, st)
+        return out
+
+    def kernel_taper(self):
+        """The kernel taper of the current geometry, float64 [C, N, N] (fftshifted)."""
+        torch = _torch()
+        out = torch.empty((self.n_chan, self.grid_n, self.grid_n), dtype=torch.float64,
+                          device=f"cuda:{self.device}")
+        self._bind_stream()
+        _lib.check(self.L, self._ctx, self.L.epic_kernel_taper(self._ctx, ctypes.c_void_p(out.data_ptr())))
+        return out
+
     def frontend(self, raw, c0: int = 0, c_step: int = 1, out=None):
         """Decimate and transpose a gulp in arrival order, uint8 [T, c_in, A, P]
         on the GPU, into the imaging layout [T, C, P, A] (channel i = c0 + i c_step)."""

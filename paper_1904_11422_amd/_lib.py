@@ -26,6 +26,7 @@ EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_set_antenn
            "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
            "epic_batch_serial", "epic_batch_set_serial",
            "epic_batch_destroy", "epic_batch_last_error",
+           "epic_postprocess", "epic_kernel_taper",
            "epic_frontend", "epic_pipeline_create", "epic_pipeline_push", "epic_pipeline_report",
            "epic_pipeline_destroy", "epic_pipeline_last_error")
 
@@ -112,6 +113,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_batch_destroy.restype = None
     L.epic_batch_last_error.argtypes = [vp]
     L.epic_batch_last_error.restype = ctypes.c_char_p
+    L.epic_postprocess.argtypes = [vp, vp, ctypes.c_double, vp]
+    L.epic_postprocess.restype = ctypes.c_int
+    L.epic_kernel_taper.argtypes = [vp, vp]
+    L.epic_kernel_taper.restype = ctypes.c_int
     L.epic_frontend.argtypes = [vp, vp, i64, i32, i32, i32, vp]
     L.epic_frontend.restype = ctypes.c_int
     L.epic_pipeline_create.argtypes = [vp, i64, i32, i32, i32, ctypes.c_double, ctypes.POINTER(vp)]

@@ -22,6 +22,7 @@
 #include "fused128.hpp"
 #include "autos.hpp"
 #include "frontend.hpp"
+#include "post.hpp"
 
 namespace {
 
@@ -99,6 +100,7 @@ struct epic_ctx {
   bool cpx = false;                   // the geometry carries complex kernels
   int fused_w_cpx = 0, adj_w_cpx = 0; // persistent grids of the complex-kernel variants
   DevMem csr_off, csr_ent, csr_im;
+  DevMem taper, tmax;                 // kernel taper [C][N][N] (fftshifted) and its maxima [C]
   int nnz = 0;
 
   // workspace
@@ -906,6 +908,48 @@ void launch_autos_grad(epic_ctx* x, const uint8_t* efield, int64_t n_time, const
 #undef EPIC_AG
 }
 
+// Kernel taper of the current geometry (post.hpp), built on the context's
+// stream at epic_set_antennas; the per-channel maxima are taken on the host.
+epic_status build_taper(epic_ctx* x, const Geometry& g) {
+  const int C = x->cfg.n_chan, A = x->cfg.n_ant, N = x->cfg.grid_n, K = x->cfg.kernel_support;
+  const int D2 = (2 * K - 1) * (2 * K - 1);
+  DevMem w, wi, coeff;
+  const size_t nw = g.w.size();
+  if (!w.alloc(nw * 4) || (!g.wi.empty() && !wi.alloc(nw * 4)) ||
+      !coeff.alloc((size_t)C * D2 * sizeof(double2)) ||
+      !x->taper.alloc((size_t)C * N * N * sizeof(double)) || !x->tmax.alloc((size_t)C * sizeof(double)) ||
+      hipMemcpy(w.p, g.w.data(), nw * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (!g.wi.empty() && hipMemcpy(wi.p, g.wi.data(), nw * 4, hipMemcpyHostToDevice) != hipSuccess))
+    return x->fail(EPIC_E_NOMEM, "kernel taper allocation failed");
+  (void)hipGetLastError();
+  epic::TaperCoeffArgs ca;
+  ca.w = w.as<float>();
+  ca.wi = g.wi.empty() ? nullptr : wi.as<float>();
+  ca.coeff = coeff.as<double2>();
+  ca.n_chan = C;
+  ca.n_ant = A;
+  ca.K = K;
+  hipLaunchKernelGGL(epic::taper_coeff_kernel, dim3((unsigned)((int64_t)C * D2)), dim3(256), 0, x->stream, ca);
+  epic::TaperImageArgs ia;
+  ia.coeff = coeff.as<double2>();
+  ia.taper = x->taper.as<double>();
+  ia.n_chan = C;
+  ia.n_ant = A;
+  ia.N = N;
+  ia.K = K;
+  hipLaunchKernelGGL(epic::taper_image_kernel, dim3((unsigned)((int64_t)C * ((N * N + 255) / 256))),
+                     dim3(256), 0, x->stream, ia);
+  std::vector<double> t((size_t)C * N * N), mx(C, 0.0);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(x->stream) != hipSuccess ||
+      hipMemcpy(t.data(), x->taper.p, t.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    return x->fail(EPIC_E_DEVICE, "kernel taper computation failed");
+  for (int c = 0; c < C; ++c)
+    for (int i = 0; i < N * N; ++i) mx[c] = std::max(mx[c], t[(size_t)c * N * N + i]);
+  if (hipMemcpy(x->tmax.p, mx.data(), C * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+    return x->fail(EPIC_E_DEVICE, "kernel taper upload failed");
+  return EPIC_OK;
+}
+
 // The float32 paths: fused kernels, or the staged comparator.
 epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
                      double* image, int32_t reset) {
@@ -1244,6 +1288,8 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
       (!x->au_w.alloc(g.w.size() * sizeof(float)) ||
        hipMemcpy(x->au_w.p, g.w.data(), g.w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess))
     return x->fail(EPIC_E_NOMEM, "kernel weight upload failed");
+  s = build_taper(x, g);
+  if (s != EPIC_OK) return s;
   if (x->cfg.precision != EPIC_FP32) {
     s = build_split_tables(x, g);
     if (s != EPIC_OK) return s;
@@ -1443,6 +1489,42 @@ epic_status epic_last_autos_timing(epic_ctx* x, float* sum_kernel_ms, float* rem
   return EPIC_OK;
 }
 
+epic_status epic_postprocess(epic_ctx* x, const double* image, double taper_floor, double* out) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!image || !out) return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  if (std::isnan(taper_floor) || taper_floor > 1.0)
+    return x->fail(EPIC_E_INVALID, "taper_floor must be <= 1 (negative: no correction)");
+  DeviceGuard guard(x->device);
+  const int N = x->cfg.grid_n;
+  epic::PostArgs a;
+  a.image = reinterpret_cast<const double2*>(image);
+  a.taper = taper_floor >= 0.0 ? x->taper.as<double>() : nullptr;
+  a.tmax = x->tmax.as<double>();
+  a.out = out;
+  a.floor = taper_floor;
+  a.npix = N * N;
+  a.n = (int64_t)x->cfg.n_chan * N * N;
+  (void)hipGetLastError();
+  const dim3 grid((unsigned)((a.n + 255) / 256));
+  if (x->cfg.n_pol == 2) hipLaunchKernelGGL(epic::postprocess_kernel<2>, grid, dim3(256), 0, x->stream, a);
+  else hipLaunchKernelGGL(epic::postprocess_kernel<1>, grid, dim3(256), 0, x->stream, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
+epic_status epic_kernel_taper(epic_ctx* x, double* taper) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!taper) return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  DeviceGuard guard(x->device);
+  const size_t bytes = (size_t)x->cfg.n_chan * x->cfg.grid_n * x->cfg.grid_n * sizeof(double);
+  if (hipMemcpyAsync(taper, x->taper.p, bytes, hipMemcpyDeviceToDevice, x->stream) != hipSuccess)
+    return x->fail(EPIC_E_LAUNCH, "copy failed");
+  return EPIC_OK;
+}
+
 const char* epic_last_kernel_name(const epic_ctx* x) { return x ? x->last_kernel : "none"; }
 
 void epic_destroy(epic_ctx* x) {
@@ -1453,7 +1535,7 @@ void epic_destroy(epic_ctx* x) {
     for (auto& e : x->ev)
       if (e) (void)hipEventDestroy(e);
     x->prog.reset(); x->twiddle.reset(); x->taps.reset(); x->prog_im.reset(); x->taps_im.reset();
-    x->csr_im.reset();
+    x->csr_im.reset(); x->taper.reset(); x->tmax.reset();
     x->csr_off.reset(); x->csr_ent.reset(); x->partial.reset(); x->gpartial.reset(); x->gtab.reset();
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
