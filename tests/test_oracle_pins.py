@@ -628,3 +628,35 @@ def test_p17_taper_of_a_unit_point_kernel_is_one():
     ones = np.ones((2, 5, 1, 1), complex)
     t = oracle.kernel_taper(inp.xy_m, inp.freq_hz, 32, 1, 0.5, kernels=ones)
     assert np.max(np.abs(t - 1.0)) <= 1e-12
+
+
+def test_p16_autos_removed_with_complex_kernels_equals_fx_form_without_diagonal():
+    """With each antenna's own complex kernel, the image minus its
+    autocorrelation image is still the visibility form without its diagonal."""
+    inp = _kinp(230, 5, A=8, C=2, P=2, T=4)
+    got = oracle.image_without_autos_from(inp)
+    V = oracle.visibilities(inp.gains, inp.efield)
+    V[:, :, np.arange(8), np.arange(8)] = 0.0
+    ref = oracle.image_fx(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, 5, 0.5, 0.5, vis=V,
+                          kernels=inp.kernels)
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.abs(oracle.image_from(inp)).max()
+
+
+def test_p16_gradient_without_autos_with_complex_kernels_matches_finite_differences():
+    inp = _kinp(231, 3, A=6, C=1, P=2, T=3)
+    rng = _rng(232)
+    model = rng.normal(size=oracle.image_from(inp).shape) * 20.0
+    g = inp.gains.astype(np.complex128)
+
+    def loss(gg):
+        return oracle.l2_loss(oracle.image_without_autos(inp.xy_m, inp.freq_hz, gg, inp.efield, 32,
+                                                         3, kernels=inp.kernels), model)
+    img = oracle.image_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32, 3,
+                                     kernels=inp.kernels)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, g, inp.efield, 32, gam, 3,
+                                           kernels=inp.kernels)
+    coords = [tuple(i) for i in np.ndindex(*g.shape)]
+    fd = oracle.fd_grad(loss, g, coords)
+    an = np.array([grad[c] for c in coords])
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
