@@ -116,9 +116,9 @@ epic_status epic_set_antennas(epic_ctx *ctx, const double *xy_m, const double *f
  * di inner), the weight of antenna a at cell (i0 + di - K/2, j0 + dj - K/2)
  * of channel c, where (i0, j0) is the cell nearest to the antenna (as for
  * the Gaussian).  Copied; kernels == NULL is epic_set_antennas.  Works on
- * every path (fused, staged, split) and in epic_image_backward.
- * Errors: as epic_set_antennas; EPIC_E_INVALID (a non-finite kernel value),
- * EPIC_E_UNSUPPORTED (context created with EPIC_FLAG_REMOVE_AUTOS). */
+ * every path (fused, staged, split), in epic_image_backward and with
+ * EPIC_FLAG_REMOVE_AUTOS (kernel_support <= 7 there).
+ * Errors: as epic_set_antennas; EPIC_E_INVALID (a non-finite kernel value). */
 epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const double *freq_hz,
                                       const float *kernels);
 

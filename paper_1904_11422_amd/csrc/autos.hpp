@@ -13,7 +13,10 @@
 // per channel and product,
 //   S_PQ(d)     = sum_a V_PQ[a] R_a(d)                 ((2K-1)^2 values)
 //   autos_PQ(k) = sum_d S_PQ(d) cos(2 pi d.k / N)      (S_PQ(d) = S_PQ(-d))
-// and YX = conj(XY).  Three kernels:
+// and YX = conj(XY).  With complex kernels R_a(d) = sum_u w_a(u) conj(w_a(u - d))
+// is Hermitian, and autos_PQ(k) = sum_d [S^c_PQ(d) cos - S^s_PQ(d) sin](2 pi d.k / N)
+// with S^c, S^s the sums of V_PQ[a] Re R_a(d) and V_PQ[a] Im R_a(d): the
+// tables then hold both (NQT = 2 NQ values per offset).  Kernels:
 //   auto_sum_kernel    streams the 4+4-bit samples once (HBM bound) and forms
 //                      the integer sums sum_t e_P conj(e_Q) of every antenna
 //                      exactly, four samples per signed 4-bit dot product;
@@ -204,7 +207,9 @@ struct AutoTableArgs {
   const double* sums;       // [C][A][NQ] from auto_fold_kernel
   const float2* gains;      // [C][P][A]
   const float* w;           // [C][A][K*K] tap weights, tap order dj outer, di inner
-  double* table;            // [C][(2K-1)^2][NQ]: {XX, YY, Re XY, Im XY} or {XX}
+  const float* wi;          // [C][A][K*K] imaginary parts (complex kernels)
+  double* table;            // [C][(2K-1)^2][NQT]: {XX, YY, Re XY, Im XY} (cos part, then
+                            // for complex kernels the sin part), or {XX}[, {XX}]
   int n_chan, n_ant;
 };
 
@@ -258,22 +263,42 @@ __device__ __forceinline__ void load_taps(const float* src, float (&w)[K * K]) {
   for (int i = 0; i < K * K; ++i) w[i] = src[i];
 }
 
+// Complex kernel: R(d) = sum_u w(u) conj(w(u - d)) = rr + i ri.
+template <int K>
+__device__ __forceinline__ void tap_autocorrelation_c(const float (&w)[K * K], const float (&wi)[K * K],
+                                                      int dj, int di, double& rr, double& ri) {
+  rr = 0.0;
+  ri = 0.0;
+#pragma unroll
+  for (int uj = 0; uj < K; ++uj)
+#pragma unroll
+    for (int ui = 0; ui < K; ++ui) {
+      const int vj = uj - dj, vi = ui - di;
+      if (vj >= 0 && vj < K && vi >= 0 && vi < K) {
+        const double ar = w[uj * K + ui], ai = wi[uj * K + ui];
+        const double br = w[vj * K + vi], bi = wi[vj * K + vi];
+        rr = fma(ar, br, fma(ai, bi, rr));
+        ri = fma(ai, br, fma(-ar, bi, ri));
+      }
+    }
+}
+
 // S_PQ(d) for one (channel, tap offset) per wave, the wave's lanes taking
 // antennas lane, lane + 64, ...  Grid: 8 * ceil(C / 8) * ceil((2K-1)^2 / 4)
 // workgroups of four waves; workgroup b takes channel
 // (r / G) * 8 + b % 8 and offsets 4 (r % G) + wave, r = b / 8, G =
 // ceil((2K-1)^2 / 4), so the workgroups of a channel share one XCD.
-template <int P, int K>
+template <int P, int K, bool CPX>
 __global__ void __launch_bounds__(256) auto_table_kernel(AutoTableArgs a) {
-  constexpr int NQ = AutoShape<P>::NQ;
+  constexpr int NQ = AutoShape<P>::NQ, NQT = CPX ? 2 * NQ : NQ;
   constexpr int D = 2 * K - 1, D2 = D * D, KK = K * K, G = (D2 + 3) / 4;
   const int r = blockIdx.x / 8, wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int c = (r / G) * 8 + blockIdx.x % 8, d = (r % G) * 4 + wave;
   if (c >= a.n_chan || d >= D2) return;
   const int dj = d / D - (K - 1), di = d % D - (K - 1);
-  double s[NQ];
+  double s[NQT];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+  for (int q = 0; q < NQT; ++q) s[q] = 0.0;
 #pragma unroll 4
   for (int ant = lane; ant < a.n_ant; ant += 64) {
     const int64_t ca = (int64_t)c * a.n_ant + ant;
@@ -282,78 +307,99 @@ __global__ void __launch_bounds__(256) auto_table_kernel(AutoTableArgs a) {
     for (int q = 0; q < NQ; ++q) m[q] = a.sums[ca * NQ + q];
     float w[KK];
     load_taps<K>(a.w + ca * KK, w);
-    const double rr = tap_autocorrelation<K>(w, dj, di);
+    double rr, ri = 0.0;
+    if constexpr (CPX) {
+      float wi[KK];
+      load_taps<K>(a.wi + ca * KK, wi);
+      tap_autocorrelation_c<K>(w, wi, dj, di, rr, ri);
+    } else {
+      rr = tap_autocorrelation<K>(w, dj, di);
+    }
+    // V_PQ[a] as NQ reals: |g_X|^2 m0, |g_Y|^2 m1, g_X conj(g_Y) (m2 + i m3)
+    double v[NQ];
     const float2 gx = a.gains[(int64_t)c * P * a.n_ant + ant];
     const double gxr = gx.x, gxi = gx.y;
-    s[0] = fma((gxr * gxr + gxi * gxi) * m[0], rr, s[0]);
+    v[0] = (gxr * gxr + gxi * gxi) * m[0];
     if constexpr (P == 2) {
       const float2 gy = a.gains[((int64_t)c * P + 1) * a.n_ant + ant];
       const double gyr = gy.x, gyi = gy.y;
-      s[1] = fma((gyr * gyr + gyi * gyi) * m[1], rr, s[1]);
-      // g_X conj(g_Y) (m2 + i m3)
+      v[1 % NQ] = (gyr * gyr + gyi * gyi) * m[1 % NQ];
       const double hr = gxr * gyr + gxi * gyi, hi = gxi * gyr - gxr * gyi;
-      s[2] = fma(hr * m[2] - hi * m[3], rr, s[2]);
-      s[3] = fma(hr * m[3] + hi * m[2], rr, s[3]);
+      v[2 % NQ] = hr * m[2 % NQ] - hi * m[3 % NQ];
+      v[3 % NQ] = hr * m[3 % NQ] + hi * m[2 % NQ];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      s[q] = fma(v[q], rr, s[q]);
+      if constexpr (CPX) s[NQ + q] = fma(v[q], ri, s[NQ + q]);
     }
   }
   // fixed-order sum over the wave
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int q = 0; q < NQT; ++q)
     for (int off = 32; off > 0; off >>= 1) s[q] += __shfl_down(s[q], off, 64);
   if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) a.table[((int64_t)c * D2 + d) * NQ + q] = s[q];
+    for (int q = 0; q < NQT; ++q) a.table[((int64_t)c * D2 + d) * NQT + q] = s[q];
 }
 
-// The removed term at unshifted pixel (km, kl) from a channel's table st
-// (in LDS, [(2K-1)^2][NQ]) and cs[m] = cos(2 pi m / N): v[q] = sum_d
-// st[d][q] cos(2 pi (di kl + dj km) / N).
-template <int NQ>
-__device__ __forceinline__ void autos_at(const double (*st)[NQ], const double* cs, int N, int K,
-                                         int km, int kl, double (&v)[NQ]) {
+// The removed term at unshifted pixel (km, kl) from a channel's table st (in
+// LDS, [(2K-1)^2][NQT]) and cs[m], sn[m] = cos, sin(2 pi m / N): v[q] =
+// sum_d st[d][q] cos(2 pi (di kl + dj km) / N) (- st[d][NQ + q] sin(...) when CPX).
+template <int NQ, bool CPX>
+__device__ __forceinline__ void autos_at(const double* st, const double* cs, const double* sn, int N,
+                                         int K, int km, int kl, double (&v)[NQ]) {
+  constexpr int NQT = CPX ? 2 * NQ : NQ;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) v[q] = 0.0;
   for (int dj = -(K - 1), d = 0; dj <= K - 1; ++dj)
     for (int di = -(K - 1); di <= K - 1; ++di, ++d) {
-      const double e = cs[(di * kl + dj * km) & (N - 1)];
+      const int m = (di * kl + dj * km) & (N - 1);
+      const double e = cs[m];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] = fma(st[d][q], e, v[q]);
+      for (int q = 0; q < NQ; ++q) v[q] = fma(st[d * NQT + q], e, v[q]);
+      if constexpr (CPX) {
+        const double f = sn[m];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] = fma(-st[d * NQT + NQ + q], f, v[q]);
+      }
     }
 }
 
-// Stage channel c's table and the cosine table into LDS (all threads of the
-// workgroup take part; a barrier follows).
-template <int NQ>
-__device__ __forceinline__ void stage_autos(const double* table, int c, int N, int K,
-                                            double (*st)[NQ], double* cs) {
+// Stage channel c's table (nqt values per offset) and the cosine and sine
+// tables into LDS (all threads of the workgroup take part; a barrier follows).
+__device__ __forceinline__ void stage_autos(const double* table, int c, int N, int K, int nqt,
+                                            double* st, double* cs, double* sn) {
   const int D = 2 * K - 1;
-  for (int i = threadIdx.x; i < D * D * NQ; i += blockDim.x)
-    (&st[0][0])[i] = table[(int64_t)c * D * D * NQ + i];
-  for (int m = threadIdx.x; m < N; m += blockDim.x) cs[m] = cospi(2.0 * m / N);
+  for (int i = threadIdx.x; i < D * D * nqt; i += blockDim.x)
+    st[i] = table[(int64_t)c * D * D * nqt + i];
+  for (int m = threadIdx.x; m < N; m += blockDim.x) sincospi(2.0 * m / N, &sn[m], &cs[m]);
   __syncthreads();
 }
 
 struct AutoRemoveArgs {
-  const double* table;      // [C][(2K-1)^2][NQ]
+  const double* table;      // [C][(2K-1)^2][NQT]
   double2* image;           // [C][NPROD][N][N], fftshifted
   int n_chan, N, K;
+  int cpx;                  // the table holds the sin part too (complex kernels)
 };
 
 // Grid: C * ceil(N^2 / 256) workgroups, channel-major; one thread per pixel.
 template <int P>
 __global__ void __launch_bounds__(256) auto_remove_kernel(AutoRemoveArgs a) {
   constexpr int NQ = AutoShape<P>::NQ;
-  __shared__ double st[AUTO_MAX_D2][NQ];
-  __shared__ double cs[128];
+  __shared__ double st[AUTO_MAX_D2 * 2 * NQ];
+  __shared__ double cs[128], sn[128];
   const int N = a.N, K = a.K, tiles = (N * N + 255) / 256;
   const int c = blockIdx.x / tiles, tile = blockIdx.x % tiles;
-  stage_autos<NQ>(a.table, c, N, K, st, cs);
+  stage_autos(a.table, c, N, K, a.cpx ? 2 * NQ : NQ, st, cs, sn);
   const int pix = tile * 256 + threadIdx.x;
   if (pix >= N * N) return;
   // pixel (q_m, q_l) of the shifted image holds k = (q - N/2) mod N
   const int km = (pix / N + N / 2) & (N - 1), kl = (pix % N + N / 2) & (N - 1);
   double v[NQ];
-  autos_at<NQ>(st, cs, N, K, km, kl, v);
+  if (a.cpx) autos_at<NQ, true>(st, cs, sn, N, K, km, kl, v);
+  else autos_at<NQ, false>(st, cs, sn, N, K, km, kl, v);
   constexpr int NPROD = P == 2 ? 4 : 1;
   double2* img = a.image + (int64_t)c * NPROD * N * N + pix;
   img[0].x -= v[0];
@@ -377,73 +423,90 @@ __global__ void __launch_bounds__(256) auto_remove_kernel(AutoRemoveArgs a) {
 // s_PQ the integer sums of auto_sum_kernel (returned as dL/dRe g + i dL/dIm g).
 struct AutoHatArgs {
   const double2* grad_image;  // [C][NPROD][N][N], fftshifted
-  double* hat;                // [C][(2K-1)^2][NQ]: {Re Gxx, Re Gyy, Re H, Im H} or {Re Gxx}
+  double* hat;                // [C][(2K-1)^2][NQT]: {Re Gxx, Re Gyy, Re H, Im H} or {Re Gxx}
+                              // summed against cos, then (complex kernels) against sin
   int n_chan, N, K;
 };
 
 // Workgroup (c, d) as in auto_table_kernel (grid 8 * ceil(C / 8) * (2K-1)^2),
 // so a channel's upstream gradient is read through one XCD's L2.
-template <int P>
+template <int P, bool CPX>
 __global__ void __launch_bounds__(256) auto_hat_kernel(AutoHatArgs a) {
-  constexpr int NQ = AutoShape<P>::NQ, NPROD = P == 2 ? 4 : 1;
-  __shared__ double cs[128];
-  __shared__ double red[NQ][4];
+  constexpr int NQ = AutoShape<P>::NQ, NPROD = P == 2 ? 4 : 1, NQT = CPX ? 2 * NQ : NQ;
+  __shared__ double cs[128], sn[128];
+  __shared__ double red[NQT][4];
   const int N = a.N, K = a.K, D = 2 * K - 1, D2 = D * D;
   int c, d;
   xcd_channel_offset(D2, c, d);
   if (c >= a.n_chan) return;
   const int dj = d / D - (K - 1), di = d % D - (K - 1);
-  for (int m = threadIdx.x; m < N; m += 256) cs[m] = cospi(2.0 * m / N);
+  for (int m = threadIdx.x; m < N; m += 256) sincospi(2.0 * m / N, &sn[m], &cs[m]);
   __syncthreads();
   const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
-  double v[NQ];
+  double v[NQT];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+  for (int q = 0; q < NQT; ++q) v[q] = 0.0;
   for (int pix = threadIdx.x; pix < N * N; pix += 256) {
     const int km = (pix / N + N / 2) & (N - 1), kl = (pix % N + N / 2) & (N - 1);
-    const double e = cs[(di * kl + dj * km) & (N - 1)];
-    v[0] = fma(gi[pix].x, e, v[0]);
+    const int m = (di * kl + dj * km) & (N - 1);
+    double gq[NQ];
+    gq[0] = gi[pix].x;
     if constexpr (P == 2) {
-      v[1] = fma(gi[3 * N * N + pix].x, e, v[1]);
+      gq[1 % NQ] = gi[3 * N * N + pix].x;
       const double2 xy = gi[N * N + pix], yx = gi[2 * N * N + pix];
-      v[2] = fma(xy.x + yx.x, e, v[2]);
-      v[3] = fma(xy.y - yx.y, e, v[3]);
+      gq[2 % NQ] = xy.x + yx.x;
+      gq[3 % NQ] = xy.y - yx.y;
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      v[q] = fma(gq[q], cs[m], v[q]);
+      if constexpr (CPX) v[NQ + q] = fma(gq[q], sn[m], v[NQ + q]);
     }
   }
-  block_sum256<NQ>(v, red);
+  block_sum256<NQT>(v, red);
   if (threadIdx.x == 0)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) a.hat[((int64_t)c * D2 + d) * NQ + q] = v[q];
+    for (int q = 0; q < NQT; ++q) a.hat[((int64_t)c * D2 + d) * NQT + q] = v[q];
 }
 
 struct AutoGradArgs {
   const double* sums;       // [C][A][NQ] from auto_fold_kernel
   const float2* gains;      // [C][P][A]
   const float* w;           // [C][A][K*K]
-  const double* hat;        // [C][(2K-1)^2][NQ]
+  const float* wi;          // [C][A][K*K] imaginary parts (complex kernels)
+  const double* hat;        // [C][(2K-1)^2][NQT]
   double2* gauto;           // [C][P][A]: the removed term's gradient
   int n_chan, n_ant;
 };
 
-// One thread per (channel, antenna).
-template <int P, int K>
+// One thread per (channel, antenna); U = sum_d Re R(d) Ghat_cos(d) - Im R(d) Ghat_sin(d).
+template <int P, int K, bool CPX>
 __global__ void __launch_bounds__(256) auto_grad_kernel(AutoGradArgs a) {
-  constexpr int NQ = AutoShape<P>::NQ, D = 2 * K - 1, KK = K * K;
+  constexpr int NQ = AutoShape<P>::NQ, D = 2 * K - 1, KK = K * K, NQT = CPX ? 2 * NQ : NQ;
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t CA = (int64_t)a.n_chan * a.n_ant;
   if (idx >= CA) return;
   const int c = (int)(idx / a.n_ant), ant = (int)(idx % a.n_ant);
-  float w[KK];
+  float w[KK], wi[CPX ? KK : 1];
   load_taps<K>(a.w + idx * KK, w);
+  if constexpr (CPX) load_taps<K>(a.wi + idx * KK, wi);
   double u[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) u[q] = 0.0;
-  const double* hc = a.hat + (int64_t)c * D * D * NQ;
+  const double* hc = a.hat + (int64_t)c * D * D * NQT;
   for (int dj = -(K - 1), d = 0; dj <= K - 1; ++dj)
     for (int di = -(K - 1); di <= K - 1; ++di, ++d) {
-      const double r = tap_autocorrelation<K>(w, dj, di);
+      if constexpr (CPX) {
+        double rr, ri;
+        tap_autocorrelation_c<K>(w, wi, dj, di, rr, ri);
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) u[q] = fma(r, hc[d * NQ + q], u[q]);
+        for (int q = 0; q < NQ; ++q)
+          u[q] = fma(rr, hc[d * NQT + q], fma(-ri, hc[d * NQT + NQ + q], u[q]));
+      } else {
+        const double r = tap_autocorrelation<K>(w, dj, di);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) u[q] = fma(r, hc[d * NQ + q], u[q]);
+      }
     }
   double m[NQ];
 #pragma unroll

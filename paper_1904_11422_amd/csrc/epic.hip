@@ -126,6 +126,7 @@ struct epic_ctx {
   DevMem au_tab;                      // [C][(2K-1)^2][NQ] float64
   DevMem au_sums;                     // [C][A][NQ] float64 (exact integer sums)
   DevMem au_w;                        // [C][A][K*K] float32 tap weights
+  DevMem au_wi;                       // [C][A][K*K] imaginary parts (complex kernels)
   DevMem au_hat;                      // [C][(2K-1)^2][NQ] float64 upstream-gradient sums
   DevMem au_gauto;                    // [C][P][A] complex float64 gradient of the removed term
 
@@ -850,13 +851,18 @@ void launch_auto_table(epic_ctx* x, const uint8_t* efield, int64_t n_time, const
   ta.sums = x->au_sums.as<double>();
   ta.gains = reinterpret_cast<const float2*>(gains);
   ta.w = x->au_w.as<float>();
+  ta.wi = x->cpx ? x->au_wi.as<float>() : nullptr;
   ta.table = x->au_tab.as<double>();
   ta.n_chan = C;
   ta.n_ant = A;
   const dim3 tg((unsigned)((int64_t)8 * ((C + 7) / 8) * ((D2 + 3) / 4)));
-#define EPIC_AT(PP, KK_)                                                                      \
-  if (P == PP && K == KK_) hipLaunchKernelGGL((epic::auto_table_kernel<PP, KK_>), tg, dim3(256), 0, \
-                                              x->stream, ta);
+#define EPIC_AT(PP, KK_)                                                                           \
+  if (P == PP && K == KK_) {                                                                       \
+    if (x->cpx) hipLaunchKernelGGL((epic::auto_table_kernel<PP, KK_, true>), tg, dim3(256), 0,      \
+                                   x->stream, ta);                                                 \
+    else hipLaunchKernelGGL((epic::auto_table_kernel<PP, KK_, false>), tg, dim3(256), 0, x->stream, \
+                            ta);                                                                   \
+  }
   EPIC_AT(1, 1) EPIC_AT(1, 3) EPIC_AT(1, 5) EPIC_AT(1, 7)
   EPIC_AT(2, 1) EPIC_AT(2, 3) EPIC_AT(2, 5) EPIC_AT(2, 7)
 #undef EPIC_AT
@@ -871,6 +877,7 @@ void launch_auto_remove(epic_ctx* x, double* image) {
   ra.n_chan = C;
   ra.N = N;
   ra.K = K;
+  ra.cpx = x->cpx ? 1 : 0;
   const dim3 rg((unsigned)((int64_t)C * ((N * N + 255) / 256)));
   if (P == 2) hipLaunchKernelGGL(epic::auto_remove_kernel<2>, rg, dim3(256), 0, x->stream, ra);
   else hipLaunchKernelGGL(epic::auto_remove_kernel<1>, rg, dim3(256), 0, x->stream, ra);
@@ -889,20 +896,30 @@ void launch_autos_grad(epic_ctx* x, const uint8_t* efield, int64_t n_time, const
   ha.N = N;
   ha.K = K;
   const dim3 hg((unsigned)((int64_t)8 * ((C + 7) / 8) * D2));
-  if (P == 2) hipLaunchKernelGGL(epic::auto_hat_kernel<2>, hg, dim3(256), 0, x->stream, ha);
-  else hipLaunchKernelGGL(epic::auto_hat_kernel<1>, hg, dim3(256), 0, x->stream, ha);
+  if (P == 2) {
+    if (x->cpx) hipLaunchKernelGGL((epic::auto_hat_kernel<2, true>), hg, dim3(256), 0, x->stream, ha);
+    else hipLaunchKernelGGL((epic::auto_hat_kernel<2, false>), hg, dim3(256), 0, x->stream, ha);
+  } else {
+    if (x->cpx) hipLaunchKernelGGL((epic::auto_hat_kernel<1, true>), hg, dim3(256), 0, x->stream, ha);
+    else hipLaunchKernelGGL((epic::auto_hat_kernel<1, false>), hg, dim3(256), 0, x->stream, ha);
+  }
   epic::AutoGradArgs ga;
   ga.sums = x->au_sums.as<double>();
   ga.gains = reinterpret_cast<const float2*>(gains);
   ga.w = x->au_w.as<float>();
+  ga.wi = x->cpx ? x->au_wi.as<float>() : nullptr;
   ga.hat = x->au_hat.as<double>();
   ga.gauto = x->au_gauto.as<double2>();
   ga.n_chan = C;
   ga.n_ant = A;
   const dim3 gg((unsigned)(((int64_t)C * A + 255) / 256));
-#define EPIC_AG(PP, KK_)                                                                     \
-  if (P == PP && K == KK_) hipLaunchKernelGGL((epic::auto_grad_kernel<PP, KK_>), gg, dim3(256), 0, \
-                                              x->stream, ga);
+#define EPIC_AG(PP, KK_)                                                                          \
+  if (P == PP && K == KK_) {                                                                      \
+    if (x->cpx) hipLaunchKernelGGL((epic::auto_grad_kernel<PP, KK_, true>), gg, dim3(256), 0,      \
+                                   x->stream, ga);                                                \
+    else hipLaunchKernelGGL((epic::auto_grad_kernel<PP, KK_, false>), gg, dim3(256), 0, x->stream, \
+                            ga);                                                                  \
+  }
   EPIC_AG(1, 1) EPIC_AG(1, 3) EPIC_AG(1, 5) EPIC_AG(1, 7)
   EPIC_AG(2, 1) EPIC_AG(2, 3) EPIC_AG(2, 5) EPIC_AG(2, 7)
 #undef EPIC_AG
@@ -1017,6 +1034,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
     r.autos = nullptr;
     r.K = x->cfg.kernel_support;
+    r.autos_cpx = x->cpx ? 1 : 0;
     if (x->autos) {
       launch_auto_table(x, efield, n_time, gains);
       r.autos = x->au_tab.as<double>();
@@ -1080,6 +1098,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.sub = 1;
     r.autos = nullptr;
     r.K = x->cfg.kernel_support;
+    r.autos_cpx = x->cpx ? 1 : 0;
     if (x->autos) {
       launch_auto_table(x, efield, n_time, gains);
       r.autos = x->au_tab.as<double>();
@@ -1190,9 +1209,9 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
                                    : occupancy_blocks(epic::auto_sum_kernel<1, 4>, st);
     x->au_nseg_cap = (int)std::max<size_t>(1, std::min<size_t>(epic::AUTO_MAX_SEG, (256u << 20) / per_seg));
     if (!x->au_part.alloc(x->au_nseg_cap * per_seg) ||
-        !x->au_tab.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
+        !x->au_tab.alloc((size_t)cfg->n_chan * D * D * 2 * NQ * sizeof(double)) ||
         !x->au_sums.alloc((size_t)cfg->n_chan * cfg->n_ant * NQ * sizeof(double)) ||
-        !x->au_hat.alloc((size_t)cfg->n_chan * D * D * NQ * sizeof(double)) ||
+        !x->au_hat.alloc((size_t)cfg->n_chan * D * D * 2 * NQ * sizeof(double)) ||
         !x->au_gauto.alloc((size_t)cfg->n_chan * x->PA * 2 * sizeof(double))) {
       g_init_error = "autocorrelation workspace allocation failed";
       delete x;
@@ -1272,8 +1291,6 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
                                       const float* kernels) {
   if (!x) return EPIC_E_INVALID;
   if (!xy_m || !freq_hz) return x->fail(EPIC_E_INVALID, "xy_m or freq_hz is NULL");
-  if (kernels && x->autos)
-    return x->fail(EPIC_E_UNSUPPORTED, "EPIC_FLAG_REMOVE_AUTOS takes the Gaussian kernel only");
   Geometry g;
   std::string m;
   epic_status s = build_geometry(x->cfg, xy_m, freq_hz, kernels, g, m);
@@ -1286,7 +1303,10 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
   x->cpx = kernels != nullptr;
   if (x->autos &&
       (!x->au_w.alloc(g.w.size() * sizeof(float)) ||
-       hipMemcpy(x->au_w.p, g.w.data(), g.w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess))
+       hipMemcpy(x->au_w.p, g.w.data(), g.w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+       (x->cpx && (!x->au_wi.alloc(g.wi.size() * sizeof(float)) ||
+                   hipMemcpy(x->au_wi.p, g.wi.data(), g.wi.size() * sizeof(float),
+                             hipMemcpyHostToDevice) != hipSuccess))))
     return x->fail(EPIC_E_NOMEM, "kernel weight upload failed");
   s = build_taper(x, g);
   if (s != EPIC_OK) return s;
@@ -1540,7 +1560,7 @@ void epic_destroy(epic_ctx* x) {
     x->st_e.reset(); x->st_grid.reset(); x->st_acc.reset();
     x->sp_beta.reset(); x->sp_betamax.reset(); x->sp_bmat.reset(); x->sp_scale.reset();
     x->sp_partial.reset();
-    x->au_part.reset(); x->au_tab.reset(); x->au_sums.reset(); x->au_w.reset(); x->au_hat.reset();
+    x->au_part.reset(); x->au_tab.reset(); x->au_sums.reset(); x->au_wi.reset(); x->au_w.reset(); x->au_hat.reset();
     x->au_gauto.reset();
   }
   delete x;

@@ -459,8 +459,9 @@ struct ReduceArgs {
   int n_chan, W, reset;
   int sub;                  // 1, 4 or 16 sub-lanes per pixel
   const double* autos;      // table of the antenna autocorrelations to subtract
-                            // ([C][(2K-1)^2][NACC], autos.hpp), or null
+                            // ([C][(2K-1)^2][NACC (x2 with autos_cpx)], autos.hpp), or null
   int K;
+  int autos_cpx;            // the table has the sin part (complex kernels)
 };
 
 // Workgroup whose range contains flat index f: the largest w with
@@ -485,8 +486,8 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int NPIX = N * N;
   __shared__ double red[NACC * 256];
-  __shared__ double ast[AUTO_MAX_D2][NACC];
-  __shared__ double acs[128];
+  __shared__ double ast[AUTO_MAX_D2 * 2 * NACC];
+  __shared__ double acs[128], asn[128];
   const int ppb = 256 / a.sub;
   const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
   const int64_t idx = (int64_t)blockIdx.x * ppb + lp;
@@ -507,7 +508,9 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
     }
   }
   // a workgroup's pixels lie in one channel (N^2 is a multiple of 256 / sub)
-  if (a.autos) stage_autos<NACC>(a.autos, (int)((int64_t)blockIdx.x * ppb / NPIX), N, a.K, ast, acs);
+  if (a.autos)
+    stage_autos(a.autos, (int)((int64_t)blockIdx.x * ppb / NPIX), N, a.K,
+                a.autos_cpx ? 2 * NACC : NACC, ast, acs, asn);
   combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
   if (!valid || j != 0) return;
   int km, kl;
@@ -533,7 +536,8 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   }
   if (a.autos) {
     double v[NACC];
-    autos_at<NACC>(ast, acs, N, a.K, km, kl, v);
+    if (a.autos_cpx) autos_at<NACC, true>(ast, acs, asn, N, a.K, km, kl, v);
+    else autos_at<NACC, false>(ast, acs, asn, N, a.K, km, kl, v);
     val[0].x -= v[0];
     if (P == 2) {
       val[3 % NPROD].x -= v[1 % NACC];

@@ -29,8 +29,12 @@ def _imager(inp, remove_autos=True, staged=False, precision="fp32", timing=False
     im = Imager(inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.kernel_support,
                 inp.kernel_sigma_cells, inp.cell_wavelengths, precision=precision,
                 staged=staged, timing=timing, remove_autos=remove_autos)
-    im.set_antennas(inp.xy_m, inp.freq_hz)
+    im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
     return im
+
+
+def _cplx(seed, N, A, C, P, T, K, fill=0.4):
+    return synth.with_kernels(synth.random_problem(seed, N, A, C, P, T, fill=fill), K, seed + 1)
 
 
 def _dev(inp):
@@ -83,6 +87,12 @@ CASES = {
     "split_bf16_p1_A7": (lambda: synth.random_problem(409, 32, 7, 3, 1, 33),
                          {"precision": "split_bf16"}),
     "cfg1": (lambda: synth.config1(), {}),
+    # the caller's complex kernels
+    "n64_p2_k5_complex": (lambda: _cplx(441, 64, 96, 2, 2, 9, 5), {}),
+    "n32_p1_k3_complex": (lambda: _cplx(442, 32, 36, 2, 1, 11, 3), {}),
+    "n128_p2_k7_complex": (lambda: _cplx(443, 128, 200, 2, 2, 4, 7, fill=0.4), {}),
+    "n64_p2_k3_complex_staged": (lambda: _cplx(444, 64, 50, 2, 2, 6, 3), {"staged": True}),
+    "split16_p2_k5_complex": (lambda: _cplx(445, 32, 16, 2, 2, 30, 5), {"precision": "split_fp16"}),
 }
 
 
@@ -95,7 +105,7 @@ def test_removed_image_matches_oracle(name):
     ref_full = oracle.image_from(inp)
     autos = oracle.autocorrelation_image(inp.xy_m, inp.freq_hz, inp.gains, inp.efield,
                                          inp.grid_n, inp.kernel_support, inp.kernel_sigma_cells,
-                                         inp.cell_wavelengths)
+                                         inp.cell_wavelengths, inp.kernels)
     assert np.all(np.isfinite(got))
     # the removed term alone, to the weights' rounding
     dr = np.linalg.norm((full - got - autos).reshape(inp.n_chan, -1), axis=-1)
@@ -153,17 +163,18 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("seed,N,A,C,P,T", [(421, 32, 16, 2, 2, 5), (422, 32, 20, 1, 1, 7),
-                                          (423, 64, 256, 3, 2, 11), (424, 64, 90, 2, 1, 4),
-                                          (425, 64, 150, 2, 2, 6)])
-def test_grad_without_autos_matches_oracle(seed, N, A, C, P, T):
+@pytest.mark.parametrize("seed,N,A,C,P,T,K", [(421, 32, 16, 2, 2, 5, 0), (422, 32, 20, 1, 1, 7, 0),
+                                            (423, 64, 256, 3, 2, 11, 0), (424, 64, 90, 2, 1, 4, 0),
+                                            (425, 64, 150, 2, 2, 6, 0), (426, 32, 24, 2, 2, 5, 5),
+                                            (427, 64, 80, 2, 1, 4, 3)])
+def test_grad_without_autos_matches_oracle(seed, N, A, C, P, T, K):
     """Gain gradient of an L2 loss on the removed image (bar of the gradient:
     1e-4 relative); the removed term's share (full-image gradient minus this
     one, both float32-rounded from identical float64 sums) to 1e-6 of the
     full gradient."""
     import torch
-    inp = synth.random_problem(seed, N, A, C, P, T)
-    print(f"case {inp.name}: N={N} C={C} P={P} A={A} T={T}", flush=True)
+    inp = _cplx(seed, N, A, C, P, T, K, fill=0.35) if K else synth.random_problem(seed, N, A, C, P, T)
+    print(f"case {inp.name}: N={N} C={C} P={P} A={A} T={T} K={inp.kernel_support}", flush=True)
     ef, g = _dev(inp)
     im = _imager(inp)
     img = im.accumulate(ef, g).cpu().numpy()
@@ -172,10 +183,13 @@ def test_grad_without_autos_matches_oracle(seed, N, A, C, P, T):
     gam = oracle.l2_loss_grad_image(img, model)
     gam_d = torch.from_numpy(gam).cuda()
     got = im.backward(ef, g, gam_d).cpu().numpy()
-    ref = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam)
+    Kk = inp.kernel_support
+    ref = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam, Kk,
+                                          kernels=inp.kernels)
     assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
     full = _imager(inp, remove_autos=False).backward(ef, g, gam_d).cpu().numpy()
-    share = oracle.grad_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam)
+    share = oracle.grad_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam, Kk,
+                              kernels=inp.kernels)
     d = np.linalg.norm((full - got) - share) / np.linalg.norm(full)
     print(f"  grad err {_rel(got, ref):.3e}, share err {d:.3e}")
     assert d <= TOL_AUTOS, f"{d:.3e}"
