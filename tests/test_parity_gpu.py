@@ -204,3 +204,24 @@ def test_config2_full_size_sampled_channels():
     assert np.all(got[:, 0].real >= 0) and np.all(got[:, 3].real >= 0)
     assert np.all(np.abs(got[:, 1]) ** 2 <= got[:, 0].real * got[:, 3].real * (1 + 1e-5) + 1e-3)
     del torch
+
+
+@pytest.mark.parametrize("seed,N,A,C,P,T,fill,route", [
+    (801, 128, 4096, 1, 2, 2, 0.9, "staged_fft_kernel"),     # the largest antenna count taken
+    (802, 64, 1024, 2, 1, 3, 0.48, "fused_image_kernel"),    # 2 samples per thread
+    (803, 64, 2048, 1, 2, 2, 0.9, "staged_fft_kernel"),      # beyond 4 samples per thread
+])
+def test_maximum_antenna_counts(seed, N, A, C, P, T, fill, route):
+    """The largest configurations: A = 4096 (the limit), and the switch from
+    the fused kernels to the staged ones once a thread would hold more than
+    four samples or the aperture leaves N/2 cells."""
+    inp = synth.random_problem(seed, N, A, C, P, T, fill=fill)
+    got, im = _run(inp)
+    assert im.last_kernel_name() == route
+    assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
+
+
+def test_antenna_limit_is_enforced():
+    from paper_1904_11422_amd import EpicError, Imager
+    with pytest.raises(EpicError, match="INVALID"):
+        Imager(64, 1, 2, 4097)
