@@ -21,6 +21,9 @@ def hipcc_command(out: str = LIB, extra=()) -> list:
     return [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off (see the design notes)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # matrix-core results in ordinary VGPRs: the split-precision
+            # epilogue reads them without accumulator-register moves
+            "-mllvm", "-amdgpu-mfma-vgpr-form",
             "-I", os.path.join(ROOT, "include"), *extra, "-o", out, *SOURCES]
 
 

@@ -734,18 +734,20 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   pa.n_ant = A;
   pa.a_pad = x->sp_apad;
   pa.ng = NG;
-  // chunks of about 2048 matrix entries per workgroup
-  const unsigned pchunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)NG * x->sp_apad + 2047) / 2048));
+  // chunks of about 256 matrix entries per workgroup (one per thread: the
+  // work is latency-bound, not bandwidth-bound)
+  const unsigned pchunks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, ((int64_t)NG * x->sp_apad + 255) / 256));
   const dim3 pgrid((unsigned)(C * P), pchunks);
   if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, pgrid, dim3(256), 0, x->stream, pa);
   else hipLaunchKernelGGL(epic::split_prep_kernel<false>, pgrid, dim3(256), 0, x->stream, pa);
-  // tile groups of TPW 32-pixel tiles per wave (two while the operands of
-  // two tiles fit the registers); time chunks so that about three waves per
-  // SIMD are resident, each at least 256 samples long
+  // tile groups of TPW 32-pixel tiles per wave: four for one polarisation
+  // and one antenna block (the sample conversion is shared by four tiles;
+  // two waves per SIMD fit), else one; time chunks so that the resident
+  // waves fill every SIMD, each at least 256 samples long
   const int qb = x->sp_qb;
-  const int tpw = (P == 1 && qb == 1) ? 2 : 1;
+  const int tpw = (P == 1 && qb == 1) ? 4 : 1;
   const int64_t groups = (int64_t)(NG / 32 / tpw) * C;
-  const int64_t want_waves = 3LL * 4 * x->n_cu;
+  const int64_t want_waves = (tpw == 4 ? 2LL : 3LL) * 4 * x->n_cu;
   int64_t n_ch = std::max<int64_t>(1, (want_waves + groups - 1) / groups);
   int64_t chunk = (n_time + n_ch - 1) / n_ch;
   chunk = std::max<int64_t>(256, (chunk + 31) / 32 * 32);
@@ -763,13 +765,14 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   sa.ng = NG;
   sa.chunk = (int)chunk;
   sa.n_chunks = n_chunks;
-  const dim3 grid((unsigned)((NG / 32 / tpw + 3) / 4), (unsigned)n_chunks, (unsigned)C);
+  sa.tile_wgs = (NG / 32 / tpw + 3) / 4;
+  const dim3 grid((unsigned)((int64_t)sa.tile_wgs * n_chunks * C));
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   // 8-byte sample loads need A % 8 == 0 and an 8-byte aligned E-field
   const bool vec = A % 8 == 0 && (reinterpret_cast<uintptr_t>(efield) & 7) == 0;
   if (P == 1) {
-    if (bf) { if (qb == 1) launch_split_image<1, true, 1, 2>(x, sa, grid, vec); else launch_split_image<1, true, 2, 1>(x, sa, grid, vec); }
-    else    { if (qb == 1) launch_split_image<1, false, 1, 2>(x, sa, grid, vec); else launch_split_image<1, false, 2, 1>(x, sa, grid, vec); }
+    if (bf) { if (qb == 1) launch_split_image<1, true, 1, 4>(x, sa, grid, vec); else launch_split_image<1, true, 2, 1>(x, sa, grid, vec); }
+    else    { if (qb == 1) launch_split_image<1, false, 1, 4>(x, sa, grid, vec); else launch_split_image<1, false, 2, 1>(x, sa, grid, vec); }
   } else {
     if (bf) launch_split_image<2, true, 1, 1>(x, sa, grid, vec);
     else launch_split_image<2, false, 1, 1>(x, sa, grid, vec);

@@ -61,23 +61,18 @@ struct SplitPrepArgs {
   int n_chan, n_pol, n_ant, a_pad, ng;
 };
 
-// Workgroups (channel and polarisation, chunk of the matrix); each computes
-// the scale of its (channel, polarisation) from the gains (A <= 32 values).
+// Workgroups (channel and polarisation, chunk of about 256 matrix entries,
+// one per thread); every wave computes the scale of its (channel,
+// polarisation) from the gains itself (A <= 32 values, a wave-wide maximum).
 template <bool BF>
 __global__ void __launch_bounds__(256) split_prep_kernel(SplitPrepArgs a) {
   const int cp = blockIdx.x;
   const int c = cp / a.n_pol;
   const float2* g = a.gains + (int64_t)cp * a.n_ant;
-  __shared__ double red[256];
   double m = 0.0;
-  for (int i = threadIdx.x; i < a.n_ant; i += 256) m = fmax(m, hypot((double)g[i].x, (double)g[i].y));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  const double bmax = red[0] * a.beta_max[c];
+  for (int i = threadIdx.x & 63; i < a.n_ant; i += 64) m = fmax(m, hypot((double)g[i].x, (double)g[i].y));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  const double bmax = m * a.beta_max[c];
   // scale so that |B s| < 2^14: the hi parts stay finite, the lo parts normal
   const double sc = bmax > 0.0 ? ldexp(1.0, 13 - ilogb(bmax)) : 1.0;
   if (threadIdx.x == 0 && blockIdx.y == 0) a.scale[cp] = (float)sc;
@@ -119,6 +114,7 @@ struct SplitArgs {
   double* partial;          // [C][n_chunks][NACC][2][NG]
   int64_t n_time;
   int n_chan, n_ant, a_pad, ng, chunk, n_chunks;
+  int tile_wgs;             // workgroups per (chunk, channel)
 };
 
 template <bool BF> struct SplitOps;
@@ -127,11 +123,29 @@ template <> struct SplitOps<false> {
   static __device__ __forceinline__ float16v_t mfma(v8 x, v8 y, float16v_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ v8 from_ints(const int (&q)[8]) {
-    v8 r;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = (_Float16)q[i];
-    return r;
+  // The 8 complex samples of one row (a byte each: real part in the high
+  // nibble, imaginary in the low, two's complement) as float16 real and
+  // imaginary parts.  w ^ 0x88888888 biases every nibble by 8 (m = v + 8 in
+  // 0..15); m placed under the high byte 0x64 is the float16 pattern of
+  // 1024 + m, exactly, and one packed subtraction of 1032 leaves v.
+  static __device__ __forceinline__ void unpack(uint2 w, v8& er, v8& ei) {
+    const uint32_t tx = w.x ^ 0x88888888u, ty = w.y ^ 0x88888888u;
+    const uint32_t ix = tx & 0x0F0F0F0Fu, iy = ty & 0x0F0F0F0Fu;
+    const uint32_t rx = (tx >> 4) & 0x0F0F0F0Fu, ry = (ty >> 4) & 0x0F0F0F0Fu;
+    constexpr uint32_t kExp = 0x64646464u;
+    // bytes m0 m1 (selectors 0x04010400) or m2 m3 (0x04030402), each under 0x64
+    const uint4 rb = make_uint4(__builtin_amdgcn_perm(kExp, rx, 0x04010400u),
+                                __builtin_amdgcn_perm(kExp, rx, 0x04030402u),
+                                __builtin_amdgcn_perm(kExp, ry, 0x04010400u),
+                                __builtin_amdgcn_perm(kExp, ry, 0x04030402u));
+    const uint4 ib = make_uint4(__builtin_amdgcn_perm(kExp, ix, 0x04010400u),
+                                __builtin_amdgcn_perm(kExp, ix, 0x04030402u),
+                                __builtin_amdgcn_perm(kExp, iy, 0x04010400u),
+                                __builtin_amdgcn_perm(kExp, iy, 0x04030402u));
+    const _Float16 b = (_Float16)1032.0f;
+    const v8 bias = {b, b, b, b, b, b, b, b};
+    er = __builtin_bit_cast(v8, rb) - bias;
+    ei = __builtin_bit_cast(v8, ib) - bias;
   }
 };
 template <> struct SplitOps<true> {
@@ -139,11 +153,18 @@ template <> struct SplitOps<true> {
   static __device__ __forceinline__ float16v_t mfma(v8 x, v8 y, float16v_t c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ v8 from_ints(const int (&q)[8]) {
-    v8 r;
+  // as for float16, through the sign-extended nibbles (no packed bfloat16
+  // add on this chip); small integers are exact in bfloat16.  The sign
+  // extension is written as shifts: the compiler used here converts the
+  // result of __builtin_amdgcn_sbfe to float as if it were unsigned.
+  static __device__ __forceinline__ void unpack(uint2 w, v8& er, v8& ei) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) r[i] = (__bf16)(float)q[i];   // small integers: exact
-    return r;
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t x = (i < 4) ? w.x : w.y;
+      const int sh = 8 * (i & 3);
+      er[i] = (__bf16)(float)((int)(x << (24 - sh)) >> 28);   // high nibble
+      ei[i] = (__bf16)(float)((int)(x << (28 - sh)) >> 28);   // low nibble
+    }
   }
 };
 
@@ -171,19 +192,35 @@ __device__ __forceinline__ uint2 load_e8(const uint8_t* row, int first_ant, int 
   return make_uint2(w[0], w[1]);
 }
 
+// Sample-row blocks loaded ahead of the one on the matrix units: the rows
+// come from HBM and a block's matrix work is shorter than that latency
+// (two polarisations: half the depth, which keeps three waves per SIMD).
+template <int P> constexpr int split_prefetch() { return P == 2 ? 2 : 4; }
+
+// Workgroup id -> logical index such that consecutive logical indices share
+// an XCD (workgroups are dealt to the 8 XCDs round-robin by id): XCD j holds
+// logical indices [j q + min(j, r), ...) of the n = 8 q + r workgroups.
+__device__ __forceinline__ int xcd_contiguous_index(int id, int n) {
+  const int q = n >> 3, r = n & 7, j = id & 7;
+  return j * q + (j < r ? j : r) + (id >> 3);
+}
+
 // One wave per (TPW 32-pixel tiles, time chunk, channel); 4 waves per
-// workgroup on consecutive tile groups.  QB antenna blocks of 16
-// (A <= 16 QB).  The samples of the next 32-row block are loaded while the
-// current one is on the matrix units.
+// workgroup on consecutive tile groups; the workgroups of one (chunk,
+// channel), which read the same sample rows, share an XCD and its L2.  QB
+// antenna blocks of 16 (A <= 16 QB).
 template <int P, bool BF, int QB, int TPW, bool VEC>
 __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
   using Ops = SplitOps<BF>;
   using v8 = typename Ops::v8;
   constexpr int NACC = (P == 2) ? 4 : 1;
+  constexpr int PD = split_prefetch<P>();
   const int lane = threadIdx.x & 63;
-  const int tile0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * TPW;
-  const int c = blockIdx.z;
-  const int chunk = blockIdx.y;
+  const int logical = xcd_contiguous_index((int)blockIdx.x, (int)gridDim.x);
+  const int rest = logical / a.tile_wgs;
+  const int tile0 = ((logical - rest * a.tile_wgs) * 4 + (threadIdx.x >> 6)) * TPW;
+  const int chunk = rest % a.n_chunks;
+  const int c = rest / a.n_chunks;
   if (tile0 * 32 >= a.ng) return;
   const int n = lane & 31, h = lane >> 5;
 
@@ -215,24 +252,30 @@ __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
   const int64_t row_bytes = (int64_t)a.n_chan * P * a.n_ant;
   const uint8_t* chan = a.efield + (int64_t)c * P * a.n_ant;
 
-  uint2 nxt[P][QB];
-  auto load_block = [&](int64_t t0) {
+  // ring of PD sample-row blocks; block k sits in slot k % PD
+  uint2 ring[PD][P][QB];
+  auto load_block = [&](uint2 (&dst)[P][QB], int64_t t0) {
     const int64_t t = t0 + n;                  // this lane's sample row of E
     const uint8_t* row = chan + t * row_bytes;
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < QB; ++q)
-        nxt[p][q] = load_e8<VEC>(row + p * a.n_ant, 16 * q + 8 * h, a.n_ant, t < t_end);
+        dst[p][q] = load_e8<VEC>(row + p * a.n_ant, 16 * q + 8 * h, a.n_ant, t < t_end);
   };
-  load_block(t_begin);
-  for (int64_t t0 = t_begin; t0 < t_end; t0 += 32) {
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load_block(ring[d], t_begin + 32 * d);
+  for (int64_t tb = t_begin; tb < t_end; tb += 32 * PD)
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int64_t t0 = tb + 32 * d;
+    if (t0 >= t_end) break;
     uint2 cur[P][QB];
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int q = 0; q < QB; ++q) cur[p][q] = nxt[p][q];
-    if (t0 + 32 < t_end) load_block(t0 + 32);
+      for (int q = 0; q < QB; ++q) cur[p][q] = ring[d][p][q];
+    if (t0 + 32 * PD < t_end) load_block(ring[d], t0 + 32 * PD);
 
     float16v_t dre[TPW][P], dim[TPW][P];
 #pragma unroll
@@ -246,14 +289,8 @@ __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
-        int re[8], im[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const uint32_t w = (i < 4) ? cur[p][q].x : cur[p][q].y;
-          re[i] = __builtin_amdgcn_sbfe((int)w, 8 * (i & 3) + 4, 4);   // high nibble
-          im[i] = __builtin_amdgcn_sbfe((int)w, 8 * (i & 3), 4);       // low nibble
-        }
-        const v8 er = Ops::from_ints(re), ei = Ops::from_ints(im);
+        v8 er, ei;
+        Ops::unpack(cur[p][q], er, ei);
         // Re(F s) = Br er - Bi ei ; Im(F s) = Bi er + Br ei   (hi and lo terms)
 #pragma unroll
         for (int u = 0; u < TPW; ++u)
