@@ -39,6 +39,12 @@ CASES = {
     "p2_a16": lambda: synth.random_problem(301, 32, 16, 2, 2, 45),
     "p1_a32_n64": lambda: synth.random_problem(302, 64, 32, 2, 1, 70),
     "p1_a7_ragged": lambda: synth.random_problem(303, 32, 7, 3, 1, 33),
+    # chunks of 9 blocks (not a multiple of the 4-block sample ring), a
+    # 16-sample last chunk
+    "cfg3_t70000": lambda: synth.config3(n_time=70_000),
+    # two polarisations over 12 chunks of 256 samples (2-block ring), the last
+    # one 184 samples long
+    "p2_a16_t3000": lambda: synth.random_problem(305, 32, 16, 1, 2, 3000),
 }
 
 
