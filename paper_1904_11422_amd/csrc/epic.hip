@@ -112,6 +112,7 @@ struct epic_ctx {
   // split-precision matrix form
   DevMem sp_beta, sp_betamax, sp_bmat, sp_scale, sp_partial;
   int sp_apad = 0, sp_qb = 0, sp_max_chunks = 0;
+  int sp_wgs_per_cu[2] = {1, 1};     // resident split-image workgroups per CU (byte, 8-byte loads)
 
   // timing
   bool timing = false, timed = false;
@@ -663,6 +664,49 @@ bool alloc_staged(epic_ctx* x) {
 // Split-precision tables: beta[c][pix][a] = sum_taps w exp(+2 pi i (i kl + j km)/N)
 // in float64 (pix = km*N + kl), its per-channel maximum modulus, and the
 // workspace of the matrix kernels.
+// pixel tiles per wave of the split-image kernel: two for one polarisation and
+// one antenna block (the sample conversion is shared by both tiles), else one
+int split_tpw(int P, int qb) { return (P == 1 && qb == 1) ? 2 : 1; }
+
+template <int P, bool BF, int QB, int TPW>
+void launch_split_image(epic_ctx* x, const epic::SplitArgs& a, dim3 grid, bool vec) {
+  if (vec) hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, true>), grid, dim3(256), 0, x->stream, a);
+  else hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, false>), grid, dim3(256), 0, x->stream, a);
+}
+
+template <int P, bool BF, int QB, int TPW>
+void split_occupancy(epic_ctx* x) {
+  x->sp_wgs_per_cu[0] = occupancy_blocks(epic::split_image_kernel<P, BF, QB, TPW, false>, 256);
+  x->sp_wgs_per_cu[1] = occupancy_blocks(epic::split_image_kernel<P, BF, QB, TPW, true>, 256);
+}
+
+struct SplitOccupancy {
+  epic_ctx* x;
+  template <int P, bool BF, int QB, int TPW> void operator()() const { split_occupancy<P, BF, QB, TPW>(x); }
+};
+struct SplitLaunch {
+  epic_ctx* x;
+  const epic::SplitArgs* a;
+  dim3 grid;
+  bool vec;
+  template <int P, bool BF, int QB, int TPW> void operator()() const {
+    launch_split_image<P, BF, QB, TPW>(x, *a, grid, vec);
+  }
+};
+
+// dispatch on (P, precision, antenna blocks) to the instantiated split-image
+// kernels: f.operator()<P, BF, QB, TPW>()
+template <typename F>
+void split_dispatch(int P, bool bf, int qb, F&& f) {
+  if (P == 1) {
+    if (bf) { if (qb == 1) f.template operator()<1, true, 1, 2>(); else f.template operator()<1, true, 2, 1>(); }
+    else    { if (qb == 1) f.template operator()<1, false, 1, 2>(); else f.template operator()<1, false, 2, 1>(); }
+  } else {
+    if (bf) f.template operator()<2, true, 1, 1>();
+    else f.template operator()<2, false, 1, 1>();
+  }
+}
+
 epic_status build_split_tables(epic_ctx* x, const Geometry& g) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, A = x->cfg.n_ant, P = x->cfg.n_pol;
   const int NG = N * N;
@@ -709,14 +753,10 @@ epic_status build_split_tables(epic_ctx* x, const Geometry& g) {
   x->sp_apad = apad;
   x->sp_qb = qb;
   x->sp_max_chunks = max_chunks;
+  split_dispatch(P, x->cfg.precision == EPIC_SPLIT_BF16, qb, SplitOccupancy{x});
   return EPIC_OK;
 }
 
-template <int P, bool BF, int QB, int TPW>
-void launch_split_image(epic_ctx* x, const epic::SplitArgs& a, dim3 grid, bool vec) {
-  if (vec) hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, true>), grid, dim3(256), 0, x->stream, a);
-  else hipLaunchKernelGGL((epic::split_image_kernel<P, BF, QB, TPW, false>), grid, dim3(256), 0, x->stream, a);
-}
 
 epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
                       double* image, int32_t reset) {
@@ -740,14 +780,15 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   const dim3 pgrid((unsigned)(C * P), pchunks);
   if (bf) hipLaunchKernelGGL(epic::split_prep_kernel<true>, pgrid, dim3(256), 0, x->stream, pa);
   else hipLaunchKernelGGL(epic::split_prep_kernel<false>, pgrid, dim3(256), 0, x->stream, pa);
-  // tile groups of TPW 32-pixel tiles per wave: four for one polarisation
-  // and one antenna block (the sample conversion is shared by four tiles;
-  // two waves per SIMD fit), else one; time chunks so that the resident
-  // waves fill every SIMD, each at least 256 samples long
+  // tile groups of split_tpw(P, qb) 32-pixel tiles per wave; time chunks so
+  // that the resident waves (the kernel's occupancy, queried once per
+  // geometry) fill every SIMD, each at least 256 samples long
   const int qb = x->sp_qb;
-  const int tpw = (P == 1 && qb == 1) ? 4 : 1;
+  const int tpw = split_tpw(P, qb);
+  // 8-byte sample loads need A % 8 == 0 and an 8-byte aligned E-field
+  const bool vec = A % 8 == 0 && (reinterpret_cast<uintptr_t>(efield) & 7) == 0;
   const int64_t groups = (int64_t)(NG / 32 / tpw) * C;
-  const int64_t want_waves = (tpw == 4 ? 2LL : 3LL) * 4 * x->n_cu;
+  const int64_t want_waves = (int64_t)x->sp_wgs_per_cu[vec ? 1 : 0] * 4 * x->n_cu;
   int64_t n_ch = std::max<int64_t>(1, (want_waves + groups - 1) / groups);
   int64_t chunk = (n_time + n_ch - 1) / n_ch;
   chunk = std::max<int64_t>(256, (chunk + 31) / 32 * 32);
@@ -768,15 +809,7 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   sa.tile_wgs = (NG / 32 / tpw + 3) / 4;
   const dim3 grid((unsigned)((int64_t)sa.tile_wgs * n_chunks * C));
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
-  // 8-byte sample loads need A % 8 == 0 and an 8-byte aligned E-field
-  const bool vec = A % 8 == 0 && (reinterpret_cast<uintptr_t>(efield) & 7) == 0;
-  if (P == 1) {
-    if (bf) { if (qb == 1) launch_split_image<1, true, 1, 4>(x, sa, grid, vec); else launch_split_image<1, true, 2, 1>(x, sa, grid, vec); }
-    else    { if (qb == 1) launch_split_image<1, false, 1, 4>(x, sa, grid, vec); else launch_split_image<1, false, 2, 1>(x, sa, grid, vec); }
-  } else {
-    if (bf) launch_split_image<2, true, 1, 1>(x, sa, grid, vec);
-    else launch_split_image<2, false, 1, 1>(x, sa, grid, vec);
-  }
+  split_dispatch(P, bf, qb, SplitLaunch{x, &sa, grid, vec});
   x->last_kernel = "split_image_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
   epic::SplitReduceArgs ra;

@@ -196,6 +196,8 @@ __device__ __forceinline__ uint2 load_e8(const uint8_t* row, int first_ant, int 
 // come from HBM and a block's matrix work is shorter than that latency
 // (two polarisations: half the depth, which keeps three waves per SIMD).
 template <int P> constexpr int split_prefetch() { return P == 2 ? 2 : 4; }
+static_assert(split_prefetch<1>() % 2 == 0 && split_prefetch<2>() % 2 == 0,
+              "the accumulator double buffer takes block parity from the ring slot");
 
 // Workgroup id -> logical index such that consecutive logical indices share
 // an XCD (workgroups are dealt to the 8 XCDs round-robin by id): XCD j holds
@@ -263,27 +265,17 @@ __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
       for (int q = 0; q < QB; ++q)
         dst[p][q] = load_e8<VEC>(row + p * a.n_ant, 16 * q + 8 * h, a.n_ant, t < t_end);
   };
-#pragma unroll
-  for (int d = 0; d < PD; ++d) load_block(ring[d], t_begin + 32 * d);
-  for (int64_t tb = t_begin; tb < t_end; tb += 32 * PD)
-#pragma unroll
-  for (int d = 0; d < PD; ++d) {
-    const int64_t t0 = tb + 32 * d;
-    if (t0 >= t_end) break;
-    uint2 cur[P][QB];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-      for (int q = 0; q < QB; ++q) cur[p][q] = ring[d][p][q];
-    if (t0 + 32 * PD < t_end) load_block(ring[d], t0 + 32 * PD);
-
-    float16v_t dre[TPW][P], dim[TPW][P];
+  // Software pipeline over blocks: the matrix products of block k go into
+  // accumulator set k % 2 while the epilogue of block k - 1 reads the other
+  // set, so the epilogue's VALU work is independent of the MFMAs in flight.
+  float16v_t dre[2][TPW][P], dim[2][TPW][P];
+  auto products = [&](const uint2 (&cur)[P][QB], float16v_t (&xr)[TPW][P], float16v_t (&xi)[TPW][P]) {
 #pragma unroll
     for (int u = 0; u < TPW; ++u)
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        dre[u][p] = float16v_t{};
-        dim[u][p] = float16v_t{};
+        xr[u][p] = float16v_t{};
+        xi[u][p] = float16v_t{};
       }
 #pragma unroll
     for (int p = 0; p < P; ++p)
@@ -296,13 +288,15 @@ __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
         for (int u = 0; u < TPW; ++u)
 #pragma unroll
           for (int hl = 0; hl < 2; ++hl) {
-            dre[u][p] = Ops::mfma(er, bm[u][p][q][0][hl], dre[u][p]);
-            dre[u][p] = Ops::mfma(ei, bm[u][p][q][2][hl], dre[u][p]);
-            dim[u][p] = Ops::mfma(er, bm[u][p][q][1][hl], dim[u][p]);
-            dim[u][p] = Ops::mfma(ei, bm[u][p][q][0][hl], dim[u][p]);
+            xr[u][p] = Ops::mfma(er, bm[u][p][q][0][hl], xr[u][p]);
+            xr[u][p] = Ops::mfma(ei, bm[u][p][q][2][hl], xr[u][p]);
+            xi[u][p] = Ops::mfma(er, bm[u][p][q][1][hl], xi[u][p]);
+            xi[u][p] = Ops::mfma(ei, bm[u][p][q][0][hl], xi[u][p]);
           }
       }
-    // epilogue: products summed over the 16 samples of this lane
+  };
+  // products summed over the 16 samples of this lane, then into float64
+  auto epilogue = [&](const float16v_t (&xr)[TPW][P], const float16v_t (&xi)[TPW][P]) {
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
       float sm[NACC];
@@ -310,19 +304,61 @@ __global__ void __launch_bounds__(256) split_image_kernel(SplitArgs a) {
       for (int k = 0; k < NACC; ++k) sm[k] = 0.f;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float xr = dre[u][0][r], xi = dim[u][0][r];
-        sm[0] = fmaf(xi, xi, fmaf(xr, xr, sm[0]));
+        const float fxr = xr[u][0][r], fxi = xi[u][0][r];
+        sm[0] = fmaf(fxi, fxi, fmaf(fxr, fxr, sm[0]));
         if (P == 2) {
-          const float yr = dre[u][P - 1][r], yi = dim[u][P - 1][r];
-          sm[1 % NACC] = fmaf(yi, yi, fmaf(yr, yr, sm[1 % NACC]));
-          sm[2 % NACC] = fmaf(xi, yi, fmaf(xr, yr, sm[2 % NACC]));
-          sm[3 % NACC] = fmaf(-xr, yi, fmaf(xi, yr, sm[3 % NACC]));
+          const float fyr = xr[u][P - 1][r], fyi = xi[u][P - 1][r];
+          sm[1 % NACC] = fmaf(fyi, fyi, fmaf(fyr, fyr, sm[1 % NACC]));
+          sm[2 % NACC] = fmaf(fxi, fyi, fmaf(fxr, fyr, sm[2 % NACC]));
+          sm[3 % NACC] = fmaf(-fxr, fyi, fmaf(fxi, fyr, sm[3 % NACC]));
         }
       }
 #pragma unroll
       for (int k = 0; k < NACC; ++k) acc[u][k] += (double)sm[k];
     }
+  };
+#pragma unroll
+  for (int d = 0; d < PD; ++d) load_block(ring[d], t_begin + 32 * d);
+  // Block k of the chunk uses accumulator set k % 2 = d % 2 (PD is even and
+  // tb advances by 32 PD).  The first block's predecessor is an all-zero set,
+  // whose epilogue adds exact zeros.
+#pragma unroll
+  for (int u = 0; u < TPW; ++u)
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      dre[1][u][p] = float16v_t{};
+      dim[1][u][p] = float16v_t{};
+    }
+  // instruction counts of one block, for the issue pattern below: the sample
+  // conversion, then one MFMA followed by an equal share of the epilogue
+  constexpr int kMfma = 8 * TPW * P * QB;
+  constexpr int kConv = (BF ? 40 : 24) * P * QB;
+  constexpr int kEpi = TPW * (32 * NACC + 2 * NACC);
+  constexpr int kPer = (kEpi + kMfma - 1) / kMfma;
+  for (int64_t tb = t_begin; tb < t_end; tb += 32 * PD)
+#pragma unroll
+  for (int d = 0; d < PD; ++d) {
+    const int64_t t0 = tb + 32 * d;
+    if (t0 >= t_end) break;
+    uint2 cur[P][QB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int q = 0; q < QB; ++q) cur[p][q] = ring[d][p][q];
+    if (t0 + 32 * PD < t_end) load_block(ring[d], t0 + 32 * PD);
+    products(cur, dre[d & 1], dim[d & 1]);
+    epilogue(dre[(d & 1) ^ 1], dim[(d & 1) ^ 1]);
+    __builtin_amdgcn_sched_group_barrier(0x002, kConv, 0);      // VALU: conversion
+#pragma unroll
+    for (int i = 0; i < kMfma; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);        // one MFMA
+      __builtin_amdgcn_sched_group_barrier(0x002, kPer, 0);     // VALU: epilogue share
+    }
   }
+  // the last block's epilogue
+  const int last = (int)(((t_end - t_begin + 31) / 32 - 1) & 1);
+  if (last == 0) epilogue(dre[0], dim[0]);
+  else epilogue(dre[1], dim[1]);
   double* out = a.partial + (((int64_t)c * a.n_chunks + chunk) * NACC * 2) * a.ng;
 #pragma unroll
   for (int u = 0; u < TPW; ++u)
