@@ -506,16 +506,19 @@ int fused_blocks_per_cu(bool cpx) {
              : occupancy_blocks(epic::fused_image_kernel<N, P, GPT, false>, epic::FusedShape<N>::NT);
 }
 
+template <int P>
+int fused128_blocks_per_cu(int gpt, bool cpx) {
+  const int NT = epic::FusedShape<128>::NT;
+  if (gpt == 1) return cpx ? occupancy_blocks(epic::fused_image128_kernel<P, 1, true>, NT)
+                           : occupancy_blocks(epic::fused_image128_kernel<P, 1, false>, NT);
+  if (gpt == 2) return cpx ? occupancy_blocks(epic::fused_image128_kernel<P, 2, true>, NT)
+                           : occupancy_blocks(epic::fused_image128_kernel<P, 2, false>, NT);
+  return cpx ? occupancy_blocks(epic::fused_image128_kernel<P, 4, true>, NT)
+             : occupancy_blocks(epic::fused_image128_kernel<P, 4, false>, NT);
+}
+
 int fused_blocks_per_cu(int N, int P, int gpt, bool cpx) {
-  if (N == 128) {
-    const int NT = epic::FusedShape<128>::NT;
-    if (gpt == 1) return cpx ? occupancy_blocks(epic::fused_image128_kernel<1, true>, NT)
-                             : occupancy_blocks(epic::fused_image128_kernel<1, false>, NT);
-    if (gpt == 2) return cpx ? occupancy_blocks(epic::fused_image128_kernel<2, true>, NT)
-                             : occupancy_blocks(epic::fused_image128_kernel<2, false>, NT);
-    return cpx ? occupancy_blocks(epic::fused_image128_kernel<4, true>, NT)
-               : occupancy_blocks(epic::fused_image128_kernel<4, false>, NT);
-  }
+  if (N == 128) return P == 2 ? fused128_blocks_per_cu<2>(gpt, cpx) : fused128_blocks_per_cu<1>(gpt, cpx);
 #define EPIC_OCC(NN, PP, GG) if (N == NN && P == PP && gpt == GG) return fused_blocks_per_cu<NN, PP, GG>(cpx);
   EPIC_OCC(32, 1, 1) EPIC_OCC(32, 1, 2) EPIC_OCC(32, 1, 4)
   EPIC_OCC(32, 2, 1) EPIC_OCC(32, 2, 2) EPIC_OCC(32, 2, 4)
@@ -564,22 +567,27 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   return false;
 }
 
+template <int P>
 bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
   const dim3 grid(a.W), block(epic::FusedShape<128>::NT);
   if (x->cpx) {
     switch (x->fused_gpt) {
-      case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<1, true>), grid, block, 0, x->stream, a); return true;
-      case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<2, true>), grid, block, 0, x->stream, a); return true;
-      case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<4, true>), grid, block, 0, x->stream, a); return true;
+      case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 1, true>), grid, block, 0, x->stream, a); return true;
+      case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 2, true>), grid, block, 0, x->stream, a); return true;
+      case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 4, true>), grid, block, 0, x->stream, a); return true;
       default: return false;
     }
   }
   switch (x->fused_gpt) {
-    case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<1, false>), grid, block, 0, x->stream, a); return true;
-    case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<2, false>), grid, block, 0, x->stream, a); return true;
-    case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<4, false>), grid, block, 0, x->stream, a); return true;
+    case 1: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 1, false>), grid, block, 0, x->stream, a); return true;
+    case 2: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 2, false>), grid, block, 0, x->stream, a); return true;
+    case 4: hipLaunchKernelGGL((epic::fused_image128_kernel<P, 4, false>), grid, block, 0, x->stream, a); return true;
     default: return false;
   }
+}
+
+bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
+  return x->cfg.n_pol == 2 ? launch_fused128<2>(x, a) : launch_fused128<1>(x, a);
 }
 
 // Sub-lanes per output value in the reduction kernels: enough that a channel
@@ -1038,8 +1046,12 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.reset = reset ? 1 : 0;
     r.sub = reduce_sub(slots_per_channel(n_time, a.total, a.W));
     const int64_t n = (int64_t)C * N * N, ppb = 256 / r.sub;
-    hipLaunchKernelGGL(epic::reduce_image128_kernel, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
-                       x->stream, r);
+    if (P == 2)
+      hipLaunchKernelGGL(epic::reduce_image128_kernel<2>, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
+                         x->stream, r);
+    else
+      hipLaunchKernelGGL(epic::reduce_image128_kernel<1>, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
+                         x->stream, r);
   } else if (x->fused) {
     epic::FusedArgs a;
     a.efield = efield;
@@ -1196,8 +1208,8 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   }
 
   const bool want_staged = (cfg->flags & EPIC_FLAG_STAGED) != 0;
-  // fused kernels: N = 32 and 64 (one or two polarisations), N = 128 with two
-  x->fused_ok = !want_staged && cfg->precision == EPIC_FP32 && (N <= 64 || cfg->n_pol == 2);
+  // fused kernels: N = 32, 64 and 128, one or two polarisations
+  x->fused_ok = !want_staged && cfg->precision == EPIC_FP32;
   if (x->fused_ok) {
     const int NT = fused_threads(N);
     int gpt = (x->PA + NT - 1) / NT;

@@ -1,23 +1,25 @@
-// Fused imaging kernel for 128 x 128 grids with two polarisations (paper
-// Sec. 2.1 Eq. (4)-(5), Sec. 3.2), the same per-sample path as
-// fused_image_kernel with a different split of the work.
+// Fused imaging kernel for 128 x 128 grids (paper Sec. 2.1 Eq. (4)-(5),
+// Sec. 3.2), the same per-sample path as fused_image_kernel with a different
+// split of the work.
 //
-// The 64 x 64 aperture block of both polarisations fills most of the LDS, and
-// the float32 sums of all 128 x 128 pixels would not fit the registers of one
-// workgroup.  So a workgroup of 512 threads images one half of the output
+// With two polarisations the 64 x 64 aperture block fills most of the LDS,
+// and the float32 sums of all 128 x 128 pixels would not fit the registers of
+// one workgroup.  So a workgroup of 512 threads images one half of the output
 // columns of a sample, kl in [64 h, 64 h + 64):
 //   1. unpack + gain, barrier, gridding of the whole aperture (wave-local rows,
 //      as fused_image_kernel);
-//   2. row transforms: a group of 8 lanes takes one aperture row of both
-//      polarisations (16-point first pass with half of its inputs zero, one
+//   2. row transforms: a group of 8 lanes takes one aperture row of every
+//      polarisation (16-point first pass with half of its inputs zero, one
 //      exchange through the row's 128 slots, two 8-point passes) and writes
 //      the 64 outputs of half h back to the row's first 64 columns;  barrier;
-//   3. column transforms: a group of 8 lanes takes one local column of both
-//      polarisations, exchanging through the column's 64 aperture rows and the
-//      same rows' upper 64 columns; every lane then holds F_X and F_Y of 16
+//   3. column transforms: a group of 8 lanes takes one local column of every
+//      polarisation, exchanging through the column's 64 aperture rows and the
+//      same rows' upper 64 columns; every lane then holds F_X (and F_Y) of 16
 //      pixels;
-//   4. XX, YY, Re XY, Im XY into float32 sums, added every 128 samples and at a
-//      segment boundary into the workgroup's float64 slot.
+//   4. XX (and YY, Re XY, Im XY) into float32 sums, added every 128 samples
+//      and at a segment boundary into the workgroup's float64 slot.
+// One polarisation uses the same split: half the LDS (two workgroups per CU)
+// and a quarter of the sums.
 // Work units are (channel, half, sample), flattened as ((2 c + h) T + t); a
 // (channel, half) pair is one accumulation segment.
 #pragma once
@@ -26,12 +28,12 @@
 namespace epic {
 
 struct Fused128Args {
-  const uint8_t* efield;    // [T][C][2][A]
-  const float2* gains;      // [C][2][A]
+  const uint8_t* efield;    // [T][C][P][A]
+  const float2* gains;      // [C][P][A]
   const uint2* prog;        // [C][1 + L][NT], as fused_image_kernel
   const float* wim;         // [C][1 + L][NT] imaginary step weights (complex kernels), or null
   const float2* twiddle;    // [128] exp(+2 pi i k / 128)
-  double* partial;          // [W + 2 C - 1][4][16][NT] (thread-major)
+  double* partial;          // [W + 2 C - 1][NACC][16][NT] (thread-major)
   int64_t n_time;
   int64_t total;            // 2 C T units
   int n_chan, n_ant, L, W;
@@ -43,22 +45,27 @@ __host__ __device__ __forceinline__ int km128(int n0, int i) {
   return 2 * n0 + (i >> 3) + 16 * (i & 7);
 }
 
-template <int GPT, bool CPX>
-__global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
+// Two polarisations: one workgroup per CU (LDS), registers up to 256; one
+// polarisation: two workgroups per CU, so at most 128 VGPRs.
+template <int P> struct Fused128Waves { static constexpr int value = P == 2 ? 2 : 4; };
+
+template <int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Fused128Waves<P>::value)))
+fused_image128_kernel(Fused128Args a) {
   using SH = FusedShape<128>;
   constexpr int N = 128, S = SH::S, R = SH::R, NT = SH::NT, RS = SH::RS, PS = SH::PSTRIDE;
-  constexpr int P = 2, NACC = 4, KB = SH::KBLOCK, H = N / 2, NPX = 16;
+  constexpr int NACC = P == 2 ? 4 : 1, KB = SH::KBLOCK, H = N / 2, NPX = 16;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   // E'[p][a] (zero slots at a = A .. A+15), the grid (64 rows per
   // polarisation), then the twiddles w^(n0 k0) of the 8 lane roles n0, rows of
   // 17 so that the roles of a half-wave read distinct banks
   constexpr int TWS = 17;
-  __shared__ float2 lds2[P * ES + PS + H * RS + R * TWS];
+  __shared__ float2 lds2[P * ES + (P - 1) * PS + H * RS + R * TWS];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
-  float2* TW = X + PS + H * RS;
+  float2* TW = X + (P - 1) * PS + H * RS;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -173,14 +180,17 @@ __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
                                    [kl](int p, int s) { return p * PS + (s & 63) * RS + kl + (s & 64); });
     // v[p][q R + k1] = F_p[2 n0 + q + 16 k1][64 h + kl]
 
-    // 4. products of the 16 pixels: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
+    // 4. products of the 16 pixels: XX (, YY, Re XY, Im XY; XY = F_X conj(F_Y))
 #pragma unroll
     for (int i = 0; i < NPX; ++i) {
-      const float2 fx = v[0][i], fy = v[1][i];
+      const float2 fx = v[0][i];
       acc[i][0] = fmaf(fx.y, fx.y, fmaf(fx.x, fx.x, acc[i][0]));
-      acc[i][1] = fmaf(fy.y, fy.y, fmaf(fy.x, fy.x, acc[i][1]));
-      acc[i][2] = fmaf(fx.y, fy.y, fmaf(fx.x, fy.x, acc[i][2]));
-      acc[i][3] = fmaf(-fx.x, fy.y, fmaf(fx.y, fy.x, acc[i][3]));
+      if (P == 2) {
+        const float2 fy = v[P - 1][i];
+        acc[i][1 % NACC] = fmaf(fy.y, fy.y, fmaf(fy.x, fy.x, acc[i][1 % NACC]));
+        acc[i][2 % NACC] = fmaf(fx.y, fy.y, fmaf(fx.x, fy.x, acc[i][2 % NACC]));
+        acc[i][3 % NACC] = fmaf(-fx.x, fy.y, fmaf(fx.y, fy.x, acc[i][3 % NACC]));
+      }
     }
     ++nblk;
   }
@@ -191,13 +201,15 @@ __global__ void __launch_bounds__(512) fused_image128_kernel(Fused128Args a) {
 // pixels of half h; sub-lanes as reduce_image_kernel.
 struct Reduce128Args {
   const double* partial;
-  double* image;            // complex128 [C][4][128][128]
+  double* image;            // complex128 [C][NPROD][128][128]
   int64_t n_time, total;
   int n_chan, W, reset, sub;
 };
 
+template <int P>
 __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
-  constexpr int N = 128, NT = FusedShape<128>::NT, NACC = 4, NLOC = 16 * NT;   // local pixels per half
+  constexpr int N = 128, NT = FusedShape<128>::NT, NLOC = 16 * NT;   // local pixels per half
+  constexpr int NACC = P == 2 ? 4 : 1, NPROD = P == 2 ? 4 : 1;
   __shared__ double red[NACC * 256];
   const int ppb = 256 / a.sub;
   const int j = threadIdx.x / ppb, lp = threadIdx.x % ppb;
@@ -226,11 +238,16 @@ __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
   const int km = km128(r.n0, i), kl = 64 * h + r.kl;
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
   double2* img = reinterpret_cast<double2*>(a.image);
-  const int64_t base = (int64_t)c * 4 * N * N + qm * N + ql;
-  const double2 val[4] = {make_double2(s[0], 0.0), make_double2(s[2], s[3]),
-                          make_double2(s[2], -s[3]), make_double2(s[1], 0.0)};
+  const int64_t base = (int64_t)c * NPROD * N * N + qm * N + ql;
+  double2 val[NPROD];
+  val[0] = make_double2(s[0], 0.0);
+  if (P == 2) {
+    val[1 % NPROD] = make_double2(s[2 % NACC], s[3 % NACC]);
+    val[2 % NPROD] = make_double2(s[2 % NACC], -s[3 % NACC]);
+    val[3 % NPROD] = make_double2(s[1 % NACC], 0.0);
+  }
 #pragma unroll
-  for (int pr = 0; pr < 4; ++pr) {
+  for (int pr = 0; pr < NPROD; ++pr) {
     double2* o = img + base + (int64_t)pr * N * N;
     if (a.reset) {
       *o = val[pr];

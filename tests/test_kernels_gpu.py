@@ -39,6 +39,7 @@ CASES = {
     "n64_p1_k5": (lambda: _case(603, 64, 120, 3, 1, 6, 5, 0.4), {}, "fused_image_kernel"),
     "n128_p2_k9": (lambda: _case(604, 128, 300, 2, 2, 4, 9, 0.38), {}, "fused_image128_kernel"),
     "n128_p2_k15": (lambda: _case(605, 128, 200, 1, 2, 3, 15, 0.25), {}, "fused_image128_kernel"),
+    "n128_p1_k7": (lambda: _case(609, 128, 400, 2, 1, 4, 7, 0.4), {}, "fused_image128_kernel"),
     "n64_p2_k11_wide": (lambda: _case(606, 64, 80, 2, 2, 5, 11, 0.45), {}, "staged_fft_kernel"),
     "n32_p2_k5_staged": (lambda: _case(607, 32, 40, 2, 2, 6, 5, 0.4), {"staged": True},
                          "staged_fft_kernel"),

@@ -54,6 +54,10 @@ CASES = {
     "one_sample": lambda: synth.random_problem(107, 64, 256, 3, 2, 1),
     "n128_p2_ragged": lambda: synth.random_problem(109, 128, 400, 2, 2, 7, fill=0.45),
     "n128_p2_A1024": lambda: synth.random_problem(110, 128, 1024, 2, 2, 3, fill=0.47),
+    # one polarisation at 128^2: one, two (A = 1024) and four (A = 2000) bytes per thread
+    "n128_p1_ragged": lambda: synth.random_problem(119, 128, 300, 3, 1, 7, fill=0.45),
+    "n128_p1_A1024": lambda: synth.random_problem(120, 128, 1024, 2, 1, 5, fill=0.47),
+    "n128_p1_A2000": lambda: synth.random_problem(121, 128, 2000, 1, 1, 3, fill=0.48),
 }
 
 
@@ -72,15 +76,19 @@ def test_image_matches_oracle(name, staged):
 
 
 def test_grid128_routes():
-    """128^2: two polarisations run the fused kernel, one the staged kernels."""
+    """128^2: one and two polarisations run the fused kernel; the staged flag
+    takes the staged kernels."""
     inp = synth.random_problem(108, 128, 400, 2, 2, 3, fill=0.45)
     got, im = _run(inp, staged=False)
     assert im.last_kernel_name() == "fused_image128_kernel"
     assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
     inp1 = synth.random_problem(112, 128, 300, 2, 1, 3, fill=0.45)
     got1, im1 = _run(inp1, staged=False)
-    assert im1.last_kernel_name() == "staged_fft_kernel"
+    assert im1.last_kernel_name() == "fused_image128_kernel"
     assert oracle.rel_errors(got1, oracle.image_from(inp1)).max() <= TOL_FP32
+    got2, im2 = _run(inp1, staged=True)
+    assert im2.last_kernel_name() == "staged_fft_kernel"
+    assert oracle.rel_errors(got2, oracle.image_from(inp1)).max() <= TOL_FP32
 
 
 def test_reset_zero_continues_integration():
@@ -109,9 +117,22 @@ def test_reset_zero_continues_integration_n128():
     assert oracle.rel_errors(img.cpu().numpy(), oracle.image_from(inp)).max() <= TOL_FP32
 
 
-def test_bitwise_deterministic_n128():
+def test_reset_zero_continues_integration_n128_one_pol():
     import torch
-    inp = synth.random_problem(118, 128, 700, 2, 2, 11, fill=0.45)
+    inp = synth.random_problem(122, 128, 600, 3, 1, 10, fill=0.45)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    img = im.accumulate(ef[:3], g)
+    im.accumulate(ef[3:], g, image=img, reset=False)
+    torch.cuda.synchronize()
+    assert im.last_kernel_name() == "fused_image128_kernel"
+    assert oracle.rel_errors(img.cpu().numpy(), oracle.image_from(inp)).max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("P", [1, 2])
+def test_bitwise_deterministic_n128(P):
+    import torch
+    inp = synth.random_problem(118, 128, 700, 2, P, 11, fill=0.45)
     im = _imager(inp)
     ef, g = _dev(inp)
     a = im.accumulate(ef, g).clone()
