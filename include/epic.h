@@ -125,8 +125,8 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
 /* Host-side view of the gridding programs the fused kernels run for a
  * configuration and geometry (Sec. 2.1 Eq. (4): the kernel taps of every
  * antenna, gathered per grid cell).  No device work: usable without a GPU, for
- * verification tools.  cfg must select the fused float32 path (grid_n 32 or 64,
- * EPIC_FP32, no EPIC_FLAG_STAGED).  out receives, as epic_set_antennas uploads it,
+ * verification tools.  cfg must select the fused float32 path (EPIC_FP32, no
+ * EPIC_FLAG_STAGED).  out receives, as epic_set_antennas uploads it,
  *   uint32 [n_chan][1 + L][NT][2]:
  *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
  *                    (int32 -1: none); word 1: 0;
@@ -180,8 +180,12 @@ epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t 
  *   grad_gains: device complex64 [n_chan][n_pol][n_ant], overwritten with
  *               dL/dRe(g) + i dL/dIm(g).
  * The per-sample transforms are recomputed, not stored; the reduction over
- * time is float64.  Allocates nothing.  Errors as epic_image_accumulate;
- * EPIC_E_UNSUPPORTED for a context with EPIC_FLAG_REMOVE_AUTOS. */
+ * time is float64.  With EPIC_FLAG_REMOVE_AUTOS the loss is that of the image
+ * without the autocorrelation terms.  Runs on the fused float32 kernels
+ * (grid_n 32, 64 and 128).  Allocates nothing.  Errors as
+ * epic_image_accumulate; EPIC_E_UNSUPPORTED for the split precisions and for
+ * geometries on the staged kernels (EPIC_FLAG_STAGED, or a channel's taps
+ * outside an N/2 x N/2 block). */
 epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
                                 const float *gains, const double *grad_image,
                                 float *grad_gains);

@@ -20,6 +20,7 @@
 #include "adjoint.hpp"
 #include "split.hpp"
 #include "fused128.hpp"
+#include "adjoint128.hpp"
 #include "autos.hpp"
 #include "frontend.hpp"
 #include "post.hpp"
@@ -535,7 +536,19 @@ int adjoint_blocks_per_cu(int gpt) {
   return occupancy_blocks(epic::adjoint_kernel<N, P, 4, CPX>, epic::FusedShape<N>::NT);
 }
 
+template <int P, bool CPX>
+int adjoint128_blocks_per_cu(int gpt) {
+  const int NT = epic::FusedShape<128>::NT;
+  if (gpt == 1) return occupancy_blocks(epic::adjoint128_kernel<P, 1, CPX>, NT);
+  if (gpt == 2) return occupancy_blocks(epic::adjoint128_kernel<P, 2, CPX>, NT);
+  return occupancy_blocks(epic::adjoint128_kernel<P, 4, CPX>, NT);
+}
+
 int adjoint_blocks_per_cu(int N, int P, int gpt, bool cpx) {
+  if (N == 128) {
+    if (cpx) return P == 1 ? adjoint128_blocks_per_cu<1, true>(gpt) : adjoint128_blocks_per_cu<2, true>(gpt);
+    return P == 1 ? adjoint128_blocks_per_cu<1, false>(gpt) : adjoint128_blocks_per_cu<2, false>(gpt);
+  }
   if (cpx) {
     if (N == 32) return P == 1 ? adjoint_blocks_per_cu<32, 1, true>(gpt) : adjoint_blocks_per_cu<32, 2, true>(gpt);
     return P == 1 ? adjoint_blocks_per_cu<64, 1, true>(gpt) : adjoint_blocks_per_cu<64, 2, true>(gpt);
@@ -635,6 +648,17 @@ bool launch_adjoint(epic_ctx* x, const epic::AdjointArgs& a) {
   EPIC_LA(64, 1, 1) EPIC_LA(64, 1, 2) EPIC_LA(64, 1, 4)
   EPIC_LA(64, 2, 1) EPIC_LA(64, 2, 2) EPIC_LA(64, 2, 4)
 #undef EPIC_LA
+#define EPIC_LA128(PP, GG)                                                                   \
+  if (N == 128 && P == PP && G == GG) {                                                      \
+    if (x->cpx) hipLaunchKernelGGL((epic::adjoint128_kernel<PP, GG, true>), grid, block, 0,   \
+                                   x->stream, a);                                            \
+    else hipLaunchKernelGGL((epic::adjoint128_kernel<PP, GG, false>), grid, block, 0,         \
+                            x->stream, a);                                                   \
+    return true;                                                                             \
+  }
+  EPIC_LA128(1, 1) EPIC_LA128(1, 2) EPIC_LA128(1, 4)
+  EPIC_LA128(2, 1) EPIC_LA128(2, 2) EPIC_LA128(2, 4)
+#undef EPIC_LA128
   return false;
 }
 
@@ -1231,11 +1255,11 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
       delete x;
       return EPIC_E_NOMEM;
     }
-    x->adj_w = N == 128 ? 1 : adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, false) * x->n_cu;
-    x->adj_w_cpx = N == 128 ? 1 : std::min(x->adj_w, adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
+    x->adj_w = adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, false) * x->n_cu;
+    x->adj_w_cpx = std::min(x->adj_w, adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
     if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
-        (N <= 64 && !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4)))) {
+        !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4))) {
       g_init_error = "gradient workspace allocation failed";
       delete x;
       return EPIC_E_NOMEM;
@@ -1293,7 +1317,7 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   if (s != EPIC_OK) { g_init_error = m; return s; }
   if (!xy_m || !freq_hz || !words || !layout) { g_init_error = "null pointer"; return EPIC_E_INVALID; }
   const int N = cfg->grid_n, P = cfg->n_pol;
-  if ((N > 64 && P != 2) || cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
+  if (cfg->precision != EPIC_FP32 || (cfg->flags & EPIC_FLAG_STAGED)) {
     g_init_error = "the configuration has no fused kernel";
     return EPIC_E_UNSUPPORTED;
   }
@@ -1467,12 +1491,14 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
   if (x->autos && n_time > epic::AUTO_SEG_MAX_SAMPLES)
     return x->fail(EPIC_E_UNSUPPORTED, "with EPIC_FLAG_REMOVE_AUTOS a call takes at most 2^24 - 1 samples");
-  if (!x->fused || x->cfg.precision != EPIC_FP32 || x->cfg.grid_n > 64)
+  if (!x->fused || x->cfg.precision != EPIC_FP32)
     return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path "
-                   "(N <= 64, aperture within N/2 x N/2 cells)");
+                   "(aperture within N/2 x N/2 cells)");
   DeviceGuard guard(x->device);
   const int C = x->cfg.n_chan;
-  const int64_t total = (int64_t)C * n_time;
+  // work units per channel: samples, or (half, sample) pairs at N = 128
+  const int64_t upc = x->cfg.grid_n == 128 ? 2 * n_time : n_time;
+  const int64_t total = (int64_t)C * upc;
   (void)hipGetLastError();
   {
     epic::GradTableArgs ta;
@@ -1483,8 +1509,10 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
     const dim3 tg((unsigned)(((int64_t)C * N * N + 255) / 256));
     if (N == 32 && P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<32, 1>), tg, dim3(256), 0, x->stream, ta);
     else if (N == 32) hipLaunchKernelGGL((epic::grad_table_kernel<32, 2>), tg, dim3(256), 0, x->stream, ta);
-    else if (P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<64, 1>), tg, dim3(256), 0, x->stream, ta);
-    else hipLaunchKernelGGL((epic::grad_table_kernel<64, 2>), tg, dim3(256), 0, x->stream, ta);
+    else if (N == 64 && P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<64, 1>), tg, dim3(256), 0, x->stream, ta);
+    else if (N == 64) hipLaunchKernelGGL((epic::grad_table_kernel<64, 2>), tg, dim3(256), 0, x->stream, ta);
+    else if (P == 1) hipLaunchKernelGGL((epic::grad_table128_kernel<1>), tg, dim3(256), 0, x->stream, ta);
+    else hipLaunchKernelGGL((epic::grad_table128_kernel<2>), tg, dim3(256), 0, x->stream, ta);
   }
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   epic::AdjointArgs a;
@@ -1505,18 +1533,18 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.L = x->L;
   a.W = (int)std::min<int64_t>(x->cpx ? x->adj_w_cpx : x->adj_w, total);
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
-  x->last_kernel = "adjoint_kernel";
+  x->last_kernel = x->cfg.grid_n == 128 ? "adjoint128_kernel" : "adjoint_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
   if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
   epic::GradReduceArgs r;
   r.gpartial = x->gpartial.as<double2>();
   r.grad = reinterpret_cast<float2*>(grad_gains);
-  r.n_time = n_time;
+  r.n_time = upc;                              // the kernel's units per channel
   r.total = total;
   r.n_chan = C;
   r.PA = x->PA;
   r.W = a.W;
-  r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
+  r.sub = reduce_sub(slots_per_channel(upc, total, a.W));
   r.minus = x->autos ? x->au_gauto.as<double2>() : nullptr;
   const int64_t n = (int64_t)C * x->PA, gppb = 256 / r.sub;
   hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + gppb - 1) / gppb)), dim3(256), 0,

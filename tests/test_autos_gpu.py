@@ -168,7 +168,8 @@ def _rel(a, b):
 @pytest.mark.parametrize("seed,N,A,C,P,T,K", [(421, 32, 16, 2, 2, 5, 0), (422, 32, 20, 1, 1, 7, 0),
                                             (423, 64, 256, 3, 2, 11, 0), (424, 64, 90, 2, 1, 4, 0),
                                             (425, 64, 150, 2, 2, 6, 0), (426, 32, 24, 2, 2, 5, 5),
-                                            (427, 64, 80, 2, 1, 4, 3)])
+                                            (427, 64, 80, 2, 1, 4, 3), (429, 128, 300, 2, 2, 3, 0),
+                                            (430, 128, 200, 1, 1, 4, 5)])
 def test_grad_without_autos_matches_oracle(seed, N, A, C, P, T, K):
     """Gain gradient of an L2 loss on the removed image (bar of the gradient:
     1e-4 relative); the removed term's share (full-image gradient minus this

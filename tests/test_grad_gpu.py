@@ -33,10 +33,13 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("seed,N,A,C,P,T", [(201, 32, 16, 2, 2, 5), (202, 32, 16, 1, 1, 7),
-                                          (203, 64, 256, 3, 2, 11), (204, 64, 90, 2, 1, 4)])
+                                          (203, 64, 256, 3, 2, 11), (204, 64, 90, 2, 1, 4),
+                                          # 128^2: one, two and four sample bytes per thread
+                                          (206, 128, 200, 2, 2, 3), (207, 128, 300, 3, 1, 4),
+                                          (208, 128, 1024, 1, 2, 2), (209, 128, 1024, 2, 1, 3)])
 def test_grad_matches_oracle_l2_loss(seed, N, A, C, P, T):
     import torch
-    inp = synth.random_problem(seed, N, A, C, P, T)
+    inp = synth.random_problem(seed, N, A, C, P, T, fill=0.45)
     im, ef, g = _setup(inp)
     img = im.accumulate(ef, g).cpu().numpy()
     rng = np.random.default_rng(seed)

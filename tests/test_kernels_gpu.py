@@ -104,7 +104,8 @@ def test_gaussian_given_as_kernels_matches_the_built_in_path():
 
 
 @pytest.mark.parametrize("seed,N,A,C,P,T,K", [(621, 32, 16, 2, 2, 5, 5), (622, 32, 20, 1, 1, 7, 3),
-                                              (623, 64, 96, 2, 2, 6, 7), (624, 64, 50, 2, 1, 4, 9)])
+                                              (623, 64, 96, 2, 2, 6, 7), (624, 64, 50, 2, 1, 4, 9),
+                                              (625, 128, 150, 1, 2, 3, 7), (626, 128, 120, 2, 1, 3, 11)])
 def test_complex_kernel_gradient_matches_oracle(seed, N, A, C, P, T, K):
     import torch
     inp = _case(seed, N, A, C, P, T, K, 0.35)

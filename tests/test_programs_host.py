@@ -69,8 +69,6 @@ def _subset(inp, n):
 @pytest.mark.parametrize("one_pol", [False, True])
 def test_programs_reproduce_gridding(name, one_pol):
     inp = CASES[name]()
-    if one_pol and inp.grid_n == 128:
-        pytest.skip("128^2 with one polarisation runs the staged kernels (no program)")
     P = 1 if one_pol else inp.n_pol
     prog, g = _program(inp, P)
     N, A, H = inp.grid_n, inp.n_ant, inp.grid_n // 2
