@@ -181,11 +181,11 @@ epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t 
  *               dL/dRe(g) + i dL/dIm(g).
  * The per-sample transforms are recomputed, not stored; the reduction over
  * time is float64.  With EPIC_FLAG_REMOVE_AUTOS the loss is that of the image
- * without the autocorrelation terms.  Runs on the fused float32 kernels
- * (grid_n 32, 64 and 128).  Allocates nothing.  Errors as
- * epic_image_accumulate; EPIC_E_UNSUPPORTED for the split precisions and for
- * geometries on the staged kernels (EPIC_FLAG_STAGED, or a channel's taps
- * outside an N/2 x N/2 block). */
+ * without the autocorrelation terms.  Runs wherever the float32 image runs:
+ * the fused kernels (grid_n 32, 64 and 128) or the staged ones
+ * (EPIC_FLAG_STAGED, or a channel's taps outside an N/2 x N/2 block).
+ * Allocates nothing.  Errors as epic_image_accumulate; EPIC_E_UNSUPPORTED for
+ * the split precisions. */
 epic_status epic_image_backward(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
                                 const float *gains, const double *grad_image,
                                 float *grad_gains);

@@ -689,6 +689,13 @@ bool alloc_staged(epic_ctx* x) {
       !x->st_grid.alloc((size_t)tb * c.n_chan * c.n_pol * N * N * sizeof(float2)) ||
       !x->st_acc.alloc((size_t)c.n_chan * x->nacc * N * N * sizeof(double)))
     return false;
+  // the staged gradient: upstream gradient table [C][N*N] and per-antenna
+  // float64 sums [C][P*A] (a context with fused kernels already holds both,
+  // sized at least that large)
+  if (c.precision == EPIC_FP32 &&
+      ((!x->gtab.p && !x->gtab.alloc((size_t)c.n_chan * N * N * sizeof(float4))) ||
+       (!x->gpartial.p && !x->gpartial.alloc((size_t)c.n_chan * x->PA * 2 * sizeof(double)))))
+    return false;
   x->tb = tb;
   return true;
 }
@@ -1180,6 +1187,101 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
   return EPIC_OK;
 }
 
+// Gain gradient on the staged kernels (EPIC_FLAG_STAGED, or apertures wider
+// than N/2): per batch, the forward stages, then the adjoint stages of
+// staged.hpp, float64 sums per (channel, polarisation, antenna) in time order.
+epic_status staged_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                            const double* grad_image, float* grad_gains) {
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol, npix = N * N;
+  (void)hipGetLastError();
+  {
+    epic::StagedGradTableArgs ta;
+    ta.grad_image = reinterpret_cast<const double2*>(grad_image);
+    ta.gtab = x->gtab.as<float4>();
+    ta.n_chan = C;
+    ta.N = N;
+    const dim3 tg((unsigned)(((int64_t)C * npix + 255) / 256));
+    if (P == 2) hipLaunchKernelGGL(epic::staged_grad_table_kernel<2>, tg, dim3(256), 0, x->stream, ta);
+    else hipLaunchKernelGGL(epic::staged_grad_table_kernel<1>, tg, dim3(256), 0, x->stream, ta);
+  }
+  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  const int tbu = x->tb_override > 0 ? std::min(x->tb_override, x->tb) : x->tb;
+  for (int64_t t0 = 0; t0 < n_time; t0 += tbu) {
+    const int tb = (int)std::min<int64_t>(tbu, n_time - t0);
+    epic::StagedUnpackArgs u;
+    u.efield = efield;
+    u.gains = reinterpret_cast<const float2*>(gains);
+    u.e = x->st_e.as<float2>();
+    u.t0 = t0;
+    u.per_t = (int64_t)C * x->PA;
+    u.count = tb * u.per_t;
+    u.PA = x->PA;
+    hipLaunchKernelGGL(epic::staged_unpack_kernel, dim3(grid_for(u.count)), dim3(256), 0, x->stream, u);
+    epic::StagedGridArgs gr;
+    gr.e = x->st_e.as<float2>();
+    gr.off = x->csr_off.as<int>();
+    gr.ent = x->csr_ent.as<uint2>();
+    gr.ent_im = x->cpx ? x->csr_im.as<float>() : nullptr;
+    gr.grid = x->st_grid.as<float2>();
+    gr.count = (int64_t)tb * C * P * npix;
+    gr.n_chan = C;
+    gr.n_pol = P;
+    gr.n_ant = x->cfg.n_ant;
+    gr.nnz = x->nnz;
+    gr.npix = npix;
+    hipLaunchKernelGGL(epic::staged_grid_kernel, dim3(grid_for(gr.count)), dim3(256), 0, x->stream, gr);
+    launch_staged_fft(x, x->st_grid.as<float2>(), (int64_t)tb * C * P);
+    epic::StagedGformArgs gf;
+    gf.img = x->st_grid.as<float2>();
+    gf.gtab = x->gtab.as<float4>();
+    gf.count = (int64_t)tb * C * npix;
+    gf.n_chan = C;
+    gf.npix = npix;
+    if (P == 2) hipLaunchKernelGGL(epic::staged_gform_kernel<2>, dim3(grid_for(gf.count)), dim3(256), 0, x->stream, gf);
+    else hipLaunchKernelGGL(epic::staged_gform_kernel<1>, dim3(grid_for(gf.count)), dim3(256), 0, x->stream, gf);
+    launch_staged_fft(x, x->st_grid.as<float2>(), (int64_t)tb * C * P);
+    epic::StagedDegridArgs dg;
+    dg.img = x->st_grid.as<float2>();
+    dg.efield = efield;
+    dg.taps = x->taps.as<uint2>();
+    dg.tapim = x->cpx ? x->taps_im.as<float>() : nullptr;
+    dg.gsum = x->gpartial.as<double2>();
+    dg.t0 = t0;
+    dg.tb = tb;
+    dg.n_chan = C;
+    dg.n_ant = x->cfg.n_ant;
+    dg.kk = x->cfg.kernel_support * x->cfg.kernel_support;
+    dg.npix = npix;
+    dg.PA = x->PA;
+    dg.first = t0 == 0;
+    hipLaunchKernelGGL(epic::staged_degrid_kernel, dim3((unsigned)(((int64_t)C * x->PA + 255) / 256)),
+                       dim3(256), 0, x->stream, dg);
+  }
+  x->last_kernel = "staged_degrid_kernel";
+  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
+  // 2 dL/dg* (minus the autocorrelation term) from the single slot per channel
+  epic::GradReduceArgs r;
+  r.gpartial = x->gpartial.as<double2>();
+  r.grad = reinterpret_cast<float2*>(grad_gains);
+  r.n_time = n_time;
+  r.total = (int64_t)C * n_time;
+  r.n_chan = C;
+  r.PA = x->PA;
+  r.W = 1;
+  r.sub = 1;
+  r.minus = x->autos ? x->au_gauto.as<double2>() : nullptr;
+  const int64_t n = (int64_t)C * x->PA;
+  hipLaunchKernelGGL(epic::reduce_grad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, x->stream, r);
+  if (x->timing) {
+    (void)hipEventRecord(x->ev[2], x->stream);
+    x->timed = true;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1449,6 +1551,17 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
                    hipMemcpy(x->csr_im.p, ent_im.data(), ent_im.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       return x->fail(EPIC_E_NOMEM, "gridding table upload failed");
     x->nnz = nnz;
+    // degridding taps of the staged gradient [C][A][KK] {cell j*N + i, w}
+    std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
+    for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
+      taps[2 * o] = (uint32_t)g.cell[o];
+      std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
+    }
+    if (!x->taps.alloc(taps.size() * 4) ||
+        hipMemcpy(x->taps.p, taps.data(), taps.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (x->cpx && (!x->taps_im.alloc(g.wi.size() * 4) ||
+                    hipMemcpy(x->taps_im.p, g.wi.data(), g.wi.size() * 4, hipMemcpyHostToDevice) != hipSuccess)))
+      return x->fail(EPIC_E_NOMEM, "degridding table upload failed");
   }
   x->have_geom = true;
   return EPIC_OK;
@@ -1491,10 +1604,10 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
   if (x->autos && n_time > epic::AUTO_SEG_MAX_SAMPLES)
     return x->fail(EPIC_E_UNSUPPORTED, "with EPIC_FLAG_REMOVE_AUTOS a call takes at most 2^24 - 1 samples");
-  if (!x->fused || x->cfg.precision != EPIC_FP32)
-    return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the fused FP32 path "
-                   "(aperture within N/2 x N/2 cells)");
+  if (x->cfg.precision != EPIC_FP32)
+    return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the float32 paths");
   DeviceGuard guard(x->device);
+  if (!x->fused) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
   const int C = x->cfg.n_chan;
   // work units per channel: samples, or (half, sample) pairs at N = 128
   const int64_t upc = x->cfg.grid_n == 128 ? 2 * n_time : n_time;

@@ -157,4 +157,121 @@ __global__ void __launch_bounds__(256) staged_accum_kernel(StagedAccumArgs a) {
   for (int u = 0; u < NACC; ++u) out[(int64_t)u * a.npix] = s[u];
 }
 
+// ---- gain gradient on the staged path (the adjoint of the stages above) ----
+//
+// Per batch of samples: the forward stages recompute F; staged_gform_kernel
+// replaces F by conj(dL/dF*) (Wirtinger calculus, as adjoint_kernel); the same
+// forward transform then gives conj(H) with H = sum_k G exp(-2 pi i ...), the
+// adjoint transform of G; staged_degrid_kernel gathers H at every antenna's
+// taps and adds conj(w) H conj(e) to float64 sums per (channel, polarisation,
+// antenna), in time order.
+
+// The upstream gradient in natural pixel order: gtab[c][pix] =
+// {Re Gxx, Re Gyy, Re h, Im h}, h = (Gxy + conj(Gyx)) / 2, from the
+// fftshifted complex128 image gradient.
+struct StagedGradTableArgs {
+  const double2* grad_image;  // [C][NPROD][N][N] (fftshifted)
+  float4* gtab;               // [C][N*N]
+  int n_chan, N;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) staged_grad_table_kernel(StagedGradTableArgs a) {
+  constexpr int NPROD = (P == 2) ? 4 : 1;
+  const int N = a.N, npix = N * N;
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_chan * npix) return;
+  const int c = (int)(idx / npix), pix = (int)(idx % npix);
+  const int km = pix / N, kl = pix % N;
+  const int sp = ((km + N / 2) % N) * N + (kl + N / 2) % N;
+  const double2* gi = a.grad_image + (int64_t)c * NPROD * npix;
+  float4 t;
+  t.x = (float)gi[sp].x;
+  if (P == 2) {
+    const double2 xy = gi[npix + sp], yx = gi[2 * npix + sp];
+    t.y = (float)gi[3 * npix + sp].x;
+    t.z = (float)(0.5 * (xy.x + yx.x));
+    t.w = (float)(0.5 * (xy.y - yx.y));
+  } else {
+    t.y = t.z = t.w = 0.f;
+  }
+  a.gtab[idx] = t;
+}
+
+struct StagedGformArgs {
+  float2* img;              // [Tb][C][P][N*N]: F in, conj(dL/dF*) out
+  const float4* gtab;       // [C][N*N]
+  int64_t count;            // Tb * C * N*N
+  int n_chan, npix;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) staged_gform_kernel(StagedGformArgs a) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.count;
+       i += (int64_t)gridDim.x * 256) {
+    const int pix = (int)(i % a.npix);
+    const int64_t tc = i / a.npix;                   // t*C + c
+    const int c = (int)(tc % a.n_chan);
+    const float4 t = a.gtab[(int64_t)c * a.npix + pix];
+    float2* f = a.img + tc * P * a.npix + pix;
+    const float2 fx = f[0];
+    if (P == 2) {
+      const float2 fy = f[a.npix];
+      // G_X = Re Gxx F_X + h F_Y,  G_Y = Re Gyy F_Y + conj(h) F_X
+      const float2 gx = make_float2(fmaf(t.x, fx.x, t.z * fy.x - t.w * fy.y),
+                                    fmaf(t.x, fx.y, t.z * fy.y + t.w * fy.x));
+      const float2 gy = make_float2(fmaf(t.y, fy.x, t.z * fx.x + t.w * fx.y),
+                                    fmaf(t.y, fy.y, t.z * fx.y - t.w * fx.x));
+      f[0] = make_float2(gx.x, -gx.y);
+      f[a.npix] = make_float2(gy.x, -gy.y);
+    } else {
+      f[0] = make_float2(t.x * fx.x, -t.x * fx.y);
+    }
+  }
+}
+
+struct StagedDegridArgs {
+  const float2* img;        // [Tb][C][P][N*N]: conj(H)
+  const uint8_t* efield;    // full [T][C][P][A]
+  const uint2* taps;        // [C][A][KK] {natural cell j*N + i, w bits}
+  const float* tapim;       // [C][A][KK] imaginary tap weights (complex kernels), or null
+  double2* gsum;            // [C][P*A]: float64 sums of dL/dg* over the samples so far
+  int64_t t0;               // first sample of the batch
+  int tb, n_chan, n_ant, kk, npix, PA, first;
+};
+
+// One thread per (channel, polarisation, antenna); the batch's samples in order.
+__global__ void __launch_bounds__(256) staged_degrid_kernel(StagedDegridArgs a) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)a.n_chan * a.PA) return;
+  const int c = (int)(idx / a.PA), k = (int)(idx % a.PA);
+  const int p = k / a.n_ant, ant = k - p * a.n_ant;
+  const int64_t tbase = ((int64_t)c * a.n_ant + ant) * a.kk;
+  const int P = a.PA / a.n_ant;
+  double2 acc = a.first ? make_double2(0.0, 0.0) : a.gsum[idx];
+  for (int t = 0; t < a.tb; ++t) {
+    const float2* h = a.img + (((int64_t)t * a.n_chan + c) * P + p) * a.npix;
+    float2 s = make_float2(0.f, 0.f);
+    for (int q = 0; q < a.kk; ++q) {                // sum_taps conj(w) H, H = conj(stored)
+      const uint2 tq = a.taps[tbase + q];
+      const float w = __uint_as_float(tq.y);
+      const float2 y = h[tq.x];
+      s.x = fmaf(w, y.x, s.x);
+      s.y = fmaf(-w, y.y, s.y);
+      if (a.tapim) {
+        const float wi = a.tapim[tbase + q];
+        s.x = fmaf(-wi, y.y, s.x);                  // conj(w) H with w = wr + i wi, H = y*
+        s.y = fmaf(-wi, y.x, s.y);
+      }
+    }
+    const int b = a.efield[((a.t0 + t) * a.n_chan + c) * a.PA + k];
+    const float er = (float)((b >> 4) - ((b & 0x80) ? 16 : 0));
+    const float ei = (float)((b & 0xF) - ((b & 0x8) ? 16 : 0));
+    // s conj(e)
+    acc.x += (double)fmaf(s.x, er, s.y * ei);
+    acc.y += (double)fmaf(s.y, er, -s.x * ei);
+  }
+  a.gsum[idx] = acc;
+}
+
 }  // namespace epic

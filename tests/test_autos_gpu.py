@@ -198,6 +198,23 @@ def test_grad_without_autos_matches_oracle(seed, N, A, C, P, T, K):
     assert d <= TOL_AUTOS, f"{d:.3e}"
 
 
+@pytest.mark.parametrize("P", [1, 2])
+def test_grad_without_autos_on_staged_kernels(P):
+    """The staged gradient with the autocorrelation terms removed."""
+    import torch
+    inp = synth.random_problem(431 + P, 32, 30, 2, P, 6)
+    ef, g = _dev(inp)
+    im = _imager(inp, staged=True)
+    img = im.accumulate(ef, g).cpu().numpy()
+    rng = np.random.default_rng(431)
+    model = img * (1 + 0.05 * rng.normal(size=img.shape)) + rng.normal(size=img.shape)
+    gam = oracle.l2_loss_grad_image(img, model)
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    assert im.last_kernel_name() == "staged_degrid_kernel"
+    ref = oracle.grad_gains_without_autos(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, gam)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
+
+
 def test_grad_single_antenna_vanishes():
     import torch
     inp = synth.random_problem(426, 32, 1, 2, 2, 9)
@@ -244,9 +261,9 @@ def test_limits_and_unsupported_calls_leave_outputs_untouched():
                                   ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                   ctypes.c_void_p(gg.data_ptr()))
     assert st == _lib.EPIC_E_UNSUPPORTED
-    big = synth.random_problem(428, 128, 64, 1, 2, 2)
-    ef2, g2 = _dev(big)
-    im2 = _imager(big, staged=True)
+    small = synth.random_problem(428, 32, 16, 1, 2, 2)
+    ef2, g2 = _dev(small)
+    im2 = _imager(small, precision="split_fp16")           # no gradient on the split forms
     with pytest.raises(EpicError, match="UNSUPPORTED"):
         im2.backward(ef2, g2, torch.ones(im2.image_shape(), dtype=torch.complex128, device="cuda"))
     torch.cuda.synchronize()

@@ -50,6 +50,51 @@ def test_grad_matches_oracle_l2_loss(seed, N, A, C, P, T):
     assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
 
 
+@pytest.mark.parametrize("seed,N,A,C,P,T,fill,staged", [
+    (231, 64, 120, 2, 2, 7, 0.62, False),    # aperture wider than N/2: staged kernels
+    (232, 32, 40, 2, 1, 9, 0.7, False),
+    (233, 64, 256, 2, 2, 5, 0.45, True),     # EPIC_FLAG_STAGED
+    (234, 128, 300, 1, 1, 3, 0.45, True),
+])
+def test_staged_grad_matches_oracle(seed, N, A, C, P, T, fill, staged):
+    """The gradient on the staged kernels (batches of the forward stages, then
+    the adjoint stages) against the oracle."""
+    import torch
+    from paper_1904_11422_amd import Imager
+    inp = synth.random_problem(seed, N, A, C, P, T, fill=fill)
+    print(f"case {seed}: N={N} A={A} C={C} P={P} T={T} fill={fill} staged={staged}", flush=True)
+    im = Imager(N, C, P, A, staged=staged)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    img = im.accumulate(ef, g)
+    assert im.last_kernel_name() == "staged_fft_kernel"
+    img = img.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    gam = oracle.l2_loss_grad_image(img, img * (1 + 0.05 * rng.normal(size=img.shape)))
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    assert im.last_kernel_name() == "staged_degrid_kernel"
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, N, gam)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
+
+
+def test_staged_grad_spans_batches():
+    """More samples than one staged batch: the float64 sums carry across batches."""
+    import torch
+    from paper_1904_11422_amd import Imager
+    inp = synth.random_problem(235, 32, 24, 2, 2, 150, fill=0.7)
+    im = Imager(32, 2, 2, 24)
+    im.set_antennas(inp.xy_m, inp.freq_hz)
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    img = im.accumulate(ef, g).cpu().numpy()
+    rng = np.random.default_rng(235)
+    gam = oracle.l2_loss_grad_image(img, img * (1 + 0.05 * rng.normal(size=img.shape)))
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 32, gam)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
+
+
 def test_grad_cross_products_only():
     """Upstream gradient on XY and YX alone exercises the h terms."""
     import torch
