@@ -1021,7 +1021,8 @@ epic_status build_taper(epic_ctx* x, const Geometry& g) {
   ca.n_chan = C;
   ca.n_ant = A;
   ca.K = K;
-  hipLaunchKernelGGL(epic::taper_coeff_kernel, dim3((unsigned)((int64_t)C * D2)), dim3(256), 0, x->stream, ca);
+  hipLaunchKernelGGL(epic::taper_coeff_kernel, dim3((unsigned)((int64_t)C * ((D2 + 255) / 256))), dim3(256), 0,
+                     x->stream, ca);
   epic::TaperImageArgs ia;
   ia.coeff = coeff.as<double2>();
   ia.taper = x->taper.as<double>();

@@ -28,42 +28,41 @@ struct TaperCoeffArgs {
   int n_chan, n_ant, K;
 };
 
-// One workgroup per (channel, offset d); threads over antennas, a fixed-order
-// sum (halving within waves, then the four waves in order).
+constexpr int TAPER_MAX_KK = 15 * 15;
+constexpr int TAPER_ANT_BATCH = 8;             // antennas staged through LDS at a time
+
+// One workgroup per (channel, block of 256 offsets d), one thread per offset;
+// the antennas' taps are staged through LDS a batch at a time and every
+// thread adds its offset's overlap sum antenna by antenna, in antenna order.
 __global__ void __launch_bounds__(256) taper_coeff_kernel(TaperCoeffArgs a) {
-  __shared__ double red[2][4];
+  __shared__ double2 wt[TAPER_ANT_BATCH][TAPER_MAX_KK];
   const int K = a.K, D = 2 * K - 1, D2 = D * D, KK = K * K;
-  const int c = blockIdx.x / D2, d = blockIdx.x % D2;
-  const int dj = d / D - (K - 1), di = d % D - (K - 1);
+  const int blocks = (D2 + 255) / 256;
+  const int c = blockIdx.x / blocks, d = (blockIdx.x % blocks) * 256 + threadIdx.x;
+  const bool valid = d < D2;
+  const int dj = valid ? d / D - (K - 1) : 0, di = valid ? d % D - (K - 1) : 0;
   const int uj0 = dj > 0 ? dj : 0, uj1 = dj < 0 ? K + dj : K;
   const int ui0 = di > 0 ? di : 0, ui1 = di < 0 ? K + di : K;
   double sr = 0.0, si = 0.0;
-  for (int ant = threadIdx.x; ant < a.n_ant; ant += 256) {
-    const int64_t base = ((int64_t)c * a.n_ant + ant) * KK;
-    const float* w = a.w + base;
-    const float* wi = a.wi ? a.wi + base : nullptr;
-    for (int uj = uj0; uj < uj1; ++uj)
-      for (int ui = ui0; ui < ui1; ++ui) {
-        const int p = uj * K + ui, q = (uj - dj) * K + (ui - di);
-        // w(u) conj(w(u - d))
-        const double xr = w[p], xi = wi ? wi[p] : 0.0;
-        const double yr = w[q], yi = wi ? wi[q] : 0.0;
-        sr = fma(xr, yr, fma(xi, yi, sr));
-        si = fma(xi, yr, fma(-xr, yi, si));
-      }
+  for (int a0 = 0; a0 < a.n_ant; a0 += TAPER_ANT_BATCH) {
+    const int nb = a.n_ant - a0 < TAPER_ANT_BATCH ? a.n_ant - a0 : TAPER_ANT_BATCH;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb * KK; i += 256) {
+      const int64_t o = ((int64_t)c * a.n_ant + a0) * KK + i;
+      wt[i / KK][i % KK] = make_double2(a.w[o], a.wi ? a.wi[o] : 0.0);
+    }
+    __syncthreads();
+    if (!valid) continue;
+    for (int b = 0; b < nb; ++b)
+      for (int uj = uj0; uj < uj1; ++uj)
+        for (int ui = ui0; ui < ui1; ++ui) {
+          // w(u) conj(w(u - d))
+          const double2 x = wt[b][uj * K + ui], y = wt[b][(uj - dj) * K + (ui - di)];
+          sr = fma(x.x, y.x, fma(x.y, y.y, sr));
+          si = fma(x.y, y.x, fma(-x.x, y.y, si));
+        }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sr += __shfl_down(sr, off, 64);
-    si += __shfl_down(si, off, 64);
-  }
-  if (threadIdx.x % 64 == 0) {
-    red[0][threadIdx.x / 64] = sr;
-    red[1][threadIdx.x / 64] = si;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0)
-    a.coeff[blockIdx.x] = make_double2(((red[0][0] + red[0][1]) + red[0][2]) + red[0][3],
-                                       ((red[1][0] + red[1][1]) + red[1][2]) + red[1][3]);
+  if (valid) a.coeff[(int64_t)c * D2 + d] = make_double2(sr, si);
 }
 
 struct TaperImageArgs {
