@@ -59,7 +59,7 @@ typedef enum epic_status {
   EPIC_E_OFFGRID = 4,     /* a kernel tap of some antenna leaves the grid */
   EPIC_E_STATE = 5,       /* antennas not set before an imaging call */
   EPIC_E_LAUNCH = 6,      /* a kernel launch was rejected */
-  EPIC_E_UNSUPPORTED = 7  /* valid request outside what this build runs */
+  EPIC_E_UNSUPPORTED = 7  /* valid request outside what the library implements */
 } epic_status;
 
 /* epic_config.precision */
