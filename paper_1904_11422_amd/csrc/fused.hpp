@@ -218,19 +218,35 @@ __device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&s
   }
 }
 
-// 2'. Gather gridding of a long list (L a multiple of kStepChunk).
+// 2'. Gather gridding of a long list (L a multiple of kStepChunk).  The
+// steps come from global memory (L2) a chunk at a time; the next chunk is
+// loaded while the current one is gridded, so its latency is hidden.
 template <int N, int P, int RS, int ES, bool CPX>
 __device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* prog, const float* wim,
                                              int stride, int L) {
   float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
+  uint2 nsteps[kStepChunk];
+  float nwis[kStepChunk];
+#pragma unroll
+  for (int st = 0; st < kStepChunk; ++st) {
+    nsteps[st] = prog[st * stride];
+    nwis[st] = CPX ? wim[st * stride] : 0.f;
+  }
   for (int st0 = 0; st0 < L; st0 += kStepChunk) {
     uint2 steps[kStepChunk];
     float wis[kStepChunk];
     float2 e0[kStepChunk], e1[kStepChunk];
 #pragma unroll
     for (int st = 0; st < kStepChunk; ++st) {
-      steps[st] = prog[(st0 + st) * stride];
-      wis[st] = CPX ? wim[(st0 + st) * stride] : 0.f;
+      steps[st] = nsteps[st];
+      wis[st] = nwis[st];
+    }
+    if (st0 + kStepChunk < L) {
+#pragma unroll
+      for (int st = 0; st < kStepChunk; ++st) {
+        nsteps[st] = prog[(st0 + kStepChunk + st) * stride];
+        nwis[st] = CPX ? wim[(st0 + kStepChunk + st) * stride] : 0.f;
+      }
     }
 #pragma unroll
     for (int st = 0; st < kStepChunk; ++st) read_e<P, ES>(lds, steps[st], e0[st], e1[st]);
