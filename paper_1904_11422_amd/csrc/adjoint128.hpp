@@ -139,13 +139,21 @@ adjoint128_kernel(AdjointArgs a) {
 #pragma unroll
         for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
       line_transform<N, +1, P, true>(v, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
+      if (h) {
 #pragma unroll
-      for (int p = 0; p < P; ++p)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+          for (int q = 0; q < 2; ++q)
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            X[p * PS + rb + 2 * r.n0 + q + 16 * k] = h ? v[p][q * R + 4 + k] : v[p][q * R + k];
+            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + 4 + k];
+      } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + k];
+      }
     }
     __syncthreads();
 
@@ -190,15 +198,26 @@ adjoint128_kernel(AdjointArgs a) {
     //    the other half's are zero; keep the aperture columns 8 n1 + n0 < 64
     if (line >= 0) {
       float2 u[P][S];
+      // (h is uniform over the workgroup: a branch, not a per-value select)
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int i = 0; i < S; ++i) u[p][i] = make_float2(0.f, 0.f);
+      if (h) {
 #pragma unroll
-          for (int k1 = 0; k1 < R; ++k1) {
-            const bool mine = (k1 >> 2) == h;
-            u[p][q * R + k1] = mine ? X[p * PS + rb + 2 * r.n0 + q + 16 * (k1 & 3)] : make_float2(0.f, 0.f);
-          }
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[p][q * R + 4 + k] = X[p * PS + rb + 2 * r.n0 + q + 16 * k];
+      } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) u[p][q * R + k] = X[p * PS + rb + 2 * r.n0 + q + 16 * k];
+      }
       line_transform_rev<N, -1, P>(u, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
 #pragma unroll
       for (int p = 0; p < P; ++p)

@@ -159,13 +159,22 @@ fused_image128_kernel(Fused128Args a) {
         for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
       line_transform<N, +1, P, true>(v, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
       // v[p][q R + k1] = X_p[2 n0 + q + 16 k1]; half h holds k1 in [4 h, 4 h + 4)
+      // (h is uniform over the workgroup: a branch, not a per-value select)
+      if (h) {
 #pragma unroll
-      for (int p = 0; p < P; ++p)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+          for (int q = 0; q < 2; ++q)
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            X[p * PS + rb + 2 * r.n0 + q + 16 * k] = h ? v[p][q * R + 4 + k] : v[p][q * R + k];
+            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + 4 + k];
+      } else {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + k];
+      }
     }
     __syncthreads();
 
