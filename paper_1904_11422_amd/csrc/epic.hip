@@ -407,6 +407,19 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
             s.started = true;
           }
         }
+        // lanes reading the same antenna share one LDS access (a broadcast),
+        // so only the distinct antennas of the step load the banks
+        int picked[16], npicked = 0;
+        auto is_picked = [&](int ant) {
+          for (int i = 0; i < npicked; ++i)
+            if (picked[i] == ant) return true;
+          return false;
+        };
+        auto take = [&](int ant) {
+          if (is_picked(ant)) return;
+          picked[npicked++] = ant;
+          used[ant % 16]++;
+        };
         for (int l = 0; l < 16; ++l) {                 // lanes with one entry left
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
@@ -415,7 +428,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
             pick_w[l] = s.left[0].second;
             pick_cell[l] = runs[s.run]->cell;
             pick_last[l] = true;
-            used[pick_e[l] % 16]++;
+            take(pick_e[l]);
             decided[l] = true;
           }
         }
@@ -424,22 +437,31 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
           Lane& s = st[l];
           const auto& runs = lane_runs[16 * q + l];
           if (s.run >= runs.size() || s.left.empty()) continue;
+          // an antenna another lane already reads costs nothing, else its bank's load
+          auto cost = [&](int ant) { return is_picked(ant) ? -1 : used[ant % 16]; };
           size_t best = 0;
           for (size_t k = 1; k < s.left.size(); ++k)
-            if (used[s.left[k].first % 16] < used[s.left[best].first % 16]) best = k;
+            if (cost(s.left[k].first) < cost(s.left[best].first)) best = k;
           pick_e[l] = s.left[best].first;
           pick_w[l] = s.left[best].second;
           pick_cell[l] = runs[s.run]->cell;
           pick_last[l] = false;
-          used[pick_e[l] % 16]++;
+          take(pick_e[l]);
           decided[l] = true;
         }
         for (int l = 0; l < 16; ++l) {                 // empty cells and padding
           if (decided[l]) continue;
-          int z = 0;
-          for (int k = 1; k < 16; ++k)
-            if (used[(A + k) % 16] < used[(A + z) % 16]) z = k;
-          used[(A + z) % 16]++;
+          // a zero slot another lane already reads (a broadcast), else the
+          // zero slot on the least loaded bank
+          int z = -1;
+          for (int k = 0; k < 16 && z < 0; ++k)
+            if (is_picked(A + k)) z = k;
+          if (z < 0) {
+            z = 0;
+            for (int k = 1; k < 16; ++k)
+              if (used[(A + k) % 16] < used[(A + z) % 16]) z = k;
+          }
+          take(A + z);
           pick_e[l] = A + z;
           pick_w[l] = kNoTap;
           const Lane& s = st[l];
