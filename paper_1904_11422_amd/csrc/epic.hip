@@ -363,25 +363,71 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     // cells of each wave's rows, longest first, to the least loaded lane of the wave
     std::vector<std::vector<const Run*>> lane_runs(NT);
     std::vector<int> load(NT, 0);
+    std::vector<std::vector<std::vector<const Run*>>> spat_w(NWR);
+    std::vector<std::vector<int>> spat_ld(NWR);
+    int plain_max = 1;
     for (int w = 0; w < NWR; ++w) {
       std::vector<const Run*> wc;
       for (int sl = 0; sl < SPW; ++sl)
         for (int i = 0; i < H; ++i) wc.push_back(&cells[row_of[w][sl] * H + i]);
-      std::stable_sort(wc.begin(), wc.end(), [](const Run* x, const Run* y) {
-        return std::max<size_t>(1, x->ent.size()) > std::max<size_t>(1, y->ent.size());
-      });
       using Load = std::pair<int, int>;                // (steps, thread)
-      std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-      for (int t = 64 * w; t < 64 * w + 64; ++t) pq.push({0, t});
-      for (const Run* r : wc) {
-        Load ld = pq.top();
-        pq.pop();
-        lane_runs[ld.second].push_back(r);
-        ld.first += (int)std::max<size_t>(1, r->ent.size());
-        load[ld.second] = ld.first;
-        pq.push(ld);
+      auto steps_of = [](const Run* r) { return (int)std::max<size_t>(1, r->ent.size()); };
+      // longest cell first to the least loaded of the given lanes
+      auto lpt = [&](const std::vector<const Run*>& cells_in, int t0, int nl,
+                     std::vector<std::vector<const Run*>>& out, std::vector<int>& ld_out) {
+        std::vector<const Run*> cs(cells_in);
+        std::stable_sort(cs.begin(), cs.end(), [&](const Run* x, const Run* y) { return steps_of(x) > steps_of(y); });
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+        for (int t = t0; t < t0 + nl; ++t) pq.push({0, t});
+        for (const Run* r : cs) {
+          Load ld = pq.top();
+          pq.pop();
+          out[ld.second - 64 * w].push_back(r);
+          ld.first += steps_of(r);
+          ld_out[ld.second - 64 * w] = ld.first;
+          pq.push(ld);
+        }
+      };
+      // the whole wave by longest cell first
+      std::vector<std::vector<const Run*>> plain(64), spat(64);
+      std::vector<int> lp(64, 0), ls(64, 0);
+      lpt(wc, 64 * w, 64, plain, lp);
+      // each half-wave a run of neighbouring cells (the wave's cells in
+      // column-major order cut into two runs of equal step counts), so that
+      // lanes reading E' together grid cells that share antennas and their
+      // reads can be broadcasts
+      std::vector<const Run*> sp(wc);
+      std::stable_sort(sp.begin(), sp.end(), [&](const Run* x, const Run* y) {
+        const int cx = x->cell % RS, cy = y->cell % RS;
+        return cx != cy ? cx < cy : x->cell < y->cell;
+      });
+      int tot = 0;
+      for (const Run* r : sp) tot += steps_of(r);
+      std::vector<const Run*> half[2];
+      {
+        int acc = 0;
+        for (const Run* r : sp) {
+          half[std::min(1, (int)((acc + steps_of(r) / 2) * 2LL / std::max(1, tot)))].push_back(r);
+          acc += steps_of(r);
+        }
       }
+      lpt(half[0], 64 * w, 32, spat, ls);
+      lpt(half[1], 64 * w + 32, 32, spat, ls);
+      for (int l = 0; l < 64; ++l) {
+        lane_runs[64 * w + l] = plain[l];
+        load[64 * w + l] = lp[l];
+      }
+      plain_max = std::max(plain_max, *std::max_element(lp.begin(), lp.end()));
+      spat_w[w] = std::move(spat);
+      spat_ld[w] = std::move(ls);
     }
+    // the spatial assignment of a wave wherever it does not lengthen the program
+    for (int w = 0; w < NWR; ++w)
+      if (*std::max_element(spat_ld[w].begin(), spat_ld[w].end()) <= plain_max)
+        for (int l = 0; l < 64; ++l) {
+          lane_runs[64 * w + l] = spat_w[w][l];
+          load[64 * w + l] = spat_ld[w][l];
+        }
     const int Lc = std::max(1, *std::max_element(load.begin(), load.end()));
     L = std::max(L, Lc);
     // step-by-step choice of the E' entries, per quarter-wave (measured faster
