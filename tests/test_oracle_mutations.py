@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from oracle import moff
+import tests.test_golden_host as golden
 import tests.test_oracle_pins as pins
 
 _transform = moff.transform
@@ -15,6 +16,7 @@ _auto_vis = moff.auto_visibilities
 _front = moff.decimate_transpose
 _stokes = moff.pseudo_stokes
 _taper = moff.kernel_taper
+_cells = moff.antenna_cells
 
 
 def _wrong_sign(a):
@@ -126,6 +128,11 @@ def _grad_kernel_unconjugated(xy_m, freq_hz, gains, efield, grid_n, grad_image, 
     return 2.0 * out
 
 
+def _cells_of_one_wavelength(xy_m, freq_hz, grid_n, cell_wavelengths=0.5):
+    """Grid cells one wavelength wide whatever the spacing asked for."""
+    return _cells(xy_m, freq_hz, grid_n, 1.0)
+
+
 def _stokes_v_flipped(img):
     out = _stokes(img)
     if out.shape[1] == 4:
@@ -183,6 +190,9 @@ MUTATIONS = {
     "kernel taper not squared": (
         "kernel_taper", _taper_not_squared,
         [pins.test_p17_taper_correction_is_exact_for_identical_kernels]),
+    "grid cells a whole wavelength wide": (
+        "antenna_cells", _cells_of_one_wavelength,
+        [golden.test_half_wavelength_grid_of_the_deployed_aperture_is_about_64_cells]),
     "autocorrelation gradient without the factor 2": (
         "grad_autos", _grad_autos_variant(two=1.0),
         [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),
