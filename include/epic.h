@@ -129,19 +129,22 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
  * EPIC_FLAG_STAGED).  out receives, as epic_set_antennas uploads it,
  *   uint32 [n_chan][1 + L][NT][2]:
  *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
- *                    (int32 -1: none); word 1: 0;
+ *                    (int32 -1: none); word 1: 0, or for the wide block (below)
+ *                    the line of the second row pass (int32 -1: none);
  *     rows 1..L:     steps {LDS byte offset of the cell, relative to the grid
  *                    base, << 15 | LDS byte offset of E'[p = 0][a] (a multiple
  *                    of 8), bit 0 set on a cell's last entry; float32 weight}.
  * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
  * layout: out, int32 [7] = {NT, L, row stride, polarisation stride, grid base,
  * E' polarisation stride, row order}, strides and base in float2 units; row
- * order 1: aperture row j < N/2 is stored at physical row
+ * order 1: aperture row j is stored at physical row
  * 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and cell offsets use
- * physical rows), 0: at row j.
+ * physical rows), 0: at row j.  The aperture block is N/2 x N/2 cells, or at
+ * N = 64, when some channel's taps do not fit that, 48 x 48 (the wide block,
+ * two row passes; its gradient runs the staged kernels).
  * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
  * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
- * taps do not fit an N/2 x N/2 block), EPIC_E_NOMEM (capacity too small;
+ * taps do not fit the block), EPIC_E_NOMEM (capacity too small;
  * *words holds the size).  Messages: epic_last_error(NULL). */
 epic_status epic_gridding_program(const epic_config *cfg, const double *xy_m,
                                   const double *freq_hz, uint32_t *out, int64_t *words,

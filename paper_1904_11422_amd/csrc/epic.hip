@@ -60,6 +60,7 @@ struct Geometry {
   std::vector<float> w;               // [C][A][KK] (real parts for complex kernels)
   std::vector<float> wi;              // [C][A][KK] imaginary parts, empty for real kernels
   bool fits_half = true;              // every channel's taps fit an N/2 x N/2 block
+  bool fits_wide = true;              // ... a 3N/4 x 3N/4 block (the wide fused variant)
 };
 
 struct DeviceGuard {
@@ -86,6 +87,9 @@ struct epic_ctx {
   // path selection: fused_ok = the configuration has fused kernels (decided at
   // init); fused = the current geometry uses them (decided at set_antennas)
   bool fused_ok = true, fused = false;
+  bool wide = false;                  // fused, with the wide variant (N = 64, apertures up to 3N/4);
+                                      // the gradient then runs the staged kernels
+  int fused_w_wide = 0, fused_w_wide_cpx = 0;
   int fused_gpt = 1;
   int fused_w = 0;                    // persistent workgroups (upper bound)
   int w_override = 0;                 // tuned grid size (0: fused_w)
@@ -211,6 +215,7 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
       if (!std::isfinite(kernels[o])) { m = "kernel value is not finite"; return EPIC_E_INVALID; }
   }
   g.fits_half = true;
+  g.fits_wide = true;
   for (int c = 0; c < C; ++c) {
     const double cell_m = kC0 / freq[c] * cfg.cell_wavelengths;
     int jmin = N, jmax = -1, imin = N, imax = -1;
@@ -244,6 +249,7 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
         }
     }
     if (jmax - jmin + 1 > N / 2 || imax - imin + 1 > N / 2) g.fits_half = false;
+    if (jmax - jmin + 1 > 3 * N / 4 || imax - imin + 1 > 3 * N / 4) g.fits_wide = false;
     for (size_t o = (size_t)c * A * g.KK; o < (size_t)(c + 1) * A * g.KK; ++o)
       g.tcell[o] = (g.cell[o] / N - jmin) * N + (g.cell[o] % N - imin);
   }
@@ -270,7 +276,7 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
 //    and write nothing.
 template <int N>
 void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& out, int& L,
-                    std::vector<float>* out_im = nullptr) {
+                    std::vector<float>* out_im = nullptr, bool wide = false) {
   constexpr int NT = epic::FusedShape<N>::NT, RS = epic::FusedShape<N>::RS, H = N / 2;
   constexpr int CPW = epic::FusedShape<N>::CPW, NWAVE = NT / 64;
   const int C = g.C, A = g.A, KK = g.KK;
@@ -280,7 +286,12 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   // row slots per wave: CPW / P lines of one polarisation each, or at N = 128
   // CPW rows whose lane group takes both polarisations
   const int SPW = N == 128 ? CPW : CPW / P;
-  const int NWR = H / SPW;                             // waves that own rows
+  // wide (N = 64): an HW x HW block, HW / NWAVE rows per wave, whose lines
+  // take one row pass (the first SPW rows of each polarisation) and a second
+  // one (the rest); the header's second word is the second pass's line
+  const int HB = wide ? SH::HW : H;                    // aperture block side
+  const int RPW = wide ? HB / NWAVE : SPW;             // rows per wave
+  const int NWR = wide ? NWAVE : H / SPW;              // waves that own rows
   // residue rule (row j of slot s in a wave of group t has j mod M = residue):
   // at N = 64 it puts the 4 (P = 2) or 8 (P = 1) rows a half-wave transforms
   // on distinct bank ranges given the interleaved physical rows and the
@@ -319,28 +330,28 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   };
   std::vector<std::vector<uint32_t>> words((size_t)C * NT);   // [c][thread] -> step words
   std::vector<std::vector<float>> wims(cpx ? (size_t)C * NT : 0);
-  std::vector<int32_t> header((size_t)C * NT, -1);
+  std::vector<int32_t> header((size_t)C * NT, -1), header2((size_t)C * NT, -1);
   L = 1;
   for (int c = 0; c < C; ++c) {
-    std::vector<Run> cells(H * H);
-    for (int j = 0; j < H; ++j)
-      for (int i = 0; i < H; ++i) cells[j * H + i].cell = SH::phys_row(j) * RS + i;
+    std::vector<Run> cells(HB * HB);
+    for (int j = 0; j < HB; ++j)
+      for (int i = 0; i < HB; ++i) cells[j * HB + i].cell = SH::phys_row(j) * RS + i;
     for (int a = 0; a < A; ++a)
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-        cells[j * H + i].ent.push_back({a, o});
+        cells[j * HB + i].ent.push_back({a, o});
       }
     // rows to (wave, slot): slot s of a wave in group t takes a row j with
     // j mod M = residue(s, t); each residue class has exactly as many rows as
     // the group has waves, dealt heaviest first to the least loaded wave
-    std::vector<int> row_load(H, 0);
-    for (int j = 0; j < H; ++j)
-      for (int i = 0; i < H; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * H + i].ent.size());
+    std::vector<int> row_load(HB, 0);
+    for (int j = 0; j < HB; ++j)
+      for (int i = 0; i < HB; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * HB + i].ent.size());
     std::vector<int> wave_load(NWAVE, 0);
-    std::vector<std::vector<int>> row_of(NWAVE, std::vector<int>(SPW, -1));
+    std::vector<std::vector<int>> row_of(NWAVE, std::vector<int>(RPW, -1));
     const int WPG = NWR / NGRP;                        // waves per group
-    for (int t = 0; t < NGRP; ++t)
+    for (int t = 0; t < (wide ? 0 : NGRP); ++t)
       for (int sl = 0; sl < SPW; ++sl) {
         const int rho = residue(sl, t);
         std::vector<int> rows;
@@ -354,11 +365,27 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
           wave_load[bw] += row_load[j];
         }
       }
+    if (wide) {                                        // heaviest row to the least loaded wave
+      std::vector<int> rows(HB);
+      for (int j = 0; j < HB; ++j) rows[j] = j;
+      std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
+      std::vector<int> used(NWAVE, 0);
+      for (int j : rows) {
+        int bw = -1;
+        for (int w = 0; w < NWAVE; ++w)
+          if (used[w] < RPW && (bw < 0 || wave_load[w] < wave_load[bw])) bw = w;
+        row_of[bw][used[bw]++] = j;
+        wave_load[bw] += row_load[j];
+      }
+    }
     for (int t = 0; t < NT; ++t) {
       const epic::Roles<N> ro(t);
       if (ro.wave >= NWR) continue;
       const int p = ro.sub / SPW, sl = ro.sub % SPW;     // N = 128: p = 0, both polarisations
-      if (p < P) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
+      if (p >= P) continue;
+      if (sl < RPW) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
+      if (wide && SPW + sl < RPW)
+        header2[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][SPW + sl]);
     }
     // cells of each wave's rows, longest first, to the least loaded lane of the wave
     std::vector<std::vector<const Run*>> lane_runs(NT);
@@ -368,8 +395,8 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     int plain_max = 1;
     for (int w = 0; w < NWR; ++w) {
       std::vector<const Run*> wc;
-      for (int sl = 0; sl < SPW; ++sl)
-        for (int i = 0; i < H; ++i) wc.push_back(&cells[row_of[w][sl] * H + i]);
+      for (int sl = 0; sl < RPW; ++sl)
+        for (int i = 0; i < HB; ++i) wc.push_back(&cells[row_of[w][sl] * HB + i]);
       using Load = std::pair<int, int>;                // (steps, thread)
       auto steps_of = [](const Run* r) { return (int)std::max<size_t>(1, r->ent.size()); };
       // longest cell first to the least loaded of the given lanes
@@ -545,7 +572,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     for (int t = 0; t < NT; ++t) {
       const size_t h = ((size_t)c * (L + 1) * NT + t) * 2;
       out[h] = (uint32_t)header[(size_t)c * NT + t];
-      out[h + 1] = 0u;
+      out[h + 1] = wide ? (uint32_t)header2[(size_t)c * NT + t] : 0u;
       const auto& wv = words[(size_t)c * NT + t];
       const uint32_t pad = code(0, A + t % 16, false);
       for (int s2 = 0; s2 < L; ++s2) {
@@ -573,6 +600,19 @@ template <int N, int P, int GPT>
 int fused_blocks_per_cu(bool cpx) {
   return cpx ? occupancy_blocks(epic::fused_image_kernel<N, P, GPT, true>, epic::FusedShape<N>::NT)
              : occupancy_blocks(epic::fused_image_kernel<N, P, GPT, false>, epic::FusedShape<N>::NT);
+}
+
+template <int P, int GPT>
+int fused_wide_blocks_per_cu(bool cpx) {
+  return cpx ? occupancy_blocks(epic::fused_wide_image_kernel<64, P, GPT, true>, epic::FusedShape<64>::NT)
+             : occupancy_blocks(epic::fused_wide_image_kernel<64, P, GPT, false>, epic::FusedShape<64>::NT);
+}
+
+int fused_wide_blocks_per_cu(int P, int gpt, bool cpx) {
+  if (P == 1) return gpt == 1 ? fused_wide_blocks_per_cu<1, 1>(cpx)
+                   : gpt == 2 ? fused_wide_blocks_per_cu<1, 2>(cpx) : fused_wide_blocks_per_cu<1, 4>(cpx);
+  return gpt == 1 ? fused_wide_blocks_per_cu<2, 1>(cpx)
+       : gpt == 2 ? fused_wide_blocks_per_cu<2, 2>(cpx) : fused_wide_blocks_per_cu<2, 4>(cpx);
 }
 
 template <int P>
@@ -632,6 +672,20 @@ int fused_threads(int N) {
 bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
   const dim3 grid(a.W), block(fused_threads(N));
+  if (x->wide) {
+    if (N != 64) return false;
+#define EPIC_LW(PP, GG)                                                                      \
+    if (P == PP && G == GG) {                                                                \
+      if (x->cpx) hipLaunchKernelGGL((epic::fused_wide_image_kernel<64, PP, GG, true>), grid, block, 0, \
+                                     x->stream, a);                                          \
+      else hipLaunchKernelGGL((epic::fused_wide_image_kernel<64, PP, GG, false>), grid, block, 0, \
+                              x->stream, a);                                                 \
+      return true;                                                                           \
+    }
+    EPIC_LW(1, 1) EPIC_LW(1, 2) EPIC_LW(1, 4) EPIC_LW(2, 1) EPIC_LW(2, 2) EPIC_LW(2, 4)
+#undef EPIC_LW
+    return false;
+  }
 #define EPIC_LF(NN, PP, GG)                                                                 \
   if (N == NN && P == PP && G == GG) {                                                      \
     if (x->cpx) hipLaunchKernelGGL((epic::fused_image_kernel<NN, PP, GG, true>), grid, block, 0, \
@@ -1165,11 +1219,12 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
+    const int w_cap = x->wide ? (x->cpx ? x->fused_w_wide_cpx : x->fused_w_wide)
+                              : (x->cpx ? x->fused_w_cpx : x->fused_w);
     const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
     a.W = (int)std::min<int64_t>(w_max, total);
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
-    x->last_kernel = "fused_image_kernel";
+    x->last_kernel = x->wide ? "fused_wide_image_kernel" : "fused_image_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::ReduceArgs r;
     r.partial = x->partial.as<double>();
@@ -1417,6 +1472,10 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     x->fused_w = bpc * x->n_cu;
     // complex-kernel variants: never more workgroups than the slots allow
     x->fused_w_cpx = std::min(x->fused_w, fused_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
+    if (N == 64) {
+      x->fused_w_wide = std::min(x->fused_w, fused_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, false) * x->n_cu);
+      x->fused_w_wide_cpx = std::min(x->fused_w, fused_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, true) * x->n_cu);
+    }
     // N = 128: two accumulation segments (column halves) per channel
     const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
     const size_t slots = (size_t)x->fused_w + segs - 1;
@@ -1502,11 +1561,12 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   Geometry g;
   s = build_geometry(*cfg, xy_m, freq_hz, nullptr, g, m);
   if (s != EPIC_OK) { g_init_error = m; return s; }
-  if (!g.fits_half) { g_init_error = "taps do not fit an N/2 x N/2 block"; return EPIC_E_UNSUPPORTED; }
+  const bool wide = N == 64 && !g.fits_half && g.fits_wide;
+  if (!g.fits_half && !wide) { g_init_error = "taps do not fit the fused kernels' aperture block"; return EPIC_E_UNSUPPORTED; }
   std::vector<uint32_t> prog;
   int L = 0;
   if (N == 32) build_programs<32>(g, P, gpt, prog, L);
-  else if (N == 64) build_programs<64>(g, P, gpt, prog, L);
+  else if (N == 64) build_programs<64>(g, P, gpt, prog, L, nullptr, wide);
   else build_programs<128>(g, P, gpt, prog, L);
   if (L == 0) { g_init_error = "gridding program fields overflow"; return EPIC_E_UNSUPPORTED; }
   const int64_t need = (int64_t)prog.size(), cap = *words;
@@ -1559,9 +1619,12 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
     x->have_geom = true;
     return EPIC_OK;
   }
-  // The fused kernels need every channel's taps inside an N/2 x N/2 block;
-  // larger apertures (aliased images) run the staged kernels.
-  x->fused = x->fused_ok && g.fits_half;
+  // The fused kernels need every channel's taps inside an N/2 x N/2 block, or
+  // at N = 64 inside a 3N/4 x 3N/4 block (wide variant); larger apertures
+  // (aliased images) run the staged kernels.  The wide variant's gradient runs
+  // the staged kernels, so it keeps their tables too.
+  x->wide = x->fused_ok && N == 64 && !g.fits_half && g.fits_wide;
+  x->fused = x->fused_ok && (g.fits_half || x->wide);
 
   if (x->fused) {
     // adjoint taps [C][A][KK] {translated cell, w}
@@ -1575,7 +1638,7 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
     std::vector<float> prog_im;
     int L = 0;
     if (N == 32) build_programs<32>(g, P, x->fused_gpt, prog, L, &prog_im);
-    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L, &prog_im);
+    else if (N == 64) build_programs<64>(g, P, x->fused_gpt, prog, L, &prog_im, x->wide);
     else build_programs<128>(g, P, x->fused_gpt, prog, L, &prog_im);
     if (L == 0) return x->fail(EPIC_E_UNSUPPORTED, "gridding program fields overflow");
     if (!x->taps.alloc(taps.size() * 4) || !x->prog.alloc(prog.size() * 4) ||
@@ -1588,7 +1651,8 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
          hipMemcpy(x->taps_im.p, g.wi.data(), g.wi.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
     x->L = L;
-  } else {
+  }
+  if (!x->fused || x->wide) {
     if (!alloc_staged(x)) return x->fail(EPIC_E_NOMEM, "staged workspace allocation failed");
     // per-cell CSR over the whole grid, entries in (antenna, tap) order
     const int npix = N * N, nnz = A * g.KK;
@@ -1676,7 +1740,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (x->cfg.precision != EPIC_FP32)
     return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the float32 paths");
   DeviceGuard guard(x->device);
-  if (!x->fused) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
+  if (!x->fused || x->wide) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
   const int C = x->cfg.n_chan;
   // work units per channel: samples, or (half, sample) pairs at N = 128
   const int64_t upc = x->cfg.grid_n == 128 ? 2 * n_time : n_time;

@@ -74,6 +74,9 @@ template <int N> struct FusedShape {
     return N == 64 ? 8 * (j >> 3) + 2 * (j & 3) + ((j >> 2) & 1) : j;
   }
   static constexpr int H = N / 2;              // aperture block side
+  // aperture block side of the wide variant (N = 64): rows and columns
+  // R n1 + n0 < HW are the inputs n1 < HW / R of a line
+  static constexpr int HW = 3 * N / 4;
   static constexpr int KBLOCK = 128;           // samples summed in float32 before a float64 flush
   // waves per SIMD the register budget is sized for: two resident workgroups
   // per CU (4 waves/SIMD, <= 128 VGPRs) at N = 64
@@ -301,14 +304,26 @@ __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, 
 // forward, the row holds cells at columns < H.  SG < 0: adjoint, the row
 // holds the forward output layout and the columns < H of the result are
 // written back.
-template <int N, int P, int SG>
+// WIDE (forward only): the row holds cells at columns < HW; the inputs
+// n1 >= HW / R are zero.
+template <int N, int P, int SG, bool WIDE = false>
 __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw, int line) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
   constexpr int RS = FusedShape<N>::RS, PS = FusedShape<N>::PSTRIDE;
+  static_assert(!WIDE || (SG > 0 && FusedShape<N>::HW % R == 0), "wide rows: forward, whole inputs");
   if (line >= 0) {
     float2* row = X + (line >> 16) * PS + (line & 0xFFFF) * RS;
     float2 v[1][S];
-    if (SG > 0) {
+    if constexpr (SG > 0 && WIDE) {
+      constexpr int NIN = FusedShape<N>::HW / R;
+#pragma unroll
+      for (int n1 = 0; n1 < S; ++n1) v[0][n1] = n1 < NIN ? row[R * n1 + r.n0] : make_float2(0.f, 0.f);
+      line_transform<N, +1, 1, false>(v, tw, r.n0, row, [](int, int s) { return s; });
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+#pragma unroll
+        for (int k1 = 0; k1 < R; ++k1) row[r.n0 * D + q + S * k1] = v[0][q * R + k1];
+    } else if (SG > 0) {
 #pragma unroll
       for (int n1 = 0; n1 < S / 2; ++n1) v[0][n1] = row[R * n1 + r.n0];
       line_transform<N, +1, 1, true>(v, tw, r.n0, row, [](int, int s) { return s; });
@@ -329,27 +344,32 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 }
 
 // 3b. Forward column transforms of column r.kl for all polarisations; only
-// rows < H are nonzero (stored at their physical rows).  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
-template <int N, int P>
+// rows < H (WIDE: < HW) are nonzero (stored at their physical rows).
+// Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
+template <int N, int P, bool WIDE = false>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
                                                 const Roles<N>& r, const float2* tw) {
   using SH = FusedShape<N>;
   constexpr int S = Line<N>::S, R = Line<N>::R, RS = SH::RS, PS = SH::PSTRIDE;
+  constexpr int NIN = WIDE ? SH::HW / R : S / 2;
   const int kl = r.kl;
 #pragma unroll
   for (int p = 0; p < P; ++p) {                 // one polarisation at a time
     float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
 #pragma unroll
-    for (int n1 = 0; n1 < S / 2; ++n1) vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
-    line_transform<N, +1, 1, true, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
-                                   [kl](int, int s) { return s * RS + kl; });
+    for (int n1 = 0; n1 < S; ++n1)
+      if (n1 < NIN) vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
+      else if (WIDE) vp[0][n1] = make_float2(0.f, 0.f);
+    line_transform<N, +1, 1, !WIDE, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
+                                    [kl](int, int s) { return s * RS + kl; });
   }
 }
 
-template <int N, int P, int GPT, bool CPX>
-__global__ void __launch_bounds__(FusedShape<N>::NT)
-__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
-fused_image_kernel(FusedArgs a) {
+// The whole per-workgroup loop.  WIDE (N = 64): apertures up to HW x HW
+// cells; the programs' header gives each thread a second row-pass line
+// (prog[tid].y, < 0: none) and both passes take their lines' inputs n1 < HW / R.
+template <int N, int P, int GPT, bool CPX, bool WIDE>
+__device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   using SH = FusedShape<N>;
   constexpr int S = SH::S, NT = SH::NT, RS = SH::RS, KB = SH::KBLOCK;
   constexpr int NACC = (P == 2) ? 4 : 1;
@@ -379,7 +399,7 @@ fused_image_kernel(FusedArgs a) {
   float acc[S][NACC];                          // float32 sums over <= KB samples
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, nblk = 0, nflush = 0, line = -1;
+  int c = -1, nblk = 0, nflush = 0, line = -1, line2 = -1;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -418,6 +438,7 @@ fused_image_kernel(FusedArgs a) {
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
       if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
+      if (WIDE) line2 = (int)prog[tid].y;
       prog += NT;
 #pragma unroll
       for (int i = 0; i < S; ++i)
@@ -439,10 +460,11 @@ fused_image_kernel(FusedArgs a) {
     if (left > 1) load_bytes(cc, tt, nxt);
 
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
-    row_pass<N, P, +1>(X, r, tw, line);
+    row_pass<N, P, +1, WIDE>(X, r, tw, line);
+    if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P>(v, X, r, tw);
+    column_pass_fwd<N, P, WIDE>(v, X, r, tw);
 
     // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
 #pragma unroll
@@ -459,6 +481,22 @@ fused_image_kernel(FusedArgs a) {
     ++nblk;
   }
   flush();
+}
+
+template <int N, int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
+fused_image_kernel(FusedArgs a) {
+  fused_image_body<N, P, GPT, CPX, false>(a);
+}
+
+// Apertures wider than N/2 cells (up to 3N/4) at N = 64.
+template <int N, int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
+fused_wide_image_kernel(FusedArgs a) {
+  static_assert(N == 64, "the wide variant is built for N = 64");
+  fused_image_body<N, P, GPT, CPX, true>(a);
 }
 
 // image[c][prod][qm][ql] (+)= sum over the workgroups covering channel c of

@@ -317,6 +317,23 @@ def config5(k: int = 5, n_time: int = 200, n_chan: int = 64, n_src: int = 20,
                   name="cfg5")
 
 
+def deployment(seed: int = 50, n_time: int = 1250, n_chan: int = 4, n_pol: int = 2) -> Inputs:
+    """The deployed geometry of the paper (Sec. 4.1-4.2): 256 antennas uniform in
+    a 110 m x 100 m ellipse elongated north-south, 25 kHz channels centred on
+    55.25 MHz, a 64-cell grid at lambda / 2 (about 43 cells across with the
+    taps), 3 x 3 Gaussian; random gains and uniformly random bytes.  The
+    default n_time is one 50 ms image of 40 us samples."""
+    rng = np.random.default_rng(seed)
+    A = 256
+    r = np.sqrt(rng.uniform(0.0, 1.0, A))
+    t = rng.uniform(0.0, 2 * np.pi, A)
+    xy = np.stack([50.0 * r * np.cos(t), 55.0 * r * np.sin(t)], 1)
+    freq = lwa_channels(n_chan, 55.25e6)
+    gains = random_gains(rng, (n_chan, n_pol, A))
+    ef = random_bytes(rng, (n_time, n_chan, n_pol, A))
+    return Inputs(64, n_chan, n_pol, A, 3, 0.5, 0.5, xy, freq, gains, ef, name=f"deployment{seed}")
+
+
 def random_problem(seed: int, grid_n: int, n_ant: int, n_chan: int, n_pol: int,
                    n_time: int, centre_hz: float = 38e6, fill: float = 0.45,
                    min_sep_cells: float = 1.0) -> Inputs:

@@ -81,6 +81,7 @@ CASES = {
     "n64_p2_k5": (lambda: _k5(404, 64, 96, 2, 2, 13), {}),
     "n128_p2": (lambda: synth.random_problem(405, 128, 400, 2, 2, 5, fill=0.45), {}),
     "n64_p2_staged": (lambda: synth.random_problem(406, 64, 64, 2, 2, 9), {"staged": True}),
+    "n64_p2_wide": (lambda: synth.random_problem(410, 64, 140, 2, 2, 9, fill=0.66), {}),
     "n128_p1": (lambda: synth.random_problem(407, 128, 200, 1, 1, 4, fill=0.45), {}),
     "n128_p1_staged": (lambda: synth.random_problem(407, 128, 200, 1, 1, 4, fill=0.45),
                        {"staged": True}),

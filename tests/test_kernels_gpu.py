@@ -40,7 +40,8 @@ CASES = {
     "n128_p2_k9": (lambda: _case(604, 128, 300, 2, 2, 4, 9, 0.38), {}, "fused_image128_kernel"),
     "n128_p2_k15": (lambda: _case(605, 128, 200, 1, 2, 3, 15, 0.25), {}, "fused_image128_kernel"),
     "n128_p1_k7": (lambda: _case(609, 128, 400, 2, 1, 4, 7, 0.4), {}, "fused_image128_kernel"),
-    "n64_p2_k11_wide": (lambda: _case(606, 64, 80, 2, 2, 5, 11, 0.45), {}, "staged_fft_kernel"),
+    "n64_p2_k11_wide": (lambda: _case(606, 64, 80, 2, 2, 5, 11, 0.45), {}, "fused_wide_image_kernel"),
+    "n64_p1_k15_beyond_wide": (lambda: _case(610, 64, 60, 2, 1, 4, 15, 0.6), {}, "staged_fft_kernel"),
     "n32_p2_k5_staged": (lambda: _case(607, 32, 40, 2, 2, 6, 5, 0.4), {"staged": True},
                          "staged_fft_kernel"),
     "split16_p2_k5": (lambda: _case(608, 32, 16, 2, 2, 40, 5, 0.4), {"precision": "split_fp16"},
@@ -104,6 +105,7 @@ def test_gaussian_given_as_kernels_matches_the_built_in_path():
 
 
 @pytest.mark.parametrize("seed,N,A,C,P,T,K", [(621, 32, 16, 2, 2, 5, 5), (622, 32, 20, 1, 1, 7, 3),
+                                              (627, 64, 90, 2, 2, 4, 9),
                                               (623, 64, 96, 2, 2, 6, 7), (624, 64, 50, 2, 1, 4, 9),
                                               (625, 128, 150, 1, 2, 3, 7), (626, 128, 120, 2, 1, 3, 11)])
 def test_complex_kernel_gradient_matches_oracle(seed, N, A, C, P, T, K):

@@ -91,6 +91,48 @@ def test_grid128_routes():
     assert oracle.rel_errors(got2, oracle.image_from(inp1)).max() <= TOL_FP32
 
 
+WIDE = {
+    # apertures wider than N/2 cells at N = 64 (up to 48): the wide fused kernel
+    "p2_a200": lambda: synth.random_problem(131, 64, 200, 3, 2, 9, fill=0.7),
+    "p1_a150_ragged": lambda: synth.random_problem(132, 64, 150, 2, 1, 13, fill=0.6),
+    "p2_a600_four_per_thread": lambda: synth.random_problem(133, 64, 600, 2, 2, 4, fill=0.62),
+    "deployment_ellipse_55mhz": lambda: synth.deployment(134, n_time=30),
+}
+
+
+@pytest.mark.parametrize("name", list(WIDE))
+def test_wide_aperture_matches_oracle_and_staged(name):
+    """Apertures of 33-48 cells at N = 64 run the wide fused kernel (two row
+    passes, inputs of rows and columns < 48); the image matches the oracle and
+    the staged kernels, which handled such apertures before."""
+    inp = WIDE[name]()
+    got, im = _run(inp, staged=False)
+    assert im.last_kernel_name() == "fused_wide_image_kernel"
+    err = oracle.rel_errors(got, oracle.image_from(inp))
+    print(f"  max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= TOL_FP32, f"{err.max():.3e}"
+    got2, im2 = _run(inp, staged=True)
+    assert im2.last_kernel_name() == "staged_fft_kernel"
+    assert oracle.rel_errors(got, got2).max() <= TOL_FP32
+    if inp.n_pol == 2:
+        assert np.array_equal(got[:, 2], np.conj(got[:, 1]))
+
+
+def test_wide_aperture_is_deterministic_and_continues():
+    import torch
+    inp = synth.random_problem(135, 64, 180, 2, 2, 10, fill=0.66)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    a = im.accumulate(ef, g).cpu().numpy()
+    b = im.accumulate(ef, g).cpu().numpy()
+    assert im.last_kernel_name() == "fused_wide_image_kernel"
+    assert np.array_equal(a, b)
+    out = im.accumulate(ef[:3], g)
+    im.accumulate(ef[3:], g, image=out, reset=False)
+    torch.cuda.synchronize()
+    assert oracle.rel_errors(out.cpu().numpy(), oracle.image_from(inp)).max() <= TOL_FP32
+
+
 def test_reset_zero_continues_integration():
     import torch
     inp = synth.random_problem(111, 64, 128, 3, 2, 17)

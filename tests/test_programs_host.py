@@ -5,7 +5,9 @@ Eq. (4)-(5)) of every channel; every aperture cell is stored exactly once, by
 a thread of the wave that transforms its row; every LDS offset stays inside
 its region; the row-pass lines cover each aperture row of each polarisation
 once, with a wave's rows distinct modulo 4 (N = 64) so the row transform stays
-free of bank conflicts."""
+free of bank conflicts.  Apertures wider than N/2 cells at N = 64 take the wide
+block (48 x 48 cells, a second row-pass line per thread in the header's second
+word)."""
 import ctypes
 
 import numpy as np
@@ -55,7 +57,15 @@ CASES = {
     "n32_p2_a24": lambda: synth.random_problem(3, 32, 24, 2, 2, 2),
     "n64_p2_a300_two_per_thread": lambda: synth.random_problem(5, 64, 300, 3, 2, 2),
     "n128_p2_a1024": lambda: synth.random_problem(7, 128, 1024, 2, 2, 2, fill=0.47),
+    "n64_wide_p2_a200": lambda: synth.random_problem(9, 64, 200, 3, 2, 2, fill=0.7),
+    "n64_wide_p2_a600": lambda: synth.random_problem(10, 64, 600, 2, 2, 2, fill=0.62),
+    "deployment_ellipse_55mhz": lambda: _deployment(),
 }
+
+
+def _deployment():
+    """The paper's deployed geometry (synth.deployment): the wide block."""
+    return synth.deployment(n_time=2)
 
 
 def _subset(inp, n):
@@ -71,24 +81,33 @@ def test_programs_reproduce_gridding(name, one_pol):
     inp = CASES[name]()
     P = 1 if one_pol else inp.n_pol
     prog, g = _program(inp, P)
-    N, A, H = inp.grid_n, inp.n_ant, inp.grid_n // 2
+    N, A = inp.grid_n, inp.n_ant
     NT, RS, PS, ES, nsteps = g["NT"], g["RS"], g["PS"], g["ES"], g["L"]
     R = R_OF[N]
     X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
     ii, jj, w = oracle.kernel_taps(X, Y, N)
+    ext = max(int((ii.max(axis=(1, 2)) - ii.min(axis=(1, 2))).max()),
+              int((jj.max(axis=(1, 2)) - jj.min(axis=(1, 2))).max())) + 1
+    wide = ext > N // 2
+    assert not wide or (N == 64 and ext <= 48 and "wide" in name or "deployment" in name)
+    H = 48 if wide else N // 2
     rng = np.random.default_rng(0)
     phys = _phys(np.arange(H), g["order"])
     assert sorted(phys) == list(range(H))
     for c in range(inp.n_chan):
         # header: every (p, physical row < H) owned by R lanes of one wave
         hdr = prog[c, 0, :, 0].view(np.int32)
+        hdr2 = prog[c, 0, :, 1].view(np.int32)
+        if not wide:
+            assert np.all(hdr2 == 0)
         rows_of_wave = {}
         seen = {}
-        for t in np.nonzero(hdr >= 0)[0]:
-            p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
-            assert p < P and j < H
-            seen.setdefault((p, j), []).append(t // 64)
-            rows_of_wave.setdefault(t // 64, set()).add(j)
+        for hh in ([hdr, hdr2] if wide else [hdr]):
+            for t in np.nonzero(hh >= 0)[0]:
+                p, j = int(hh[t]) >> 16, int(hh[t]) & 0xFFFF
+                assert p < P and j < H
+                seen.setdefault((p, j), []).append(t // 64)
+                rows_of_wave.setdefault(t // 64, set()).add(j)
         # at N = 128 a lane group transforms both polarisations of its row
         PL = 1 if N == 128 else P
         assert sorted(seen) == [(p, j) for p in range(PL) for j in range(H)]
@@ -97,7 +116,7 @@ def test_programs_reproduce_gridding(name, one_pol):
         # first load of the row transform (64-bit reads are served 32 lanes at
         # a time from 64 banks): each half-wave's float2 addresses distinct
         # modulo 32 (at N = 64, where the layout is chosen for it)
-        if N == 64:
+        if N == 64 and not wide:
             for hw in range(NT // 32):
                 banks = []
                 for t in range(32 * hw, 32 * hw + 32):
