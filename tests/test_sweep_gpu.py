@@ -1,7 +1,7 @@
 """Seeded sweep over the configuration space against the FP64 oracle: grid
 size, polarisations, antenna and channel counts, sample counts, kernel
-support, the caller's complex kernels, apertures wider than N/2 (the staged
-route), the staged flag and autocorrelation removal, each through the image
+support, the caller's complex kernels, apertures wider than N/2 (the wide
+fused variant at N = 64 up to 48 cells, else the staged route), the staged flag and autocorrelation removal, each through the image
 and through the gain gradient; and the split forms within their antenna
 limits.  Each case is drawn from its own seed, so a failure names a
 reproducible configuration.
@@ -27,7 +27,7 @@ def _draw(seed):
     rng = np.random.default_rng(seed)
     N = int(rng.choice([32, 64, 128], p=[0.4, 0.4, 0.2]))
     P = int(rng.integers(1, 3))
-    wide = rng.random() < 0.2                      # aperture wider than N/2: staged kernels
+    wide = rng.random() < 0.2                      # aperture wider than N/2: wide fused or staged
     fill = float(rng.uniform(0.55, 0.7) if wide else rng.uniform(0.25, 0.45))
     # antennas the seeded disk can hold at half-cell separation
     room = int(0.3 * ((fill * N - 3) / 0.5) ** 2)
