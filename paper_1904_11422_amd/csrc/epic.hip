@@ -365,17 +365,48 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
           wave_load[bw] += row_load[j];
         }
       }
-    if (wide) {                                        // heaviest row to the least loaded wave
-      std::vector<int> rows(HB);
-      for (int j = 0; j < HB; ++j) rows[j] = j;
-      std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
-      std::vector<int> used(NWAVE, 0);
-      for (int j : rows) {
-        int bw = -1;
-        for (int w = 0; w < NWAVE; ++w)
-          if (used[w] < RPW && (bw < 0 || wave_load[w] < wave_load[bw])) bw = w;
-        row_of[bw][used[bw]++] = j;
-        wave_load[bw] += row_load[j];
+    if (wide) {
+      // Rows a row pass loads together must fall on distinct bank ranges: with
+      // the interleaved rows this holds when, per pass, a wave's rows differ in
+      // cls(j) = 2 (j & 1) + ((j >> 2) & 1) (P = 2: phys_row mod 4, both
+      // polarisations at once) or in j mod 8 (P = 1, phys_row mod 8).  So every
+      // slot takes one class: P = 2, pass-1 slot s class s, pass-2 slots the
+      // classes {0, 1} (even waves) or {2, 3}; P = 1, wave w all classes but
+      // w and w + 1 (mod 8).  Within a class, heaviest row first to the least
+      // loaded wave with a free slot of that class.
+      const int NCLS = P == 2 ? 4 : 8;
+      auto cls = [&](int j) { return P == 2 ? 2 * (j & 1) + ((j >> 2) & 1) : (j & 7); };
+      std::vector<std::vector<int>> slot_cls(NWAVE, std::vector<int>(RPW, -1));
+      for (int w = 0; w < NWAVE; ++w)
+        for (int sl = 0, k = 0; sl < RPW; ++sl) {
+          if (P == 2) slot_cls[w][sl] = sl < SPW ? sl : (w % 2 ? 2 : 0) + (sl - SPW);
+          else {
+            while (k == w % 8 || k == (w + 1) % 8) ++k;
+            slot_cls[w][sl] = k++;
+          }
+        }
+      for (int k = 0; k < NCLS; ++k) {
+        std::vector<int> rows;
+        for (int j = 0; j < HB; ++j)
+          if (cls(j) == k) rows.push_back(j);
+        std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
+        for (int j : rows) {
+          int bw = -1, bs = -1;
+          for (int w = 0; w < NWAVE; ++w)
+            for (int sl = 0; sl < RPW; ++sl)
+              if (slot_cls[w][sl] == k && row_of[w][sl] < 0 && (bw < 0 || wave_load[w] < wave_load[bw])) {
+                bw = w;
+                bs = sl;
+                break;
+              }
+          if (bw < 0) {                                // not reached: the classes fill every slot
+            out.clear();
+            L = 0;
+            return;
+          }
+          row_of[bw][bs] = j;
+          wave_load[bw] += row_load[j];
+        }
       }
     }
     for (int t = 0; t < NT; ++t) {

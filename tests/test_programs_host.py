@@ -116,17 +116,18 @@ def test_programs_reproduce_gridding(name, one_pol):
         # first load of the row transform (64-bit reads are served 32 lanes at
         # a time from 64 banks): each half-wave's float2 addresses distinct
         # modulo 32 (at N = 64, where the layout is chosen for it)
-        if N == 64 and not wide:
-            for hw in range(NT // 32):
-                banks = []
-                for t in range(32 * hw, 32 * hw + 32):
-                    if hdr[t] < 0:
-                        continue
-                    p, j = int(hdr[t]) >> 16, int(hdr[t]) & 0xFFFF
-                    lane = t % 64
-                    n0 = 4 * ((lane >> 4) >> 1) + ((lane >> 2) & 3)
-                    banks.append((g["XB"] + p * PS + j * RS + n0) % 32)
-                assert len(banks) == len(set(banks))
+        if N == 64:                              # each row pass on its own
+            for hh in ([hdr, hdr2] if wide else [hdr]):
+                for hw in range(NT // 32):
+                    banks = []
+                    for t in range(32 * hw, 32 * hw + 32):
+                        if hh[t] < 0:
+                            continue
+                        p, j = int(hh[t]) >> 16, int(hh[t]) & 0xFFFF
+                        lane = t % 64
+                        n0 = 4 * ((lane >> 4) >> 1) + ((lane >> 2) & 3)
+                        banks.append((g["XB"] + p * PS + j * RS + n0) % 32)
+                    assert len(banks) == len(set(banks))
         # emulate the gather (pol 0; the kernel applies the same step to pol 1)
         code, wb = prog[c, 1:, :, 0], prog[c, 1:, :, 1]
         cell = (code >> 15).astype(np.int64)
