@@ -141,7 +141,7 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
  * 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and cell offsets use
  * physical rows), 0: at row j.  The aperture block is N/2 x N/2 cells, or at
  * N = 64, when some channel's taps do not fit that, 48 x 48 (the wide block,
- * two row passes; its gradient runs the staged kernels).
+ * two row passes; the image and its gradient run the wide kernels).
  * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
  * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
  * taps do not fit the block), EPIC_E_NOMEM (capacity too small;

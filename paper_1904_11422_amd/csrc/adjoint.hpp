@@ -65,10 +65,10 @@ __global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
   a.gtab[idx] = t;
 }
 
-template <int N, int P, int GPT, bool CPX>
-__global__ void __launch_bounds__(FusedShape<N>::NT)
-__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
-adjoint_kernel(AdjointArgs a) {
+// WIDE (N = 64): the wide block of the forward (rows and columns < HW, a
+// second row-pass line per thread in prog[tid].y).
+template <int N, int P, int GPT, bool CPX, bool WIDE>
+__device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
   using SH = FusedShape<N>;
   constexpr int S = SH::S, R = SH::R, D = SH::D, NT = SH::NT, RS = SH::RS;
   constexpr int ES = EStride<NT, GPT, P>::value;
@@ -98,7 +98,7 @@ adjoint_kernel(AdjointArgs a) {
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, line = -1;
+  int c = -1, line = -1, line2 = -1;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -129,6 +129,7 @@ adjoint_kernel(AdjointArgs a) {
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
       if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
+      if (WIDE) line2 = (int)prog[tid].y;
       prog += NT;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
@@ -145,10 +146,11 @@ adjoint_kernel(AdjointArgs a) {
     if (left > 1) load_bytes(cc, tt, nxt);
 
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
-    row_pass<N, P, +1>(X, r, tw, line);
+    row_pass<N, P, +1, WIDE>(X, r, tw, line);
+    if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P>(v, X, r, tw);
+    column_pass_fwd<N, P, WIDE>(v, X, r, tw);
 
     // dL/dF* at the owned pixels
     const float4* gt = a.gtab + (int64_t)c * S * NT + tid;
@@ -171,12 +173,14 @@ adjoint_kernel(AdjointArgs a) {
     const int kl = r.kl;
     line_transform_rev<N, -1, P>(v, tw, r.n0, X,
                                  [kl](int p, int s) { return p * PS + s * RS + kl; });
+    constexpr int NOUT = WIDE ? SH::HW / R : S / 2;   // aperture rows written back
 #pragma unroll
     for (int p = 0; p < P; ++p)
 #pragma unroll
-      for (int n1 = 0; n1 < S / 2; ++n1) X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl] = v[p][n1];
+      for (int n1 = 0; n1 < NOUT; ++n1) X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl] = v[p][n1];
     __syncthreads();
-    row_pass<N, P, -1>(X, r, tw, line);
+    row_pass<N, P, -1, WIDE>(X, r, tw, line);
+    if (WIDE) row_pass<N, P, -1, WIDE>(X, r, tw, line2);
     __syncthreads();
 
     // degrid: dL/de'* at each antenna, times conj(e)
@@ -209,6 +213,22 @@ adjoint_kernel(AdjointArgs a) {
     }
   }
   flush();
+}
+
+template <int N, int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
+adjoint_kernel(AdjointArgs a) {
+  adjoint_body<N, P, GPT, CPX, false>(a);
+}
+
+// The adjoint of fused_wide_image_kernel (N = 64, apertures up to 48 cells).
+template <int N, int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
+adjoint_wide_kernel(AdjointArgs a) {
+  static_assert(N == 64, "the wide variant is built for N = 64");
+  adjoint_body<N, P, GPT, CPX, true>(a);
 }
 
 struct GradReduceArgs {

@@ -87,9 +87,8 @@ struct epic_ctx {
   // path selection: fused_ok = the configuration has fused kernels (decided at
   // init); fused = the current geometry uses them (decided at set_antennas)
   bool fused_ok = true, fused = false;
-  bool wide = false;                  // fused, with the wide variant (N = 64, apertures up to 3N/4);
-                                      // the gradient then runs the staged kernels
-  int fused_w_wide = 0, fused_w_wide_cpx = 0;
+  bool wide = false;                  // fused, with the wide variant (N = 64, apertures up to 3N/4)
+  int fused_w_wide = 0, fused_w_wide_cpx = 0, adj_w_wide = 0, adj_w_wide_cpx = 0;
   int fused_gpt = 1;
   int fused_w = 0;                    // persistent workgroups (upper bound)
   int w_override = 0;                 // tuned grid size (0: fused_w)
@@ -668,6 +667,18 @@ int fused_blocks_per_cu(int N, int P, int gpt, bool cpx) {
   return 1;
 }
 
+template <int P, bool CPX>
+int adjoint_wide_blocks_per_cu(int gpt) {
+  if (gpt == 1) return occupancy_blocks(epic::adjoint_wide_kernel<64, P, 1, CPX>, epic::FusedShape<64>::NT);
+  if (gpt == 2) return occupancy_blocks(epic::adjoint_wide_kernel<64, P, 2, CPX>, epic::FusedShape<64>::NT);
+  return occupancy_blocks(epic::adjoint_wide_kernel<64, P, 4, CPX>, epic::FusedShape<64>::NT);
+}
+
+int adjoint_wide_blocks_per_cu(int P, int gpt, bool cpx) {
+  if (cpx) return P == 1 ? adjoint_wide_blocks_per_cu<1, true>(gpt) : adjoint_wide_blocks_per_cu<2, true>(gpt);
+  return P == 1 ? adjoint_wide_blocks_per_cu<1, false>(gpt) : adjoint_wide_blocks_per_cu<2, false>(gpt);
+}
+
 template <int N, int P, bool CPX>
 int adjoint_blocks_per_cu(int gpt) {
   if (gpt == 1) return occupancy_blocks(epic::adjoint_kernel<N, P, 1, CPX>, epic::FusedShape<N>::NT);
@@ -788,6 +799,20 @@ bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {
 bool launch_adjoint(epic_ctx* x, const epic::AdjointArgs& a) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol, G = x->fused_gpt;
   const dim3 grid(a.W), block(fused_threads(N));
+  if (x->wide) {
+    if (N != 64) return false;
+#define EPIC_LAW(PP, GG)                                                                     \
+    if (P == PP && G == GG) {                                                                \
+      if (x->cpx) hipLaunchKernelGGL((epic::adjoint_wide_kernel<64, PP, GG, true>), grid, block, 0, \
+                                     x->stream, a);                                          \
+      else hipLaunchKernelGGL((epic::adjoint_wide_kernel<64, PP, GG, false>), grid, block, 0, \
+                              x->stream, a);                                                 \
+      return true;                                                                           \
+    }
+    EPIC_LAW(1, 1) EPIC_LAW(1, 2) EPIC_LAW(1, 4) EPIC_LAW(2, 1) EPIC_LAW(2, 2) EPIC_LAW(2, 4)
+#undef EPIC_LAW
+    return false;
+  }
 #define EPIC_LA(NN, PP, GG)                                                                  \
   if (N == NN && P == PP && G == GG) {                                                       \
     if (x->cpx) hipLaunchKernelGGL((epic::adjoint_kernel<NN, PP, GG, true>), grid, block, 0,  \
@@ -1518,6 +1543,10 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
     }
     x->adj_w = adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, false) * x->n_cu;
     x->adj_w_cpx = std::min(x->adj_w, adjoint_blocks_per_cu(N, cfg->n_pol, x->fused_gpt, true) * x->n_cu);
+    if (N == 64) {
+      x->adj_w_wide = std::min(x->adj_w, adjoint_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, false) * x->n_cu);
+      x->adj_w_wide_cpx = std::min(x->adj_w, adjoint_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, true) * x->n_cu);
+    }
     const size_t gslots = (size_t)x->adj_w + cfg->n_chan - 1;
     if (!x->gpartial.alloc(gslots * x->PA * 2 * sizeof(double)) ||
         !x->gtab.alloc((size_t)cfg->n_chan * N * N * sizeof(float4))) {
@@ -1652,8 +1681,7 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
   }
   // The fused kernels need every channel's taps inside an N/2 x N/2 block, or
   // at N = 64 inside a 3N/4 x 3N/4 block (wide variant); larger apertures
-  // (aliased images) run the staged kernels.  The wide variant's gradient runs
-  // the staged kernels, so it keeps their tables too.
+  // (aliased images) run the staged kernels.
   x->wide = x->fused_ok && N == 64 && !g.fits_half && g.fits_wide;
   x->fused = x->fused_ok && (g.fits_half || x->wide);
 
@@ -1682,8 +1710,7 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
          hipMemcpy(x->taps_im.p, g.wi.data(), g.wi.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
       return x->fail(EPIC_E_NOMEM, "gridding program upload failed");
     x->L = L;
-  }
-  if (!x->fused || x->wide) {
+  } else {
     if (!alloc_staged(x)) return x->fail(EPIC_E_NOMEM, "staged workspace allocation failed");
     // per-cell CSR over the whole grid, entries in (antenna, tap) order
     const int npix = N * N, nnz = A * g.KK;
@@ -1771,7 +1798,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   if (x->cfg.precision != EPIC_FP32)
     return x->fail(EPIC_E_UNSUPPORTED, "the gain gradient runs on the float32 paths");
   DeviceGuard guard(x->device);
-  if (!x->fused || x->wide) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
+  if (!x->fused) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
   const int C = x->cfg.n_chan;
   // work units per channel: samples, or (half, sample) pairs at N = 128
   const int64_t upc = x->cfg.grid_n == 128 ? 2 * n_time : n_time;
@@ -1808,9 +1835,10 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.n_ant = x->cfg.n_ant;
   a.kk = x->cfg.kernel_support * x->cfg.kernel_support;
   a.L = x->L;
-  a.W = (int)std::min<int64_t>(x->cpx ? x->adj_w_cpx : x->adj_w, total);
+  const int aw = x->wide ? (x->cpx ? x->adj_w_wide_cpx : x->adj_w_wide) : (x->cpx ? x->adj_w_cpx : x->adj_w);
+  a.W = (int)std::min<int64_t>(aw, total);
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
-  x->last_kernel = x->cfg.grid_n == 128 ? "adjoint128_kernel" : "adjoint_kernel";
+  x->last_kernel = x->cfg.grid_n == 128 ? "adjoint128_kernel" : x->wide ? "adjoint_wide_kernel" : "adjoint_kernel";
   if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
   if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
   epic::GradReduceArgs r;

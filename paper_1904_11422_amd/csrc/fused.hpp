@@ -304,13 +304,13 @@ __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, 
 // forward, the row holds cells at columns < H.  SG < 0: adjoint, the row
 // holds the forward output layout and the columns < H of the result are
 // written back.
-// WIDE (forward only): the row holds cells at columns < HW; the inputs
-// n1 >= HW / R are zero.
+// WIDE: forward, the row holds cells at columns < HW (the inputs n1 >= HW / R
+// are zero); adjoint, the columns < HW of the result are written back.
 template <int N, int P, int SG, bool WIDE = false>
 __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const float2* tw, int line) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
   constexpr int RS = FusedShape<N>::RS, PS = FusedShape<N>::PSTRIDE;
-  static_assert(!WIDE || (SG > 0 && FusedShape<N>::HW % R == 0), "wide rows: forward, whole inputs");
+  static_assert(!WIDE || FusedShape<N>::HW % R == 0, "wide rows: whole inputs");
   if (line >= 0) {
     float2* row = X + (line >> 16) * PS + (line & 0xFFFF) * RS;
     float2 v[1][S];
@@ -337,8 +337,9 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 #pragma unroll
         for (int k1 = 0; k1 < R; ++k1) v[0][q * R + k1] = row[r.n0 * D + q + S * k1];
       line_transform_rev<N, -1, 1>(v, tw, r.n0, row, [](int, int s) { return s; });
+      constexpr int NOUT = WIDE ? FusedShape<N>::HW / R : S / 2;
 #pragma unroll
-      for (int n1 = 0; n1 < S / 2; ++n1) row[R * n1 + r.n0] = v[0][n1];
+      for (int n1 = 0; n1 < NOUT; ++n1) row[R * n1 + r.n0] = v[0][n1];
     }
   }
 }

@@ -51,7 +51,6 @@ def test_grad_matches_oracle_l2_loss(seed, N, A, C, P, T):
 
 
 @pytest.mark.parametrize("seed,N,A,C,P,T,fill,staged", [
-    (231, 64, 120, 2, 2, 7, 0.62, False),    # aperture wider than N/2: wide fused image, staged gradient
     (232, 32, 40, 2, 1, 9, 0.7, False),
     (233, 64, 256, 2, 2, 5, 0.45, True),     # EPIC_FLAG_STAGED
     (234, 128, 300, 1, 1, 3, 0.45, True),
@@ -68,8 +67,7 @@ def test_staged_grad_matches_oracle(seed, N, A, C, P, T, fill, staged):
     ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
     g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
     img = im.accumulate(ef, g)
-    wide = N == 64 and not staged
-    assert im.last_kernel_name() == ("fused_wide_image_kernel" if wide else "staged_fft_kernel")
+    assert im.last_kernel_name() == "staged_fft_kernel"
     img = img.cpu().numpy()
     rng = np.random.default_rng(seed)
     gam = oracle.l2_loss_grad_image(img, img * (1 + 0.05 * rng.normal(size=img.shape)))
@@ -153,3 +151,30 @@ def test_config5_gradient_and_autograd():
     assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
     ref_img = oracle.image_from(inp)
     assert oracle.rel_errors(img_np, ref_img).max() <= 1e-5
+
+
+@pytest.mark.parametrize("seed,A,C,P,T,fill,K", [(231, 120, 2, 2, 7, 0.62, 3), (241, 90, 2, 1, 9, 0.7, 3),
+                                                 (242, 600, 1, 2, 3, 0.62, 3), (243, 80, 2, 2, 5, 0.45, 11)])
+def test_wide_grad_matches_oracle(seed, A, C, P, T, fill, K):
+    """Apertures of 33-48 cells at N = 64: the wide fused image and its adjoint
+    (adjoint_wide_kernel) against the oracle's gradient; K > 3 with complex kernels."""
+    import torch
+    from paper_1904_11422_amd import Imager
+    inp = synth.random_problem(seed, 64, A, C, P, T, fill=fill)
+    if K != 3:
+        inp = synth.with_kernels(inp, K, seed + 1)
+    print(f"case {seed}: A={A} C={C} P={P} T={T} fill={fill} K={K}", flush=True)
+    im = Imager(64, C, P, A, kernel_support=K)
+    im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    img = im.accumulate(ef, g)
+    assert im.last_kernel_name() == "fused_wide_image_kernel"
+    img = img.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    gam = oracle.l2_loss_grad_image(img, img * (1 + 0.05 * rng.normal(size=img.shape)))
+    got = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    assert im.last_kernel_name() == "adjoint_wide_kernel"
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 64, gam, K,
+                            kernels=inp.kernels)
+    assert _rel(got, ref) <= TOL_GRAD, f"{_rel(got, ref):.3e}"
