@@ -479,7 +479,19 @@ def bench_deployment(args) -> int:
         dt = (time.perf_counter() - t0) / steps
         k_ms = float(np.mean(ks))
         fl = flops_per_tc(N, P, A) * C * T
+        # one gain-gradient evaluation (image + adjoint) per call, same route
+        gam = torch.randn(im.image_shape(), dtype=torch.complex128, device="cuda")
+        im.backward(ef, g, gam)
+        torch.cuda.synchronize()
+        nb = max(2, steps // 4)
+        t1 = time.perf_counter()
+        for _ in range(nb):
+            im.backward(ef, g, gam)
+        torch.cuda.synchronize()
+        grad_ms = (time.perf_counter() - t1) / nb * 1e3
+        grad_kernel = im.last_kernel_name()
         out["staged" if staged else "fused"] = {
+            "gradient_ms_per_call": grad_ms, "gradient_kernel": grad_kernel,
             "value": C / dt, "unit": "channel-images/s", "ms_per_step": dt * 1e3, "steps": steps,
             "kernel": im.last_kernel_name(), "kernel_ms": k_ms,
             "roofline": {"bound": "alu", "achieved": fl / (k_ms * 1e-3) / 1e12,
@@ -489,6 +501,8 @@ def bench_deployment(args) -> int:
         im.close()
     main = out["fused"]
     main["speedup_over_staged"] = main["value"] / out["staged"]["value"]
+    main["gradient_speedup_over_staged"] = (out["staged"]["gradient_ms_per_call"]
+                                            / main["gradient_ms_per_call"])
     line = {"metric": "channel-images/s (4-pol, 64\u00b2 grid), the paper's deployed geometry",
             "value": main["value"], "unit": "channel-images/s", "n_gpus": 1,
             "steps": main["steps"], "warmup": args.warmup, "ms_per_step": main["ms_per_step"],
