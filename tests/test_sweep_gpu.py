@@ -119,3 +119,45 @@ def test_split_forms(seed):
     err = np.linalg.norm((got - ref).reshape(C, got.shape[1], -1), axis=-1) / nrm
     print(f"  image err {err.max():.3e}", flush=True)
     assert err.max() <= TOL_SPLIT, f"{err.max():.3e}"
+
+
+@pytest.mark.parametrize("seed", range(5200, 5210))
+def test_wide_block_image_and_gradient(seed):
+    """Apertures of 33-48 cells at N = 64 (the wide fused kernel and its
+    adjoint): random polarisations, antenna and channel counts, samples, kernel
+    support (Gaussian or the caller's complex kernels) and autocorrelation
+    removal."""
+    import torch
+    from paper_1904_11422_amd import Imager
+    rng = np.random.default_rng(seed)
+    P = int(rng.integers(1, 3))
+    K = int(rng.choice([3, 3, 5, 7]))
+    fill = float(rng.uniform(0.55, 0.74 - (K - 3) / 64))
+    A = int(rng.integers(2, 500))
+    C = int(rng.integers(1, 4))
+    T = int(rng.integers(1, 16))
+    autos = bool(rng.random() < 0.3) and K <= 7
+    inp = synth.random_problem(seed, 64, A, C, P, T, fill=fill)
+    if K != 3 or rng.random() < 0.3:
+        inp = synth.with_kernels(inp, K, seed + 7)
+    print(f"seed {seed}: P={P} A={A} C={C} T={T} K={K} fill={fill:.3f} autos={autos}", flush=True)
+    im = Imager(64, C, P, A, inp.kernel_support, remove_autos=autos)
+    im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
+    ef = torch.from_numpy(np.ascontiguousarray(inp.efield)).cuda()
+    g = torch.from_numpy(np.ascontiguousarray(inp.gains)).cuda()
+    got = im.accumulate(ef, g).cpu().numpy()
+    kname = im.last_kernel_name()
+    print(f"  route {kname}", flush=True)
+    assert kname == "fused_wide_image_kernel"
+    full = oracle.image_from(inp)
+    ref = oracle.image_without_autos_from(inp) if autos else full
+    err = np.linalg.norm((got - ref).reshape(C, got.shape[1], -1), axis=-1) / _norms(full, C, P)
+    assert err.max() <= TOL_FP32, f"{err.max():.3e}"
+    gam = oracle.l2_loss_grad_image(got, got * (1 + 0.05 * rng.normal(size=got.shape)))
+    gg = im.backward(ef, g, torch.from_numpy(gam).cuda()).cpu().numpy()
+    fn = oracle.grad_gains_without_autos if autos else oracle.grad_gains
+    gref = fn(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 64, gam, inp.kernel_support,
+              kernels=inp.kernels)
+    gerr = np.linalg.norm(gg - gref) / np.linalg.norm(gref)
+    print(f"  image err {err.max():.3e}, gradient err {gerr:.3e}", flush=True)
+    assert gerr <= TOL_GRAD, f"{gerr:.3e}"
