@@ -153,6 +153,38 @@ def test_config5_gradient_and_autograd():
     assert oracle.rel_errors(img_np, ref_img).max() <= 1e-5
 
 
+def test_config5_full_shape_gradient():
+    """The calibration workload at its full shape (256 dual-pol antennas,
+    64 channels, 64 x 64, 200 samples, 20 sources): gains shared over channels
+    through the autograd Function, loss |I - M|^2 with M the oracle's model image
+    of the same sources.  The gradient against the oracle's (pinned to finite
+    differences at this shape) within 1e-4, the image against the oracle on
+    sampled channels within 1e-5."""
+    import torch
+    from paper_1904_11422_amd import image
+    inp = synth.config5()
+    im, ef, _ = _setup(inp)
+    src = inp.sources
+    model = oracle.model_image(inp.xy_m, inp.freq_hz, 64, inp.n_time, src["lm"],
+                               src["amp"] ** 2, src["noise_sigma"])
+    g_pa = torch.from_numpy(src["g_eval"]).cuda().requires_grad_(True)       # [P, A]
+    img = image(im, g_pa[None].expand(inp.n_chan, 2, 256), ef)
+    loss = ((img - torch.from_numpy(model).cuda()).abs() ** 2).sum()
+    loss.backward()
+    assert im.last_kernel_name() == "adjoint_kernel"
+    got = g_pa.grad.cpu().numpy()
+    img_np = img.detach().cpu().numpy()
+    gam = oracle.l2_loss_grad_image(img_np, model)
+    ref = oracle.grad_gains(inp.xy_m, inp.freq_hz, inp.gains, inp.efield, 64, gam).sum(0)
+    err = _rel(got, ref)
+    print(f"config5 gradient rel err {err:.3e}", flush=True)
+    assert err <= TOL_GRAD, f"{err:.3e}"
+    for c in (0, 31, 63):
+        ref_c = oracle.image(inp.xy_m, inp.freq_hz[c:c + 1], inp.gains[c:c + 1],
+                             inp.efield[:, c:c + 1], 64)
+        assert oracle.rel_errors(img_np[c:c + 1], ref_c).max() <= 1e-5
+
+
 @pytest.mark.parametrize("seed,A,C,P,T,fill,K", [(231, 120, 2, 2, 7, 0.62, 3), (241, 90, 2, 1, 9, 0.7, 3),
                                                  (242, 600, 1, 2, 3, 0.62, 3), (243, 80, 2, 2, 5, 0.45, 11)])
 def test_wide_grad_matches_oracle(seed, A, C, P, T, fill, K):

@@ -17,6 +17,8 @@ _front = moff.decimate_transpose
 _stokes = moff.pseudo_stokes
 _taper = moff.kernel_taper
 _cells = moff.antenna_cells
+_model = moff.model_image
+_rel_errors = moff.rel_errors
 
 
 def _wrong_sign(a):
@@ -151,6 +153,41 @@ def _auto_vis_swapped(gains, efield):
     return v
 
 
+def _model_sources_mirrored(xy_m, freq_hz, grid_n, n_time, src_lm, src_power, noise_sigma, **k):
+    """Source phase exp(+2 pi i (u l + v m)): every model source lands at -(l, m)."""
+    return _model(xy_m, freq_hz, grid_n, n_time, -np.asarray(src_lm), src_power, noise_sigma, **k)
+
+
+def _model_noise_without_two(xy_m, freq_hz, grid_n, n_time, src_lm, src_power, noise_sigma, **k):
+    """Noise visibility sigma^2 Id instead of 2 sigma^2 Id (one component only)."""
+    return _model(xy_m, freq_hz, grid_n, n_time, src_lm, src_power, noise_sigma / np.sqrt(2), **k)
+
+
+def _model_per_sample(xy_m, freq_hz, grid_n, n_time, src_lm, src_power, noise_sigma, **k):
+    """The model of one sample, not of the integration."""
+    return _model(xy_m, freq_hz, grid_n, 1, src_lm, src_power, noise_sigma, **k)
+
+
+def _rel_errors_xy_own_norm(img, ref):
+    """XY and YX measured against their own norm."""
+    out = _rel_errors(img, ref)
+    if img.shape[1] == 4:
+        d = np.linalg.norm((img - ref).reshape(img.shape[0], 4, -1), axis=-1)
+        r = np.linalg.norm(ref.reshape(ref.shape[0], 4, -1), axis=-1)
+        out[:, 1:3] = d[:, 1:3] / np.maximum(r[:, 1:3], 1e-300)
+    return out
+
+
+def _rel_errors_xy_by_xx(img, ref):
+    """XY and YX scaled by ||XX|| alone."""
+    out = _rel_errors(img, ref)
+    if img.shape[1] == 4:
+        d = np.linalg.norm((img - ref).reshape(img.shape[0], 4, -1), axis=-1)
+        r = np.linalg.norm(ref.reshape(ref.shape[0], 4, -1), axis=-1)
+        out[:, 1:3] = d[:, 1:3] / r[:, :1]
+    return out
+
+
 MUTATIONS = {
     "transform with the -i sign": ("transform", _wrong_sign,
                                    [pins.test_p1_transform_sign_single_cell]),
@@ -197,6 +234,19 @@ MUTATIONS = {
         "grad_autos", _grad_autos_variant(two=1.0),
         [lambda: pins.test_p14_gradient_without_autos_matches_finite_differences(1),
          pins.test_p14_homogeneity_without_autos]),
+    "model sources at the mirrored direction": (
+        "model_image", _model_sources_mirrored,
+        [lambda: pins.test_p18_model_image_whole_cell_closed_form(2)]),
+    "model noise term without the factor 2": (
+        "model_image", _model_noise_without_two,
+        [lambda: pins.test_p18_model_image_whole_cell_closed_form(1),
+         pins.test_p18_model_image_zenith_off_cell]),
+    "model of one sample instead of the integration": (
+        "model_image", _model_per_sample, [pins.test_p18_model_image_zenith_off_cell]),
+    "error metric: XY against its own norm": (
+        "rel_errors", _rel_errors_xy_own_norm, [pins.test_p19_error_metric_hand_values]),
+    "error metric: XY scaled by ||XX|| alone": (
+        "rel_errors", _rel_errors_xy_by_xx, [pins.test_p19_error_metric_hand_values]),
 }
 
 

@@ -660,3 +660,178 @@ def test_p16_gradient_without_autos_with_complex_kernels_matches_finite_differen
     fd = oracle.fd_grad(loss, g, coords)
     an = np.array([grad[c] for c in coords])
     assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+
+# ------------------------------------------------------------------ P18 (O11)
+def _whole_cell_array(n_ant, seed, N=32, freq=50e6):
+    """Antennas on distinct whole cells within +-8 cells of the centre."""
+    rng = _rng(seed)
+    cells = set()
+    while len(cells) < n_ant:
+        cells.add(tuple(int(v) for v in rng.integers(-8, 9, size=2)))
+    cxy = np.array(sorted(cells), dtype=float)
+    return cxy, cxy * (oracle.C0 / freq * 0.5), np.array([freq])
+
+
+@pytest.mark.parametrize("n_pol", [1, 2])
+def test_p18_model_image_whole_cell_closed_form(n_pol):
+    """Model image of point sources on whole-cell antennas, every pixel.
+
+    Antenna a at relative cell (cx, cy) has the footprint transform
+    b_a(k) = e^{2 pi i ((cx + N/2) kl + (cy + N/2) km)/N} B(k), with the hand
+    Gaussian B(k) = (1 + 2e^-2 cos(2 pi kl/N))(1 + 2e^-2 cos(2 pi km/N)).  A
+    source at the on-pixel direction (ql, qm) (l = ql / (N du)) reaches it with
+    phase e^{-2 pi i (cx ql + cy qm)/N}, so the model visibilities
+    V = T (sum_s S_s p_s p_s^H + 2 sigma^2 Id) image to
+        XX(k) = YY(k) = T B(k)^2 [ sum_s S_s |AF_s(k)|^2 + 2 sigma^2 A ],
+    AF_s(k) = sum_a e^{2 pi i (cx (kl - ql_s) + cy (km - qm_s))/N} (array factor,
+    summed here antenna by antenna), and XY = YX = 0.  Catches the sign of the
+    source phase (sources mirrored), a missing T, the noise term's factor,
+    |.| not squared and the pixel order."""
+    N, A, T, sigma = 32, 14, 7, 1.5
+    cxy, xy, f = _whole_cell_array(A, 3)
+    q = [(5, -3), (-9, 2), (0, 11)]
+    S = [2.0, 0.7, 1.3]
+    lm = np.array([[ql / (N * 0.5), qm / (N * 0.5)] for ql, qm in q])
+    got = oracle.model_image(xy, f, N, T, lm, np.array(S), sigma, n_pol=n_pol)
+    k = np.arange(N) - N // 2                       # shifted pixel order
+    b1 = 1 + 2 * E2 * np.cos(2 * np.pi * k / N)
+    B2 = np.outer(b1, b1) ** 2                      # [row km, col kl]
+    km, kl = np.meshgrid(k, k, indexing="ij")
+    expect = np.full((N, N), 2 * sigma ** 2 * A)
+    for (ql, qm), s in zip(q, S):
+        af = np.zeros((N, N), complex)
+        for cx, cy in cxy:
+            af += np.exp(2j * np.pi * (cx * (kl - ql) + cy * (km - qm)) / N)
+        expect += s * np.abs(af) ** 2
+    expect *= T * B2
+    assert got.shape == (1, 1 if n_pol == 1 else 4, N, N)
+    assert np.max(np.abs(got[0, 0] - expect)) <= 1e-12 * expect.max()
+    if n_pol == 2:
+        assert np.max(np.abs(got[0, 3] - expect)) <= 1e-12 * expect.max()
+        assert np.all(got[0, 1] == 0) and np.all(got[0, 2] == 0)
+    # each source's own pixel holds T B^2 (S A^2 + the others' sidelobes + noise)
+    r, c = q[0][1] + N // 2, q[0][0] + N // 2
+    assert got[0, 0, r, c].real >= T * B2[r, c] * S[0] * A ** 2
+
+
+def test_p18_model_image_zenith_off_cell():
+    """Off-cell antennas, zenith pixel: a source at the zenith adds
+    T S (sum_a sum_taps w_a)^2 and the noise term is 2 sigma^2 T sum_a (sum_taps w_a)^2,
+    with w the Gaussian evaluated tap by tap from its definition."""
+    rng = _rng(17)
+    A, N, T, sigma, S = 11, 32, 5, 2.0, 3.5
+    xy = rng.uniform(-9, 9, size=(A, 2))
+    f = np.array([50e6])
+    cell = oracle.C0 / 50e6 * 0.5
+    X = xy[:, 0] / cell + N / 2
+    Y = xy[:, 1] / cell + N / 2
+    wsum = np.zeros(A)
+    for a in range(A):
+        i0, j0 = np.floor(X[a] + 0.5), np.floor(Y[a] + 0.5)
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                wsum[a] += np.exp(-2.0 * ((i0 + di - X[a]) ** 2 + (j0 + dj - Y[a]) ** 2))
+    noise_only = oracle.model_image(xy, f, N, T, np.zeros((0, 2)), np.zeros(0), sigma)
+    expect_n = 2 * sigma ** 2 * T * np.sum(wsum ** 2)
+    assert abs(noise_only[0, 0, N // 2, N // 2].real - expect_n) <= 1e-12 * expect_n
+    both = oracle.model_image(xy, f, N, T, np.zeros((1, 2)), np.array([S]), sigma)
+    expect = expect_n + T * S * np.sum(wsum) ** 2
+    assert abs(both[0, 3, N // 2, N // 2].real - expect) <= 1e-12 * expect
+
+
+def test_p18_model_image_is_the_mean_of_simulated_images():
+    """The model is what the imager sees on average: the oracle image of data
+    drawn from the same sky (unit gains, a source 4x brighter than the noise
+    in the image, no clipping) matches the model within the sampling error of
+    4000 samples once the int4 rounding (uniform, variance 1/12 per
+    component) is added to the noise power; a model with the source mirrored
+    or the noise power halved is 25x further off."""
+    N, A, T = 32, 10, 4000
+    cxy, xy, f = _whole_cell_array(A, 9)
+    sigma = 1.5
+    lm = np.array([[4 / 16, -2 / 16]])
+    power = np.array([2.0])
+    ef = synth.simulate_efield(_rng(31), _rng(32), xy, f, T, 1, lm, np.sqrt(power),
+                               np.zeros(1), sigma)
+    got = oracle.image(xy, f, np.ones((1, 1, A), np.complex64), ef, N)
+    s_eff = np.sqrt(sigma ** 2 + 1 / 12)
+
+    def err(m):
+        return np.linalg.norm(got - m) / np.linalg.norm(m)
+    assert err(oracle.model_image(xy, f, N, T, lm, power, s_eff, n_pol=1)) < 0.03
+    assert err(oracle.model_image(xy, f, N, T, -lm, power, s_eff, n_pol=1)) > 0.3
+    assert err(oracle.model_image(xy, f, N, T, lm, power, s_eff / np.sqrt(2), n_pol=1)) > 0.3
+
+
+# ------------------------------------------------------------------ P19 (Q27)
+def test_p19_error_metric_hand_values():
+    """rel_errors on hand-built 2 x 2 images with known norms: XX, YY relative to
+    their own norms; XY, YX relative to sqrt(||XX|| ||YY||)."""
+    ref = np.zeros((2, 4, 2, 2), complex)
+    ref[0, 0] = [[3, 0], [0, 4]]                 # ||XX|| = 5
+    ref[0, 3] = [[0, 0], [0, 20]]                # ||YY|| = 20 -> scale 10
+    ref[0, 1] = [[1j, 0], [0, 0]]                # ||XY|| = 1 (not the scale)
+    ref[0, 2] = np.conj(ref[0, 1])
+    ref[1, 0] = [[0, 0], [6, 8]]                 # ||XX|| = 10
+    ref[1, 3] = [[0, 2.5], [0, 0]]               # ||YY|| = 2.5 -> scale 5
+    img = ref.copy()
+    img[0, 0, 0, 1] += 0.3 + 0.4j                # |d| = 0.5 -> 0.1
+    img[0, 3, 1, 0] -= 2.0                       # 2 / 20 = 0.1
+    img[0, 1, 1, 1] += 0.5                       # 0.5 / 10 = 0.05
+    img[0, 2, 0, 0] += 3.0                       # 3 / 10 = 0.3
+    img[1, 0] += 1.0                             # ||d|| = 2 -> 0.2
+    img[1, 1, 0, 0] += 1.2 - 1.6j                # 2 / 5 = 0.4
+    img[1, 2, 1, 1] += 0.05                      # 0.05 / 5 = 0.01
+    img[1, 3, 0, 1] += 0.25                      # 0.25 / 2.5 = 0.1
+    got = oracle.rel_errors(img, ref)
+    expect = np.array([[0.1, 0.05, 0.3, 0.1], [0.2, 0.4, 0.01, 0.1]])
+    assert np.allclose(got, expect, rtol=1e-14, atol=0)
+    one = oracle.rel_errors(img[:, :1], ref[:, :1])
+    assert np.allclose(one[:, 0], [0.1, 0.2], rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------ P10 at the calibration shape
+@pytest.mark.slow
+def test_p10_calibration_shape_finite_differences():
+    """The calibration workload at its full shape (256 dual-pol antennas,
+    64 channels, 64 x 64, 200 samples, 20 sources, loss |I - M|^2 with M the
+    model image of the same sources): the analytic gradient against central
+    differences on 16 seeded (c, p, a) -- each evaluated on its own channel's
+    loss, the only one g[c] enters -- and against 4 directional derivatives of
+    the whole loss (two along directions shared by all channels, as when the
+    gains are shared over channels, two along directions over every (c, p, a))."""
+    inp = synth.config5()
+    src = inp.sources
+    N, C = inp.grid_n, inp.n_chan
+    model = oracle.model_image(inp.xy_m, inp.freq_hz, N, inp.n_time, src["lm"],
+                               src["amp"] ** 2, src["noise_sigma"])
+    g = inp.gains.astype(np.complex128)
+    img = oracle.image_from(inp)
+    gam = oracle.l2_loss_grad_image(img, model)
+    grad = oracle.grad_gains(inp.xy_m, inp.freq_hz, g, inp.efield, N, gam)
+    rng = _rng(505)
+    coords = [(int(rng.integers(C)), int(rng.integers(2)), int(rng.integers(256)))
+              for _ in range(16)]
+    fd = []
+    for c, p, a in coords:
+        def loss_c(gc, c=c):
+            im = oracle.image(inp.xy_m, inp.freq_hz[c:c + 1], gc[None], inp.efield[:, c:c + 1], N)
+            return oracle.l2_loss(im, model[c:c + 1])
+        fd.append(oracle.fd_grad(loss_c, g[c], [(p, a)])[0])
+    an = np.array([grad[c] for c in coords])
+    fd = np.array(fd)
+    assert np.linalg.norm(an - fd) / np.linalg.norm(fd) < 1e-6
+
+    def loss(gg):
+        return oracle.l2_loss(oracle.image(inp.xy_m, inp.freq_hz, gg, inp.efield, N), model)
+    dirs = []
+    for _ in range(2):
+        d = rng.normal(size=(2, 256)) + 1j * rng.normal(size=(2, 256))
+        dirs.append(np.broadcast_to(d[None], g.shape).copy())
+    for _ in range(2):
+        dirs.append(rng.normal(size=g.shape) + 1j * rng.normal(size=g.shape))
+    for d in dirs:
+        num = oracle.fd_directional(loss, g, d)
+        ana = float(np.sum(np.conj(d) * grad).real)
+        assert abs(num - ana) <= 1e-6 * abs(ana), (num, ana)
