@@ -88,7 +88,11 @@ typedef struct epic_config {
 
 typedef struct epic_ctx epic_ctx;
 
-/* Create a context on `device` (a HIP device ordinal).  All later work of the
+/* Create a context on `device` (a HIP device ordinal).  Not an operation of
+ * the paper: it holds the imager's configuration -- the grid side, channel,
+ * polarisation and antenna counts and the gridding kernel of Sec. 2.1 and
+ * Sec. 3.2 -- and the workspace every later call reuses, so that no imaging
+ * call allocates.  All later work of the
  * context is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream).
  * The config is copied.  Allocates the library-owned tables and workspace.
  * Errors: EPIC_E_INVALID (bad config or out == NULL), EPIC_E_DEVICE (not a
@@ -176,7 +180,11 @@ epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t 
 
 /* Gradient of a real loss L with respect to the gains, given the gradient of
  * L with respect to the image accumulated by epic_image_accumulate(reset=1)
- * over the same efield and gains.
+ * over the same efield and gains.  The paper does not compute this: it leaves
+ * calibration of the per-antenna gains as future work (Sec. 6, "EPICal").
+ * The call is the exact adjoint (chain rule) of the forward path above:
+ * products, the transform of Sec. 2.1 Eq. (5) with the opposite sign, and the
+ * gridding of Eq. (4) read back at each antenna's kernel taps.
  *   grad_image: device complex128 like image, holding dL/dRe(I) + i dL/dIm(I);
  *               the imaginary parts for XX and YY are ignored (those products
  *               are real);
@@ -371,11 +379,14 @@ void epic_batch_destroy(epic_batch *b);
 /* Message of the last failed batch call (NULL: the last failed create). */
 const char *epic_batch_last_error(const epic_batch *b);
 
-/* Free the context and its library-owned memory (waits for its stream). */
+/* Free the context and its library-owned memory (waits for its stream).
+ * Resource management only; no operation of the paper. */
 void epic_destroy(epic_ctx *ctx);
 
 /* Message of the last failed call on ctx, valid until the next call on ctx.
- * With ctx == NULL: the message of the last failed epic_init in this thread. */
+ * With ctx == NULL: the message of the last failed epic_init in this thread.
+ * Error reporting only; no operation of the paper.  Never NULL ("" before
+ * any failure). */
 const char *epic_last_error(const epic_ctx *ctx);
 
 #ifdef __cplusplus

@@ -12,8 +12,6 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libepic.so")
 SOURCES = [os.path.join(PKG, "csrc", "epic.hip")]
-HEADERS = [os.path.join(PKG, "csrc", h) for h in ("dft.hpp", "fused.hpp", "staged.hpp",
-                                                  "adjoint.hpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -138,6 +138,12 @@ def test_wide_block_image_and_gradient(seed):
     T = int(rng.integers(1, 16))
     autos = bool(rng.random() < 0.3) and K <= 7
     inp = synth.random_problem(seed, 64, A, C, P, T, fill=fill)
+    # two antennas at opposite ends of the disk's east-west diameter: the
+    # aperture spans fill * 64 - 3 > 32 cells at every channel, so the case
+    # always takes the wide block whatever the draw
+    radius = 0.5 * (fill * 64 - 3) * 0.5 * synth.C0 / inp.freq_hz.max()
+    inp.xy_m[0] = (radius, 0.0)
+    inp.xy_m[1] = (-radius, 0.0)
     if K != 3 or rng.random() < 0.3:
         inp = synth.with_kernels(inp, K, seed + 7)
     print(f"seed {seed}: P={P} A={A} C={C} T={T} K={K} fill={fill:.3f} autos={autos}", flush=True)
