@@ -26,7 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "channel-images/s (4-pol, 64² grid) vs plain FP32; % HBM/MFMA roofline"
-PEAK_FP32_VALU = 157.3e12       # MI355X fp32 vector, FLOP/s
+PEAK_FP32_VALU = 157.3e12       # MI355X fp32 vector, FLOP/s (counts packed FP32)
+PEAK_FP32_VALU_NONPACKED = PEAK_FP32_VALU / 2   # the issue ceiling with packed FP32 off
 PEAK_HBM = 8.0e12               # MI355X HBM3E, B/s
 
 
@@ -62,7 +63,31 @@ def _worker_ready(_):
     return os.getpid()
 
 
-def cpu_baseline(inp, n_chan: int, max_workers: int = 16):
+def host_cpu() -> dict:
+    """What the host offers: logical CPUs the OS reports, those this process
+    may run on, and the processor model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable": usable, "model": model}
+
+
+# worker processes for the CPU baseline: the machine's CPU share per GPU (the
+# host may report more logical CPUs than one GPU's share)
+CPU_SHARE = 16
+
+
+def cpu_baseline(inp, n_chan: int, max_workers: int = CPU_SHARE):
     """The FP64 oracle as it stands, on the first n_chan channels, all samples:
     once in this process (one thread: numpy's FFT and the oracle's array code
     are single-threaded), and once with one spawned process per channel on up
@@ -93,10 +118,12 @@ def cpu_baseline(inp, n_chan: int, max_workers: int = 16):
         list(pool.map(_oracle_channel, jobs))
         dtn = time.perf_counter() - t0
     return {"value": n_chan / dtn, "unit": "channel-images/s", "cores": workers, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{n_chan} of {inp.n_chan} channels x all {inp.n_time} samples, one "
                       f"process per channel on {workers} cores ({len(pids)} workers started): "
                       f"{dtn:.2f} s; the same sample in one thread: {dt1:.1f} s "
-                      f"(numpy float64)",
+                      f"(numpy float64); workers capped at the per-GPU CPU share of "
+                      f"{max_workers}",
             "tc_images_per_s": n_chan * inp.n_time / dtn, "one_core": one}
 
 
@@ -114,7 +141,7 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
-def bench_batch(args) -> int:
+def batch_results(steps: int, warmup: int, sequential: bool = True) -> dict:
     """Six blocks of different (N, A, C) advanced together: autotuned launch
     shapes, one HIP graph replay per step."""
     import tempfile
@@ -131,44 +158,55 @@ def bench_batch(args) -> int:
     g = [torch.from_numpy(i.gains).cuda() for i in inputs]
     imgs = b.new_images()
     cache = os.path.join(tempfile.gettempdir(), "epic_batch_plans.txt")
+    print("bench: tuning and capturing the batch", file=sys.stderr, flush=True)
     b.tune(ef, g, imgs, cache)
     b.capture(ef, g, imgs)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.replay()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    # the same batch, one block after another, no graph, default launch shapes
-    seq = [None] * len(inputs)
-    from paper_1904_11422_amd import Imager
-    ims = []
-    for k, i in enumerate(inputs):
-        im = Imager(i.grid_n, i.n_chan, i.n_pol, i.n_ant)
-        im.set_antennas(i.xy_m, i.freq_hz)
-        ims.append(im)
-    for k in range(len(inputs)):
-        seq[k] = ims[k].accumulate(ef[k], g[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        for k in range(len(inputs)):
-            ims[k].accumulate(ef[k], g[k], image=seq[k])
-    torch.cuda.synchronize()
-    dts = (time.perf_counter() - t1) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     tc = sum(i.n_chan for i in inputs) * T
     fl = sum(flops_per_tc(i.grid_n, i.n_pol, i.n_ant) * i.n_chan * T for i in inputs)
-    out = {"metric": "heterogeneous batch (t,c)-images/s", "value": tc / dt,
-           "unit": "(t,c)-images/s", "ms_per_step": dt * 1e3, "steps": args.steps,
+    out = {"value": tc / dt, "unit": "(t,c)-images/s", "ms_per_step": dt * 1e3, "steps": steps,
            "channel_images_per_s": sum(i.n_chan for i in inputs) / dt,
            "blocks": [dict(grid_n=i.grid_n, n_ant=i.n_ant, n_chan=i.n_chan, grid=p[0],
                            staged_batch=p[1]) for i, p in zip(inputs, b.plan())],
            "serial": b.serial,
-           "roofline": {"bound": "alu", "achieved": fl / dt / 1e12, "peak": PEAK_FP32_VALU / 1e12,
-                        "unit": "TFLOP/s", "frac": fl / dt / PEAK_FP32_VALU},
-           "sequential_no_graph_ms": dts * 1e3, "n_time": T, "data": "synthetic"}
+           "roofline": {"bound": "alu", "kernel": "whole batch (graph replay, wall clock)",
+                        "achieved": fl / dt / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                        "unit": "TFLOP/s", "frac": fl / dt / PEAK_FP32_VALU,
+                        "frac_nonpacked": fl / dt / PEAK_FP32_VALU_NONPACKED,
+                        "flops_per_step": fl},
+           "n_time": T}
+    if sequential:
+        # the same batch, one block after another, no graph, default launch shapes
+        from paper_1904_11422_amd import Imager
+        ims = []
+        for i in inputs:
+            im = Imager(i.grid_n, i.n_chan, i.n_pol, i.n_ant)
+            im.set_antennas(i.xy_m, i.freq_hz)
+            ims.append(im)
+        seq = [ims[k].accumulate(ef[k], g[k]) for k in range(len(inputs))]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            for k in range(len(inputs)):
+                ims[k].accumulate(ef[k], g[k], image=seq[k])
+        torch.cuda.synchronize()
+        out["sequential_no_graph_ms"] = (time.perf_counter() - t1) / steps * 1e3
+        for im in ims:
+            im.close()
+    b.close()
+    return out
+
+
+def bench_batch(args) -> int:
+    r = batch_results(args.steps, args.warmup)
+    out = {"metric": "heterogeneous batch (t,c)-images/s", **r, "data": "synthetic"}
     print(json.dumps(out))
     return 0
 
@@ -176,7 +214,7 @@ def bench_batch(args) -> int:
 PEAK_MFMA_F16 = 2.5e15          # MI355X dense fp16 / bf16 MFMA, FLOP/s
 
 
-def bench_split(args) -> int:
+def split_results(steps: int, with_oracle: bool = True) -> dict:
     """16 antennas, one channel, 32x32 grid, 10^5 samples: the float32 fused
     path and the float16 / bfloat16 hi+lo matrix forms on the same input."""
     import torch
@@ -188,49 +226,59 @@ def bench_split(args) -> int:
     T, N, A, P = inp.n_time, inp.grid_n, inp.n_ant, inp.n_pol
     ef = torch.from_numpy(inp.efield).cuda()
     g = torch.from_numpy(inp.gains).cuda()
-    print("bench: FP64 oracle over all samples", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    ref = oracle.image_from(inp)
-    t_oracle = time.perf_counter() - t0
+    ref, t_oracle = None, None
+    if with_oracle:
+        print("bench: FP64 oracle over all samples", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        ref = oracle.image_from(inp)
+        t_oracle = time.perf_counter() - t0
     res = {}
     for prec in ("fp32", "split_fp16", "split_bf16"):
         im = Imager(N, 1, P, A, precision=prec, timing=True)
         im.set_antennas(inp.xy_m, inp.freq_hz)
         img = im.accumulate(ef, g)
         torch.cuda.synchronize()
-        err = oracle.rel_errors(img.cpu().numpy(), ref)[0]
         ks = []
         t1 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             im.accumulate(ef, g, image=img)
             ks.append(im.last_timing()[0])
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t1) / args.steps
+        dt = (time.perf_counter() - t1) / steps
         r = {"samples_per_s": T / dt, "ms_per_call": dt * 1e3, "kernel": im.last_kernel_name(),
-             "kernel_ms": float(np.mean(ks)), "rel_err_vs_fp64": {"XX": float(err[0])}}
+             "kernel_ms": float(np.mean(ks))}
+        if ref is not None:
+            r["rel_err_vs_fp64"] = {"XX": float(oracle.rel_errors(img.cpu().numpy(), ref)[0][0])}
         if prec != "fp32":
             # v_mfma_f32_32x32x16: 32*32*16 MACs; per 32 samples x 32 pixels x 16 antennas:
             # (Re, Im) x (er, ei) = 4 products, x 2 for the hi and lo parts
             qb = (A + 15) // 16
             n_mfma = (N * N // 32) * ((T + 31) // 32) * qb * P * 8
             hw = n_mfma * 32 * 32 * 16 * 2
-            r["mfma_roofline"] = {"bound": "mfma", "achieved": hw / (r["kernel_ms"] * 1e-3) / 1e12,
-                                  "peak": PEAK_MFMA_F16 / 1e12, "unit": "TFLOP/s",
-                                  "frac": hw / (r["kernel_ms"] * 1e-3) / PEAK_MFMA_F16,
-                                  "hardware_flops": hw, "useful_flops": hw // 2}
+            k_s = r["kernel_ms"] * 1e-3
+            r["roofline"] = {"bound": "mfma", "kernel": "split_image_kernel",
+                             "achieved": hw / k_s / 1e12, "peak": PEAK_MFMA_F16 / 1e12,
+                             "unit": "TFLOP/s", "frac": hw / k_s / PEAK_MFMA_F16,
+                             "frac_useful": hw / 2 / k_s / PEAK_MFMA_F16,
+                             "hardware_flops": hw, "useful_flops": hw // 2}
         res[prec] = r
         im.close()
+    out = {"workload": "16 single-pol antennas in a 20 m square, 1 channel at 50 MHz, 32x32 "
+                       "grid, 100000 samples", "results": res}
+    if t_oracle is not None:
+        out["cpu_baseline"] = {"value": T / t_oracle, "unit": "samples/s", "cores": 1,
+                               "kind": "oracle", "sample": "all 100000 samples"}
+    return out
+
+
+def bench_split(args) -> int:
     out = {"metric": "split-precision matrix forms, samples/s and error per product",
-           "workload": "16 single-pol antennas in a 20 m square, 1 channel at 50 MHz, 32x32 "
-                       "grid, 100000 samples", "results": res,
-           "cpu_baseline": {"value": T / t_oracle, "unit": "samples/s", "cores": 1,
-                            "kind": "oracle", "sample": "all 100000 samples"},
-           "data": "synthetic"}
+           **split_results(args.steps), "data": "synthetic"}
     print(json.dumps(out))
     return 0
 
 
-def bench_grad(args) -> int:
+def grad_results(steps: int, warmup: int) -> dict:
     """Calibration workload: 256 dual-pol antennas, 64 channels, 64x64 grid,
     200 samples; one forward image and one gain gradient per step."""
     import torch
@@ -245,35 +293,44 @@ def bench_grad(args) -> int:
     im.set_antennas(inp.xy_m, inp.freq_hz)
     img = im.accumulate(ef, g)
     gam = (2.0 * img).contiguous()
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         im.accumulate(ef, g, image=img)
         im.backward(ef, g, gam)
     torch.cuda.synchronize()
     fw, bw = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         im.accumulate(ef, g, image=img)
         fw.append(im.last_timing()[0])
+        fname = im.last_kernel_name()
         im.backward(ef, g, gam)
         bw.append(im.last_timing()[0])
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
+    bname = im.last_kernel_name()
+    im.close()
     # adjoint work per (t,c): the forward recompute without the products, dL/dF*
     # (20 flop per pixel at P = 2), the adjoint transform, the degridding
     # (K^2 taps, 4 flop each, and conj(e) h, 6 flop, per (p, a))
     fl_fwd = flops_per_tc(N, P, A) - 16 * N * N
     fl_adj = fl_fwd + 20 * N * N + P * 5 * N * N * int(math.log2(N * N)) + (4 * 9 + 6) * P * A
-    adj_ms = float(np.mean(bw))
-    out = {"metric": "forward + gain-gradient evaluations/s", "value": 1.0 / dt,
-           "unit": "evaluations/s", "ms_per_step": dt * 1e3, "steps": args.steps,
-           "forward_kernel_ms": float(np.mean(fw)), "adjoint_kernel_ms": float(np.mean(bw)),
-           "adjoint_tc_images_per_s": C * T / (adj_ms * 1e-3),
-           "roofline": {"bound": "alu", "kernel": "adjoint_kernel",
-                        "achieved": fl_adj * C * T / (adj_ms * 1e-3) / 1e12,
-                        "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-                        "frac": fl_adj * C * T / (adj_ms * 1e-3) / PEAK_FP32_VALU,
-                        "flops_per_tc_image": fl_adj},
-           "workload": "256 dual-pol antennas, 64 channels, 64x64 grid, 200 samples",
+    adj_s = float(np.mean(bw)) * 1e-3
+    return {"value": 1.0 / dt, "unit": "evaluations/s", "ms_per_step": dt * 1e3, "steps": steps,
+            "forward_kernel": fname, "forward_kernel_ms": float(np.mean(fw)),
+            "adjoint_kernel_ms": adj_s * 1e3,
+            "adjoint_tc_images_per_s": C * T / adj_s,
+            "roofline": {"bound": "alu", "kernel": bname,
+                         "achieved": fl_adj * C * T / adj_s / 1e12,
+                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": fl_adj * C * T / adj_s / PEAK_FP32_VALU,
+                         "frac_nonpacked": fl_adj * C * T / adj_s / PEAK_FP32_VALU_NONPACKED,
+                         "flops_per_tc_image": fl_adj},
+            "workload": "256 dual-pol antennas, 64 channels, 64x64 grid, 200 samples, "
+                        "20 sources"}
+
+
+def bench_grad(args) -> int:
+    out = {"metric": "forward + gain-gradient evaluations/s", **grad_results(args.steps, args.warmup),
            "data": "synthetic"}
     print(json.dumps(out))
     return 0
@@ -592,6 +649,17 @@ def measured_traffic(profile=PROFILE, sources=PROFILED_SOURCES):
     return int(val.group(1)) if h.hexdigest() == want.group(1) else None
 
 
+def measured_clock(profile=PROFILE, sources=PROFILED_SOURCES):
+    """Mean shader clock (GHz) under the main kernel, from the committed
+    counter summary (GRBM_GUI_ACTIVE cycles over the kernel's traced time),
+    or None when the kernel sources have changed since."""
+    import re
+    if measured_traffic(profile, sources) is None:
+        return None
+    m = re.search(r"clock_ghz: ([0-9.]+)", open(profile).read())
+    return float(m.group(1)) if m else None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -601,6 +669,8 @@ def main() -> int:
                     help="channels of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-staged", action="store_true")
+    ap.add_argument("--no-rows", action="store_true",
+                    help="leave out the compact split-precision, gradient and batch results")
     ap.add_argument("--batch", action="store_true",
                     help="measure the heterogeneous batch (grids 32/64/128, 64/256/1024 "
                          "antennas, 16-264 channels, 200 samples) instead of the default line")
@@ -687,6 +757,8 @@ def main() -> int:
     achieved = fl / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VALU, "traffic": measured_traffic(),
+                "frac_nonpacked": achieved / PEAK_FP32_VALU_NONPACKED,
+                "clock_ghz_measured": measured_clock(),
                 "kernel": kname, "kernel_ms": k_ms,
                 "flops_per_launch": fl, "flops_per_tc_image": flops_per_tc(N, P, A),
                 "input_bytes_per_launch": C * T * P * A}
@@ -710,6 +782,18 @@ def main() -> int:
                   "speedup_of_fused": value / (C * n_st / dts)}
         ims.close()
 
+    subs = {}
+    if not args.no_rows:
+        # the other hot-path rows, compact: split-precision matrix forms (16 antennas,
+        # 10^5 samples), forward + gain gradient (calibration workload), the
+        # heterogeneous batch (graph replay)
+        del ef, g, img
+        torch.cuda.empty_cache()
+        sub_steps = max(5, args.steps)
+        subs["split_precision"] = split_results(sub_steps, with_oracle=not args.no_cpu)
+        subs["gradient"] = grad_results(sub_steps, args.warmup)
+        subs["batch"] = batch_results(sub_steps, args.warmup, sequential=False)
+
     cpu = None
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
@@ -729,6 +813,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fp32_staged": staged,
+        **subs,
     }
     print(json.dumps(out))
     return 0
