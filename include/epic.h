@@ -178,6 +178,26 @@ epic_status epic_gridding_program(const epic_config *cfg, const double *xy_m,
 epic_status epic_image_accumulate(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
                                   const float *gains, double *image, int32_t reset);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * imaging call as epic_image_accumulate, with the same arguments, ownership,
+ * product order and result, but its partial-image slots live in a static
+ * device array of the library (96 MiB, held by each device the library runs
+ * on until the process ends) instead of the context's workspace.  The call
+ * allocates nothing and runs the fused float32 kernels only (grid_n 32, 64
+ * and 128 with the taps inside an N/2 x N/2 block, or 3N/4 x 3N/4 at N = 64).
+ * The slots need (W + C - 1) * n_prod * N * N * 8 bytes, W the persistent
+ * grid (at N = 128: (W + 2C - 1) * n_prod * N * N * 4); larger calls are
+ * refused before anything is enqueued.  Every call on one device shares that
+ * device's array: calls that overlap in time on one device (any contexts,
+ * any streams) race, so serialise them.  Nothing needs clearing between
+ * calls (each call writes its slots before it reads them).
+ * Errors: as epic_image_accumulate; EPIC_E_UNSUPPORTED for the staged and
+ * split paths and for calls whose slots exceed the array; EPIC_E_DEVICE when
+ * the array has no address on this device. */
+epic_status epic_image_accumulate_noalloc(epic_ctx *ctx, const uint8_t *efield, int64_t n_time,
+                                          const float *gains, double *image, int32_t reset);
+
 /* Gradient of a real loss L with respect to the gains, given the gradient of
  * L with respect to the image accumulated by epic_image_accumulate(reset=1)
  * over the same efield and gains.  The paper does not compute this: it leaves

@@ -119,6 +119,24 @@ class Imager:
         _lib.check(self.L, self._ctx, st)
         return image
 
+    def accumulate_noalloc(self, efield, gains, image, reset: bool = True):
+        """accumulate() through epic_image_accumulate_noalloc: the caller passes
+        the image, and the library's partial slots are its static scratch
+        array, so the call allocates nothing (fused float32 kernels only)."""
+        torch = _torch()
+        efield, gains = self._check_inputs(efield, gains)
+        if image.dtype != torch.complex128 or tuple(image.shape) != self.image_shape() or \
+                not image.is_contiguous() or not image.is_cuda:
+            raise ValueError("image must be a contiguous complex128 CUDA tensor "
+                             f"{self.image_shape()}")
+        self._bind_stream()
+        st = self.L.epic_image_accumulate_noalloc(self._ctx, ctypes.c_void_p(efield.data_ptr()),
+                                                  int(efield.shape[0]),
+                                                  ctypes.c_void_p(gains.data_ptr()),
+                                                  ctypes.c_void_p(image.data_ptr()), 1 if reset else 0)
+        _lib.check(self.L, self._ctx, st)
+        return image
+
     def postprocess(self, image, taper_floor: Optional[float] = None, out=None):
         """Pseudo-Stokes planes I, Q, U, V (XX for one polarisation), float64
         [C, 4 or 1, N, N]; with taper_floor (0..1) divided by the kernel taper

@@ -18,7 +18,7 @@ EPIC_FLAG_STAGED, EPIC_FLAG_TIMING, EPIC_FLAG_REMOVE_AUTOS = 1, 2, 4
 # Every function declared in include/epic.h, with its ctypes signature.
 EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_set_antennas_kernels",
            "epic_gridding_program",
-           "epic_image_accumulate",
+           "epic_image_accumulate", "epic_image_accumulate_noalloc",
            "epic_image_backward", "epic_last_timing", "epic_last_autos_timing",
            "epic_last_kernel_name",
            "epic_destroy", "epic_last_error",
@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_gridding_program.restype = ctypes.c_int
     L.epic_image_accumulate.argtypes = [vp, vp, i64, vp, vp, i32]
     L.epic_image_accumulate.restype = ctypes.c_int
+    L.epic_image_accumulate_noalloc.argtypes = [vp, vp, i64, vp, vp, i32]
+    L.epic_image_accumulate_noalloc.restype = ctypes.c_int
     L.epic_image_backward.argtypes = [vp, vp, i64, vp, vp, vp]
     L.epic_image_backward.restype = ctypes.c_int
     L.epic_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <queue>
 #include <string>
 #include <utility>
@@ -76,8 +77,41 @@ struct DeviceGuard {
 
 }  // namespace
 
+// Partial-image slots of epic_image_accumulate_noalloc: a static device array,
+// so that call allocates nothing.  Every device the library runs on holds its
+// own copy for the life of the process.  Host code never passes `scratch`
+// itself to a kernel (on the host the name is a stand-in, not a device
+// address): epic_init looks up each device's address once and keeps it.
+constexpr size_t kScratchBytes = (size_t)96 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_tried[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device;
+// looked up on the first call per device, nullptr if that failed.
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_tried[device]) {
+    g_scratch_tried[device] = true;
+    void* ptr = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? ptr : nullptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 struct epic_ctx {
   epic_config cfg{};
+  void* scratch = nullptr;            // this device's address of `scratch` (no-allocation call)
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -1222,8 +1256,36 @@ epic_status build_taper(epic_ctx* x, const Geometry& g) {
 }
 
 // The float32 paths: fused kernels, or the staged comparator.
+// Persistent grid of the fused imaging kernels for n_time samples, and the
+// bytes of partial-image slots that grid writes.
+struct FusedGrid {
+  int W;
+  size_t slot_bytes;
+};
+
+FusedGrid fused_grid(const epic_ctx* x, int64_t n_time) {
+  const int N = x->cfg.grid_n, C = x->cfg.n_chan;
+  const int64_t total = (int64_t)C * n_time;
+  FusedGrid g;
+  if (N == 128) {
+    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
+    g.W = (int)std::min<int64_t>(w_max, 2 * total);
+    g.slot_bytes = ((size_t)g.W + 2 * (size_t)C - 1) * x->nacc * N * N / 2 * sizeof(double);
+  } else {
+    const int w_cap = x->wide ? (x->cpx ? x->fused_w_wide_cpx : x->fused_w_wide)
+                              : (x->cpx ? x->fused_w_cpx : x->fused_w);
+    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
+    g.W = (int)std::min<int64_t>(w_max, total);
+    g.slot_bytes = ((size_t)g.W + (size_t)C - 1) * x->nacc * N * N * sizeof(double);
+  }
+  return g;
+}
+
+// partial: the fused kernels' partial-image slots (the context's workspace,
+// or the static scratch of the no-allocation call); unused on the staged path.
 epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
-                     double* image, int32_t reset) {
+                     double* image, int32_t reset, double* partial) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
@@ -1234,20 +1296,18 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.prog = x->prog.as<uint2>();
     a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
     a.twiddle = x->twiddle.as<float2>();
-    a.partial = x->partial.as<double>();
+    a.partial = partial;
     a.n_time = n_time;
     a.total = 2 * total;
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
-    a.W = (int)std::min<int64_t>(w_max, a.total);
+    a.W = fused_grid(x, n_time).W;
     if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image128_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::Reduce128Args r;
-    r.partial = x->partial.as<double>();
+    r.partial = partial;
     r.image = image;
     r.n_time = n_time;
     r.total = a.total;
@@ -1269,21 +1329,18 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.prog = x->prog.as<uint2>();
     a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
     a.twiddle = x->twiddle.as<float2>();
-    a.partial = x->partial.as<double>();
+    a.partial = partial;
     a.n_time = n_time;
     a.total = total;
     a.n_chan = C;
     a.n_ant = x->cfg.n_ant;
     a.L = x->L;
-    const int w_cap = x->wide ? (x->cpx ? x->fused_w_wide_cpx : x->fused_w_wide)
-                              : (x->cpx ? x->fused_w_cpx : x->fused_w);
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
-    a.W = (int)std::min<int64_t>(w_max, total);
+    a.W = fused_grid(x, n_time).W;
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = x->wide ? "fused_wide_image_kernel" : "fused_image_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::ReduceArgs r;
-    r.partial = x->partial.as<double>();
+    r.partial = partial;
     r.image = image;
     r.n_time = n_time;
     r.total = total;
@@ -1462,6 +1519,26 @@ epic_status staged_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time, 
   return EPIC_OK;
 }
 
+// After the imaging kernels of an accumulate call: the autocorrelation pass
+// where the reduction does not subtract it (N = 128, split), the closing
+// timing event, the launch status.
+epic_status finish_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
+                              double* image) {
+  // the N <= 64 reductions subtract the table themselves; the others need a pass
+  if (x->autos && (x->cfg.precision != EPIC_FP32 || (x->fused && x->cfg.grid_n == 128))) {
+    launch_auto_table(x, efield, n_time, gains);
+    launch_auto_remove(x, image);
+  }
+  x->autos_timed = x->autos && x->timing;
+  if (x->timing) {
+    (void)hipEventRecord(x->ev[2], x->stream);
+    x->timed = true;
+  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
+  return EPIC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1493,6 +1570,7 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   if (!x) { g_init_error = "host allocation failed"; return EPIC_E_NOMEM; }
   x->cfg = *cfg;
   x->device = device;
+  x->scratch = scratch_address(device);
   x->stream = static_cast<hipStream_t>(hip_stream);
   x->nprod = cfg->n_pol == 2 ? 4 : 1;
   x->nacc = cfg->n_pol == 2 ? 4 : 1;
@@ -1770,21 +1848,34 @@ epic_status epic_image_accumulate(epic_ctx* x, const uint8_t* efield, int64_t n_
   (void)hipGetLastError();
   const epic_status s = x->cfg.precision != EPIC_FP32
                             ? run_split(x, efield, n_time, gains, image, reset)
-                            : run_fp32(x, efield, n_time, gains, image, reset);
+                            : run_fp32(x, efield, n_time, gains, image, reset, x->partial.as<double>());
   if (s != EPIC_OK) return s;
-  // the N <= 64 reductions subtract the table themselves; the others need a pass
-  if (x->autos && (x->cfg.precision != EPIC_FP32 || (x->fused && x->cfg.grid_n == 128))) {
-    launch_auto_table(x, efield, n_time, gains);
-    launch_auto_remove(x, image);
-  }
-  x->autos_timed = x->autos && x->timing;
-  if (x->timing) {
-    (void)hipEventRecord(x->ev[2], x->stream);
-    x->timed = true;
-  }
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return x->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
-  return EPIC_OK;
+  return finish_accumulate(x, efield, n_time, gains, image);
+}
+
+epic_status epic_image_accumulate_noalloc(epic_ctx* x, const uint8_t* efield, int64_t n_time,
+                                          const float* gains, double* image, int32_t reset) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->have_geom) return x->fail(EPIC_E_STATE, "epic_set_antennas has not succeeded");
+  if (!efield || !gains || !image) return x->fail(EPIC_E_INVALID, "NULL device pointer");
+  if (n_time <= 0) return x->fail(EPIC_E_INVALID, "n_time must be positive");
+  if (x->autos && n_time > epic::AUTO_SEG_MAX_SAMPLES)
+    return x->fail(EPIC_E_UNSUPPORTED, "with EPIC_FLAG_REMOVE_AUTOS a call takes at most 2^24 - 1 samples");
+  if (x->cfg.precision != EPIC_FP32 || !x->fused)
+    return x->fail(EPIC_E_UNSUPPORTED,
+                   "the no-allocation call runs the fused float32 kernels only (not the staged or split paths)");
+  if (!x->scratch)
+    return x->fail(EPIC_E_DEVICE, "the static scratch array has no device address on this device");
+  const FusedGrid fg = fused_grid(x, n_time);
+  if (fg.slot_bytes > kScratchBytes)
+    return x->fail(EPIC_E_UNSUPPORTED,
+                   "this call needs " + std::to_string(fg.slot_bytes) + " bytes of partial-image slots; the "
+                   "static scratch holds " + std::to_string(kScratchBytes) + " (fewer channels per call fit)");
+  DeviceGuard guard(x->device);
+  (void)hipGetLastError();
+  const epic_status s = run_fp32(x, efield, n_time, gains, image, reset, static_cast<double*>(x->scratch));
+  if (s != EPIC_OK) return s;
+  return finish_accumulate(x, efield, n_time, gains, image);
 }
 epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time,
                                 const float* gains, const double* grad_image, float* grad_gains) {
