@@ -332,11 +332,19 @@ const char *epic_pipeline_last_error(const epic_pipeline *p);
 
 /* ------------------------------------------------------------------------
  * Heterogeneous batch: n_blocks independent configurations (different grid
- * sizes, antenna and channel counts) imaged together.  Every block gets its
- * own context and stream; a batch call forks from hip_stream to the block
- * streams and joins back, so the blocks run concurrently.  All pointer-array
- * arguments are host arrays of n_blocks device pointers, laid out per block
- * exactly as for epic_image_accumulate; n_time is common to all blocks.
+ * sizes, antenna and channel counts) imaged together.  The paper sizes its
+ * gulp, channel count and grid by measurement for its GPUs (Sec. 5.1) and
+ * leaves optimisation as future work (Sec. 6); the batch makes that sizing a
+ * tuning step.  Every block gets its own context.  Blocks that run the fused
+ * float32 kernels (no autocorrelation removal) and share the grid side,
+ * polarisation count, sample bytes per thread and aperture class are imaged
+ * by one persistent launch that walks all their channels as one (channel,
+ * time) list -- one launch per such group (at most 8 blocks each), plus one
+ * reduction writing the group's images; any other block runs through its own
+ * context.  A batch call forks from hip_stream to one stream per launch and
+ * joins back.  All pointer-array arguments are host arrays of n_blocks device
+ * pointers, laid out per block exactly as for epic_image_accumulate; n_time
+ * is common to all blocks.
  * ------------------------------------------------------------------------ */
 typedef struct epic_batch epic_batch;
 
@@ -346,12 +354,17 @@ typedef struct epic_batch epic_batch;
 epic_status epic_batch_create(const epic_config *cfgs, int32_t n_blocks, int device,
                               void *hip_stream, epic_batch **out);
 
-/* epic_set_antennas for one block. */
+/* epic_set_antennas for one block.  Once every block has its antennas the
+ * batch cuts its launches and allocates the grouped launches' workspace (a
+ * later call rebuilds them, and drops a captured graph). */
 epic_status epic_batch_set_antennas(epic_batch *b, int32_t block, const double *xy_m,
                                     const double *freq_hz);
 
-/* epic_image_accumulate for every block, concurrently, ordered after earlier
- * work on hip_stream; later work on hip_stream waits for all blocks. */
+/* The images of every block, as epic_image_accumulate would give them
+ * (the same tolerance; grouped blocks sum in another order), ordered after
+ * earlier work on hip_stream; later work on hip_stream waits for all blocks.
+ * Allocates nothing.  Errors: EPIC_E_STATE (a block has no antennas), as
+ * epic_image_accumulate otherwise. */
 epic_status epic_batch_accumulate(epic_batch *b, const uint8_t *const *efields, int64_t n_time,
                                   const float *const *gains, double *const *images,
                                   int32_t reset);
@@ -367,9 +380,13 @@ epic_status epic_batch_capture(epic_batch *b, const uint8_t *const *efields, int
 /* Launch the captured graph on hip_stream.  Errors: EPIC_E_STATE (none). */
 epic_status epic_batch_replay(epic_batch *b);
 
-/* Autotune the per-block launch shape (persistent grid size of the fused
- * kernels, sample batch of the staged kernels) on these inputs: runs and
- * times the blocks alone and the whole batch (overwriting images), or, when
+/* Autotune the launch shapes on these inputs -- for a grouped launch its
+ * persistent grid size (samples per workgroup), the float32 block length
+ * before a float64 flush (128 or 64 samples) and whether consecutive
+ * workgroup ranges are dealt to one XCD; for a single block its context's
+ * grid or staged sample batch -- and whether the launches run concurrently
+ * or one after another: runs and times each launch alone and the whole
+ * batch (overwriting images), or, when
  * cache_path names a file holding a plan for the same device, block shapes
  * and n_time, loads it.  A measured plan is appended to cache_path (if not
  * NULL).  *measured = 1 when timings were taken, 0 when the cache was used.
@@ -384,8 +401,25 @@ epic_status epic_batch_tune(epic_batch *b, const uint8_t *const *efields, int64_
 epic_status epic_batch_plan(const epic_batch *b, int32_t block, int32_t *grid,
                             int32_t *staged_batch);
 
-/* 1 if the blocks of b run one after another (each persistent launch with the
- * whole GPU), 0 if they run concurrently on their own streams; set by
+/* Which launch images a block and its tuned shape: launch = index of the
+ * launch, n_blocks = blocks that launch walks (0: the block runs alone
+ * through its context), kblock = samples summed in float32 before a float64
+ * flush, xcd = 1 if consecutive workgroup ranges share an XCD.  Errors:
+ * EPIC_E_INVALID (no such block), EPIC_E_STATE (launches not cut yet). */
+epic_status epic_batch_launch_plan(const epic_batch *b, int32_t block, int32_t *launch,
+                                   int32_t *n_blocks, int32_t *kblock, int32_t *xcd);
+
+/* Set a grouped launch's shape by hand (as epic_batch_tune would): grid =
+ * persistent workgroups (0: as many as stay resident; larger values are
+ * capped there), kblock = float32 block length in samples (1 .. 128), xcd
+ * != 0: consecutive workgroup ranges on one XCD.  Applies to later
+ * accumulate and capture calls.  Errors: EPIC_E_INVALID (no such launch, bad
+ * values), EPIC_E_UNSUPPORTED (a block running alone). */
+epic_status epic_batch_set_launch(epic_batch *b, int32_t launch, int32_t grid, int32_t kblock,
+                                  int32_t xcd);
+
+/* 1 if the launches of b run one after another (each persistent launch with
+ * the whole GPU), 0 if they run concurrently on their own streams; set by
  * epic_batch_tune (default 0) and applied to accumulate and capture. */
 int32_t epic_batch_serial(const epic_batch *b);
 

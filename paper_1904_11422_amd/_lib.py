@@ -24,6 +24,7 @@ EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_set_antenn
            "epic_destroy", "epic_last_error",
            "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
            "epic_batch_capture", "epic_batch_replay", "epic_batch_tune", "epic_batch_plan",
+           "epic_batch_launch_plan", "epic_batch_set_launch",
            "epic_batch_serial", "epic_batch_set_serial",
            "epic_batch_destroy", "epic_batch_last_error",
            "epic_postprocess", "epic_kernel_taper",
@@ -107,6 +108,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_batch_tune.restype = ctypes.c_int
     L.epic_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.epic_batch_plan.restype = ctypes.c_int
+    L.epic_batch_launch_plan.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+    L.epic_batch_launch_plan.restype = ctypes.c_int
+    L.epic_batch_set_launch.argtypes = [vp, i32, i32, i32, i32]
+    L.epic_batch_set_launch.restype = ctypes.c_int
     L.epic_batch_serial.argtypes = [vp]
     L.epic_batch_serial.restype = i32
     L.epic_batch_set_serial.argtypes = [vp, i32]

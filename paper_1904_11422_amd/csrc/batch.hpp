@@ -1,31 +1,59 @@
 // Heterogeneous batch: several imaging configurations (grid size, antennas,
-// channels) advanced together.  Each block owns a context whose kernels run on
-// a stream of their own; a call forks from the caller's stream to the block
-// streams and joins back, so independent blocks share the GPU.  The same
-// fork-join can be captured once into a HIP graph and replayed with one launch
-// per batch.  The autotuner measures, per block, the persistent-grid size
-// (fused path) or the sample batch (staged path), then picks, by timing the
-// whole batch, between running every block at its best standalone setting
-// concurrently, a work-proportional split of the GPU between concurrent
-// blocks, and the blocks one after another (each persistent launch then has
-// the whole GPU); the choice is cached in a text file keyed by the device and
-// the block shapes.
+// channels) advanced together, the paper sizing its gulp, channel count and
+// grid by measurement (Sec. 5.1) made a per-batch tuning step.
+//
+// The blocks' work is cut into launches.  Blocks that run the fused float32
+// kernels and share a grid side, polarisation count, sample bytes per thread
+// and aperture class form one launch: a single persistent kernel
+// (fused_multi_image_kernel / fused_multi_image128_kernel) walks their
+// channels as one flattened (channel, time) list, every workgroup taking an
+// equal contiguous range of it across block boundaries, followed by one
+// reduction that writes every block's image.  A block on another path
+// (staged, split precision, autocorrelation removal) is a launch of its own
+// through its context.  Each launch runs on a stream of its own; a call forks
+// from the caller's stream to the launch streams and joins back, with the
+// launches concurrent or one after another.  The same fork-join can be
+// captured once into a HIP graph and replayed with one graph launch per
+// step.  The autotuner measures, per launch, its shape -- persistent grid
+// size (samples per workgroup), float32 block length before a float64 flush,
+// and the order in which workgroups are dealt to the XCDs -- or, for a
+// single block, its context's grid or staged batch; then it times the whole
+// batch with every launch at its best shape concurrently, with the GPU split
+// between concurrent launches in proportion to their standalone time, and
+// one after another, and caches the winner in a text file keyed by the
+// device and the block shapes.
 #pragma once
 
 #include <fstream>
+#include <memory>
 #include <sstream>
+
+// One launch of the batch (see above).
+struct BatchLaunch {
+  std::vector<int> blocks;            // in channel order
+  bool grouped = false;               // a fused_multi launch over `blocks`
+  int N = 0, P = 0, gpt = 0;
+  bool wide = false;
+  int C = 0;                          // channels of all its blocks
+  int w_cap = 0;                      // persistent workgroups (occupancy x CUs)
+  DevMem partial;                     // grouped: the partial-image slots of w_cap
+  int W = 0;                          // tuned grid (0: w_cap)
+  int kblock = epic::FusedShape<64>::KBLOCK;
+  int xcd = 0;
+};
 
 struct epic_batch {
   int device = 0;
   hipStream_t main = nullptr;         // the caller's stream (may be the null stream)
   hipStream_t cap = nullptr;          // fork stream used while capturing a graph
   std::vector<epic_ctx*> ctx;
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> done;
+  std::vector<hipStream_t> streams;   // one per block; a launch uses its first block's
+  std::vector<hipEvent_t> done;       // one per launch (at most one per block)
+  std::vector<std::unique_ptr<BatchLaunch>> launches;
   hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  bool serial = false;                // blocks one after another instead of concurrently
+  bool serial = false;                // launches one after another instead of concurrently
   std::string err;
 
   epic_status fail(epic_status s, const std::string& m) {
@@ -38,25 +66,213 @@ namespace {
 
 thread_local std::string g_batch_init_error;
 
+template <int N, int P, int GPT, bool WIDE>
+int multi_blocks_per_cu() {
+  return occupancy_blocks(epic::fused_multi_image_kernel<N, P, GPT, WIDE>, epic::FusedShape<N>::NT);
+}
+
+template <int P, int GPT>
+int multi128_blocks_per_cu() {
+  return occupancy_blocks(epic::fused_multi_image128_kernel<P, GPT>, epic::FusedShape<128>::NT);
+}
+
+int multi_blocks_per_cu(int N, int P, int gpt, bool wide) {
+#define EPIC_MO(NN, PP, GG, WW) \
+  if (N == NN && P == PP && gpt == GG && wide == WW) return multi_blocks_per_cu<NN, PP, GG, WW>();
+  EPIC_MO(32, 1, 1, false) EPIC_MO(32, 1, 2, false) EPIC_MO(32, 1, 4, false)
+  EPIC_MO(32, 2, 1, false) EPIC_MO(32, 2, 2, false) EPIC_MO(32, 2, 4, false)
+  EPIC_MO(64, 1, 1, false) EPIC_MO(64, 1, 2, false) EPIC_MO(64, 1, 4, false)
+  EPIC_MO(64, 2, 1, false) EPIC_MO(64, 2, 2, false) EPIC_MO(64, 2, 4, false)
+  EPIC_MO(64, 1, 1, true) EPIC_MO(64, 1, 2, true) EPIC_MO(64, 1, 4, true)
+  EPIC_MO(64, 2, 1, true) EPIC_MO(64, 2, 2, true) EPIC_MO(64, 2, 4, true)
+#undef EPIC_MO
+  if (N == 128 && P == 1) return gpt == 1 ? multi128_blocks_per_cu<1, 1>()
+                               : gpt == 2 ? multi128_blocks_per_cu<1, 2>() : multi128_blocks_per_cu<1, 4>();
+  if (N == 128 && P == 2) return gpt == 1 ? multi128_blocks_per_cu<2, 1>()
+                               : gpt == 2 ? multi128_blocks_per_cu<2, 2>() : multi128_blocks_per_cu<2, 4>();
+  return 0;
+}
+
+bool launch_multi(const BatchLaunch& L, dim3 grid, hipStream_t s, const epic::FusedArgs& a) {
+  const dim3 block(fused_threads(L.N));
+#define EPIC_ML(NN, PP, GG, WW)                                                                     \
+  if (L.N == NN && L.P == PP && L.gpt == GG && L.wide == WW) {                                      \
+    hipLaunchKernelGGL((epic::fused_multi_image_kernel<NN, PP, GG, WW>), grid, block, 0, s, a);     \
+    return true;                                                                                    \
+  }
+  EPIC_ML(32, 1, 1, false) EPIC_ML(32, 1, 2, false) EPIC_ML(32, 1, 4, false)
+  EPIC_ML(32, 2, 1, false) EPIC_ML(32, 2, 2, false) EPIC_ML(32, 2, 4, false)
+  EPIC_ML(64, 1, 1, false) EPIC_ML(64, 1, 2, false) EPIC_ML(64, 1, 4, false)
+  EPIC_ML(64, 2, 1, false) EPIC_ML(64, 2, 2, false) EPIC_ML(64, 2, 4, false)
+  EPIC_ML(64, 1, 1, true) EPIC_ML(64, 1, 2, true) EPIC_ML(64, 1, 4, true)
+  EPIC_ML(64, 2, 1, true) EPIC_ML(64, 2, 2, true) EPIC_ML(64, 2, 4, true)
+#undef EPIC_ML
+#define EPIC_ML128(PP, GG)                                                                          \
+  if (L.N == 128 && L.P == PP && L.gpt == GG) {                                                     \
+    hipLaunchKernelGGL((epic::fused_multi_image128_kernel<PP, GG>), grid, block, 0, s, a);          \
+    return true;                                                                                    \
+  }
+  EPIC_ML128(1, 1) EPIC_ML128(1, 2) EPIC_ML128(1, 4) EPIC_ML128(2, 1) EPIC_ML128(2, 2) EPIC_ML128(2, 4)
+#undef EPIC_ML128
+  return false;
+}
+
+// Blocks whose fused kernels one multi-block launch can walk together.
+bool groupable(const epic_ctx* x) {
+  return x->have_geom && x->fused && x->cfg.precision == EPIC_FP32 && !x->autos && !x->cpx;
+}
+
+// Cut the blocks into launches (see the file comment) and size the grouped
+// launches' slots.  Called once every block has its geometry.
+epic_status batch_plan_launches(epic_batch* b) {
+  b->launches.clear();
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const epic_ctx* x = b->ctx[i];
+    const bool gr = groupable(x);
+    BatchLaunch* into = nullptr;
+    if (gr)
+      for (auto& L : b->launches)
+        if (L->grouped && L->N == x->cfg.grid_n && L->P == x->cfg.n_pol && L->gpt == x->fused_gpt &&
+            L->wide == x->wide && (int)L->blocks.size() < epic::kMaxLaunchBlocks)
+          into = L.get();
+    if (!into) {
+      b->launches.push_back(std::make_unique<BatchLaunch>());
+      into = b->launches.back().get();
+      into->grouped = gr;
+      into->N = x->cfg.grid_n;
+      into->P = x->cfg.n_pol;
+      into->gpt = x->fused_gpt;
+      into->wide = x->wide;
+    }
+    into->blocks.push_back((int)i);
+    into->C += x->cfg.n_chan;
+  }
+  for (auto& L : b->launches) {
+    if (!L->grouped) continue;
+    const int bpc = multi_blocks_per_cu(L->N, L->P, L->gpt, L->wide);
+    if (bpc <= 0) return b->fail(EPIC_E_UNSUPPORTED, "no multi-block kernel for a group of the batch");
+    L->w_cap = bpc * b->ctx[L->blocks[0]]->n_cu;
+    const int nacc = L->P == 2 ? 4 : 1;
+    const size_t segs = L->N == 128 ? 2 * (size_t)L->C : (size_t)L->C;
+    const size_t per_slot = L->N == 128 ? (size_t)nacc * L->N * L->N / 2 : (size_t)nacc * L->N * L->N;
+    if (!L->partial.alloc(((size_t)L->w_cap + segs - 1) * per_slot * sizeof(double)))
+      return b->fail(EPIC_E_NOMEM, "batch partial-image workspace allocation failed");
+  }
+  return EPIC_OK;
+}
+
+// Enqueue a grouped launch on stream s: the multi-block imaging kernel, then
+// one reduction writing every block's image.
+epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, const uint8_t* const* efields,
+                          int64_t n_time, const float* const* gains, double* const* images, int32_t reset) {
+  const epic_ctx* x0 = b->ctx[L.blocks[0]];
+  epic::FusedArgs a{};
+  int c0 = 0;
+  for (size_t k = 0; k < L.blocks.size(); ++k) {
+    const int i = L.blocks[k];
+    const epic_ctx* x = b->ctx[i];
+    epic::FusedBlock& fb = a.blk[k];
+    fb.efield = efields[i];
+    fb.gains = reinterpret_cast<const float2*>(gains[i]);
+    fb.prog = x->prog.as<uint2>();
+    fb.wim = nullptr;
+    fb.c0 = c0;
+    fb.n_chan = x->cfg.n_chan;
+    fb.n_ant = x->cfg.n_ant;
+    fb.L = x->L;
+    c0 += x->cfg.n_chan;
+  }
+  a.n_blk = (int)L.blocks.size();
+  a.twiddle = x0->twiddle.as<float2>();
+  a.partial = L.partial.as<double>();
+  a.n_time = n_time;
+  const int64_t total = (int64_t)L.C * n_time;
+  a.total = L.N == 128 ? 2 * total : total;
+  const int w_max = L.W > 0 ? std::min(L.W, L.w_cap) : L.w_cap;
+  a.W = (int)std::min<int64_t>(w_max, a.total);
+  a.kblock = L.kblock;
+  a.xcd = L.xcd;
+  if (!launch_multi(L, dim3(a.W), s, a)) return b->fail(EPIC_E_UNSUPPORTED, "no multi-block kernel");
+  const int sub = reduce_sub(slots_per_channel(n_time, a.total, a.W));
+  const int64_t n = (int64_t)L.C * L.N * L.N, ppb = 256 / sub;
+  const dim3 rgrid((unsigned)((n + ppb - 1) / ppb)), rblock(256);
+  if (L.N == 128) {
+    epic::Reduce128Args r{};
+    r.partial = a.partial;
+    for (int k = 0; k < a.n_blk; ++k) {
+      r.image[k] = images[L.blocks[k]];
+      r.img_c0[k] = a.blk[k].c0;
+    }
+    r.n_img = a.n_blk;
+    r.n_time = n_time;
+    r.total = a.total;
+    r.n_chan = L.C;
+    r.W = a.W;
+    r.reset = reset ? 1 : 0;
+    r.sub = sub;
+    if (L.P == 2) hipLaunchKernelGGL(epic::reduce_image128_kernel<2>, rgrid, rblock, 0, s, r);
+    else hipLaunchKernelGGL(epic::reduce_image128_kernel<1>, rgrid, rblock, 0, s, r);
+  } else {
+    epic::ReduceArgs r{};
+    r.partial = a.partial;
+    for (int k = 0; k < a.n_blk; ++k) {
+      r.image[k] = images[L.blocks[k]];
+      r.img_c0[k] = a.blk[k].c0;
+    }
+    r.n_img = a.n_blk;
+    r.n_time = n_time;
+    r.total = a.total;
+    r.n_chan = L.C;
+    r.W = a.W;
+    r.reset = reset ? 1 : 0;
+    r.sub = sub;
+    r.autos = nullptr;
+    r.K = x0->cfg.kernel_support;
+    r.autos_cpx = 0;
+#define EPIC_MR(NN, PP)                                                                       \
+    if (L.N == NN && L.P == PP)                                                               \
+      hipLaunchKernelGGL((epic::reduce_image_kernel<NN, PP, true>), rgrid, rblock, 0, s, r);
+    EPIC_MR(32, 1) EPIC_MR(32, 2) EPIC_MR(64, 1) EPIC_MR(64, 2)
+#undef EPIC_MR
+  }
+  return EPIC_OK;
+}
+
+// Enqueue launch li (grouped, or its single block through its context) on
+// its stream.
+epic_status enqueue_launch(epic_batch* b, size_t li, const uint8_t* const* efields, int64_t n_time,
+                           const float* const* gains, double* const* images, int32_t reset) {
+  const BatchLaunch& L = *b->launches[li];
+  if (L.grouped)
+    return enqueue_group(b, L, b->streams[L.blocks[0]], efields, n_time, gains, images, reset);
+  const int i = L.blocks[0];
+  const epic_status s = epic_image_accumulate(b->ctx[i], efields[i], n_time, gains[i], images[i], reset);
+  if (s != EPIC_OK) return b->fail(s, "block " + std::to_string(i) + ": " + b->ctx[i]->err);
+  return EPIC_OK;
+}
+
 epic_status batch_enqueue(epic_batch* b, hipStream_t root, const uint8_t* const* efields,
                           int64_t n_time, const float* const* gains, double* const* images,
                           int32_t reset) {
   if (hipEventRecord(b->fork, root) != hipSuccess)
     return b->fail(EPIC_E_LAUNCH, "event record failed");
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
-    // concurrent: every block waits for the fork; serial: for the block before
-    const hipEvent_t after = (b->serial && i > 0) ? b->done[i - 1] : b->fork;
-    if (hipStreamWaitEvent(b->streams[i], after, 0) != hipSuccess)
+  const size_t nl = b->launches.size();
+  for (size_t li = 0; li < nl; ++li) {
+    const hipStream_t st = b->streams[b->launches[li]->blocks[0]];
+    // concurrent: every launch waits for the fork; serial: for the launch before
+    const hipEvent_t after = (b->serial && li > 0) ? b->done[li - 1] : b->fork;
+    if (hipStreamWaitEvent(st, after, 0) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "stream wait failed");
-    const epic_status s = epic_image_accumulate(b->ctx[i], efields[i], n_time, gains[i], images[i], reset);
-    if (s != EPIC_OK)
-      return b->fail(s, "block " + std::to_string(i) + ": " + b->ctx[i]->err);
-    if (hipEventRecord(b->done[i], b->streams[i]) != hipSuccess)
+    const epic_status s = enqueue_launch(b, li, efields, n_time, gains, images, reset);
+    if (s != EPIC_OK) return s;
+    if (hipEventRecord(b->done[li], st) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "event record failed");
   }
-  for (size_t i = b->serial ? b->ctx.size() - 1 : 0; i < b->ctx.size(); ++i)
-    if (hipStreamWaitEvent(root, b->done[i], 0) != hipSuccess)
+  for (size_t li = b->serial ? nl - 1 : 0; li < nl; ++li)
+    if (hipStreamWaitEvent(root, b->done[li], 0) != hipSuccess)
       return b->fail(EPIC_E_LAUNCH, "stream wait failed");
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return b->fail(EPIC_E_LAUNCH, std::string("launch failed: ") + hipGetErrorString(e));
   return EPIC_OK;
 }
 
@@ -70,6 +286,7 @@ epic_status batch_check(epic_batch* b, const uint8_t* const* efields, const floa
     if (!efields[i] || !gains[i] || !images[i])
       return b->fail(EPIC_E_INVALID, "NULL device pointer for block " + std::to_string(i));
   }
+  if (b->launches.empty()) return b->fail(EPIC_E_STATE, "the batch has no launch plan");
   return EPIC_OK;
 }
 
@@ -92,12 +309,30 @@ float time_on(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, F fn) {
 
 std::string batch_key(const epic_batch* b, int64_t n_time) {
   std::ostringstream k;
-  k << "gfx950 v3 T=" << n_time;
+  k << "gfx950 v4 T=" << n_time;
   for (const epic_ctx* x : b->ctx)
     k << " [N=" << x->cfg.grid_n << ",P=" << x->cfg.n_pol << ",A=" << x->cfg.n_ant << ",C="
-      << x->cfg.n_chan << ",prec=" << x->cfg.precision << ",path=" << (x->fused ? "fused" : "staged")
-      << "]";
+      << x->cfg.n_chan << ",prec=" << x->cfg.precision << ",flags=" << x->cfg.flags
+      << ",path=" << (x->fused ? (x->wide ? "wide" : "fused") : "staged") << "]";
   return k.str();
+}
+
+// Launch shape of one launch: grouped {W, kblock, xcd}, single block {W, tb}.
+struct LaunchShape {
+  int W = 0, kblock = epic::FusedShape<64>::KBLOCK, xcd = 0, tb = 0;
+};
+
+void apply_shape(epic_batch* b, size_t li, const LaunchShape& sh) {
+  BatchLaunch& L = *b->launches[li];
+  if (L.grouped) {
+    L.W = sh.W;
+    L.kblock = sh.kblock;
+    L.xcd = sh.xcd;
+  } else {
+    epic_ctx* x = b->ctx[L.blocks[0]];
+    x->w_override = sh.W;
+    x->tb_override = sh.tb;
+  }
 }
 
 }  // namespace
@@ -159,7 +394,15 @@ epic_status epic_batch_set_antennas(epic_batch* b, int32_t block, const double* 
   if (block < 0 || block >= (int32_t)b->ctx.size()) return b->fail(EPIC_E_INVALID, "no such block");
   const epic_status s = epic_set_antennas(b->ctx[block], xy_m, freq_hz);
   if (s != EPIC_OK) return b->fail(s, b->ctx[block]->err);
-  return EPIC_OK;
+  // once every block has its geometry: cut the launches (a new geometry can
+  // change a block's path, so the plan is rebuilt and the graph dropped)
+  b->launches.clear();
+  DeviceGuard guard(b->device);
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  for (const epic_ctx* x : b->ctx)
+    if (!x->have_geom) return EPIC_OK;
+  return batch_plan_launches(b);
 }
 
 epic_status epic_batch_accumulate(epic_batch* b, const uint8_t* const* efields, int64_t n_time,
@@ -221,14 +464,11 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
   epic_status s = batch_check(b, efields, gains, images, n_time);
   if (s != EPIC_OK) return s;
   DeviceGuard guard(b->device);
-  const size_t nb = b->ctx.size();
+  const size_t nl = b->launches.size();
   const std::string key = batch_key(b, n_time);
   if (measured) *measured = 0;
-  auto apply = [&](const std::vector<std::pair<int, int>>& plan) {
-    for (size_t i = 0; i < nb; ++i) {
-      b->ctx[i]->w_override = plan[i].first;
-      b->ctx[i]->tb_override = plan[i].second;
-    }
+  auto apply = [&](const std::vector<LaunchShape>& plan) {
+    for (size_t li = 0; li < nl; ++li) apply_shape(b, li, plan[li]);
   };
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -236,13 +476,14 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
     while (std::getline(in, line)) {
       const size_t sep = line.find(" => ");
       if (sep == std::string::npos || line.compare(0, sep, key) != 0 || sep != key.size()) continue;
-      std::vector<std::pair<int, int>> plan;
+      std::vector<LaunchShape> plan;
       std::istringstream vals(line.substr(sep + 4));
-      int w = 0, tb = 0, serial = 0;
-      char comma = 0;
+      int serial = 0;
       if (!(vals >> serial)) continue;
-      while (vals >> w >> comma >> tb) plan.push_back({w, tb});
-      if (plan.size() == nb) {
+      LaunchShape sh;
+      char c1 = 0, c2 = 0, c3 = 0;
+      while (vals >> sh.W >> c1 >> sh.kblock >> c2 >> sh.xcd >> c3 >> sh.tb) plan.push_back(sh);
+      if (plan.size() == nl) {
         apply(plan);
         b->serial = serial != 0;
         return EPIC_OK;
@@ -250,42 +491,64 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
     }
   }
   if (hipStreamSynchronize(b->main) != hipSuccess) return b->fail(EPIC_E_DEVICE, "stream sync failed");
-  // 1. standalone cost of every block for a few settings
-  std::vector<std::pair<int, int>> best(nb);
-  std::vector<float> best_ms(nb);
-  for (size_t i = 0; i < nb; ++i) {
-    epic_ctx* x = b->ctx[i];
-    std::vector<std::pair<int, int>> cands;
-    if (x->fused) {
-      for (int den : {1, 2, 4}) cands.push_back({std::max(1, x->fused_w / den), 0});
-      cands.push_back({std::max(1, x->fused_w * 3 / 4), 0});
+  // 1. standalone cost of every launch for its candidate shapes
+  std::vector<LaunchShape> best(nl);
+  std::vector<float> best_ms(nl);
+  for (size_t li = 0; li < nl; ++li) {
+    const BatchLaunch& L = *b->launches[li];
+    const hipStream_t st = b->streams[L.blocks[0]];
+    std::vector<LaunchShape> cands;
+    if (L.grouped) {
+      for (int den : {4, 3, 2, 1})        // grid of w_cap * den / 4: samples per workgroup
+        for (int kb : {epic::FusedShape<64>::KBLOCK, epic::FusedShape<64>::KBLOCK / 2})
+          for (int xcd : {0, 1}) {
+            LaunchShape sh;
+            sh.W = std::max(1, L.w_cap * den / 4);
+            sh.kblock = kb;
+            sh.xcd = xcd;
+            cands.push_back(sh);
+          }
     } else {
-      for (int den : {1, 2, 4}) cands.push_back({0, std::max(1, x->tb / den)});
+      const epic_ctx* x = b->ctx[L.blocks[0]];
+      if (x->fused) {
+        for (int den : {1, 2, 4}) { LaunchShape sh; sh.W = std::max(1, x->fused_w / den); cands.push_back(sh); }
+        LaunchShape sh;
+        sh.W = std::max(1, x->fused_w * 3 / 4);
+        cands.push_back(sh);
+      } else {
+        for (int den : {1, 2, 4}) { LaunchShape sh; sh.tb = std::max(1, x->tb / den); cands.push_back(sh); }
+      }
     }
-    best_ms[i] = 1e30f;
+    best_ms[li] = 1e30f;
     for (const auto& c : cands) {
-      x->w_override = c.first;
-      x->tb_override = c.second;
-      s = epic_image_accumulate(x, efields[i], n_time, gains[i], images[i], 1);      // warm
-      if (s != EPIC_OK) return b->fail(s, x->err);
-      const float ms = time_on(b->streams[i], b->t0, b->t1, 3, [&] {
-        (void)epic_image_accumulate(x, efields[i], n_time, gains[i], images[i], 1);
+      apply_shape(b, li, c);
+      s = enqueue_launch(b, li, efields, n_time, gains, images, 1);      // warm
+      if (s != EPIC_OK) return s;
+      const float ms = time_on(st, b->t0, b->t1, 3, [&] {
+        (void)enqueue_launch(b, li, efields, n_time, gains, images, 1);
       });
-      if (ms < best_ms[i]) { best_ms[i] = ms; best[i] = c; }
+      if (ms < best_ms[li]) { best_ms[li] = ms; best[li] = c; }
     }
+    apply_shape(b, li, best[li]);
   }
-  // 2. the whole batch: every block at its standalone best, or the GPU split
-  //    between the fused blocks in proportion to their standalone time
-  std::vector<std::pair<int, int>> split = best;
+  // 2. the whole batch: every launch at its standalone best, or the GPU split
+  //    between the fused launches in proportion to their standalone time
+  std::vector<LaunchShape> split = best;
   double tot = 0.0;
-  for (size_t i = 0; i < nb; ++i) if (b->ctx[i]->fused) tot += best_ms[i];
-  for (size_t i = 0; i < nb; ++i)
-    if (b->ctx[i]->fused && tot > 0)
-      split[i].first = std::max(1, (int)std::lround(b->ctx[i]->fused_w * best_ms[i] / tot));
-  std::vector<std::pair<int, int>> chosen = best;
+  auto cap_of = [&](size_t li) {
+    const BatchLaunch& L = *b->launches[li];
+    if (L.grouped) return L.w_cap;
+    const epic_ctx* x = b->ctx[L.blocks[0]];
+    return x->fused ? x->fused_w : 0;
+  };
+  for (size_t li = 0; li < nl; ++li) if (cap_of(li) > 0) tot += best_ms[li];
+  for (size_t li = 0; li < nl; ++li)
+    if (cap_of(li) > 0 && tot > 0)
+      split[li].W = std::max(1, (int)std::lround(cap_of(li) * best_ms[li] / tot));
+  std::vector<LaunchShape> chosen = best;
   bool chosen_serial = false;
   float chosen_ms = 1e30f;
-  const std::pair<const std::vector<std::pair<int, int>>*, bool> trials[] = {
+  const std::pair<const std::vector<LaunchShape>*, bool> trials[] = {
       {&best, false}, {&split, false}, {&best, true}};
   // each trial is timed as it will run: captured into a graph and replayed
   // (concurrent persistent launches behave differently when launched eagerly)
@@ -322,7 +585,7 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << key << " => " << (chosen_serial ? 1 : 0);
-    for (const auto& p : chosen) out << " " << p.first << "," << p.second;
+    for (const auto& p : chosen) out << " " << p.W << "," << p.kblock << "," << p.xcd << "," << p.tb;
     out << "\n";
   }
   return EPIC_OK;
@@ -331,8 +594,42 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
 epic_status epic_batch_plan(const epic_batch* b, int32_t block, int32_t* grid, int32_t* staged_batch) {
   if (!b || block < 0 || block >= (int32_t)b->ctx.size()) return EPIC_E_INVALID;
   const epic_ctx* x = b->ctx[block];
+  for (const auto& L : b->launches)
+    if (L->grouped && std::find(L->blocks.begin(), L->blocks.end(), block) != L->blocks.end()) {
+      if (grid) *grid = L->W > 0 ? std::min(L->W, L->w_cap) : L->w_cap;
+      if (staged_batch) *staged_batch = 0;
+      return EPIC_OK;
+    }
   if (grid) *grid = x->fused ? (x->w_override > 0 ? std::min(x->w_override, x->fused_w) : x->fused_w) : 0;
   if (staged_batch) *staged_batch = x->fused ? 0 : (x->tb_override > 0 ? std::min(x->tb_override, x->tb) : x->tb);
+  return EPIC_OK;
+}
+
+epic_status epic_batch_launch_plan(const epic_batch* b, int32_t block, int32_t* launch, int32_t* n_blocks,
+                                   int32_t* kblock, int32_t* xcd) {
+  if (!b || block < 0 || block >= (int32_t)b->ctx.size()) return EPIC_E_INVALID;
+  for (size_t li = 0; li < b->launches.size(); ++li) {
+    const BatchLaunch& L = *b->launches[li];
+    if (std::find(L.blocks.begin(), L.blocks.end(), block) == L.blocks.end()) continue;
+    if (launch) *launch = (int32_t)li;
+    if (n_blocks) *n_blocks = L.grouped ? (int32_t)L.blocks.size() : 0;
+    if (kblock) *kblock = L.grouped ? L.kblock : epic::FusedShape<64>::KBLOCK;
+    if (xcd) *xcd = L.grouped ? L.xcd : 0;
+    return EPIC_OK;
+  }
+  return EPIC_E_STATE;
+}
+
+epic_status epic_batch_set_launch(epic_batch* b, int32_t launch, int32_t grid, int32_t kblock, int32_t xcd) {
+  if (!b) return EPIC_E_INVALID;
+  if (launch < 0 || launch >= (int32_t)b->launches.size()) return b->fail(EPIC_E_INVALID, "no such launch");
+  BatchLaunch& L = *b->launches[launch];
+  if (!L.grouped) return b->fail(EPIC_E_UNSUPPORTED, "a block running alone has no grouped launch shape");
+  if (grid < 0 || kblock < 1 || kblock > epic::FusedShape<64>::KBLOCK)
+    return b->fail(EPIC_E_INVALID, "grid must be >= 0 and kblock in 1..128");
+  L.W = grid;
+  L.kblock = kblock;
+  L.xcd = xcd ? 1 : 0;
   return EPIC_OK;
 }
 
@@ -349,11 +646,10 @@ void epic_batch_destroy(epic_batch* b) {
   DeviceGuard guard(b->device);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+  b->launches.clear();
   for (epic_ctx* x : b->ctx) epic_destroy(x);
-  for (hipStream_t s : b->streams) {
-    (void)hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-  }
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   for (hipEvent_t e : b->done) (void)hipEventDestroy(e);
   if (b->cap) {
     (void)hipStreamSynchronize(b->cap);

@@ -779,7 +779,7 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
 }
 
 template <int P>
-bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
+bool launch_fused128(epic_ctx* x, const epic::FusedArgs& a) {
   const dim3 grid(a.W), block(epic::FusedShape<128>::NT);
   if (x->cpx) {
     switch (x->fused_gpt) {
@@ -797,7 +797,7 @@ bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
   }
 }
 
-bool launch_fused128(epic_ctx* x, const epic::Fused128Args& a) {
+bool launch_fused128(epic_ctx* x, const epic::FusedArgs& a) {
   return x->cfg.n_pol == 2 ? launch_fused128<2>(x, a) : launch_fused128<1>(x, a);
 }
 
@@ -1256,6 +1256,30 @@ epic_status build_taper(epic_ctx* x, const Geometry& g) {
 }
 
 // The float32 paths: fused kernels, or the staged comparator.
+// Arguments of a fused imaging launch over this context alone (one block,
+// all channels); total and W are set by the caller.
+epic::FusedArgs single_block_args(const epic_ctx* x, const uint8_t* efield, const float* gains,
+                                  double* partial, int64_t n_time) {
+  epic::FusedArgs a{};
+  epic::FusedBlock& b = a.blk[0];
+  b.efield = efield;
+  b.gains = reinterpret_cast<const float2*>(gains);
+  b.prog = x->prog.as<uint2>();
+  b.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
+  b.c0 = 0;
+  b.n_chan = x->cfg.n_chan;
+  b.n_ant = x->cfg.n_ant;
+  b.L = x->L;
+  a.n_blk = 1;
+  a.twiddle = x->twiddle.as<float2>();
+  a.partial = partial;
+  a.n_time = n_time;
+  a.total = (int64_t)x->cfg.n_chan * n_time;
+  a.kblock = epic::FusedShape<64>::KBLOCK;
+  a.xcd = 0;
+  return a;
+}
+
 // Persistent grid of the fused imaging kernels for n_time samples, and the
 // bytes of partial-image slots that grid writes.
 struct FusedGrid {
@@ -1290,25 +1314,17 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   if (x->fused && N == 128) {
-    epic::Fused128Args a;
-    a.efield = efield;
-    a.gains = reinterpret_cast<const float2*>(gains);
-    a.prog = x->prog.as<uint2>();
-    a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
-    a.twiddle = x->twiddle.as<float2>();
-    a.partial = partial;
-    a.n_time = n_time;
+    epic::FusedArgs a = single_block_args(x, efield, gains, partial, n_time);
     a.total = 2 * total;
-    a.n_chan = C;
-    a.n_ant = x->cfg.n_ant;
-    a.L = x->L;
     a.W = fused_grid(x, n_time).W;
     if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image128_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::Reduce128Args r;
     r.partial = partial;
-    r.image = image;
+    r.image[0] = image;
+    r.img_c0[0] = 0;
+    r.n_img = 1;
     r.n_time = n_time;
     r.total = a.total;
     r.n_chan = C;
@@ -1323,25 +1339,16 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
       hipLaunchKernelGGL(epic::reduce_image128_kernel<1>, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
                          x->stream, r);
   } else if (x->fused) {
-    epic::FusedArgs a;
-    a.efield = efield;
-    a.gains = reinterpret_cast<const float2*>(gains);
-    a.prog = x->prog.as<uint2>();
-    a.wim = x->cpx ? x->prog_im.as<float>() : nullptr;
-    a.twiddle = x->twiddle.as<float2>();
-    a.partial = partial;
-    a.n_time = n_time;
-    a.total = total;
-    a.n_chan = C;
-    a.n_ant = x->cfg.n_ant;
-    a.L = x->L;
+    epic::FusedArgs a = single_block_args(x, efield, gains, partial, n_time);
     a.W = fused_grid(x, n_time).W;
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = x->wide ? "fused_wide_image_kernel" : "fused_image_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::ReduceArgs r;
     r.partial = partial;
-    r.image = image;
+    r.image[0] = image;
+    r.img_c0[0] = 0;
+    r.n_img = 1;
     r.n_time = n_time;
     r.total = total;
     r.n_chan = C;
@@ -1405,7 +1412,9 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
     epic::ReduceArgs r;
     r.partial = x->st_acc.as<double>();
-    r.image = image;
+    r.image[0] = image;
+    r.img_c0[0] = 0;
+    r.n_img = 1;
     r.n_time = n_time;
     r.total = total;
     r.n_chan = C;

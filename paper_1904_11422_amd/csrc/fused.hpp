@@ -91,17 +91,50 @@ template <int NT, int GPT, int P> struct EStride {
   static constexpr int value = (NT * GPT) / P + 64;
 };
 
+// One imaging configuration of a launch: its inputs, its gridding programs
+// and the place of its channels in the launch's channel order.  A launch of
+// the batch walks the channels of up to kMaxLaunchBlocks blocks (the same
+// grid, polarisations and sample bytes per thread; different antenna counts
+// and channel counts) as one flattened (channel, time) space; a launch of a
+// single context has one block.
+constexpr int kMaxLaunchBlocks = 8;
+struct FusedBlock {
+  const uint8_t* efield;    // [T][C_b][P][A_b]
+  const float2* gains;      // [C_b][P][A_b]
+  const uint2* prog;        // [C_b][1 + L_b][NT]: row-pass line of each thread, then L_b steps
+  const float* wim;         // [C_b][1 + L_b][NT] imaginary step weights (complex kernels), or null
+  int c0;                   // first channel of the block in the launch's channel order
+  int n_chan, n_ant, L;
+};
+
 struct FusedArgs {
-  const uint8_t* efield;    // [T][C][P][A]
-  const float2* gains;      // [C][P][A]
-  const uint2* prog;        // [C][1 + L][NT]: row-pass line of each thread, then L steps
-  const float* wim;         // [C][1 + L][NT] imaginary step weights (complex kernels), or null
+  FusedBlock blk[kMaxLaunchBlocks];   // in channel order: blk[i + 1].c0 = blk[i].c0 + blk[i].n_chan
+  int n_blk;
   const float2* twiddle;    // [N] exp(+2 pi i k / N)
-  double* partial;          // [W + C - 1][NACC][S][NT] (thread-major)
+  double* partial;          // [W + C - 1][NACC][S][NT] (thread-major), C = the launch's channels
   int64_t n_time;
   int64_t total;            // C * T
-  int n_chan, n_ant, L, W;
+  int W;
+  int kblock;               // samples summed in float32 before a float64 flush, 1 .. KBLOCK
+  int xcd;                  // 1: workgroup ranges dealt XCD by XCD (see wg_range_index)
 };
+
+// Workgroup ids are dealt to the 8 XCDs round-robin.  With xcd = 1 the range
+// index of workgroup id is chosen so that consecutive ranges (which share a
+// channel and its gridding program) run on one XCD and its L2.
+__device__ __forceinline__ int wg_range_index(int id, int n, int xcd) {
+  if (!xcd) return id;
+  const int q = n >> 3, r = n & 7, j = id & 7;
+  return j * q + (j < r ? j : r) + (id >> 3);
+}
+
+// Block of channel c: the last block whose first channel is <= c.
+__device__ __forceinline__ int block_of(const FusedArgs& a, int c) {
+  int b = 0;
+  for (int i = 1; i < a.n_blk; ++i)
+    if (a.blk[i].c0 <= c) b = i;
+  return b;
+}
 
 // Flat range of workgroup w: [w*total/W, (w+1)*total/W).
 __device__ __forceinline__ int64_t range_begin(int64_t w, int64_t total, int64_t W) {
@@ -369,10 +402,14 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
 // The whole per-workgroup loop.  WIDE (N = 64): apertures up to HW x HW
 // cells; the programs' header gives each thread a second row-pass line
 // (prog[tid].y, < 0: none) and both passes take their lines' inputs n1 < HW / R.
-template <int N, int P, int GPT, bool CPX, bool WIDE>
+// MULTI: the launch walks several blocks (FusedArgs::blk); a workgroup whose
+// range crosses into the next block switches inputs, gains, programs and the
+// E' layout of its antenna count at that channel boundary.  Without MULTI
+// the launch has one block.
+template <int N, int P, int GPT, bool CPX, bool WIDE, bool MULTI>
 __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   using SH = FusedShape<N>;
-  constexpr int S = SH::S, NT = SH::NT, RS = SH::RS, KB = SH::KBLOCK;
+  constexpr int S = SH::S, NT = SH::NT, RS = SH::RS;
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
@@ -384,18 +421,30 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
-  const int64_t fb = range_begin(blockIdx.x, a.total, a.W);
-  const int64_t fe = range_begin(blockIdx.x + 1, a.total, a.W);
+  const int wr = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
+  const int64_t fb = range_begin(wr, a.total, a.W);
+  const int64_t fe = range_begin(wr + 1, a.total, a.W);
   if (fb >= fe) return;
 
   float2 tw[S];
 #pragma unroll
   for (int k0 = 0; k0 < S; ++k0) tw[k0] = a.twiddle[(r.n0 * k0) % N];
 
-  const int PA = P * a.n_ant;
-  const int64_t row_bytes = (int64_t)a.n_chan * PA;   // bytes per time sample
+  // current sample (cc, tt); one division per workgroup
+  int cc = (int)(fb / a.n_time);
+  int64_t tt = fb - (int64_t)cc * a.n_time;
+  // block of the sample being prefetched (nb) and of the one being imaged (b)
+  int nb = MULTI ? block_of(a, cc) : 0;
+  int b = nb;
+  int PA = P * a.blk[b].n_ant;                 // of block b
+  int L = a.blk[b].L;
+  const int KB = a.kblock;
+  // the prefetched sample's block: bytes per time sample, channel range
+  int64_t n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+  int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
+  const uint8_t* n_src = a.blk[nb].efield;
   int eidx[GPT];
-  init_stage<NT, GPT, ES>(E, eidx, tid, a.n_ant, P);
+  init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
 
   float acc[S][NACC];                          // float32 sums over <= KB samples
   float2 g[GPT];
@@ -404,17 +453,17 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
-  auto load_bytes = [&](int cc, int64_t tt, uint32_t (&dst)[GPT]) {
-    const uint8_t* src = a.efield + tt * row_bytes + (int64_t)cc * PA;
+  auto load_bytes = [&](int ch, int64_t t, uint32_t (&dst)[GPT]) {
+    const uint8_t* src = n_src + t * n_row + (int64_t)(ch - n_c0) * n_pa;
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
       const int k = tid + i * NT;
-      dst[i] = (k < PA) ? (uint32_t)src[k] : 0u;
+      dst[i] = (k < n_pa) ? (uint32_t)src[k] : 0u;
     }
   };
   // add the float32 block sums into this workgroup's float64 slot of channel c
   auto flush = [&]() {
-    double* out = a.partial + (int64_t)(blockIdx.x + c) * NACC * S * NT + tid;
+    double* out = a.partial + (int64_t)(wr + c) * NACC * S * NT + tid;
 #pragma unroll
     for (int u = 0; u < NACC; ++u)
 #pragma unroll
@@ -427,17 +476,21 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
     nblk = 0;
   };
 
-  // current sample (cc, tt); one division per workgroup
-  int cc = (int)(fb / a.n_time);
-  int64_t tt = fb - (int64_t)cc * a.n_time;
   load_bytes(cc, tt, nxt);
   for (int64_t left = fe - fb; left > 0; --left) {
     if (cc != c) {                             // channel segment starts
       if (c >= 0) flush();
       c = cc;
       nflush = 0;
-      prog = a.prog + (int64_t)c * (a.L + 1) * NT;
-      if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
+      if (MULTI && nb != b) {                  // and a block: its antennas' E' layout
+        b = nb;
+        PA = P * a.blk[b].n_ant;
+        L = a.blk[b].L;
+        init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+      }
+      const int64_t cl = c - a.blk[b].c0;      // channel within the block
+      prog = a.blk[b].prog + cl * (L + 1) * NT;
+      if (CPX) wim = a.blk[b].wim + cl * (L + 1) * NT + NT;
       line = (int)prog[tid].x;
       if (WIDE) line2 = (int)prog[tid].y;
       prog += NT;
@@ -448,7 +501,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
         const int k = tid + i * NT;
-        g[i] = (k < PA) ? a.gains[(int64_t)c * PA + k] : make_float2(0.f, 0.f);
+        g[i] = (k < PA) ? a.blk[b].gains[cl * PA + k] : make_float2(0.f, 0.f);
       }
     } else if (nblk == KB) {
       flush();
@@ -457,10 +510,20 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
 #pragma unroll
     for (int i = 0; i < GPT; ++i) cur[i] = nxt[i];
     ++tt;                                      // advance, prefetch the next sample
-    if (tt == a.n_time) { tt = 0; ++cc; }
+    if (tt == a.n_time) {
+      tt = 0;
+      ++cc;
+      if (MULTI && nb + 1 < a.n_blk && cc == a.blk[nb + 1].c0) {
+        ++nb;
+        n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+        n_pa = P * a.blk[nb].n_ant;
+        n_c0 = a.blk[nb].c0;
+        n_src = a.blk[nb].efield;
+      }
+    }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
@@ -488,7 +551,7 @@ template <int N, int P, int GPT, bool CPX>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_image_kernel(FusedArgs a) {
-  fused_image_body<N, P, GPT, CPX, false>(a);
+  fused_image_body<N, P, GPT, CPX, false, false>(a);
 }
 
 // Apertures wider than N/2 cells (up to 3N/4) at N = 64.
@@ -497,7 +560,17 @@ __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_wide_image_kernel(FusedArgs a) {
   static_assert(N == 64, "the wide variant is built for N = 64");
-  fused_image_body<N, P, GPT, CPX, true>(a);
+  fused_image_body<N, P, GPT, CPX, true, false>(a);
+}
+
+// The heterogeneous batch: one launch over the channels of several blocks
+// of the same grid (WIDE at N = 64: apertures up to 3N/4 cells).
+template <int N, int P, int GPT, bool WIDE>
+__global__ void __launch_bounds__(FusedShape<N>::NT)
+__attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
+fused_multi_image_kernel(FusedArgs a) {
+  static_assert(!WIDE || N == 64, "the wide variant is built for N = 64");
+  fused_image_body<N, P, GPT, false, WIDE, true>(a);
 }
 
 // image[c][prod][qm][ql] (+)= sum over the workgroups covering channel c of
@@ -509,9 +582,14 @@ fused_wide_image_kernel(FusedArgs a) {
 // for a given (W, C, T, sub), so the result is reproducible run to run.
 struct ReduceArgs {
   const double* partial;
-  double* image;            // complex128 [C][NPROD][N][N]
+  // complex128 [C_b][NPROD][N][N] per block of the launch; channel c of the
+  // launch is channel c - img_c0[b] of image[b], b the last block with
+  // img_c0[b] <= c
+  double* image[kMaxLaunchBlocks];
+  int img_c0[kMaxLaunchBlocks];
+  int n_img;
   int64_t n_time, total;
-  int n_chan, W, reset;
+  int n_chan, W, reset;     // n_chan: all channels of the launch
   int sub;                  // 1, 4 or 16 sub-lanes per pixel
   const double* autos;      // table of the antenna autocorrelations to subtract
                             // ([C][(2K-1)^2][NACC (x2 with autos_cpx)], autos.hpp), or null
@@ -577,9 +655,12 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
     kl = pix % N;
   }
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
-  double2* img = reinterpret_cast<double2*>(a.image);
+  int b = 0;                                 // the image of channel c
+  for (int i = 1; i < a.n_img; ++i)
+    if (a.img_c0[i] <= c) b = i;
+  double2* img = reinterpret_cast<double2*>(a.image[b]);
   constexpr int NPROD = (P == 2) ? 4 : 1;
-  const int64_t base = (int64_t)c * NPROD * NPIX + qm * N + ql;
+  const int64_t base = (int64_t)(c - a.img_c0[b]) * NPROD * NPIX + qm * N + ql;
   double2 val[NPROD];
   if (P == 2) {
     val[0] = make_double2(s[0], 0.0);                          // XX

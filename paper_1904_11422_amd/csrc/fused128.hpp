@@ -27,17 +27,8 @@
 
 namespace epic {
 
-struct Fused128Args {
-  const uint8_t* efield;    // [T][C][P][A]
-  const float2* gains;      // [C][P][A]
-  const uint2* prog;        // [C][1 + L][NT], as fused_image_kernel
-  const float* wim;         // [C][1 + L][NT] imaginary step weights (complex kernels), or null
-  const float2* twiddle;    // [128] exp(+2 pi i k / 128)
-  double* partial;          // [W + 2 C - 1][NACC][16][NT] (thread-major)
-  int64_t n_time;
-  int64_t total;            // 2 C T units
-  int n_chan, n_ant, L, W;
-};
+// Launch arguments: FusedArgs (fused.hpp) with total = 2 C T units, C the
+// launch's channels, and partial = [W + 2 C - 1][NACC][16][NT] (thread-major).
 
 // Local pixel of float32 sum i of a thread: km = 2 n0 + q + 16 k1 with
 // q = i >> 3 and k1 = i & 7; kl = the thread's local column (Roles::kl).
@@ -49,12 +40,12 @@ __host__ __device__ __forceinline__ int km128(int n0, int i) {
 // polarisation: two workgroups per CU, so at most 128 VGPRs.
 template <int P> struct Fused128Waves { static constexpr int value = P == 2 ? 2 : 4; };
 
-template <int P, int GPT, bool CPX>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Fused128Waves<P>::value)))
-fused_image128_kernel(Fused128Args a) {
+// MULTI: the launch walks several blocks (as fused_image_body).
+template <int P, int GPT, bool CPX, bool MULTI>
+__device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   using SH = FusedShape<128>;
   constexpr int N = 128, S = SH::S, R = SH::R, NT = SH::NT, RS = SH::RS, PS = SH::PSTRIDE;
-  constexpr int NACC = P == 2 ? 4 : 1, KB = SH::KBLOCK, H = N / 2, NPX = 16;
+  constexpr int NACC = P == 2 ? 4 : 1, H = N / 2, NPX = 16;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   // E'[p][a] (zero slots at a = A .. A+15), the grid (64 rows per
@@ -69,17 +60,27 @@ fused_image128_kernel(Fused128Args a) {
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
-  const int64_t fb = range_begin(blockIdx.x, a.total, a.W);
-  const int64_t fe = range_begin(blockIdx.x + 1, a.total, a.W);
+  const int wr = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
+  const int64_t fb = range_begin(wr, a.total, a.W);
+  const int64_t fe = range_begin(wr + 1, a.total, a.W);
   if (fb >= fe) return;
 
   if (tid < R * S) TW[(tid / S) * TWS + tid % S] = a.twiddle[((tid / S) * (tid % S)) % N];
   const float2* tw = TW + r.n0 * TWS;          // read after the first barrier
 
-  const int PA = P * a.n_ant;
-  const int64_t row_bytes = (int64_t)a.n_chan * PA;
+  int64_t sg = fb / a.n_time;                  // segment 2 c + h of the current unit
+  int64_t tt = fb - sg * a.n_time;
+  // block of the unit being prefetched (nb) and of the one being imaged (b)
+  int nb = MULTI ? block_of(a, (int)(sg >> 1)) : 0;
+  int b = nb;
+  int PA = P * a.blk[b].n_ant;
+  int L = a.blk[b].L;
+  const int KB = a.kblock;
+  int64_t n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+  int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
+  const uint8_t* n_src = a.blk[nb].efield;
   int eidx[GPT];
-  init_stage<NT, GPT, ES>(E, eidx, tid, a.n_ant, P);
+  init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
 
   float acc[NPX][NACC];
   float2 g[GPT];
@@ -88,16 +89,16 @@ fused_image128_kernel(Fused128Args a) {
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
-  auto load_bytes = [&](int64_t sg, int64_t tt, uint32_t (&dst)[GPT]) {
-    const uint8_t* src = a.efield + tt * row_bytes + (sg >> 1) * PA;
+  auto load_bytes = [&](int64_t sgm, int64_t t, uint32_t (&dst)[GPT]) {
+    const uint8_t* src = n_src + t * n_row + ((sgm >> 1) - n_c0) * n_pa;
 #pragma unroll
     for (int i = 0; i < GPT; ++i) {
       const int k = tid + i * NT;
-      dst[i] = (k < PA) ? (uint32_t)src[k] : 0u;
+      dst[i] = (k < n_pa) ? (uint32_t)src[k] : 0u;
     }
   };
   auto flush = [&]() {
-    double* out = a.partial + (int64_t)(blockIdx.x + seg) * NACC * NPX * NT + tid;
+    double* out = a.partial + (int64_t)(wr + seg) * NACC * NPX * NT + tid;
 #pragma unroll
     for (int u = 0; u < NACC; ++u)
 #pragma unroll
@@ -110,8 +111,6 @@ fused_image128_kernel(Fused128Args a) {
     nblk = 0;
   };
 
-  int64_t sg = fb / a.n_time;                  // segment 2 c + h of the current unit
-  int64_t tt = fb - sg * a.n_time;
   load_bytes(sg, tt, nxt);
   for (int64_t left = fe - fb; left > 0; --left) {
     if ((int)sg != seg) {
@@ -126,14 +125,21 @@ fused_image128_kernel(Fused128Args a) {
 #pragma unroll
         for (int u = 0; u < NACC; ++u) acc[i][u] = 0.f;
       if (c != c_old) {
-        prog = a.prog + (int64_t)c * (a.L + 1) * NT;
-        if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
+        if (MULTI && nb != b) {                // a new block: its antennas' E' layout
+          b = nb;
+          PA = P * a.blk[b].n_ant;
+          L = a.blk[b].L;
+          init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+        }
+        const int64_t cl = c - a.blk[b].c0;
+        prog = a.blk[b].prog + cl * (L + 1) * NT;
+        if (CPX) wim = a.blk[b].wim + cl * (L + 1) * NT + NT;
         line = (int)prog[tid].x;
         prog += NT;
 #pragma unroll
         for (int i = 0; i < GPT; ++i) {
           const int k = tid + i * NT;
-          g[i] = (k < PA) ? a.gains[(int64_t)c * PA + k] : make_float2(0.f, 0.f);
+          g[i] = (k < PA) ? a.blk[b].gains[cl * PA + k] : make_float2(0.f, 0.f);
         }
       }
     } else if (nblk == KB) {
@@ -143,12 +149,21 @@ fused_image128_kernel(Fused128Args a) {
 #pragma unroll
     for (int i = 0; i < GPT; ++i) cur[i] = nxt[i];
     ++tt;                                      // advance, prefetch the next unit
-    if (tt == a.n_time) { tt = 0; ++sg; }
+    if (tt == a.n_time) {
+      tt = 0;
+      ++sg;
+      if (MULTI && nb + 1 < a.n_blk && (sg >> 1) == a.blk[nb + 1].c0 && !(sg & 1)) {
+        ++nb;
+        n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+        n_pa = P * a.blk[nb].n_ant;
+        n_c0 = a.blk[nb].c0;
+        n_src = a.blk[nb].efield;
+      }
+    }
     if (left > 1) load_bytes(sg, tt, nxt);
 
     // 1. stage and grid the aperture (both halves grid the whole aperture)
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
-
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
     // 2. row transforms of row `line` of both polarisations; keep half h
     if (line >= 0) {
       const int rb = (line & 0xFFFF) * RS;
@@ -206,13 +221,30 @@ fused_image128_kernel(Fused128Args a) {
   flush();
 }
 
+
+template <int P, int GPT, bool CPX>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Fused128Waves<P>::value)))
+fused_image128_kernel(FusedArgs a) {
+  fused_image128_body<P, GPT, CPX, false>(a);
+}
+
+// The heterogeneous batch: one launch over the channels of several 128 x 128 blocks.
+template <int P, int GPT>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Fused128Waves<P>::value)))
+fused_multi_image128_kernel(FusedArgs a) {
+  fused_image128_body<P, GPT, false, true>(a);
+}
+
 // image[c][prod][qm][ql] (+)= sum of the slots of segment 2 c + h, for the
 // pixels of half h; sub-lanes as reduce_image_kernel.
 struct Reduce128Args {
   const double* partial;
-  double* image;            // complex128 [C][NPROD][128][128]
+  // complex128 [C_b][NPROD][128][128] per block of the launch (as ReduceArgs)
+  double* image[kMaxLaunchBlocks];
+  int img_c0[kMaxLaunchBlocks];
+  int n_img;
   int64_t n_time, total;
-  int n_chan, W, reset, sub;
+  int n_chan, W, reset, sub;   // n_chan: all channels of the launch
 };
 
 template <int P>
@@ -246,8 +278,11 @@ __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
   const int c = sgm >> 1, h = sgm & 1;
   const int km = km128(r.n0, i), kl = 64 * h + r.kl;
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
-  double2* img = reinterpret_cast<double2*>(a.image);
-  const int64_t base = (int64_t)c * NPROD * N * N + qm * N + ql;
+  int b = 0;                                 // the image of channel c
+  for (int bi = 1; bi < a.n_img; ++bi)
+    if (a.img_c0[bi] <= c) b = bi;
+  double2* img = reinterpret_cast<double2*>(a.image[b]);
+  const int64_t base = (int64_t)(c - a.img_c0[b]) * NPROD * N * N + qm * N + ql;
   double2 val[NPROD];
   val[0] = make_double2(s[0], 0.0);
   if (P == 2) {

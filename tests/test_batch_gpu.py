@@ -1,6 +1,8 @@
 """Heterogeneous batch (grids of 32^2, 64^2, 128^2; 64, 256 and 1024
 antennas) advanced together: every block against the FP64 oracle, HIP graph
-replays against the eager batch, and the autotuner's cache."""
+replays against the eager batch, the cut into grouped launches (one
+persistent launch per grid family walking all its blocks' channels), every
+launch shape the autotuner can pick, and the autotuner's cache."""
 import numpy as np
 import pytest
 
@@ -29,6 +31,22 @@ def _batch(inputs):
     ef = [torch.from_numpy(np.ascontiguousarray(i.efield)).cuda() for i in inputs]
     g = [torch.from_numpy(np.ascontiguousarray(i.gains)).cuda() for i in inputs]
     return b, ef, g
+
+
+def _check_blocks(imgs, inputs, tol=1e-5):
+    for k, inp in enumerate(inputs):
+        print(f"block {k}: N={inp.grid_n} A={inp.n_ant} C={inp.n_chan} T={inp.n_time}", flush=True)
+        err = oracle.rel_errors(imgs[k].cpu().numpy(), oracle.image_from(inp))
+        assert err.max() <= tol, f"block {k}: {err.max():.3e}"
+
+
+def test_launches_group_blocks_by_grid(batch_inputs):
+    """The six blocks form three launches (one per grid side), two blocks each."""
+    b, ef, g = _batch(batch_inputs)
+    lp = b.launch_plan()
+    print(lp, flush=True)
+    assert [x[0] for x in lp] == [0, 0, 1, 1, 2, 2]
+    assert all(x[1] == 2 for x in lp)
 
 
 def test_batch_matches_oracle(batch_inputs):
@@ -105,3 +123,74 @@ def test_full_batch_sampled_channels():
                                inp.freq_hz[c:c + 1], inp.gains[c:c + 1], inp.efield[:, c:c + 1])
             err = oracle.rel_errors(imgs[k][c:c + 1].cpu().numpy(), oracle.image_from(sub))
             assert err.max() <= 1e-5, f"block {k} channel {c}: {err.max():.3e}"
+
+
+def test_mixed_antenna_counts_share_a_launch():
+    """Blocks of one grid side with different antenna counts (one sample byte
+    per thread) share a launch: workgroups whose range crosses a block boundary
+    switch inputs, programs and the E' layout there.  T is ragged so ranges
+    start mid-channel; one block has a single channel."""
+    import torch
+    blocks = ((64, 256, 3), (64, 97, 1), (64, 200, 2), (64, 31, 2))
+    inputs = [synth.config4_block(k, n_time=13, blocks=blocks) for k in range(len(blocks))]
+    b, ef, g = _batch(inputs)
+    lp = b.launch_plan()
+    assert [x[0] for x in lp] == [0, 0, 0, 0] and lp[0][1] == 4
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    _check_blocks(imgs, inputs)
+    # continuation: reset = 0 adds the same samples again
+    b.accumulate(ef, g, imgs, reset=False)
+    torch.cuda.synchronize()
+    for k, inp in enumerate(inputs):
+        ref = 2.0 * oracle.image_from(inp)
+        assert oracle.rel_errors(imgs[k].cpu().numpy(), ref).max() <= 1e-5
+
+
+def test_ungroupable_blocks_run_alone_and_groups_hold_eight():
+    """A staged block and a block with autocorrelation removal run through
+    their own contexts; nine groupable 32 x 32 blocks form two launches."""
+    import torch
+    from paper_1904_11422_amd import Batch
+    blocks = tuple((32, 40 + 3 * k, 1 + k % 3) for k in range(9)) + ((32, 64, 2), (32, 64, 2))
+    inputs = [synth.config4_block(k, n_time=7, blocks=blocks) for k in range(len(blocks))]
+    cfgs = [dict(grid_n=i.grid_n, n_chan=i.n_chan, n_pol=i.n_pol, n_ant=i.n_ant) for i in inputs]
+    cfgs[9]["staged"] = True
+    cfgs[10]["remove_autos"] = True
+    b = Batch(cfgs)
+    for k, i in enumerate(inputs):
+        b.set_antennas(k, i.xy_m, i.freq_hz)
+    lp = b.launch_plan()
+    print(lp, flush=True)
+    assert [x[1] for x in lp[:8]] == [8] * 8 and lp[8][1] == 1
+    assert lp[9][1] == 0 and lp[10][1] == 0
+    assert len({x[0] for x in lp}) == 4
+    ef = [torch.from_numpy(np.ascontiguousarray(i.efield)).cuda() for i in inputs]
+    g = [torch.from_numpy(np.ascontiguousarray(i.gains)).cuda() for i in inputs]
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    _check_blocks(imgs[:10], inputs[:10])
+    ref = oracle.image_without_autos_from(inputs[10])
+    full = oracle.image_from(inputs[10])
+    d = imgs[10].cpu().numpy() - ref
+    for c in range(inputs[10].n_chan):
+        for pr in range(4):
+            assert np.linalg.norm(d[c, pr]) <= 1e-5 * np.linalg.norm(full[c, pr]) + 1e-9
+
+
+@pytest.mark.parametrize("shape", [(4, 128, 0), (4, 64, 1), (2, 128, 1), (1, 64, 0)])
+def test_every_tuned_shape_matches_oracle(batch_inputs, shape):
+    """Each launch shape the tuner can choose -- grid of w_cap * den / 4,
+    float32 blocks of 128 or 64 samples, XCD order on or off -- gives the
+    oracle's images."""
+    import torch
+    den, kb, xcd = shape
+    b, ef, g = _batch(batch_inputs)
+    caps = {lp[0]: grid for lp, (grid, _) in zip(b.launch_plan(), b.plan())}
+    for li, cap in caps.items():
+        b.set_launch(li, max(1, cap * den // 4), kb, xcd)
+    assert all(x[2] == kb and x[3] == xcd for x in b.launch_plan())
+    assert all(grid == max(1, caps[lp[0]] * den // 4) for lp, (grid, _) in zip(b.launch_plan(), b.plan()))
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    _check_blocks(imgs, batch_inputs)
