@@ -1,29 +1,30 @@
 // Adjoint of fused_image128_kernel: gradient of a real loss with respect to
 // the per-antenna complex gains at 128 x 128, given dL/dI.
 //
-// Work units are (channel, half, sample), as in the imager.  A unit recomputes
-// the half image F of its sample (gridding, row transforms keeping the 64
-// frequency columns of half h, column transforms), forms G = dL/dF* at its
-// pixels (Wirtinger calculus, as adjoint_kernel), and applies the adjoint of
-// that restricted transform:
+// Work units are (channel, parity, sample), as in the imager.  A unit
+// recomputes the image of its sample at the columns of parity h (gridding,
+// row transforms onto those 64 frequency columns, column transforms), forms
+// G = dL/dF* at its pixels (Wirtinger calculus, as adjoint_kernel), and
+// applies the adjoint of that restricted transform:
 //   1. column transforms with the negative exponent, from the 128 image rows
 //      of each local column back to the 64 aperture rows;  barrier;
 //   2. row transforms with the negative exponent, from the 64 frequency
-//      columns of half h (the other half's columns enter as zeros) back to
-//      the 64 aperture columns;  barrier;
+//      columns of parity h back to the 64 aperture columns (the 64-point
+//      adjoint, then the factor conj(w128^(n h)));  barrier;
 //   3. degridding: dL/dg* += sum_taps conj(w) conj(e) H_h[tap].
-// The full adjoint is the sum of the two halves' contributions (it is linear
-// in G), so a channel's per-antenna float64 sums run over both halves and all
-// samples; one slot per (workgroup, channel), reduced by reduce_grad_kernel.
+// The full adjoint is the sum of the two parities' contributions (it is
+// linear in G), so a channel's per-antenna float64 sums run over both
+// parities and all samples; one slot per (workgroup, channel), reduced by
+// reduce_grad_kernel.
 #pragma once
 #include "adjoint.hpp"
 #include "fused128.hpp"
 
 namespace epic {
 
-// The upstream gradient at the pixels of the imager's threads, per half:
+// The upstream gradient at the pixels of the imager's threads, per parity:
 // gtab[c][h][i][tid] = {Re Gxx, Re Gyy, Re h, Im h} at km = km128(n0, i),
-// kl = 64 h + kl_local (fftshifted image coordinates undone).
+// kl = kl128(h, kl_local) (fftshifted image coordinates undone).
 template <int P>
 __global__ void __launch_bounds__(256) grad_table128_kernel(GradTableArgs a) {
   constexpr int N = 128, NT = FusedShape<128>::NT, NPROD = (P == 2) ? 4 : 1;
@@ -33,7 +34,7 @@ __global__ void __launch_bounds__(256) grad_table128_kernel(GradTableArgs a) {
   const int h = (int)((idx / (16 * NT)) % 2);
   const int i = (int)((idx / NT) % 16), tid = (int)(idx % NT);
   const Roles<N> r(tid);
-  const int km = km128(r.n0, i), kl = 64 * h + r.kl;
+  const int km = km128(r.n0, i), kl = kl128(h, r.kl);
   const int pix = ((km + N / 2) % N) * N + (kl + N / 2) % N;
   const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
   float4 t;
@@ -57,13 +58,15 @@ adjoint128_kernel(AdjointArgs a) {
   constexpr int H = N / 2, NPX = 16;
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
-  constexpr int TWS = 17;
+  constexpr int TWS = 17, TW64S = 9;
   // the LDS layout of fused_image128_kernel
-  __shared__ float2 lds2[P * ES + (P - 1) * PS + H * RS + R * TWS];
+  __shared__ float2 lds2[P * ES + (P - 1) * PS + H * RS + R * TWS + R * TW64S + H];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
   float2* TW = X + (P - 1) * PS + H * RS;
+  float2* TW64 = TW + R * TWS;
+  float2* ODD = TW64 + R * TW64S;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -72,7 +75,10 @@ adjoint128_kernel(AdjointArgs a) {
   if (fb >= fe) return;
 
   if (tid < R * S) TW[(tid / S) * TWS + tid % S] = a.twiddle[((tid / S) * (tid % S)) % N];
+  if (tid < R * 8) TW64[(tid / 8) * TW64S + tid % 8] = a.twiddle[(2 * (tid / 8) * (tid % 8)) % N];
+  if (tid < H) ODD[tid] = a.twiddle[tid];
   const float2* tw = TW + r.n0 * TWS;          // read after the first barrier
+  const float2* tw64 = TW64 + r.n0 * TW64S;
 
   const int PA = P * a.n_ant;
   const int64_t row_bytes = (int64_t)a.n_chan * PA;
@@ -129,35 +135,31 @@ adjoint128_kernel(AdjointArgs a) {
     if (tt == a.n_time) { tt = 0; ++sg; }
     if (left > 1) load_bytes(sg, tt, nxt);
 
-    // forward: stage and grid the aperture, row transforms keeping half h
+    // forward: stage and grid the aperture, row transforms onto the columns
+    // of parity h (as fused_image128_kernel)
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
     const int rb = (line & 0xFFFF) * RS;
     if (line >= 0) {
-      float2 v[P][S];
+      float2 v[P][8];
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
-      line_transform<N, +1, P, true>(v, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
+        for (int n1 = 0; n1 < 8; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
       if (h) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + 4 + k];
-      } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + k];
+          for (int n1 = 0; n1 < 8; ++n1) v[p][n1] = cmul(v[p][n1], ODD[R * n1 + r.n0]);
       }
+      line_transform<64, +1, P>(v, tw64, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) X[p * PS + rb + r.n0 + 8 * k1] = v[p][k1];
     }
     __syncthreads();
 
-    // forward column transforms of local column kl: v[p][q R + k1] = F_p[2 n0 + q + 16 k1][64 h + kl]
+    // forward column transforms of local column kl: v[p][q R + k1] = F_p[2 n0 + q + 16 k1][2 kl + h]
     const int kl = r.kl;
     auto colslot = [kl](int p, int s) { return p * PS + (s & 63) * RS + kl + (s & 64); };
     float2 v[P][S];
@@ -194,35 +196,26 @@ adjoint128_kernel(AdjointArgs a) {
     __syncthreads();
 
     // 2. adjoint row transforms of row `line`: its 64 local values are the
-    //    frequencies 64 h + (2 n0 + q + 16 k) of the forward's output layout,
-    //    the other half's are zero; keep the aperture columns 8 n1 + n0 < 64
+    //    frequencies 2 m + h, m = n0 + 8 k1 in the forward's output layout;
+    //    the 64-point adjoint gives the aperture columns n = 8 n1 + n0, then
+    //    the odd parity's factor conj(w128^n)
     if (line >= 0) {
-      float2 u[P][S];
-      // (h is uniform over the workgroup: a branch, not a per-value select)
+      float2 u[P][8];
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int i = 0; i < S; ++i) u[p][i] = make_float2(0.f, 0.f);
+        for (int k1 = 0; k1 < 8; ++k1) u[p][k1] = X[p * PS + rb + r.n0 + 8 * k1];
+      line_transform_rev<64, -1, P>(u, tw64, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
       if (h) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[p][q * R + 4 + k] = X[p * PS + rb + 2 * r.n0 + q + 16 * k];
-      } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) u[p][q * R + k] = X[p * PS + rb + 2 * r.n0 + q + 16 * k];
+          for (int n1 = 0; n1 < 8; ++n1) u[p][n1] = cmulc(u[p][n1], ODD[R * n1 + r.n0]);
       }
-      line_transform_rev<N, -1, P>(u, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int n1 = 0; n1 < S / 2; ++n1) X[p * PS + rb + R * n1 + r.n0] = u[p][n1];
+        for (int n1 = 0; n1 < 8; ++n1) X[p * PS + rb + R * n1 + r.n0] = u[p][n1];
     }
     __syncthreads();
 

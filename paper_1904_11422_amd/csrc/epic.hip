@@ -1900,7 +1900,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   DeviceGuard guard(x->device);
   if (!x->fused) return staged_backward(x, efield, n_time, gains, grad_image, grad_gains);
   const int C = x->cfg.n_chan;
-  // work units per channel: samples, or (half, sample) pairs at N = 128
+  // work units per channel: samples, or (parity, sample) pairs at N = 128
   const int64_t upc = x->cfg.grid_n == 128 ? 2 * n_time : n_time;
   const int64_t total = (int64_t)C * upc;
   (void)hipGetLastError();

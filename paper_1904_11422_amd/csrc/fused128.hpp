@@ -4,24 +4,30 @@
 //
 // With two polarisations the 64 x 64 aperture block fills most of the LDS,
 // and the float32 sums of all 128 x 128 pixels would not fit the registers of
-// one workgroup.  So a workgroup of 512 threads images one half of the output
-// columns of a sample, kl in [64 h, 64 h + 64):
+// one workgroup.  So a workgroup of 512 threads images the output columns of
+// one parity h of a sample, kl = 2 m + h (m < 64):
 //   1. unpack + gain, barrier, gridding of the whole aperture (wave-local rows,
 //      as fused_image_kernel);
 //   2. row transforms: a group of 8 lanes takes one aperture row of every
-//      polarisation (16-point first pass with half of its inputs zero, one
-//      exchange through the row's 128 slots, two 8-point passes) and writes
-//      the 64 outputs of half h back to the row's first 64 columns;  barrier;
-//   3. column transforms: a group of 8 lanes takes one local column of every
-//      polarisation, exchanging through the column's 64 aperture rows and the
-//      same rows' upper 64 columns; every lane then holds F_X (and F_Y) of 16
-//      pixels;
-//   4. XX (and YY, Re XY, Im XY) into float32 sums, added every 128 samples
+//      polarisation.  The row has 64 nonzero cells x[n], so its 128-point
+//      transform at the columns of parity h is the 64-point transform of
+//      x[n] w128^(n h):  X[2 m + h] = sum_n x[n] w128^(n h) w64^(n m).  A
+//      radix-8 x 8 line transform writes the 64 values back to the row's
+//      first 64 slots;  barrier;
+//   3. column transforms: a group of 8 lanes takes one local column m of every
+//      polarisation (128 points, the 64 aperture rows nonzero), exchanging
+//      through the column's 64 aperture rows and the same rows' upper 64
+//      columns; every lane then holds F_X (and F_Y) of 16 pixels;
+//   4. XX (and YY, Re XY, Im XY) into float32 sums, added every KBLOCK samples
 //      and at a segment boundary into the workgroup's float64 slot.
+// Splitting the columns by parity instead of into two contiguous halves makes
+// the two units' row transforms together cost one 128-point transform of the
+// row: every row value is computed once per sample.  The gridding is still
+// done by both units.
 // One polarisation uses the same split: half the LDS (two workgroups per CU)
 // and a quarter of the sums.
-// Work units are (channel, half, sample), flattened as ((2 c + h) T + t); a
-// (channel, half) pair is one accumulation segment.
+// Work units are (channel, parity, sample), flattened as ((2 c + h) T + t); a
+// (channel, parity) pair is one accumulation segment.
 #pragma once
 #include "fused.hpp"
 
@@ -36,6 +42,9 @@ __host__ __device__ __forceinline__ int km128(int n0, int i) {
   return 2 * n0 + (i >> 3) + 16 * (i & 7);
 }
 
+// Image column of local column m of the unit of parity h.
+__host__ __device__ __forceinline__ int kl128(int h, int m) { return 2 * m + h; }
+
 // Two polarisations: one workgroup per CU (LDS), registers up to 256; one
 // polarisation: two workgroups per CU, so at most 128 VGPRs.
 template <int P> struct Fused128Waves { static constexpr int value = P == 2 ? 2 : 4; };
@@ -49,14 +58,18 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   // E'[p][a] (zero slots at a = A .. A+15), the grid (64 rows per
-  // polarisation), then the twiddles w^(n0 k0) of the 8 lane roles n0, rows of
-  // 17 so that the roles of a half-wave read distinct banks
-  constexpr int TWS = 17;
-  __shared__ float2 lds2[P * ES + (P - 1) * PS + H * RS + R * TWS];
+  // polarisation), then the twiddles w128^(n0 k0) of the 8 lane roles n0 in
+  // rows of 17 (the roles of a half-wave read distinct banks), the twiddles
+  // w64^(n0 k0) = w128^(2 n0 k0) in rows of 9, and w128^n (n < 64), the
+  // factor of the odd columns' row transform
+  constexpr int TWS = 17, TW64S = 9;
+  __shared__ float2 lds2[P * ES + (P - 1) * PS + H * RS + R * TWS + R * TW64S + H];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
   float2* TW = X + (P - 1) * PS + H * RS;
+  float2* TW64 = TW + R * TWS;
+  float2* ODD = TW64 + R * TW64S;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -66,7 +79,10 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   if (fb >= fe) return;
 
   if (tid < R * S) TW[(tid / S) * TWS + tid % S] = a.twiddle[((tid / S) * (tid % S)) % N];
+  if (tid < R * 8) TW64[(tid / 8) * TW64S + tid % 8] = a.twiddle[(2 * (tid / 8) * (tid % 8)) % N];
+  if (tid < H) ODD[tid] = a.twiddle[tid];
   const float2* tw = TW + r.n0 * TWS;          // read after the first barrier
+  const float2* tw64 = TW64 + r.n0 * TW64S;
 
   int64_t sg = fb / a.n_time;                  // segment 2 c + h of the current unit
   int64_t tt = fb - sg * a.n_time;
@@ -162,34 +178,29 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
     }
     if (left > 1) load_bytes(sg, tt, nxt);
 
-    // 1. stage and grid the aperture (both halves grid the whole aperture)
+    // 1. stage and grid the aperture (both parities grid the whole aperture)
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
-    // 2. row transforms of row `line` of both polarisations; keep half h
+    // 2. row transforms of row `line` of both polarisations onto the
+    //    columns of parity h (h is uniform over the workgroup)
     if (line >= 0) {
       const int rb = (line & 0xFFFF) * RS;
-      float2 v[P][S];
+      float2 v[P][8];
 #pragma unroll
       for (int p = 0; p < P; ++p)
 #pragma unroll
-        for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
-      line_transform<N, +1, P, true>(v, tw, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
-      // v[p][q R + k1] = X_p[2 n0 + q + 16 k1]; half h holds k1 in [4 h, 4 h + 4)
-      // (h is uniform over the workgroup: a branch, not a per-value select)
+        for (int n1 = 0; n1 < 8; ++n1) v[p][n1] = X[p * PS + rb + R * n1 + r.n0];
       if (h) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + 4 + k];
-      } else {
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) X[p * PS + rb + 2 * r.n0 + q + 16 * k] = v[p][q * R + k];
+          for (int n1 = 0; n1 < 8; ++n1) v[p][n1] = cmul(v[p][n1], ODD[R * n1 + r.n0]);
       }
+      line_transform<64, +1, P>(v, tw64, r.n0, X, [rb](int p, int s) { return p * PS + rb + s; });
+      // v[p][k1] = X_p[2 (n0 + 8 k1) + h]
+#pragma unroll
+      for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) X[p * PS + rb + r.n0 + 8 * k1] = v[p][k1];
     }
     __syncthreads();
 
@@ -202,7 +213,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
       for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + (R * n1 + r.n0) * RS + kl];
     line_transform<N, +1, P, true>(v, tw, r.n0, X,
                                    [kl](int p, int s) { return p * PS + (s & 63) * RS + kl + (s & 64); });
-    // v[p][q R + k1] = F_p[2 n0 + q + 16 k1][64 h + kl]
+    // v[p][q R + k1] = F_p[2 n0 + q + 16 k1][2 kl + h]
 
     // 4. products of the 16 pixels: XX (, YY, Re XY, Im XY; XY = F_X conj(F_Y))
 #pragma unroll
@@ -236,7 +247,7 @@ fused_multi_image128_kernel(FusedArgs a) {
 }
 
 // image[c][prod][qm][ql] (+)= sum of the slots of segment 2 c + h, for the
-// pixels of half h; sub-lanes as reduce_image_kernel.
+// pixels of columns of parity h; sub-lanes as reduce_image_kernel.
 struct Reduce128Args {
   const double* partial;
   // complex128 [C_b][NPROD][128][128] per block of the launch (as ReduceArgs)
@@ -249,7 +260,7 @@ struct Reduce128Args {
 
 template <int P>
 __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
-  constexpr int N = 128, NT = FusedShape<128>::NT, NLOC = 16 * NT;   // local pixels per half
+  constexpr int N = 128, NT = FusedShape<128>::NT, NLOC = 16 * NT;   // local pixels per parity
   constexpr int NACC = P == 2 ? 4 : 1, NPROD = P == 2 ? 4 : 1;
   __shared__ double red[NACC * 256];
   const int ppb = 256 / a.sub;
@@ -276,7 +287,7 @@ __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
   const int tid = pix % NT, i = pix / NT;
   const Roles<N> r(tid);
   const int c = sgm >> 1, h = sgm & 1;
-  const int km = km128(r.n0, i), kl = 64 * h + r.kl;
+  const int km = km128(r.n0, i), kl = kl128(h, r.kl);
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
   int b = 0;                                 // the image of channel c
   for (int bi = 1; bi < a.n_img; ++bi)
