@@ -381,9 +381,10 @@ epic_status epic_batch_capture(epic_batch *b, const uint8_t *const *efields, int
 epic_status epic_batch_replay(epic_batch *b);
 
 /* Autotune the launch shapes on these inputs -- for a grouped launch its
- * persistent grid size (samples per workgroup), the float32 block length
- * before a float64 flush (128 or 64 samples) and whether consecutive
- * workgroup ranges are dealt to one XCD; for a single block its context's
+ * persistent grid size (samples per workgroup), its team size (time chunk:
+ * the workgroups that share each channel's samples), the float32 block
+ * length before a float64 flush (128 or 64 samples) and whether a team's
+ * workgroups are dealt to one XCD; for a single block its context's
  * grid or staged sample batch -- and whether the launches run concurrently
  * or one after another: runs and times each launch alone and the whole
  * batch (overwriting images), or, when
@@ -403,20 +404,24 @@ epic_status epic_batch_plan(const epic_batch *b, int32_t block, int32_t *grid,
 
 /* Which launch images a block and its tuned shape: launch = index of the
  * launch, n_blocks = blocks that launch walks (0: the block runs alone
- * through its context), kblock = samples summed in float32 before a float64
- * flush, xcd = 1 if consecutive workgroup ranges share an XCD.  Errors:
- * EPIC_E_INVALID (no such block), EPIC_E_STATE (launches not cut yet). */
+ * through its context), team = workgroups that share each channel's samples
+ * (each taking T / team of them; 0: chosen from T), kblock = samples summed
+ * in float32 before a float64 flush, xcd = 1 if a team's workgroups share an
+ * XCD.  Errors: EPIC_E_INVALID (no such block), EPIC_E_STATE (launches not
+ * cut yet). */
 epic_status epic_batch_launch_plan(const epic_batch *b, int32_t block, int32_t *launch,
-                                   int32_t *n_blocks, int32_t *kblock, int32_t *xcd);
+                                   int32_t *n_blocks, int32_t *team, int32_t *kblock,
+                                   int32_t *xcd);
 
 /* Set a grouped launch's shape by hand (as epic_batch_tune would): grid =
  * persistent workgroups (0: as many as stay resident; larger values are
- * capped there), kblock = float32 block length in samples (1 .. 128), xcd
- * != 0: consecutive workgroup ranges on one XCD.  Applies to later
- * accumulate and capture calls.  Errors: EPIC_E_INVALID (no such launch, bad
- * values), EPIC_E_UNSUPPORTED (a block running alone). */
-epic_status epic_batch_set_launch(epic_batch *b, int32_t launch, int32_t grid, int32_t kblock,
-                                  int32_t xcd);
+ * capped there, and rounded down to whole teams), team = 0 (from T), 1, 2, 4
+ * or 8, kblock = float32 block length in samples (1 .. 128), xcd != 0: a
+ * team's workgroups on one XCD.  Applies to later accumulate and capture
+ * calls.  Errors: EPIC_E_INVALID (no such launch, bad values),
+ * EPIC_E_UNSUPPORTED (a block running alone). */
+epic_status epic_batch_set_launch(epic_batch *b, int32_t launch, int32_t grid, int32_t team,
+                                  int32_t kblock, int32_t xcd);
 
 /* 1 if the launches of b run one after another (each persistent launch with
  * the whole GPU), 0 if they run concurrently on their own streams; set by

@@ -412,18 +412,20 @@ class Batch:
             out.append((gsz.value, tb.value))
         return out
 
-    def set_launch(self, launch: int, grid: int, kblock: int = 128, xcd: bool = False):
-        """Shape of grouped launch `launch` by hand (grid 0: the resident maximum)."""
+    def set_launch(self, launch: int, grid: int, team: int = 0, kblock: int = 128, xcd: bool = True):
+        """Shape of grouped launch `launch` by hand (grid 0: the resident
+        maximum; team 0: chosen from the number of samples)."""
         _lib.check_batch(self.L, self._b, self.L.epic_batch_set_launch(self._b, int(launch), int(grid),
-                                                                       int(kblock), 1 if xcd else 0))
+                                                                       int(team), int(kblock),
+                                                                       1 if xcd else 0))
 
     def launch_plan(self):
         """Per block: (launch index, blocks that launch walks -- 0 when the
-        block runs alone through its context --, float32 block length, XCD
-        order flag)."""
+        block runs alone through its context --, team size, float32 block
+        length, XCD order flag)."""
         out = []
         for i in range(self.n_blocks):
-            v = [ctypes.c_int32() for _ in range(4)]
+            v = [ctypes.c_int32() for _ in range(5)]
             _lib.check_batch(self.L, self._b,
                              self.L.epic_batch_launch_plan(self._b, i, *[ctypes.byref(x) for x in v]))
             out.append(tuple(x.value for x in v))

@@ -108,9 +108,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_batch_tune.restype = ctypes.c_int
     L.epic_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.epic_batch_plan.restype = ctypes.c_int
-    L.epic_batch_launch_plan.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 4
+    L.epic_batch_launch_plan.argtypes = [vp, i32] + [ctypes.POINTER(i32)] * 5
     L.epic_batch_launch_plan.restype = ctypes.c_int
-    L.epic_batch_set_launch.argtypes = [vp, i32, i32, i32, i32]
+    L.epic_batch_set_launch.argtypes = [vp, i32, i32, i32, i32, i32]
     L.epic_batch_set_launch.restype = ctypes.c_int
     L.epic_batch_serial.argtypes = [vp]
     L.epic_batch_serial.restype = i32

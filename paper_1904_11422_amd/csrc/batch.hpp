@@ -36,10 +36,11 @@ struct BatchLaunch {
   bool wide = false;
   int C = 0;                          // channels of all its blocks
   int w_cap = 0;                      // persistent workgroups (occupancy x CUs)
-  DevMem partial;                     // grouped: the partial-image slots of w_cap
+  DevMem partial;                     // grouped: the partial-image slots of w_cap, teams up to kMaxTeam
   int W = 0;                          // tuned grid (0: w_cap)
+  int team = 0;                       // tuned team size (0: by n_time)
   int kblock = epic::FusedShape<64>::KBLOCK;
-  int xcd = 0;
+  int xcd = 1;
 };
 
 struct epic_batch {
@@ -153,9 +154,9 @@ epic_status batch_plan_launches(epic_batch* b) {
     if (bpc <= 0) return b->fail(EPIC_E_UNSUPPORTED, "no multi-block kernel for a group of the batch");
     L->w_cap = bpc * b->ctx[L->blocks[0]]->n_cu;
     const int nacc = L->P == 2 ? 4 : 1;
-    const size_t segs = L->N == 128 ? 2 * (size_t)L->C : (size_t)L->C;
-    const size_t per_slot = L->N == 128 ? (size_t)nacc * L->N * L->N / 2 : (size_t)nacc * L->N * L->N;
-    if (!L->partial.alloc(((size_t)L->w_cap + segs - 1) * per_slot * sizeof(double)))
+    const int64_t segs = L->N == 128 ? 2 * (int64_t)L->C : (int64_t)L->C;
+    const size_t slots = (size_t)max_slot_count(segs, L->w_cap);
+    if (!L->partial.alloc(slots * fused_slot_values(L->N, nacc) * sizeof(double)))
       return b->fail(EPIC_E_NOMEM, "batch partial-image workspace allocation failed");
   }
   return EPIC_OK;
@@ -189,11 +190,14 @@ epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, co
   const int64_t total = (int64_t)L.C * n_time;
   a.total = L.N == 128 ? 2 * total : total;
   const int w_max = L.W > 0 ? std::min(L.W, L.w_cap) : L.w_cap;
-  a.W = (int)std::min<int64_t>(w_max, a.total);
+  const int w0 = (int)std::min<int64_t>(w_max, a.total);
+  a.team = team_for(n_time, L.team);
+  while (a.team > 1 && a.team > w0) a.team /= 2;
+  a.W = (w0 / a.team) * a.team;
   a.kblock = L.kblock;
   a.xcd = L.xcd;
   if (!launch_multi(L, dim3(a.W), s, a)) return b->fail(EPIC_E_UNSUPPORTED, "no multi-block kernel");
-  const int sub = reduce_sub(slots_per_channel(n_time, a.total, a.W));
+  const int sub = fused_reduce_sub(n_time, a.total, a.W, a.team);
   const int64_t n = (int64_t)L.C * L.N * L.N, ppb = 256 / sub;
   const dim3 rgrid((unsigned)((n + ppb - 1) / ppb)), rblock(256);
   if (L.N == 128) {
@@ -208,6 +212,8 @@ epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, co
     r.total = a.total;
     r.n_chan = L.C;
     r.W = a.W;
+    r.team = a.team;
+    r.kblock = a.kblock;
     r.reset = reset ? 1 : 0;
     r.sub = sub;
     if (L.P == 2) hipLaunchKernelGGL(epic::reduce_image128_kernel<2>, rgrid, rblock, 0, s, r);
@@ -224,6 +230,9 @@ epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, co
     r.total = a.total;
     r.n_chan = L.C;
     r.W = a.W;
+    r.team = a.team;
+    r.kblock = a.kblock;
+    r.f32 = 1;
     r.reset = reset ? 1 : 0;
     r.sub = sub;
     r.autos = nullptr;
@@ -309,7 +318,7 @@ float time_on(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, F fn) {
 
 std::string batch_key(const epic_batch* b, int64_t n_time) {
   std::ostringstream k;
-  k << "gfx950 v4 T=" << n_time;
+  k << "gfx950 v5 T=" << n_time;
   for (const epic_ctx* x : b->ctx)
     k << " [N=" << x->cfg.grid_n << ",P=" << x->cfg.n_pol << ",A=" << x->cfg.n_ant << ",C="
       << x->cfg.n_chan << ",prec=" << x->cfg.precision << ",flags=" << x->cfg.flags
@@ -317,15 +326,16 @@ std::string batch_key(const epic_batch* b, int64_t n_time) {
   return k.str();
 }
 
-// Launch shape of one launch: grouped {W, kblock, xcd}, single block {W, tb}.
+// Launch shape of one launch: grouped {W, team, kblock, xcd}, single block {W, tb}.
 struct LaunchShape {
-  int W = 0, kblock = epic::FusedShape<64>::KBLOCK, xcd = 0, tb = 0;
+  int W = 0, kblock = epic::FusedShape<64>::KBLOCK, xcd = 1, tb = 0, team = 0;
 };
 
 void apply_shape(epic_batch* b, size_t li, const LaunchShape& sh) {
   BatchLaunch& L = *b->launches[li];
   if (L.grouped) {
     L.W = sh.W;
+    L.team = sh.team;
     L.kblock = sh.kblock;
     L.xcd = sh.xcd;
   } else {
@@ -481,8 +491,8 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
       int serial = 0;
       if (!(vals >> serial)) continue;
       LaunchShape sh;
-      char c1 = 0, c2 = 0, c3 = 0;
-      while (vals >> sh.W >> c1 >> sh.kblock >> c2 >> sh.xcd >> c3 >> sh.tb) plan.push_back(sh);
+      char c1 = 0, c2 = 0, c3 = 0, c4 = 0;
+      while (vals >> sh.W >> c1 >> sh.kblock >> c2 >> sh.xcd >> c3 >> sh.tb >> c4 >> sh.team) plan.push_back(sh);
       if (plan.size() == nl) {
         apply(plan);
         b->serial = serial != 0;
@@ -499,15 +509,23 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
     const hipStream_t st = b->streams[L.blocks[0]];
     std::vector<LaunchShape> cands;
     if (L.grouped) {
-      for (int den : {4, 3, 2, 1})        // grid of w_cap * den / 4: samples per workgroup
-        for (int kb : {epic::FusedShape<64>::KBLOCK, epic::FusedShape<64>::KBLOCK / 2})
-          for (int xcd : {0, 1}) {
-            LaunchShape sh;
-            sh.W = std::max(1, L.w_cap * den / 4);
-            sh.kblock = kb;
-            sh.xcd = xcd;
-            cands.push_back(sh);
-          }
+      // samples per workgroup (grid w_cap den / 4) x time chunk (team: parts
+      // of T / team samples; 0 = the smallest team with parts <= 128), then
+      // the float32 block length and the XCD order at the default shape
+      for (int den : {4, 3, 2, 1})
+        for (int team : {0, 1, 2, 4, 8}) {
+          LaunchShape sh;
+          sh.W = std::max(1, L.w_cap * den / 4);
+          sh.team = team;
+          cands.push_back(sh);
+        }
+      LaunchShape sh;
+      sh.W = L.w_cap;
+      sh.kblock = epic::FusedShape<64>::KBLOCK / 2;
+      cands.push_back(sh);
+      sh.kblock = epic::FusedShape<64>::KBLOCK;
+      sh.xcd = 0;
+      cands.push_back(sh);
     } else {
       const epic_ctx* x = b->ctx[L.blocks[0]];
       if (x->fused) {
@@ -585,7 +603,7 @@ epic_status epic_batch_tune(epic_batch* b, const uint8_t* const* efields, int64_
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);
     out << key << " => " << (chosen_serial ? 1 : 0);
-    for (const auto& p : chosen) out << " " << p.W << "," << p.kblock << "," << p.xcd << "," << p.tb;
+    for (const auto& p : chosen) out << " " << p.W << "," << p.kblock << "," << p.xcd << "," << p.tb << "," << p.team;
     out << "\n";
   }
   return EPIC_OK;
@@ -606,13 +624,14 @@ epic_status epic_batch_plan(const epic_batch* b, int32_t block, int32_t* grid, i
 }
 
 epic_status epic_batch_launch_plan(const epic_batch* b, int32_t block, int32_t* launch, int32_t* n_blocks,
-                                   int32_t* kblock, int32_t* xcd) {
+                                   int32_t* team, int32_t* kblock, int32_t* xcd) {
   if (!b || block < 0 || block >= (int32_t)b->ctx.size()) return EPIC_E_INVALID;
   for (size_t li = 0; li < b->launches.size(); ++li) {
     const BatchLaunch& L = *b->launches[li];
     if (std::find(L.blocks.begin(), L.blocks.end(), block) == L.blocks.end()) continue;
     if (launch) *launch = (int32_t)li;
     if (n_blocks) *n_blocks = L.grouped ? (int32_t)L.blocks.size() : 0;
+    if (team) *team = L.grouped ? L.team : 0;
     if (kblock) *kblock = L.grouped ? L.kblock : epic::FusedShape<64>::KBLOCK;
     if (xcd) *xcd = L.grouped ? L.xcd : 0;
     return EPIC_OK;
@@ -620,14 +639,17 @@ epic_status epic_batch_launch_plan(const epic_batch* b, int32_t block, int32_t* 
   return EPIC_E_STATE;
 }
 
-epic_status epic_batch_set_launch(epic_batch* b, int32_t launch, int32_t grid, int32_t kblock, int32_t xcd) {
+epic_status epic_batch_set_launch(epic_batch* b, int32_t launch, int32_t grid, int32_t team, int32_t kblock,
+                                  int32_t xcd) {
   if (!b) return EPIC_E_INVALID;
   if (launch < 0 || launch >= (int32_t)b->launches.size()) return b->fail(EPIC_E_INVALID, "no such launch");
   BatchLaunch& L = *b->launches[launch];
   if (!L.grouped) return b->fail(EPIC_E_UNSUPPORTED, "a block running alone has no grouped launch shape");
-  if (grid < 0 || kblock < 1 || kblock > epic::FusedShape<64>::KBLOCK)
-    return b->fail(EPIC_E_INVALID, "grid must be >= 0 and kblock in 1..128");
+  if (grid < 0 || kblock < 1 || kblock > epic::FusedShape<64>::KBLOCK ||
+      !(team == 0 || team == 1 || team == 2 || team == 4 || team == 8))
+    return b->fail(EPIC_E_INVALID, "grid must be >= 0, team 0, 1, 2, 4 or 8 and kblock in 1..128");
   L.W = grid;
+  L.team = team;
   L.kblock = kblock;
   L.xcd = xcd ? 1 : 0;
   return EPIC_OK;

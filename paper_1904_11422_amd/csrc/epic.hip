@@ -126,6 +126,7 @@ struct epic_ctx {
   int fused_gpt = 1;
   int fused_w = 0;                    // persistent workgroups (upper bound)
   int w_override = 0;                 // tuned grid size (0: fused_w)
+  int team_override = 0;              // team size of the fused imaging launch (0: by n_time)
   int tb_override = 0;                // tuned staged batch (0: tb)
   int adj_w = 0;
   const char* last_kernel = "none";
@@ -813,6 +814,38 @@ int64_t slots_per_channel(int64_t n_time, int64_t total, int64_t W) {
   return (n_time * W + total - 1) / total + 1;
 }
 
+// Teams of the fused imaging launches (FusedArgs): the smallest power of two
+// that cuts a segment of n_time units into member parts of at most KBLOCK
+// units, at most kMaxTeam; `over` > 0 replaces it (a power of two <= kMaxTeam).
+constexpr int kMaxTeam = 8;
+int team_for(int64_t n_time, int over) {
+  if (over > 0) return over;
+  int m = 1;
+  while (m < kMaxTeam && (n_time + m - 1) / m > epic::FusedShape<64>::KBLOCK) m *= 2;
+  return m;
+}
+
+// Partial-image slots of a fused launch of W workgroups in teams of m over
+// segs segments: (segs + W / m - 1) m.
+int64_t slot_count(int64_t segs, int64_t W, int64_t m) { return (segs + W / m - 1) * m; }
+
+// The most slots any team size gives a launch of at most w_cap workgroups.
+int64_t max_slot_count(int64_t segs, int64_t w_cap) {
+  int64_t n = 0;
+  for (int m = 1; m <= kMaxTeam; m *= 2)
+    if (w_cap >= m) n = std::max(n, slot_count(segs, (w_cap / m) * m, m));
+  return n;
+}
+
+// float64 values per slot: NACC N^2 (N <= 64) or NACC N^2 / 2 (one parity at N = 128).
+size_t fused_slot_values(int N, int nacc) { return (size_t)nacc * N * N / (N == 128 ? 2 : 1); }
+
+// Sub-lanes of the fused reductions: parts per segment are about m times the
+// teams covering it.
+int fused_reduce_sub(int64_t n_time, int64_t units, int W, int m) {
+  return reduce_sub(slots_per_channel(n_time, units, W / m) * m);
+}
+
 bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {
   const int N = x->cfg.grid_n, P = x->cfg.n_pol;
   const int64_t n = (int64_t)x->cfg.n_chan * N * N;
@@ -1276,47 +1309,49 @@ epic::FusedArgs single_block_args(const epic_ctx* x, const uint8_t* efield, cons
   a.n_time = n_time;
   a.total = (int64_t)x->cfg.n_chan * n_time;
   a.kblock = epic::FusedShape<64>::KBLOCK;
-  a.xcd = 0;
+  a.xcd = 1;
   return a;
 }
 
-// Persistent grid of the fused imaging kernels for n_time samples, and the
-// bytes of partial-image slots that grid writes.
+// Persistent grid of the fused imaging kernels for n_time samples: W
+// workgroups in teams of `team` (FusedArgs), and the bytes of partial-image
+// slots that grid writes.  max_team caps the team (the no-allocation call
+// lowers it until the slots fit its array).
 struct FusedGrid {
-  int W;
+  int W, team;
   size_t slot_bytes;
 };
 
-FusedGrid fused_grid(const epic_ctx* x, int64_t n_time) {
+FusedGrid fused_grid(const epic_ctx* x, int64_t n_time, int max_team = kMaxTeam) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan;
-  const int64_t total = (int64_t)C * n_time;
+  const int64_t segs = N == 128 ? 2 * (int64_t)C : (int64_t)C;
+  const int64_t units = segs * n_time;
+  int w_cap;
+  if (N == 128) w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
+  else w_cap = x->wide ? (x->cpx ? x->fused_w_wide_cpx : x->fused_w_wide) : (x->cpx ? x->fused_w_cpx : x->fused_w);
+  const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
+  const int w0 = (int)std::min<int64_t>(w_max, units);
   FusedGrid g;
-  if (N == 128) {
-    const int w_cap = x->cpx ? x->fused_w_cpx : x->fused_w;
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
-    g.W = (int)std::min<int64_t>(w_max, 2 * total);
-    g.slot_bytes = ((size_t)g.W + 2 * (size_t)C - 1) * x->nacc * N * N / 2 * sizeof(double);
-  } else {
-    const int w_cap = x->wide ? (x->cpx ? x->fused_w_wide_cpx : x->fused_w_wide)
-                              : (x->cpx ? x->fused_w_cpx : x->fused_w);
-    const int w_max = x->w_override > 0 ? std::min(x->w_override, w_cap) : w_cap;
-    g.W = (int)std::min<int64_t>(w_max, total);
-    g.slot_bytes = ((size_t)g.W + (size_t)C - 1) * x->nacc * N * N * sizeof(double);
-  }
+  g.team = std::min(team_for(n_time, x->team_override), max_team);
+  while (g.team > 1 && g.team > w0) g.team /= 2;
+  g.W = (w0 / g.team) * g.team;
+  g.slot_bytes = (size_t)slot_count(segs, g.W, g.team) * fused_slot_values(N, x->nacc) * sizeof(double);
   return g;
 }
 
 // partial: the fused kernels' partial-image slots (the context's workspace,
 // or the static scratch of the no-allocation call); unused on the staged path.
 epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const float* gains,
-                     double* image, int32_t reset, double* partial) {
+                     double* image, int32_t reset, double* partial, int max_team = kMaxTeam) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
   const int64_t total = (int64_t)C * n_time;
   if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
   if (x->fused && N == 128) {
     epic::FusedArgs a = single_block_args(x, efield, gains, partial, n_time);
     a.total = 2 * total;
-    a.W = fused_grid(x, n_time).W;
+    const FusedGrid fg = fused_grid(x, n_time, max_team);
+    a.W = fg.W;
+    a.team = fg.team;
     if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image128_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
@@ -1329,8 +1364,10 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.total = a.total;
     r.n_chan = C;
     r.W = a.W;
+    r.team = a.team;
+    r.kblock = a.kblock;
     r.reset = reset ? 1 : 0;
-    r.sub = reduce_sub(slots_per_channel(n_time, a.total, a.W));
+    r.sub = fused_reduce_sub(n_time, a.total, a.W, a.team);
     const int64_t n = (int64_t)C * N * N, ppb = 256 / r.sub;
     if (P == 2)
       hipLaunchKernelGGL(epic::reduce_image128_kernel<2>, dim3((unsigned)((n + ppb - 1) / ppb)), dim3(256), 0,
@@ -1340,7 +1377,9 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
                          x->stream, r);
   } else if (x->fused) {
     epic::FusedArgs a = single_block_args(x, efield, gains, partial, n_time);
-    a.W = fused_grid(x, n_time).W;
+    const FusedGrid fg = fused_grid(x, n_time, max_team);
+    a.W = fg.W;
+    a.team = fg.team;
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = x->wide ? "fused_wide_image_kernel" : "fused_image_kernel";
     if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
@@ -1353,8 +1392,11 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.total = total;
     r.n_chan = C;
     r.W = a.W;
+    r.team = a.team;
+    r.kblock = a.kblock;
+    r.f32 = 1;
     r.reset = reset ? 1 : 0;
-    r.sub = reduce_sub(slots_per_channel(n_time, total, a.W));
+    r.sub = fused_reduce_sub(n_time, total, a.W, a.team);
     r.autos = nullptr;
     r.K = x->cfg.kernel_support;
     r.autos_cpx = x->cpx ? 1 : 0;
@@ -1419,6 +1461,9 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.total = total;
     r.n_chan = C;
     r.W = 1;
+    r.team = 1;
+    r.kblock = epic::FusedShape<64>::KBLOCK;
+    r.f32 = 0;
     r.reset = reset ? 1 : 0;
     r.sub = 1;
     r.autos = nullptr;
@@ -1619,10 +1664,11 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
       x->fused_w_wide = std::min(x->fused_w, fused_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, false) * x->n_cu);
       x->fused_w_wide_cpx = std::min(x->fused_w, fused_wide_blocks_per_cu(cfg->n_pol, x->fused_gpt, true) * x->n_cu);
     }
-    // N = 128: two accumulation segments (column halves) per channel
-    const size_t segs = N == 128 ? 2 * (size_t)cfg->n_chan : (size_t)cfg->n_chan;
-    const size_t slots = (size_t)x->fused_w + segs - 1;
-    const size_t per_slot = N == 128 ? (size_t)x->nacc * N * N / 2 : (size_t)x->nacc * N * N;
+    // N = 128: two accumulation segments (column parities) per channel; slots
+    // for the largest team (FusedArgs)
+    const int64_t segs = N == 128 ? 2 * (int64_t)cfg->n_chan : (int64_t)cfg->n_chan;
+    const size_t slots = (size_t)max_slot_count(segs, x->fused_w);
+    const size_t per_slot = fused_slot_values(N, x->nacc);
     if (!x->partial.alloc(slots * per_slot * sizeof(double))) {
       g_init_error = "partial-image workspace allocation failed";
       delete x;
@@ -1875,14 +1921,21 @@ epic_status epic_image_accumulate_noalloc(epic_ctx* x, const uint8_t* efield, in
                    "the no-allocation call runs the fused float32 kernels only (not the staged or split paths)");
   if (!x->scratch)
     return x->fail(EPIC_E_DEVICE, "the static scratch array has no device address on this device");
-  const FusedGrid fg = fused_grid(x, n_time);
+  // the largest team whose slots fit the array
+  int max_team = kMaxTeam;
+  FusedGrid fg = fused_grid(x, n_time, max_team);
+  while (fg.slot_bytes > kScratchBytes && max_team > 1) {
+    max_team /= 2;
+    fg = fused_grid(x, n_time, max_team);
+  }
   if (fg.slot_bytes > kScratchBytes)
     return x->fail(EPIC_E_UNSUPPORTED,
                    "this call needs " + std::to_string(fg.slot_bytes) + " bytes of partial-image slots; the "
                    "static scratch holds " + std::to_string(kScratchBytes) + " (fewer channels per call fit)");
   DeviceGuard guard(x->device);
   (void)hipGetLastError();
-  const epic_status s = run_fp32(x, efield, n_time, gains, image, reset, static_cast<double*>(x->scratch));
+  const epic_status s =
+      run_fp32(x, efield, n_time, gains, image, reset, static_cast<double*>(x->scratch), max_team);
   if (s != EPIC_OK) return s;
   return finish_accumulate(x, efield, n_time, gains, image);
 }

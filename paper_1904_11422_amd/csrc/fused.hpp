@@ -107,25 +107,90 @@ struct FusedBlock {
   int n_chan, n_ant, L;
 };
 
+// Work partition of a persistent launch.  The launch's units form one flat
+// list of S segments of T units each, segment-major (N <= 64: a segment is a
+// channel and a unit a sample; N = 128: a segment is a (channel, parity)
+// pair).  The W workgroups form W / team teams of `team` workgroups; team tm
+// takes the contiguous range [tm U / n_team, (tm + 1) U / n_team) of the list
+// (U = S T), and member k of the team takes the k-th of `team` equal parts of
+// each segment piece in that range.  The members of a team thus work on the
+// same segment at the same time, and with xcd = 1 (a team's workgroups on one
+// XCD, see wg_range_index) one XCD holds the gridding programs of few
+// channels in its L2 at any time; the total work per workgroup stays balanced
+// to a unit per piece.  A member's part of a piece is one accumulation
+// segment with its own partial slot, (s + tm) team + k (at most
+// (S + n_team - 1) team slots); a part of at most kblock units is written
+// once as float32, a longer one is summed in float64 (first flush writes,
+// later ones add).
 struct FusedArgs {
   FusedBlock blk[kMaxLaunchBlocks];   // in channel order: blk[i + 1].c0 = blk[i].c0 + blk[i].n_chan
   int n_blk;
   const float2* twiddle;    // [N] exp(+2 pi i k / N)
-  double* partial;          // [W + C - 1][NACC][S][NT] (thread-major), C = the launch's channels
-  int64_t n_time;
-  int64_t total;            // C * T
-  int W;
+  double* partial;          // [(S + W / team - 1) team][NACC][NV][NT] (thread-major), NV sums per thread
+  int64_t n_time;           // T
+  int64_t total;            // U = S * T
+  int W;                    // workgroups, a multiple of team
+  int team;                 // workgroups per team, 1 .. 8
   int kblock;               // samples summed in float32 before a float64 flush, 1 .. KBLOCK
-  int xcd;                  // 1: workgroup ranges dealt XCD by XCD (see wg_range_index)
+  int xcd;                  // 1: consecutive workgroup indices dealt XCD by XCD (see wg_range_index)
 };
 
-// Workgroup ids are dealt to the 8 XCDs round-robin.  With xcd = 1 the range
-// index of workgroup id is chosen so that consecutive ranges (which share a
-// channel and its gridding program) run on one XCD and its L2.
+// Workgroup ids are dealt to the 8 XCDs round-robin.  With xcd = 1 the
+// logical index of workgroup id is chosen so that consecutive indices (the
+// members of a team, which share a channel and its gridding program) run on
+// one XCD and its L2.
 __device__ __forceinline__ int wg_range_index(int id, int n, int xcd) {
   if (!xcd) return id;
   const int q = n >> 3, r = n & 7, j = id & 7;
   return j * q + (j < r ? j : r) + (id >> 3);
+}
+
+// Part of member k (of m) of the piece of segment sg inside team range
+// [ra, rb): first unit a (flat index) and length len (0: none).
+__host__ __device__ __forceinline__ void member_part(int64_t sg, int64_t T, int64_t ra, int64_t rb, int m,
+                                                     int k, int64_t& a, int64_t& len) {
+  const int64_t pa = sg * T > ra ? sg * T : ra;
+  const int64_t pb = (sg + 1) * T < rb ? (sg + 1) * T : rb;
+  const int64_t L = pb > pa ? pb - pa : 0;
+  a = pa + (k * L) / m;
+  len = pa + ((k + 1) * L) / m - a;
+}
+
+// Walks the units of one member: segment s, time t, units left in the
+// current part (including the current one).
+struct UnitWalk {
+  int64_t T, ra, rb;
+  int m, k;
+  int64_t s, t, left;
+  // move to the first unit of the first non-empty part at or after segment sg
+  __device__ __forceinline__ bool seek(int64_t sg) {
+    for (; sg * T < rb; ++sg) {
+      int64_t a, len;
+      member_part(sg, T, ra, rb, m, k, a, len);
+      if (len > 0) {
+        s = sg;
+        t = a - sg * T;
+        left = len;
+        return true;
+      }
+    }
+    return false;
+  }
+  __device__ __forceinline__ void next() {
+    if (--left > 0) ++t;
+    else seek(s + 1);
+  }
+};
+
+// Units of member k of team range [ra, rb).
+__device__ __forceinline__ int64_t member_units(int64_t T, int64_t ra, int64_t rb, int m, int k) {
+  int64_t n = 0;
+  for (int64_t sg = ra / T; sg * T < rb; ++sg) {
+    int64_t a, len;
+    member_part(sg, T, ra, rb, m, k, a, len);
+    n += len;
+  }
+  return n;
 }
 
 // Block of channel c: the last block whose first channel is <= c.
@@ -421,25 +486,28 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
-  const int wr = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
-  const int64_t fb = range_begin(wr, a.total, a.W);
-  const int64_t fe = range_begin(wr + 1, a.total, a.W);
-  if (fb >= fe) return;
+  const int wl = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
+  const int m = a.team, tm = wl / m, mk = wl - tm * m, n_team = a.W / m;
+  UnitWalk it;
+  it.T = a.n_time;
+  it.ra = range_begin(tm, a.total, n_team);
+  it.rb = range_begin(tm + 1, a.total, n_team);
+  it.m = m;
+  it.k = mk;
+  if (tm >= n_team || !it.seek(it.ra / a.n_time)) return;
+  const int64_t n_units = member_units(a.n_time, it.ra, it.rb, m, mk);
 
   float2 tw[S];
 #pragma unroll
   for (int k0 = 0; k0 < S; ++k0) tw[k0] = a.twiddle[(r.n0 * k0) % N];
 
-  // current sample (cc, tt); one division per workgroup
-  int cc = (int)(fb / a.n_time);
-  int64_t tt = fb - (int64_t)cc * a.n_time;
   // block of the sample being prefetched (nb) and of the one being imaged (b)
-  int nb = MULTI ? block_of(a, cc) : 0;
+  int nb = MULTI ? block_of(a, (int)it.s) : 0;
   int b = nb;
   int PA = P * a.blk[b].n_ant;                 // of block b
   int L = a.blk[b].L;
   const int KB = a.kblock;
-  // the prefetched sample's block: bytes per time sample, channel range
+  // the prefetched sample's block: bytes per time sample, first channel
   int64_t n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
   int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
   const uint8_t* n_src = a.blk[nb].efield;
@@ -450,6 +518,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   float2 g[GPT];
   uint32_t nxt[GPT];
   int c = -1, nblk = 0, nflush = 0, line = -1, line2 = -1;
+  int64_t part_len = 0, slot = 0;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -461,27 +530,42 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
       dst[i] = (k < n_pa) ? (uint32_t)src[k] : 0u;
     }
   };
-  // add the float32 block sums into this workgroup's float64 slot of channel c
+  // the float32 sums of the current part into its slot: written once as
+  // float32 if the part fits one block, else added in float64
   auto flush = [&]() {
-    double* out = a.partial + (int64_t)(wr + c) * NACC * S * NT + tid;
+    double* out = a.partial + slot * (NACC * S * NT) + tid;
+    if (part_len <= KB) {
+      float* o32 = reinterpret_cast<float*>(a.partial + slot * (NACC * S * NT)) + tid;
 #pragma unroll
-    for (int u = 0; u < NACC; ++u)
+      for (int u = 0; u < NACC; ++u)
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        double* o = out + (u * S + i) * NT;
-        *o = (nflush ? *o : 0.0) + (double)acc[i][u];
-        acc[i][u] = 0.f;
-      }
+        for (int i = 0; i < S; ++i) {
+          o32[(u * S + i) * NT] = acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          double* o = out + (u * S + i) * NT;
+          *o = (nflush ? *o : 0.0) + (double)acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    }
     ++nflush;
     nblk = 0;
   };
 
-  load_bytes(cc, tt, nxt);
-  for (int64_t left = fe - fb; left > 0; --left) {
-    if (cc != c) {                             // channel segment starts
+  load_bytes((int)it.s, it.t, nxt);
+  for (int64_t left = n_units; left > 0; --left) {
+    const int cc = (int)it.s;                  // channel of the current sample
+    if (cc != c) {                             // a part (accumulation segment) starts
       if (c >= 0) flush();
       c = cc;
       nflush = 0;
+      part_len = it.left;
+      slot = ((int64_t)c + tm) * m + mk;
       if (MULTI && nb != b) {                  // and a block: its antennas' E' layout
         b = nb;
         PA = P * a.blk[b].n_ant;
@@ -509,19 +593,20 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
     uint32_t cur[GPT];
 #pragma unroll
     for (int i = 0; i < GPT; ++i) cur[i] = nxt[i];
-    ++tt;                                      // advance, prefetch the next sample
-    if (tt == a.n_time) {
-      tt = 0;
-      ++cc;
-      if (MULTI && nb + 1 < a.n_blk && cc == a.blk[nb + 1].c0) {
-        ++nb;
-        n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
-        n_pa = P * a.blk[nb].n_ant;
-        n_c0 = a.blk[nb].c0;
-        n_src = a.blk[nb].efield;
+    it.next();                                 // advance, prefetch the next sample
+    if (left > 1) {
+      if (MULTI && it.s != cc) {               // the next part may be in another block
+        const int nnb = block_of(a, (int)it.s);
+        if (nnb != nb) {
+          nb = nnb;
+          n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+          n_pa = P * a.blk[nb].n_ant;
+          n_c0 = a.blk[nb].c0;
+          n_src = a.blk[nb].efield;
+        }
       }
+      load_bytes((int)it.s, it.t, nxt);
     }
-    if (left > 1) load_bytes(cc, tt, nxt);
 
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
@@ -573,13 +658,15 @@ fused_multi_image_kernel(FusedArgs a) {
   fused_image_body<N, P, GPT, false, WIDE, true>(a);
 }
 
-// image[c][prod][qm][ql] (+)= sum over the workgroups covering channel c of
-// their partial slot.  THREAD_MAJOR: slots are [NACC][S][NT] as written by
-// the fused kernel (value i of thread tid); otherwise [NACC][N*N] in natural
-// pixel order (staged path, W = 1).  A block of 256 threads handles 256/sub
-// pixels; sub-lane j of a pixel sums the slots w_lo + j, w_lo + j + sub, ...
-// and the sub-lane sums are added in the order j = 0, 1, ...: a fixed order
-// for a given (W, C, T, sub), so the result is reproducible run to run.
+// image[c][prod][qm][ql] (+)= sum over the parts of channel c (the members'
+// parts of the teams covering it, FusedArgs) of their partial slot.
+// THREAD_MAJOR: slots are [NACC][S][NT] as written by the fused kernel (value
+// i of thread tid); otherwise [NACC][N*N] in natural pixel order (staged path,
+// W = team = 1, float64).  A block of 256 threads handles 256/sub pixels;
+// sub-lane j of a pixel sums the parts j, j + sub, ... (in team, then member
+// order) and the sub-lane sums are added in the order j = 0, 1, ...: a fixed
+// order for a given (W, team, C, T, sub), so the result is reproducible run to
+// run.
 struct ReduceArgs {
   const double* partial;
   // complex128 [C_b][NPROD][N][N] per block of the launch; channel c of the
@@ -590,6 +677,8 @@ struct ReduceArgs {
   int n_img;
   int64_t n_time, total;
   int n_chan, W, reset;     // n_chan: all channels of the launch
+  int team, kblock;         // the imaging launch's partition (FusedArgs)
+  int f32;                  // parts of <= kblock units hold float32 sums (fused slots)
   int sub;                  // 1, 4 or 16 sub-lanes per pixel
   const double* autos;      // table of the antenna autocorrelations to subtract
                             // ([C][(2K-1)^2][NACC (x2 with autos_cpx)], autos.hpp), or null
@@ -597,12 +686,42 @@ struct ReduceArgs {
   int autos_cpx;            // the table has the sin part (complex kernels)
 };
 
-// Workgroup whose range contains flat index f: the largest w with
-// floor(w * total / W) <= f, i.e. ceil((f + 1) W / total) - 1.  Launches take
-// W <= total, so every range is non-empty and every workgroup from the owner
-// of a segment's first index to the owner of its last one wrote a slot.
+// Team whose range contains flat index f: the largest w with
+// floor(w * total / W) <= f, i.e. ceil((f + 1) W / total) - 1 (W: the number
+// of teams).  Launches take W <= total, so every range is non-empty.
 __device__ __forceinline__ int64_t owner_of(int64_t f, int64_t total, int64_t W) {
   return ((f + 1) * W + total - 1) / total - 1;
+}
+
+// Sum of the NV values at offset pix of every part of segment sg, sub-lane j
+// of sub: the parts of the teams covering the segment, in team then member
+// order.  Slots hold NV * stride values (float64, or float32 for parts of at
+// most kblock units when f32).
+template <int NV>
+__device__ __forceinline__ void sum_parts(const double* partial, int64_t sg, int64_t T, int64_t U, int W,
+                                          int m, int kblock, int f32, int64_t slot_vals, int64_t stride,
+                                          int64_t pix, int j, int sub, double (&s)[NV]) {
+  const int64_t n_team = W / m;
+  const int64_t t_lo = owner_of(sg * T, U, n_team);
+  const int64_t t_hi = owner_of((sg + 1) * T - 1, U, n_team);
+  const int64_t nq = (t_hi - t_lo + 1) * m;
+  for (int64_t q = j; q < nq; q += sub) {
+    const int64_t tm = t_lo + q / m;
+    const int k = (int)(q % m);
+    int64_t a0, len;
+    member_part(sg, T, range_begin(tm, U, n_team), range_begin(tm + 1, U, n_team), m, k, a0, len);
+    if (len == 0) continue;
+    const int64_t slot = (sg + tm) * m + k;
+    if (f32 && len <= kblock) {
+      const float* src = reinterpret_cast<const float*>(partial + slot * slot_vals) + pix;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) s[u] += (double)src[u * stride];
+    } else {
+      const double* src = partial + slot * slot_vals + pix;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) s[u] += src[u * stride];
+    }
+  }
 }
 
 // Pixel (km, kl) owned by value i of thread tid in the fused kernel.
@@ -630,16 +749,9 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
   double s[NACC];
 #pragma unroll
   for (int u = 0; u < NACC; ++u) s[u] = 0.0;
-  if (valid) {
-    const int64_t w_lo = owner_of((int64_t)c * a.n_time, a.total, a.W);
-    const int64_t w_hi = owner_of((int64_t)(c + 1) * a.n_time - 1, a.total, a.W);
-#pragma unroll 4
-    for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
-      const double* src = a.partial + (w + c) * NACC * NPIX + pix;
-#pragma unroll
-      for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NPIX];
-    }
-  }
+  if (valid)
+    sum_parts<NACC>(a.partial, c, a.n_time, a.total, a.W, a.team, a.kblock, a.f32, (int64_t)NACC * NPIX,
+                    NPIX, pix, j, a.sub, s);
   // a workgroup's pixels lie in one channel (N^2 is a multiple of 256 / sub)
   if (a.autos)
     stage_autos(a.autos, (int)((int64_t)blockIdx.x * ppb / NPIX), N, a.K,

@@ -73,10 +73,16 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
-  const int wr = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
-  const int64_t fb = range_begin(wr, a.total, a.W);
-  const int64_t fe = range_begin(wr + 1, a.total, a.W);
-  if (fb >= fe) return;
+  const int wl = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
+  const int m = a.team, tm = wl / m, mk = wl - tm * m, n_team = a.W / m;
+  UnitWalk it;
+  it.T = a.n_time;
+  it.ra = range_begin(tm, a.total, n_team);
+  it.rb = range_begin(tm + 1, a.total, n_team);
+  it.m = m;
+  it.k = mk;
+  if (tm >= n_team || !it.seek(it.ra / a.n_time)) return;
+  const int64_t n_units = member_units(a.n_time, it.ra, it.rb, m, mk);
 
   if (tid < R * S) TW[(tid / S) * TWS + tid % S] = a.twiddle[((tid / S) * (tid % S)) % N];
   if (tid < R * 8) TW64[(tid / 8) * TW64S + tid % 8] = a.twiddle[(2 * (tid / 8) * (tid % 8)) % N];
@@ -84,10 +90,8 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   const float2* tw = TW + r.n0 * TWS;          // read after the first barrier
   const float2* tw64 = TW64 + r.n0 * TW64S;
 
-  int64_t sg = fb / a.n_time;                  // segment 2 c + h of the current unit
-  int64_t tt = fb - sg * a.n_time;
   // block of the unit being prefetched (nb) and of the one being imaged (b)
-  int nb = MULTI ? block_of(a, (int)(sg >> 1)) : 0;
+  int nb = MULTI ? block_of(a, (int)(it.s >> 1)) : 0;
   int b = nb;
   int PA = P * a.blk[b].n_ant;
   int L = a.blk[b].L;
@@ -102,6 +106,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   float2 g[GPT];
   uint32_t nxt[GPT];
   int seg = -1, nblk = 0, nflush = 0, line = -1, h = 0;
+  int64_t part_len = 0, slot = 0;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -113,29 +118,45 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
       dst[i] = (k < n_pa) ? (uint32_t)src[k] : 0u;
     }
   };
+  // the float32 sums of the current part into its slot: written once as
+  // float32 if the part fits one block, else added in float64
   auto flush = [&]() {
-    double* out = a.partial + (int64_t)(wr + seg) * NACC * NPX * NT + tid;
+    if (part_len <= KB) {
+      float* o32 = reinterpret_cast<float*>(a.partial + slot * (NACC * NPX * NT)) + tid;
 #pragma unroll
-    for (int u = 0; u < NACC; ++u)
+      for (int u = 0; u < NACC; ++u)
 #pragma unroll
-      for (int i = 0; i < NPX; ++i) {
-        double* o = out + (u * NPX + i) * NT;
-        *o = (nflush ? *o : 0.0) + (double)acc[i][u];
-        acc[i][u] = 0.f;
-      }
+        for (int i = 0; i < NPX; ++i) {
+          o32[(u * NPX + i) * NT] = acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    } else {
+      double* out = a.partial + slot * (NACC * NPX * NT) + tid;
+#pragma unroll
+      for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) {
+          double* o = out + (u * NPX + i) * NT;
+          *o = (nflush ? *o : 0.0) + (double)acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    }
     ++nflush;
     nblk = 0;
   };
 
-  load_bytes(sg, tt, nxt);
-  for (int64_t left = fe - fb; left > 0; --left) {
-    if ((int)sg != seg) {
+  load_bytes(it.s, it.t, nxt);
+  for (int64_t left = n_units; left > 0; --left) {
+    const int64_t sg = it.s;                   // segment 2 c + h of the current unit
+    if ((int)sg != seg) {                      // a part (accumulation segment) starts
       if (seg >= 0) flush();
       const int c_old = seg >> 1;
       seg = (int)sg;
       const int c = seg >> 1;
       h = seg & 1;
       nflush = 0;
+      part_len = it.left;
+      slot = (sg + tm) * m + mk;
 #pragma unroll
       for (int i = 0; i < NPX; ++i)
 #pragma unroll
@@ -164,19 +185,20 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
     uint32_t cur[GPT];
 #pragma unroll
     for (int i = 0; i < GPT; ++i) cur[i] = nxt[i];
-    ++tt;                                      // advance, prefetch the next unit
-    if (tt == a.n_time) {
-      tt = 0;
-      ++sg;
-      if (MULTI && nb + 1 < a.n_blk && (sg >> 1) == a.blk[nb + 1].c0 && !(sg & 1)) {
-        ++nb;
-        n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
-        n_pa = P * a.blk[nb].n_ant;
-        n_c0 = a.blk[nb].c0;
-        n_src = a.blk[nb].efield;
+    it.next();                                 // advance, prefetch the next unit
+    if (left > 1) {
+      if (MULTI && (it.s >> 1) != (sg >> 1)) {  // the next part may be in another block
+        const int nnb = block_of(a, (int)(it.s >> 1));
+        if (nnb != nb) {
+          nb = nnb;
+          n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
+          n_pa = P * a.blk[nb].n_ant;
+          n_c0 = a.blk[nb].c0;
+          n_src = a.blk[nb].efield;
+        }
       }
+      load_bytes(it.s, it.t, nxt);
     }
-    if (left > 1) load_bytes(sg, tt, nxt);
 
     // 1. stage and grid the aperture (both parities grid the whole aperture)
     stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
@@ -256,6 +278,7 @@ struct Reduce128Args {
   int n_img;
   int64_t n_time, total;
   int n_chan, W, reset, sub;   // n_chan: all channels of the launch
+  int team, kblock;            // the imaging launch's partition (FusedArgs)
 };
 
 template <int P>
@@ -272,16 +295,9 @@ __global__ void __launch_bounds__(256) reduce_image128_kernel(Reduce128Args a) {
   double s[NACC];
 #pragma unroll
   for (int u = 0; u < NACC; ++u) s[u] = 0.0;
-  if (valid) {
-    const int64_t w_lo = owner_of((int64_t)sgm * a.n_time, a.total, a.W);
-    const int64_t w_hi = owner_of((int64_t)(sgm + 1) * a.n_time - 1, a.total, a.W);
-#pragma unroll 4
-    for (int64_t w = w_lo + j; w <= w_hi; w += a.sub) {
-      const double* src = a.partial + (w + sgm) * NACC * NLOC + pix;
-#pragma unroll
-      for (int u = 0; u < NACC; ++u) s[u] += src[(int64_t)u * NLOC];
-    }
-  }
+  if (valid)
+    sum_parts<NACC>(a.partial, sgm, a.n_time, a.total, a.W, a.team, a.kblock, 1, (int64_t)NACC * NLOC, NLOC,
+                    pix, j, a.sub, s);
   combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
   if (!valid || j != 0) return;
   const int tid = pix % NT, i = pix / NT;

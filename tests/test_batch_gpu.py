@@ -178,18 +178,20 @@ def test_ungroupable_blocks_run_alone_and_groups_hold_eight():
             assert np.linalg.norm(d[c, pr]) <= 1e-5 * np.linalg.norm(full[c, pr]) + 1e-9
 
 
-@pytest.mark.parametrize("shape", [(4, 128, 0), (4, 64, 1), (2, 128, 1), (1, 64, 0)])
+@pytest.mark.parametrize("shape", [(4, 0, 128, 0), (4, 8, 64, 1), (2, 2, 128, 1), (1, 1, 64, 0),
+                                   (3, 4, 128, 1), (4, 1, 5, 1)])
 def test_every_tuned_shape_matches_oracle(batch_inputs, shape):
-    """Each launch shape the tuner can choose -- grid of w_cap * den / 4,
-    float32 blocks of 128 or 64 samples, XCD order on or off -- gives the
+    """Each launch shape the tuner can choose -- grid of w_cap * den / 4, team
+    size (time chunk), float32 blocks of 128 or 64 samples (and a short one,
+    so every part spans several blocks), XCD order on or off -- gives the
     oracle's images."""
     import torch
-    den, kb, xcd = shape
+    den, team, kb, xcd = shape
     b, ef, g = _batch(batch_inputs)
     caps = {lp[0]: grid for lp, (grid, _) in zip(b.launch_plan(), b.plan())}
     for li, cap in caps.items():
-        b.set_launch(li, max(1, cap * den // 4), kb, xcd)
-    assert all(x[2] == kb and x[3] == xcd for x in b.launch_plan())
+        b.set_launch(li, max(1, cap * den // 4), team, kb, xcd)
+    assert all(x[2] == team and x[3] == kb and x[4] == xcd for x in b.launch_plan())
     assert all(grid == max(1, caps[lp[0]] * den // 4) for lp, (grid, _) in zip(b.launch_plan(), b.plan()))
     imgs = b.accumulate(ef, g, b.new_images())
     torch.cuda.synchronize()
