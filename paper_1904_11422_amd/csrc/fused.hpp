@@ -145,15 +145,16 @@ __device__ __forceinline__ int wg_range_index(int id, int n, int xcd) {
   return j * q + (j < r ? j : r) + (id >> 3);
 }
 
-// Part of member k (of m) of the piece of segment sg inside team range
-// [ra, rb): first unit a (flat index) and length len (0: none).
+// Part of member k (of m, a power of two) of the piece of segment sg inside
+// team range [ra, rb): first unit a (flat index) and length len (0: none).
 __host__ __device__ __forceinline__ void member_part(int64_t sg, int64_t T, int64_t ra, int64_t rb, int m,
                                                      int k, int64_t& a, int64_t& len) {
   const int64_t pa = sg * T > ra ? sg * T : ra;
   const int64_t pb = (sg + 1) * T < rb ? (sg + 1) * T : rb;
   const int64_t L = pb > pa ? pb - pa : 0;
-  a = pa + (k * L) / m;
-  len = pa + ((k + 1) * L) / m - a;
+  const int lg = __builtin_ctz((unsigned)m);
+  a = pa + ((k * L) >> lg);
+  len = pa + (((k + 1) * L) >> lg) - a;
 }
 
 // Walks the units of one member: segment s, time t, units left in the
@@ -702,24 +703,30 @@ __device__ __forceinline__ void sum_parts(const double* partial, int64_t sg, int
                                           int m, int kblock, int f32, int64_t slot_vals, int64_t stride,
                                           int64_t pix, int j, int sub, double (&s)[NV]) {
   const int64_t n_team = W / m;
+  const int lg = __builtin_ctz((unsigned)m);
   const int64_t t_lo = owner_of(sg * T, U, n_team);
   const int64_t t_hi = owner_of((sg + 1) * T - 1, U, n_team);
-  const int64_t nq = (t_hi - t_lo + 1) * m;
-  for (int64_t q = j; q < nq; q += sub) {
-    const int64_t tm = t_lo + q / m;
-    const int k = (int)(q % m);
-    int64_t a0, len;
-    member_part(sg, T, range_begin(tm, U, n_team), range_begin(tm + 1, U, n_team), m, k, a0, len);
-    if (len == 0) continue;
-    const int64_t slot = (sg + tm) * m + k;
-    if (f32 && len <= kblock) {
-      const float* src = reinterpret_cast<const float*>(partial + slot * slot_vals) + pix;
+  int64_t rb = range_begin(t_lo, U, n_team);
+  for (int64_t tm = t_lo; tm <= t_hi; ++tm) {
+    const int64_t ra = rb;
+    rb = range_begin(tm + 1, U, n_team);
+    const int64_t pa = sg * T > ra ? sg * T : ra;
+    const int64_t pb = (sg + 1) * T < rb ? (sg + 1) * T : rb;
+    const int64_t L = pb - pa;
+    for (int k = 0; k < m; ++k) {
+      if (((((tm - t_lo) << lg) + k) & (sub - 1)) != j) continue;     // sub: 1, 4 or 16
+      const int64_t len = (((k + 1) * L) >> lg) - ((k * L) >> lg);
+      if (len == 0) continue;
+      const int64_t slot = ((sg + tm) << lg) + k;
+      if (f32 && len <= kblock) {
+        const float* src = reinterpret_cast<const float*>(partial + slot * slot_vals) + pix;
 #pragma unroll
-      for (int u = 0; u < NV; ++u) s[u] += (double)src[u * stride];
-    } else {
-      const double* src = partial + slot * slot_vals + pix;
+        for (int u = 0; u < NV; ++u) s[u] += (double)src[u * stride];
+      } else {
+        const double* src = partial + slot * slot_vals + pix;
 #pragma unroll
-      for (int u = 0; u < NV; ++u) s[u] += src[u * stride];
+        for (int u = 0; u < NV; ++u) s[u] += src[u * stride];
+      }
     }
   }
 }
