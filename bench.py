@@ -174,7 +174,9 @@ def batch_results(steps: int, warmup: int, sequential: bool = True) -> dict:
     out = {"value": tc / dt, "unit": "(t,c)-images/s", "ms_per_step": dt * 1e3, "steps": steps,
            "channel_images_per_s": sum(i.n_chan for i in inputs) / dt,
            "blocks": [dict(grid_n=i.grid_n, n_ant=i.n_ant, n_chan=i.n_chan, grid=p[0],
-                           staged_batch=p[1]) for i, p in zip(inputs, b.plan())],
+                           staged_batch=p[1], launch=lp[0], launch_blocks=lp[1], team=lp[2],
+                           kblock=lp[3], xcd=lp[4])
+                      for i, p, lp in zip(inputs, b.plan(), b.launch_plan())],
            "serial": b.serial,
            "roofline": {"bound": "alu", "kernel": "whole batch (graph replay, wall clock)",
                         "achieved": fl / dt / 1e12, "peak": PEAK_FP32_VALU / 1e12,
