@@ -841,9 +841,10 @@ int64_t max_slot_count(int64_t segs, int64_t w_cap) {
 size_t fused_slot_values(int N, int nacc) { return (size_t)nacc * N * N / (N == 128 ? 2 : 1); }
 
 // Sub-lanes of the fused reductions: parts per segment are about m times the
-// teams covering it.
+// teams covering it (one long channel: up to one part per workgroup).
 int fused_reduce_sub(int64_t n_time, int64_t units, int W, int m) {
-  return reduce_sub(slots_per_channel(n_time, units, W / m) * m);
+  const int64_t parts = slots_per_channel(n_time, units, W / m) * m;
+  return parts > 256 ? 64 : reduce_sub(parts);
 }
 
 bool launch_reduce(epic_ctx* x, const epic::ReduceArgs& a, bool thread_major) {

@@ -663,7 +663,8 @@ fused_multi_image_kernel(FusedArgs a) {
 // parts of the teams covering it, FusedArgs) of their partial slot.
 // THREAD_MAJOR: slots are [NACC][S][NT] as written by the fused kernel (value
 // i of thread tid); otherwise [NACC][N*N] in natural pixel order (staged path,
-// W = team = 1, float64).  A block of 256 threads handles 256/sub pixels;
+// W = team = 1, float64).  A block of 256 threads handles 256/sub pixels (sub =
+// 1, 4, 16 or 64);
 // sub-lane j of a pixel sums the parts j, j + sub, ... (in team, then member
 // order) and the sub-lane sums are added in the order j = 0, 1, ...: a fixed
 // order for a given (W, team, C, T, sub), so the result is reproducible run to
@@ -680,7 +681,7 @@ struct ReduceArgs {
   int n_chan, W, reset;     // n_chan: all channels of the launch
   int team, kblock;         // the imaging launch's partition (FusedArgs)
   int f32;                  // parts of <= kblock units hold float32 sums (fused slots)
-  int sub;                  // 1, 4 or 16 sub-lanes per pixel
+  int sub;                  // 1, 4, 16 or 64 sub-lanes per pixel
   const double* autos;      // table of the antenna autocorrelations to subtract
                             // ([C][(2K-1)^2][NACC (x2 with autos_cpx)], autos.hpp), or null
   int K;
@@ -706,27 +707,35 @@ __device__ __forceinline__ void sum_parts(const double* partial, int64_t sg, int
   const int lg = __builtin_ctz((unsigned)m);
   const int64_t t_lo = owner_of(sg * T, U, n_team);
   const int64_t t_hi = owner_of((sg + 1) * T - 1, U, n_team);
-  int64_t rb = range_begin(t_lo, U, n_team);
-  for (int64_t tm = t_lo; tm <= t_hi; ++tm) {
-    const int64_t ra = rb;
-    rb = range_begin(tm + 1, U, n_team);
-    const int64_t pa = sg * T > ra ? sg * T : ra;
-    const int64_t pb = (sg + 1) * T < rb ? (sg + 1) * T : rb;
-    const int64_t L = pb - pa;
-    for (int k = 0; k < m; ++k) {
-      if (((((tm - t_lo) << lg) + k) & (sub - 1)) != j) continue;     // sub: 1, 4 or 16
-      const int64_t len = (((k + 1) * L) >> lg) - ((k * L) >> lg);
-      if (len == 0) continue;
-      const int64_t slot = ((sg + tm) << lg) + k;
-      if (f32 && len <= kblock) {
-        const float* src = reinterpret_cast<const float*>(partial + slot * slot_vals) + pix;
+  const int64_t nq = (t_hi - t_lo + 1) << lg;
+  // team ranges [tm U / n_team, (tm + 1) U / n_team) in 32-bit arithmetic where it is exact
+  const bool small = (uint64_t)U * (uint64_t)n_team < (1ull << 32);
+  auto team_begin = [&](int64_t tm) -> int64_t {
+    return small ? (int64_t)((uint32_t)(tm * U) / (uint32_t)n_team) : range_begin(tm, U, n_team);
+  };
+  int64_t tm_c = -1, L = 0;
+#pragma unroll 4
+  for (int64_t q = j; q < nq; q += sub) {        // this sub-lane's (team, member) pairs
+    const int64_t tm = t_lo + (q >> lg);
+    const int k = (int)(q & (m - 1));
+    if (tm != tm_c) {                            // the team's piece of segment sg
+      tm_c = tm;
+      const int64_t ra = team_begin(tm), rb = team_begin(tm + 1);
+      const int64_t pa = sg * T > ra ? sg * T : ra;
+      const int64_t pb = (sg + 1) * T < rb ? (sg + 1) * T : rb;
+      L = pb - pa;
+    }
+    const int64_t len = (((k + 1) * L) >> lg) - ((k * L) >> lg);
+    if (len == 0) continue;
+    const int64_t slot = ((sg + tm) << lg) + k;
+    if (f32 && len <= kblock) {
+      const float* src = reinterpret_cast<const float*>(partial + slot * slot_vals) + pix;
 #pragma unroll
-        for (int u = 0; u < NV; ++u) s[u] += (double)src[u * stride];
-      } else {
-        const double* src = partial + slot * slot_vals + pix;
+      for (int u = 0; u < NV; ++u) s[u] += (double)src[u * stride];
+    } else {
+      const double* src = partial + slot * slot_vals + pix;
 #pragma unroll
-        for (int u = 0; u < NV; ++u) s[u] += src[u * stride];
-      }
+      for (int u = 0; u < NV; ++u) s[u] += src[u * stride];
     }
   }
 }
