@@ -133,8 +133,10 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
  * EPIC_FLAG_STAGED).  out receives, as epic_set_antennas uploads it,
  *   uint32 [n_chan][1 + L][NT][2]:
  *     row 0, word 0: the line thread t transforms in the row pass, p << 16 | j
- *                    (int32 -1: none); word 1: 0, or for the wide block (below)
- *                    the line of the second row pass (int32 -1: none);
+ *                    (int32 -1: none); word 1: bits 0-23 the line of the
+ *                    second row pass of the wide block (below; 0xFFFFFF:
+ *                    none), bits 24-31 the steps thread t's wave runs (1..255;
+ *                    its later steps are padding; 0: all L);
  *     rows 1..L:     steps {LDS byte offset of the cell, relative to the grid
  *                    base, << 15 | LDS byte offset of E'[p = 0][a] (a multiple
  *                    of 8), bit 0 set on a cell's last entry; float32 weight}.
@@ -144,8 +146,10 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
  * order 1: aperture row j is stored at physical row
  * 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and cell offsets use
  * physical rows), 0: at row j.  The aperture block is N/2 x N/2 cells, or at
- * N = 64, when some channel's taps do not fit that, 48 x 48 (the wide block,
- * two row passes; the image and its gradient run the wide kernels).
+ * N = 64, when some channel's taps do not fit that, 48 x 48 (the wide block:
+ * at P = 2 waves 0-3 run two row passes and waves 4-7 one, at P = 1 waves
+ * 0-5 one and waves 6-7 none; the image and its gradient run the wide
+ * kernels).
  * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
  * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
  * taps do not fit the block), EPIC_E_NOMEM (capacity too small;

@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
 }
 
 // WIDE (N = 64): the wide block of the forward (rows and columns < HW, a
-// second row-pass line per thread in prog[tid].y).
+// second row-pass line per thread in the program header's second word).
 template <int N, int P, int GPT, bool CPX, bool WIDE>
 __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
   using SH = FusedShape<N>;
@@ -98,7 +98,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, line = -1, line2 = -1;
+  int c = -1, line = -1, line2 = -1, Lw = a.L;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -129,7 +129,8 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
       if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
-      if (WIDE) line2 = (int)prog[tid].y;
+      if (WIDE) line2 = header_line2(prog[tid].y);
+      Lw = header_steps(prog[tid].y, a.L);
       prog += NT;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
@@ -145,7 +146,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();

@@ -88,7 +88,7 @@ adjoint128_kernel(AdjointArgs a) {
   double2 gacc[GPT];
   float2 g[GPT];
   uint32_t nxt[GPT];
-  int c = -1, line = -1;
+  int c = -1, line = -1, Lw = a.L;
   const uint2* prog = nullptr;
   const float* wim = nullptr;
 
@@ -120,6 +120,7 @@ adjoint128_kernel(AdjointArgs a) {
       prog = a.prog + (int64_t)c * (a.L + 1) * NT;
       if (CPX) wim = a.wim + (int64_t)c * (a.L + 1) * NT + NT;
       line = (int)prog[tid].x;
+      Lw = header_steps(prog[tid].y, a.L);
       prog += NT;
 #pragma unroll
       for (int i = 0; i < GPT; ++i) {
@@ -137,7 +138,7 @@ adjoint128_kernel(AdjointArgs a) {
 
     // forward: stage and grid the aperture, row transforms onto the columns
     // of parity h (as fused_image128_kernel)
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, a.L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     const int rb = (line & 0xFFFF) * RS;
     if (line >= 0) {
       float2 v[P][8];
@@ -167,7 +168,7 @@ adjoint128_kernel(AdjointArgs a) {
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + (R * n1 + r.n0) * RS + kl];
-    line_transform<N, +1, P, true>(v, tw, r.n0, X, colslot);
+    line_transform<N, +1, P, Line<N>::S / 2>(v, tw, r.n0, X, colslot);
 
     // dL/dF* at the owned pixels
     const float4* gt = a.gtab + ((int64_t)c * 2 + h) * NPX * NT + tid;

@@ -320,12 +320,18 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   // row slots per wave: CPW / P lines of one polarisation each, or at N = 128
   // CPW rows whose lane group takes both polarisations
   const int SPW = N == 128 ? CPW : CPW / P;
-  // wide (N = 64): an HW x HW block, HW / NWAVE rows per wave, whose lines
-  // take one row pass (the first SPW rows of each polarisation) and a second
-  // one (the rest); the header's second word is the second pass's line
+  // wide (N = 64): an HW x HW block.  Its HW rows per polarisation fill
+  // 1.5 row passes of the 8 waves; rather than every wave running a second
+  // pass with half its lanes, whole waves take two full passes or one: at
+  // P = 2 waves 0-3 own 2 SPW rows (the header's second word holds the
+  // second pass's line) and waves 4-7 SPW rows; at P = 1 waves 0-5 own SPW
+  // rows and waves 6-7 none.  Waves 0-3 sit on the four SIMDs of the CU, one
+  // two-pass wave per SIMD and workgroup.
   const int HB = wide ? SH::HW : H;                    // aperture block side
-  const int RPW = wide ? HB / NWAVE : SPW;             // rows per wave
-  const int NWR = wide ? NWAVE : H / SPW;              // waves that own rows
+  const int NWR = wide ? (P == 2 ? NWAVE : HB / SPW) : H / SPW;   // waves that own rows
+  std::vector<int> rpw(NWAVE, 0);                      // rows per wave
+  for (int w = 0; w < NWR; ++w) rpw[w] = wide && P == 2 && w < NWAVE / 2 ? 2 * SPW : SPW;
+  const int RPW = *std::max_element(rpw.begin(), rpw.end());
   // residue rule (row j of slot s in a wave of group t has j mod M = residue):
   // at N = 64 it puts the 4 (P = 2) or 8 (P = 1) rows a half-wave transforms
   // on distinct bank ranges given the interleaved physical rows and the
@@ -365,6 +371,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   std::vector<std::vector<uint32_t>> words((size_t)C * NT);   // [c][thread] -> step words
   std::vector<std::vector<float>> wims(cpx ? (size_t)C * NT : 0);
   std::vector<int32_t> header((size_t)C * NT, -1), header2((size_t)C * NT, -1);
+  std::vector<int> wave_steps((size_t)C * NWAVE, 0);
   L = 1;
   for (int c = 0; c < C; ++c) {
     std::vector<Run> cells(HB * HB);
@@ -403,22 +410,16 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
       // Rows a row pass loads together must fall on distinct bank ranges: with
       // the interleaved rows this holds when, per pass, a wave's rows differ in
       // cls(j) = 2 (j & 1) + ((j >> 2) & 1) (P = 2: phys_row mod 4, both
-      // polarisations at once) or in j mod 8 (P = 1, phys_row mod 8).  So every
-      // slot takes one class: P = 2, pass-1 slot s class s, pass-2 slots the
-      // classes {0, 1} (even waves) or {2, 3}; P = 1, wave w all classes but
-      // w and w + 1 (mod 8).  Within a class, heaviest row first to the least
-      // loaded wave with a free slot of that class.
+      // polarisations at once) or in j mod 8 (P = 1, phys_row mod 8).  So
+      // slot s of either pass takes class s mod SPW.  Within a class, heaviest
+      // row first to the wave with a free slot of that class and the least
+      // cost: its gridding steps so far, plus, for a two-pass wave, the
+      // second pass counted as kPassSteps steps of each of its 64 lanes, so
+      // that the two-pass waves take the lighter rows.
+      constexpr int kPassSteps = 12;
       const int NCLS = P == 2 ? 4 : 8;
       auto cls = [&](int j) { return P == 2 ? 2 * (j & 1) + ((j >> 2) & 1) : (j & 7); };
-      std::vector<std::vector<int>> slot_cls(NWAVE, std::vector<int>(RPW, -1));
-      for (int w = 0; w < NWAVE; ++w)
-        for (int sl = 0, k = 0; sl < RPW; ++sl) {
-          if (P == 2) slot_cls[w][sl] = sl < SPW ? sl : (w % 2 ? 2 : 0) + (sl - SPW);
-          else {
-            while (k == w % 8 || k == (w + 1) % 8) ++k;
-            slot_cls[w][sl] = k++;
-          }
-        }
+      auto cost = [&](int w) { return wave_load[w] + (rpw[w] > SPW ? 64 * kPassSteps : 0); };
       for (int k = 0; k < NCLS; ++k) {
         std::vector<int> rows;
         for (int j = 0; j < HB; ++j)
@@ -426,9 +427,9 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
         std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
         for (int j : rows) {
           int bw = -1, bs = -1;
-          for (int w = 0; w < NWAVE; ++w)
-            for (int sl = 0; sl < RPW; ++sl)
-              if (slot_cls[w][sl] == k && row_of[w][sl] < 0 && (bw < 0 || wave_load[w] < wave_load[bw])) {
+          for (int w = 0; w < NWR; ++w)
+            for (int sl = k % SPW; sl < rpw[w]; sl += SPW)
+              if (row_of[w][sl] < 0 && (bw < 0 || cost(w) < cost(bw))) {
                 bw = w;
                 bs = sl;
                 break;
@@ -448,8 +449,8 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
       if (ro.wave >= NWR) continue;
       const int p = ro.sub / SPW, sl = ro.sub % SPW;     // N = 128: p = 0, both polarisations
       if (p >= P) continue;
-      if (sl < RPW) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
-      if (wide && SPW + sl < RPW)
+      if (sl < rpw[ro.wave]) header[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][sl]);
+      if (wide && SPW + sl < rpw[ro.wave])
         header2[(size_t)c * NT + t] = (p << 16) | SH::phys_row(row_of[ro.wave][SPW + sl]);
     }
     // cells of each wave's rows, longest first, to the least loaded lane of the wave
@@ -460,7 +461,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     int plain_max = 1;
     for (int w = 0; w < NWR; ++w) {
       std::vector<const Run*> wc;
-      for (int sl = 0; sl < RPW; ++sl)
+      for (int sl = 0; sl < rpw[w]; ++sl)
         for (int i = 0; i < HB; ++i) wc.push_back(&cells[row_of[w][sl] * HB + i]);
       using Load = std::pair<int, int>;                // (steps, thread)
       auto steps_of = [](const Run* r) { return (int)std::max<size_t>(1, r->ent.size()); };
@@ -522,6 +523,14 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
         }
     const int Lc = std::max(1, *std::max_element(load.begin(), load.end()));
     L = std::max(L, Lc);
+    // each wave stops after its own longest lane (the later steps of its
+    // lanes are padding), rounded like L to whole chunks past the fixed forms
+    for (int w = 0; w < NWAVE; ++w) {
+      int lw = std::max(1, *std::max_element(load.begin() + 64 * w, load.begin() + 64 * w + 64));
+      if (lw > epic::kMaxFixedSteps + epic::kStepChunk)
+        lw = (lw + epic::kStepChunk - 1) / epic::kStepChunk * epic::kStepChunk;
+      wave_steps[(size_t)c * NWAVE + w] = lw <= 255 ? lw : 0;
+    }
     // step-by-step choice of the E' entries, per quarter-wave (measured faster
     // than choosing per half-wave for these paired reads)
     for (int q = 0; q < NT / 16; ++q) {
@@ -637,7 +646,9 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     for (int t = 0; t < NT; ++t) {
       const size_t h = ((size_t)c * (L + 1) * NT + t) * 2;
       out[h] = (uint32_t)header[(size_t)c * NT + t];
-      out[h + 1] = wide ? (uint32_t)header2[(size_t)c * NT + t] : 0u;
+      const int32_t l2 = header2[(size_t)c * NT + t];
+      out[h + 1] = (l2 < 0 ? epic::HDR_LINE2_NONE : (uint32_t)l2) |
+                   (uint32_t)wave_steps[(size_t)c * NWAVE + t / 64] << 24;
       const auto& wv = words[(size_t)c * NT + t];
       const uint32_t pad = code(0, A + t % 16, false);
       for (int s2 = 0; s2 < L; ++s2) {

@@ -44,8 +44,22 @@ namespace epic {
 constexpr int STEP_CELL_SHIFT = 15;            // cell byte offset < 128 KB
 constexpr uint32_t STEP_E_MASK = 0x7FF8u;      // E' byte offset < 32 KB, 8-byte aligned
 constexpr uint32_t STEP_LAST_BIT = 1u;         // in the code word
-constexpr int kMaxFixedSteps = 8;              // longer lists run in chunks of 4
-constexpr int kStepChunk = 4;
+constexpr int kMaxFixedSteps = 8;              // held in registers across the barrier;
+constexpr int kStepChunk = 4;                  // up to 4 more loaded after it; longer
+                                               // lists run in chunks of 4
+
+// The second word of a thread's program header: bits 0-23 the line of the
+// wide block's second row pass (HDR_LINE2_NONE: none), bits 24-31 the steps
+// of the thread's wave (0: the block's step count L).  Every lane of a wave
+// holds the same step count, so it is read once per wave.
+constexpr uint32_t HDR_LINE2_NONE = 0xFFFFFFu;
+__device__ __forceinline__ int header_line2(uint32_t h) {
+  return (h & HDR_LINE2_NONE) == HDR_LINE2_NONE ? -1 : (int)(h & HDR_LINE2_NONE);
+}
+__device__ __forceinline__ int header_steps(uint32_t h, int L) {
+  const int s = __builtin_amdgcn_readfirstlane((int)(h >> 24));
+  return s ? s : L;
+}
 
 template <int N> struct FusedShape {
   static constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
@@ -300,22 +314,23 @@ __device__ __forceinline__ void read_e(const char* lds, uint2 step, float2& e0, 
   if (P == 2) e1 = e[ES];
 }
 
-// 2. Gather gridding with exactly LS steps, already loaded into registers
-// (wis: the imaginary weights, read only when CPX).
-template <int N, int P, int RS, int ES, int LS, bool CPX>
-__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[kMaxFixedSteps],
-                                           const float (&wis)[kMaxFixedSteps]) {
-  float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
+// 2. Gather gridding with exactly LS steps, steps[OFF .. OFF + LS), already
+// loaded into registers (wis: the imaginary weights, read only when CPX);
+// s0, s1 carry the sums of a cell whose entries continue in the next call.
+template <int N, int P, int RS, int ES, int LS, bool CPX, int OFF = 0, int SZ>
+__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[SZ],
+                                           const float (&wis)[SZ], float2& s0, float2& s1) {
+  static_assert(OFF + LS <= SZ, "more steps than loaded");
 #pragma unroll
-  for (int st0 = 0; st0 < LS; st0 += kStepChunk) {      // E' reads in groups of 4
+  for (int st0 = OFF; st0 < OFF + LS; st0 += kStepChunk) {   // E' reads in groups of 4
     constexpr int G = kStepChunk;
     float2 e0[G], e1[G];
 #pragma unroll
     for (int st = 0; st < G; ++st)
-      if (st0 + st < LS) read_e<P, ES>(lds, steps[st0 + st], e0[st], e1[st]);
+      if (st0 + st < OFF + LS) read_e<P, ES>(lds, steps[st0 + st], e0[st], e1[st]);
 #pragma unroll
     for (int st = 0; st < G; ++st)
-      if (st0 + st < LS)
+      if (st0 + st < OFF + LS)
         grid_step<N, P, RS, ES, CPX>(lds, xbase, steps[st0 + st], wis[st0 + st], e0[st], e1[st], s0, s1);
   }
 }
@@ -359,34 +374,58 @@ __device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* 
 }
 
 // Steps 1-2 of one sample: load the gridding program (exactly L steps for
-// L <= kMaxFixedSteps), stage E', barrier, grid.  A thread grids only cells
-// of rows its own wave transforms next, so gridding ends with a wave-level
-// fence.  prog is the channel's step list [L][NT] (wim: its imaginary
-// weights when CPX); the switch on L is uniform over the workgroup.
+// L <= kMaxFixedSteps + kStepChunk), stage E', barrier, grid.  A thread grids
+// only cells of rows its own wave transforms next, so gridding ends with a
+// wave-level fence.  prog is the channel's step list (wim: its imaginary
+// weights when CPX), of at least L steps; L is the wave's own step count,
+// uniform over the wave.  Steps past kMaxFixedSteps are loaded after the
+// barrier, once the first G are gridded (their registers free), while the
+// next G are.
 template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX>
 __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, const uint2* prog,
                                                const float* wim, int L, const uint32_t (&cur)[GPT],
                                                const float2 (&g)[GPT], const int (&eidx)[GPT],
                                                int tid, int PA) {
-  if (L <= kMaxFixedSteps) {
-    uint2 steps[kMaxFixedSteps];
-    float wis[kMaxFixedSteps];
+  constexpr int F = kMaxFixedSteps, G = kStepChunk;
+  if (L <= F + G) {
+    uint2 steps[F];
+    float wis[F];
 #pragma unroll
-    for (int st = 0; st < kMaxFixedSteps; ++st) {
+    for (int st = 0; st < F; ++st) {
       if (st < L) steps[st] = prog[st * NT + tid];
       wis[st] = (CPX && st < L) ? wim[st * NT + tid] : 0.f;
     }
     stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
     __syncthreads();
-    switch (L) {
-      case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, steps, wis); break;
-      case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, steps, wis); break;
-      case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, steps, wis); break;
-      case 4: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, steps, wis); break;
-      case 5: grid_fixed<N, P, RS, ES, 5, CPX>(lds, xbase, steps, wis); break;
-      case 6: grid_fixed<N, P, RS, ES, 6, CPX>(lds, xbase, steps, wis); break;
-      case 7: grid_fixed<N, P, RS, ES, 7, CPX>(lds, xbase, steps, wis); break;
-      default: grid_fixed<N, P, RS, ES, 8, CPX>(lds, xbase, steps, wis); break;
+    float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
+    if (L > F) {
+      static_assert(F == 2 * G, "the first G steps are gridded before the rest load");
+      grid_fixed<N, P, RS, ES, G, CPX>(lds, xbase, steps, wis, s0, s1);
+      uint2 more[G];
+      float wmore[G];
+#pragma unroll
+      for (int st = 0; st < G; ++st) {
+        if (F + st < L) more[st] = prog[(F + st) * NT + tid];
+        wmore[st] = (CPX && F + st < L) ? wim[(F + st) * NT + tid] : 0.f;
+      }
+      grid_fixed<N, P, RS, ES, G, CPX, G>(lds, xbase, steps, wis, s0, s1);
+      switch (L - F) {
+        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, more, wmore, s0, s1); break;
+        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, more, wmore, s0, s1); break;
+        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, more, wmore, s0, s1); break;
+        default: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, more, wmore, s0, s1); break;
+      }
+    } else {
+      switch (L) {
+        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 4: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 5: grid_fixed<N, P, RS, ES, 5, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 6: grid_fixed<N, P, RS, ES, 6, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 7: grid_fixed<N, P, RS, ES, 7, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        default: grid_fixed<N, P, RS, ES, 8, CPX>(lds, xbase, steps, wis, s0, s1); break;
+      }
     }
   } else {
     stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
@@ -417,7 +456,7 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
       constexpr int NIN = FusedShape<N>::HW / R;
 #pragma unroll
       for (int n1 = 0; n1 < S; ++n1) v[0][n1] = n1 < NIN ? row[R * n1 + r.n0] : make_float2(0.f, 0.f);
-      line_transform<N, +1, 1, false>(v, tw, r.n0, row, [](int, int s) { return s; });
+      line_transform<N, +1, 1, NIN>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
       for (int q = 0; q < D; ++q)
 #pragma unroll
@@ -425,7 +464,7 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
     } else if (SG > 0) {
 #pragma unroll
       for (int n1 = 0; n1 < S / 2; ++n1) v[0][n1] = row[R * n1 + r.n0];
-      line_transform<N, +1, 1, true>(v, tw, r.n0, row, [](int, int s) { return s; });
+      line_transform<N, +1, 1, S / 2>(v, tw, r.n0, row, [](int, int s) { return s; });
 #pragma unroll
       for (int q = 0; q < D; ++q)
 #pragma unroll
@@ -460,14 +499,15 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
     for (int n1 = 0; n1 < S; ++n1)
       if (n1 < NIN) vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
       else if (WIDE) vp[0][n1] = make_float2(0.f, 0.f);
-    line_transform<N, +1, 1, !WIDE, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
+    line_transform<N, +1, 1, NIN, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
                                     [kl](int, int s) { return s * RS + kl; });
   }
 }
 
 // The whole per-workgroup loop.  WIDE (N = 64): apertures up to HW x HW
 // cells; the programs' header gives each thread a second row-pass line
-// (prog[tid].y, < 0: none) and both passes take their lines' inputs n1 < HW / R.
+// (header_line2, -1: none; whole waves have none, so they skip the pass) and
+// both passes take their lines' inputs n1 < HW / R.
 // MULTI: the launch walks several blocks (FusedArgs::blk); a workgroup whose
 // range crosses into the next block switches inputs, gains, programs and the
 // E' layout of its antenna count at that channel boundary.  Without MULTI
@@ -506,7 +546,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   int nb = MULTI ? block_of(a, (int)it.s) : 0;
   int b = nb;
   int PA = P * a.blk[b].n_ant;                 // of block b
-  int L = a.blk[b].L;
+  int L = a.blk[b].L, Lw = L;                  // L: of block b; Lw: of this wave
   const int KB = a.kblock;
   // the prefetched sample's block: bytes per time sample, first channel
   int64_t n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
@@ -577,7 +617,8 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
       prog = a.blk[b].prog + cl * (L + 1) * NT;
       if (CPX) wim = a.blk[b].wim + cl * (L + 1) * NT + NT;
       line = (int)prog[tid].x;
-      if (WIDE) line2 = (int)prog[tid].y;
+      if (WIDE) line2 = header_line2(prog[tid].y);
+      Lw = header_steps(prog[tid].y, L);
       prog += NT;
 #pragma unroll
       for (int i = 0; i < S; ++i)
@@ -609,7 +650,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
       load_bytes((int)it.s, it.t, nxt);
     }
 
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();

@@ -94,7 +94,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
   int nb = MULTI ? block_of(a, (int)(it.s >> 1)) : 0;
   int b = nb;
   int PA = P * a.blk[b].n_ant;
-  int L = a.blk[b].L;
+  int L = a.blk[b].L, Lw = L;                  // L: of block b; Lw: of this wave
   const int KB = a.kblock;
   int64_t n_row = (int64_t)a.blk[nb].n_chan * P * a.blk[nb].n_ant;
   int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
@@ -172,6 +172,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
         prog = a.blk[b].prog + cl * (L + 1) * NT;
         if (CPX) wim = a.blk[b].wim + cl * (L + 1) * NT + NT;
         line = (int)prog[tid].x;
+        Lw = header_steps(prog[tid].y, L);
         prog += NT;
 #pragma unroll
         for (int i = 0; i < GPT; ++i) {
@@ -201,7 +202,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
     }
 
     // 1. stage and grid the aperture (both parities grid the whole aperture)
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, L, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     // 2. row transforms of row `line` of both polarisations onto the
     //    columns of parity h (h is uniform over the workgroup)
     if (line >= 0) {
@@ -233,7 +234,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
     for (int p = 0; p < P; ++p)
 #pragma unroll
       for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = X[p * PS + (R * n1 + r.n0) * RS + kl];
-    line_transform<N, +1, P, true>(v, tw, r.n0, X,
+    line_transform<N, +1, P, Line<N>::S / 2>(v, tw, r.n0, X,
                                    [kl](int p, int s) { return p * PS + (s & 63) * RS + kl + (s & 64); });
     // v[p][q R + k1] = F_p[2 n0 + q + 16 k1][2 kl + h]
 

@@ -7,7 +7,8 @@ its region; the row-pass lines cover each aperture row of each polarisation
 once, with a wave's rows distinct modulo 4 (N = 64) so the row transform stays
 free of bank conflicts.  Apertures wider than N/2 cells at N = 64 take the wide
 block (48 x 48 cells, a second row-pass line per thread in the header's second
-word)."""
+word, taken by whole waves).  Each wave's step count in the header covers
+every step of its lanes that is not padding."""
 import ctypes
 
 import numpy as np
@@ -97,9 +98,21 @@ def test_programs_reproduce_gridding(name, one_pol):
     for c in range(inp.n_chan):
         # header: every (p, physical row < H) owned by R lanes of one wave
         hdr = prog[c, 0, :, 0].view(np.int32)
-        hdr2 = prog[c, 0, :, 1].view(np.int32)
+        w2 = prog[c, 0, :, 1].astype(np.int64)
+        hdr2 = np.where((w2 & 0xFFFFFF) == 0xFFFFFF, -1, w2 & 0xFFFFFF)
+        steps_w = w2 >> 24
         if not wide:
-            assert np.all(hdr2 == 0)
+            assert np.all(hdr2 == -1)
+        for wv in range(NT // 64):
+            lw = steps_w[64 * wv:64 * wv + 64]
+            assert np.all(lw == lw[0]) and 0 < lw[0] <= nsteps
+        # a wave's second-pass lines are all present or all absent, and at
+        # P = 2 the two-pass waves are waves 0-3
+        if wide:
+            two = [bool(np.all(hdr2[64 * wv:64 * wv + 64] >= 0)) for wv in range(NT // 64)]
+            for wv in range(NT // 64):
+                assert two[wv] or np.all(hdr2[64 * wv:64 * wv + 64] < 0)
+            assert two == ([True] * 4 + [False] * 4 if P == 2 else [False] * 8)
         rows_of_wave = {}
         seen = {}
         for hh in ([hdr, hdr2] if wide else [hdr]):
@@ -137,6 +150,11 @@ def test_programs_reproduce_gridding(name, one_pol):
         assert np.all(cell % 8 == 0)
         cell //= 8
         eoff //= 8
+        # steps past a wave's own count are padding: no store, zero weight
+        lw_t = np.repeat(steps_w[::64], 64)
+        past = np.arange(nsteps)[:, None] >= lw_t[None, :]
+        assert not np.any(last & past)
+        assert np.all(prog[c, 1:, :, 1][past] == 0)
         assert eoff.max() < A + 16 and A + 16 <= ES
         wt = wb.view(np.float32).astype(np.float64)
         assert np.all(cell < N * RS) and np.all(cell % RS < RS)
