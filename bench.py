@@ -576,6 +576,57 @@ def bench_deployment(args) -> int:
     return 0
 
 
+def bench_arrays(args) -> int:
+    """Denser arrays on the LWA-like grid: 256, 512 and 1024 dual-pol antennas
+    in one 26-cell disk (64 x 64 grid, 132 channels, 250 samples).  The three
+    counts select the kernel variants that stage 1, 2 and 4 sample bytes per
+    thread; the 4-byte variant's E' region makes its LDS footprint 87 KB, so
+    one workgroup fits a CU instead of two."""
+    import torch
+    import synth
+    from paper_1904_11422_amd import Imager
+    out = {}
+    for A in (256, 512, 1024):
+        print(f"bench: generating the {A}-antenna array", file=sys.stderr, flush=True)
+        inp = synth.random_problem(8100 + A, 64, A, 132, 2, 250, fill=0.45, min_sep_cells=0.6)
+        N, C, P, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_time
+        ef = torch.from_numpy(inp.efield).cuda()
+        g = torch.from_numpy(inp.gains).cuda()
+        im = Imager(N, C, P, A, timing=True)
+        im.set_antennas(inp.xy_m, inp.freq_hz)
+        img = im.accumulate(ef, g)
+        for _ in range(args.warmup):
+            im.accumulate(ef, g, image=img)
+        torch.cuda.synchronize()
+        ks = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            im.accumulate(ef, g, image=img)
+            ks.append(im.last_timing()[0])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        k_ms = float(np.mean(ks))
+        fl = flops_per_tc(N, P, A)
+        out[f"a{A}"] = {"bytes_per_thread": -(-P * A // 512), "kernel": im.last_kernel_name(),
+                        "kernel_ms": k_ms, "ms_per_step": dt * 1e3, "value": C / dt,
+                        "tc_images_per_s": C * T / (k_ms * 1e-3),
+                        "roofline": {"bound": "alu", "achieved": fl * C * T / (k_ms * 1e-3) / 1e12,
+                                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                                     "frac": fl * C * T / (k_ms * 1e-3) / PEAK_FP32_VALU,
+                                     "traffic": None, "flops_per_tc_image": fl}}
+        im.close()
+    main = out["a1024"]
+    line = {"metric": "channel-images/s for denser arrays (64\u00b2 grid)", "value": main["value"],
+            "unit": "channel-images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": main["ms_per_step"], "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "256 / 512 / 1024 dual-pol antennas in a 26-cell disk, "
+                                   "132 channels, 250 samples, 64x64 grid", "grid_n": 64},
+            "roofline": main["roofline"], "results": out}
+    print(json.dumps(line))
+    return 0
+
+
 def bench_post(args) -> int:
     """Post-processing of the LWA-like image (132 channels, 64 x 64, 4 products):
     pseudo-Stokes I, Q, U, V with the kernel taper divided out, then FITS export."""
@@ -692,6 +743,8 @@ def main() -> int:
     ap.add_argument("--post", action="store_true",
                     help="measure post-processing (pseudo-Stokes with kernel-taper correction) "
                          "and FITS export of the LWA-like image")
+    ap.add_argument("--arrays", action="store_true",
+                    help="256, 512 and 1024 antennas (1, 2 and 4 sample bytes per thread)")
     ap.add_argument("--deployment", action="store_true",
                     help="the paper's deployed geometry (aperture wider than N/2: wide fused "
                          "kernel) against the staged kernels")
@@ -722,6 +775,8 @@ def main() -> int:
         return bench_post(args)
     if args.deployment:
         return bench_deployment(args)
+    if args.arrays:
+        return bench_arrays(args)
 
     import torch
     import synth
