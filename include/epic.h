@@ -141,15 +141,20 @@ epic_status epic_set_antennas_kernels(epic_ctx *ctx, const double *xy_m, const d
  *                    base, << 15 | LDS byte offset of E'[p = 0][a] (a multiple
  *                    of 8), bit 0 set on a cell's last entry; float32 weight}.
  * words: in, the capacity of out in uint32 (0 to query); out, the words needed.
- * layout: out, int32 [7] = {NT, L, row stride, polarisation stride, grid base,
- * E' polarisation stride, row order}, strides and base in float2 units; row
- * order 1: aperture row j is stored at physical row
- * 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and cell offsets use
- * physical rows), 0: at row j.  The aperture block is N/2 x N/2 cells, or at
- * N = 64, when some channel's taps do not fit that, 48 x 48 (the wide block:
- * at P = 2 waves 0-3 run two row passes and waves 4-7 one, at P = 1 waves
- * 0-5 one and waves 6-7 none; the image and its gradient run the wide
- * kernels).
+ * layout: out, int32 [10] = {NT, L, row stride, polarisation stride, grid
+ * base, E' polarisation stride, row order, transposed, block rows, block
+ * columns}, strides and base in float2 units; row order 1: aperture row j is
+ * stored at physical row 8 (j >> 3) + 2 (j & 3) + ((j >> 2) & 1) (headers and
+ * cell offsets use physical rows), 0: at row j.  The aperture block is
+ * N/2 x N/2 cells, or at N = 64, when some channel's taps do not fit that,
+ * the wide block of 32, 40 or 48 rows by 48 columns: the narrower of the
+ * taps' two extents (over all channels) lies along its rows, so with
+ * transposed = 1 the programs grid each tap at (column, row) swapped and the
+ * kernels image the transposed aperture (their results are transposed back).
+ * Its rows fill one row pass of the 8 waves or more: at P = 2 the waves
+ * 0-3 (48 rows) or 0 and 1 (40 rows) run two row passes and the others one;
+ * at P = 1 the first rows / 8 waves run one and the others none.  The image
+ * and its gradient run the wide kernels.
  * Errors: EPIC_E_INVALID (null pointer, bad configuration or geometry),
  * EPIC_E_OFFGRID, EPIC_E_UNSUPPORTED (no fused kernel for cfg, or a channel's
  * taps do not fit the block), EPIC_E_NOMEM (capacity too small;

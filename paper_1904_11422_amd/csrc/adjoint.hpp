@@ -27,6 +27,7 @@ struct AdjointArgs {
   double2* gpartial;        // [W + C - 1][P*A]
   int64_t n_time, total;
   int n_chan, n_ant, kk, L, W;
+  int wrows;                // wide block: its row count (the column pass reads rows below it)
 };
 
 // The upstream gradient at the pixels each thread of the fused kernels owns,
@@ -37,6 +38,7 @@ struct GradTableArgs {
   const double2* grad_image;// [C][NPROD][N][N] (fftshifted)
   float4* gtab;
   int n_chan;
+  int transposed;           // the imaging programs grid the transposed aperture
 };
 
 template <int N, int P>
@@ -50,7 +52,8 @@ __global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
   const Roles<N> r(tid);
   const int q = i / R, k1 = i % R;
   const int km = r.n0 * D + q + S * k1;
-  const int pix = ((km + N / 2) % N) * N + (r.kl + N / 2) % N;
+  const int pm = a.transposed ? r.kl : km, pl = a.transposed ? km : r.kl;   // image row, column
+  const int pix = ((pm + N / 2) % N) * N + (pl + N / 2) % N;
   const double2* gi = a.grad_image + (int64_t)c * NPROD * N * N;
   float4 t;
   t.x = (float)gi[pix].x;
@@ -75,7 +78,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   constexpr int PS = SH::PSTRIDE;
   // E'[p][a] (zero slots at a = A .. A+15), then the grid
-  __shared__ float2 lds2[P * ES + (P - 1) * PS + N * RS];
+  __shared__ __attribute__((aligned(16))) float2 lds2[P * ES + (P - 1) * PS + N * RS];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P, WIDE>(v, X, r, tw);
+    column_pass_fwd<N, P, WIDE>(v, X, r, tw, a.wrows);
 
     // dL/dF* at the owned pixels
     const float4* gt = a.gtab + (int64_t)c * S * NT + tid;

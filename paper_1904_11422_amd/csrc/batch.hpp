@@ -181,6 +181,7 @@ epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, co
     fb.n_chan = x->cfg.n_chan;
     fb.n_ant = x->cfg.n_ant;
     fb.L = x->L;
+    fb.wrows = x->wide ? x->wide_rows : epic::FusedShape<64>::HW;
     c0 += x->cfg.n_chan;
   }
   a.n_blk = (int)L.blocks.size();
@@ -224,6 +225,7 @@ epic_status enqueue_group(epic_batch* b, const BatchLaunch& L, hipStream_t s, co
     for (int k = 0; k < a.n_blk; ++k) {
       r.image[k] = images[L.blocks[k]];
       r.img_c0[k] = a.blk[k].c0;
+      if (b->ctx[L.blocks[k]]->transposed) r.transposed |= 1 << k;
     }
     r.n_img = a.n_blk;
     r.n_time = n_time;

@@ -62,7 +62,28 @@ struct Geometry {
   std::vector<float> wi;              // [C][A][KK] imaginary parts, empty for real kernels
   bool fits_half = true;              // every channel's taps fit an N/2 x N/2 block
   bool fits_wide = true;              // ... a 3N/4 x 3N/4 block (the wide fused variant)
+  int ext_j = 0, ext_i = 0;           // largest extent of a channel's taps in rows, columns
+  // the wide block (orient_wide): rows transformed in the row pass (a multiple
+  // of 8, at least N/2), and whether tcell holds the taps transposed (row and
+  // column swapped, so that the narrower extent lies along the rows)
+  int wide_rows = 0;
+  bool transposed = false;
 };
+
+// Orientation and row count of the wide block (N = 64, an aperture wider
+// than N/2): the row pass transforms one line per aperture row and
+// polarisation, the column pass all N columns, so the narrower extent goes
+// along the rows.  The rows become the smallest multiple of 8 (at least N/2)
+// that holds it; the block keeps 3N/4 columns.  Rotating the grid by a
+// transposition transposes each image, which the reduction and the gradient
+// table undo.
+void orient_wide(Geometry& g, int N) {
+  g.transposed = g.ext_j > g.ext_i;
+  const int narrow = std::min(g.ext_j, g.ext_i);
+  g.wide_rows = std::max(N / 2, (narrow + 7) / 8 * 8);
+  if (g.transposed)
+    for (int& t : g.tcell) t = (t % N) * N + t / N;
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -123,6 +144,8 @@ struct epic_ctx {
   bool fused_ok = true, fused = false;
   bool wide = false;                  // fused, with the wide variant (N = 64, apertures up to 3N/4)
   int fused_w_wide = 0, fused_w_wide_cpx = 0, adj_w_wide = 0, adj_w_wide_cpx = 0;
+  int wide_rows = 0;                  // rows of the wide block (32, 40 or 48)
+  bool transposed = false;            // the fused programs image the transposed aperture
   int fused_gpt = 1;
   int fused_w = 0;                    // persistent workgroups (upper bound)
   int w_override = 0;                 // tuned grid size (0: fused_w)
@@ -250,6 +273,9 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
   }
   g.fits_half = true;
   g.fits_wide = true;
+  g.ext_j = g.ext_i = 0;
+  g.wide_rows = 0;
+  g.transposed = false;
   for (int c = 0; c < C; ++c) {
     const double cell_m = kC0 / freq[c] * cfg.cell_wavelengths;
     int jmin = N, jmax = -1, imin = N, imax = -1;
@@ -282,6 +308,8 @@ epic_status build_geometry(const epic_config& cfg, const double* xy, const doubl
           imax = std::max(imax, (int)i);
         }
     }
+    g.ext_j = std::max(g.ext_j, jmax - jmin + 1);
+    g.ext_i = std::max(g.ext_i, imax - imin + 1);
     if (jmax - jmin + 1 > N / 2 || imax - imin + 1 > N / 2) g.fits_half = false;
     if (jmax - jmin + 1 > 3 * N / 4 || imax - imin + 1 > 3 * N / 4) g.fits_wide = false;
     for (size_t o = (size_t)c * A * g.KK; o < (size_t)(c + 1) * A * g.KK; ++o)
@@ -320,17 +348,25 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   // row slots per wave: CPW / P lines of one polarisation each, or at N = 128
   // CPW rows whose lane group takes both polarisations
   const int SPW = N == 128 ? CPW : CPW / P;
-  // wide (N = 64): an HW x HW block.  Its HW rows per polarisation fill
-  // 1.5 row passes of the 8 waves; rather than every wave running a second
-  // pass with half its lanes, whole waves take two full passes or one: at
-  // P = 2 waves 0-3 own 2 SPW rows (the header's second word holds the
-  // second pass's line) and waves 4-7 SPW rows; at P = 1 waves 0-5 own SPW
-  // rows and waves 6-7 none.  Waves 0-3 sit on the four SIMDs of the CU, one
-  // two-pass wave per SIMD and workgroup.
-  const int HB = wide ? SH::HW : H;                    // aperture block side
-  const int NWR = wide ? (P == 2 ? NWAVE : HB / SPW) : H / SPW;   // waves that own rows
+  // wide (N = 64): a block of HR = g.wide_rows (32, 40 or 48) rows by HW
+  // columns.  Its HR rows per polarisation fill HR P / 64 row passes of the 8
+  // waves (1, 1.25 or 1.5 at P = 2); rather than every wave running a second
+  // pass with part of its lanes, whole waves take two full passes or one: at
+  // P = 2, (HR - N/2) / 4 waves own 2 SPW rows (the header's second word holds
+  // the second pass's line) and the others SPW rows; at P = 1, HR / SPW waves
+  // own SPW rows and the others none.  The two-pass waves are 0-3 (HR = 48)
+  // or 0 and 1 (HR = 40): a CU puts waves w and w + 4 of a workgroup on one
+  // SIMD (measured), so these sit on different SIMDs; of the pairs that do,
+  // 0 and 1 (like 0 and 3, or 1 and 2) measured 2 % faster than 0 and 2, and
+  // a pair on one SIMD (0 and 4) 4 % slower.  Results do not depend on the
+  // choice.
+  const int HR = wide ? g.wide_rows : H;               // aperture rows of the block
+  const int HC = wide ? SH::HW : H;                    // aperture columns of the block
+  const int NWR = wide ? (P == 2 ? NWAVE : HR / SPW) : H / SPW;   // waves that own rows
+  const int NTWO = wide && P == 2 ? (HR - H) / 4 : 0;  // two-pass waves
+  auto two_pass = [&](int w) { return NTWO == 4 ? w < 4 : NTWO == 2 && w < 2; };
   std::vector<int> rpw(NWAVE, 0);                      // rows per wave
-  for (int w = 0; w < NWR; ++w) rpw[w] = wide && P == 2 && w < NWAVE / 2 ? 2 * SPW : SPW;
+  for (int w = 0; w < NWR; ++w) rpw[w] = two_pass(w) ? 2 * SPW : SPW;
   const int RPW = *std::max_element(rpw.begin(), rpw.end());
   // residue rule (row j of slot s in a wave of group t has j mod M = residue):
   // at N = 64 it puts the 4 (P = 2) or 8 (P = 1) rows a half-wave transforms
@@ -374,21 +410,21 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
   std::vector<int> wave_steps((size_t)C * NWAVE, 0);
   L = 1;
   for (int c = 0; c < C; ++c) {
-    std::vector<Run> cells(HB * HB);
-    for (int j = 0; j < HB; ++j)
-      for (int i = 0; i < HB; ++i) cells[j * HB + i].cell = SH::phys_row(j) * RS + i;
+    std::vector<Run> cells(HR * HC);
+    for (int j = 0; j < HR; ++j)
+      for (int i = 0; i < HC; ++i) cells[j * HC + i].cell = SH::phys_row(j) * RS + i;
     for (int a = 0; a < A; ++a)
       for (int k = 0; k < KK; ++k) {
         const size_t o = ((size_t)c * A + a) * KK + k;
         const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-        cells[j * HB + i].ent.push_back({a, o});
+        cells[j * HC + i].ent.push_back({a, o});
       }
     // rows to (wave, slot): slot s of a wave in group t takes a row j with
     // j mod M = residue(s, t); each residue class has exactly as many rows as
     // the group has waves, dealt heaviest first to the least loaded wave
-    std::vector<int> row_load(HB, 0);
-    for (int j = 0; j < HB; ++j)
-      for (int i = 0; i < HB; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * HB + i].ent.size());
+    std::vector<int> row_load(HR, 0);
+    for (int j = 0; j < HR; ++j)
+      for (int i = 0; i < HC; ++i) row_load[j] += (int)std::max<size_t>(1, cells[j * HC + i].ent.size());
     std::vector<int> wave_load(NWAVE, 0);
     std::vector<std::vector<int>> row_of(NWAVE, std::vector<int>(RPW, -1));
     const int WPG = NWR / NGRP;                        // waves per group
@@ -422,7 +458,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
       auto cost = [&](int w) { return wave_load[w] + (rpw[w] > SPW ? 64 * kPassSteps : 0); };
       for (int k = 0; k < NCLS; ++k) {
         std::vector<int> rows;
-        for (int j = 0; j < HB; ++j)
+        for (int j = 0; j < HR; ++j)
           if (cls(j) == k) rows.push_back(j);
         std::stable_sort(rows.begin(), rows.end(), [&](int x, int y) { return row_load[x] > row_load[y]; });
         for (int j : rows) {
@@ -462,7 +498,7 @@ void build_programs(const Geometry& g, int P, int gpt, std::vector<uint32_t>& ou
     for (int w = 0; w < NWR; ++w) {
       std::vector<const Run*> wc;
       for (int sl = 0; sl < rpw[w]; ++sl)
-        for (int i = 0; i < HB; ++i) wc.push_back(&cells[row_of[w][sl] * HB + i]);
+        for (int i = 0; i < HC; ++i) wc.push_back(&cells[row_of[w][sl] * HC + i]);
       using Load = std::pair<int, int>;                // (steps, thread)
       auto steps_of = [](const Run* r) { return (int)std::max<size_t>(1, r->ent.size()); };
       // longest cell first to the least loaded of the given lanes
@@ -1315,6 +1351,7 @@ epic::FusedArgs single_block_args(const epic_ctx* x, const uint8_t* efield, cons
   b.n_chan = x->cfg.n_chan;
   b.n_ant = x->cfg.n_ant;
   b.L = x->L;
+  b.wrows = x->wide ? x->wide_rows : epic::FusedShape<64>::HW;
   a.n_blk = 1;
   a.twiddle = x->twiddle.as<float2>();
   a.partial = partial;
@@ -1412,6 +1449,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.autos = nullptr;
     r.K = x->cfg.kernel_support;
     r.autos_cpx = x->cpx ? 1 : 0;
+    r.transposed = x->transposed ? 1 : 0;
     if (x->autos) {
       launch_auto_table(x, efield, n_time, gains);
       r.autos = x->au_tab.as<double>();
@@ -1481,6 +1519,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     r.autos = nullptr;
     r.K = x->cfg.kernel_support;
     r.autos_cpx = x->cpx ? 1 : 0;
+    r.transposed = 0;
     if (x->autos) {
       launch_auto_table(x, efield, n_time, gains);
       r.autos = x->au_tab.as<double>();
@@ -1768,6 +1807,7 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   if (s != EPIC_OK) { g_init_error = m; return s; }
   const bool wide = N == 64 && !g.fits_half && g.fits_wide;
   if (!g.fits_half && !wide) { g_init_error = "taps do not fit the fused kernels' aperture block"; return EPIC_E_UNSUPPORTED; }
+  if (wide) orient_wide(g, N);
   std::vector<uint32_t> prog;
   int L = 0;
   if (N == 32) build_programs<32>(g, P, gpt, prog, L);
@@ -1785,6 +1825,9 @@ epic_status epic_gridding_program(const epic_config* cfg, const double* xy_m, co
   layout[4] = P * ES;
   layout[5] = ES;
   layout[6] = N == 64 ? 1 : 0;
+  layout[7] = wide && g.transposed ? 1 : 0;
+  layout[8] = wide ? g.wide_rows : N == 128 ? 64 : N / 2;
+  layout[9] = wide ? epic::FusedShape<64>::HW : N == 128 ? 64 : N / 2;
   if (cap == 0) return EPIC_OK;
   if (!out || cap < need) { g_init_error = "output capacity too small"; return EPIC_E_NOMEM; }
   std::memcpy(out, prog.data(), prog.size() * sizeof(uint32_t));
@@ -1829,6 +1872,9 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
   // (aliased images) run the staged kernels.
   x->wide = x->fused_ok && N == 64 && !g.fits_half && g.fits_wide;
   x->fused = x->fused_ok && (g.fits_half || x->wide);
+  if (x->wide) orient_wide(g, N);
+  x->wide_rows = x->wide ? g.wide_rows : 0;
+  x->transposed = x->wide && g.transposed;
 
   if (x->fused) {
     // adjoint taps [C][A][KK] {translated cell, w}
@@ -1974,6 +2020,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
     ta.grad_image = reinterpret_cast<const double2*>(grad_image);
     ta.gtab = x->gtab.as<float4>();
     ta.n_chan = C;
+    ta.transposed = x->transposed ? 1 : 0;
     const int N = x->cfg.grid_n, P = x->cfg.n_pol;
     const dim3 tg((unsigned)(((int64_t)C * N * N + 255) / 256));
     if (N == 32 && P == 1) hipLaunchKernelGGL((epic::grad_table_kernel<32, 1>), tg, dim3(256), 0, x->stream, ta);
@@ -2000,6 +2047,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.n_ant = x->cfg.n_ant;
   a.kk = x->cfg.kernel_support * x->cfg.kernel_support;
   a.L = x->L;
+  a.wrows = x->wide ? x->wide_rows : epic::FusedShape<64>::HW;
   const int aw = x->wide ? (x->cpx ? x->adj_w_wide_cpx : x->adj_w_wide) : (x->cpx ? x->adj_w_cpx : x->adj_w);
   a.W = (int)std::min<int64_t>(aw, total);
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");

@@ -119,6 +119,7 @@ struct FusedBlock {
   const float* wim;         // [C_b][1 + L_b][NT] imaginary step weights (complex kernels), or null
   int c0;                   // first channel of the block in the launch's channel order
   int n_chan, n_ant, L;
+  int wrows;                // wide block: its row count (the column pass reads rows below it)
 };
 
 // Work partition of a persistent launch.  The launch's units form one flat
@@ -483,11 +484,13 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 }
 
 // 3b. Forward column transforms of column r.kl for all polarisations; only
-// rows < H (WIDE: < HW) are nonzero (stored at their physical rows).
-// Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
+// rows < H (WIDE: < rows, the wide block's row count, a multiple of R from
+// H to HW, uniform) are nonzero (stored at their physical rows, which for
+// whole groups of R rows are the same rows); the other rows of the grid are
+// not read.  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
 template <int N, int P, bool WIDE = false>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
-                                                const Roles<N>& r, const float2* tw) {
+                                                const Roles<N>& r, const float2* tw, int rows = 0) {
   using SH = FusedShape<N>;
   constexpr int S = Line<N>::S, R = Line<N>::R, RS = SH::RS, PS = SH::PSTRIDE;
   constexpr int NIN = WIDE ? SH::HW / R : S / 2;
@@ -497,7 +500,8 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
     float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
 #pragma unroll
     for (int n1 = 0; n1 < S; ++n1)
-      if (n1 < NIN) vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
+      if (n1 < S / 2 || (n1 < NIN && R * n1 < rows))
+        vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
       else if (WIDE) vp[0][n1] = make_float2(0.f, 0.f);
     line_transform<N, +1, 1, NIN, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
                                     [kl](int, int s) { return s * RS + kl; });
@@ -520,7 +524,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   constexpr int ES = EStride<NT, GPT, P>::value;
   constexpr int XBASE = P * ES * (int)sizeof(float2);
   // E'[p][a] (zero slots at a = A .. A+15), then the grid
-  __shared__ float2 lds2[P * ES + (P - 1) * SH::PSTRIDE + N * RS];
+  __shared__ __attribute__((aligned(16))) float2 lds2[P * ES + (P - 1) * SH::PSTRIDE + N * RS];
   char* lds = reinterpret_cast<char*>(lds2);
   float2* E = lds2;
   float2* X = lds2 + P * ES;
@@ -554,6 +558,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   const uint8_t* n_src = a.blk[nb].efield;
   int eidx[GPT];
   init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+  int wrows = a.blk[b].wrows;                  // wide block rows of block b
 
   float acc[S][NACC];                          // float32 sums over <= KB samples
   float2 g[GPT];
@@ -612,6 +617,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
         PA = P * a.blk[b].n_ant;
         L = a.blk[b].L;
         init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+        wrows = a.blk[b].wrows;
       }
       const int64_t cl = c - a.blk[b].c0;      // channel within the block
       prog = a.blk[b].prog + cl * (L + 1) * NT;
@@ -655,7 +661,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P, WIDE>(v, X, r, tw);
+    column_pass_fwd<N, P, WIDE>(v, X, r, tw, wrows);
 
     // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
 #pragma unroll
@@ -727,6 +733,7 @@ struct ReduceArgs {
                             // ([C][(2K-1)^2][NACC (x2 with autos_cpx)], autos.hpp), or null
   int K;
   int autos_cpx;            // the table has the sin part (complex kernels)
+  int transposed;           // bit b set: the slots of image b hold the transposed image
 };
 
 // Team whose range contains flat index f: the largest w with
@@ -815,18 +822,23 @@ __global__ void __launch_bounds__(256) reduce_image_kernel(ReduceArgs a) {
                 a.autos_cpx ? 2 * NACC : NACC, ast, acs, asn);
   combine_sublanes<NACC>(s, a.sub, ppb, j, lp, red);
   if (!valid || j != 0) return;
+  int b = 0;                                 // the image of channel c
+  for (int i = 1; i < a.n_img; ++i)
+    if (a.img_c0[i] <= c) b = i;
   int km, kl;
   if (THREAD_MAJOR) {
     constexpr int NT = FusedShape<N>::NT;
     owned_pixel<N>(pix % NT, pix / NT, km, kl);
+    if ((a.transposed >> b) & 1) {           // the kernel imaged the transposed aperture
+      const int t = km;
+      km = kl;
+      kl = t;
+    }
   } else {
     km = pix / N;
     kl = pix % N;
   }
   const int qm = (km + N / 2) % N, ql = (kl + N / 2) % N;
-  int b = 0;                                 // the image of channel c
-  for (int i = 1; i < a.n_img; ++i)
-    if (a.img_c0[i] <= c) b = i;
   double2* img = reinterpret_cast<double2*>(a.image[b]);
   constexpr int NPROD = (P == 2) ? 4 : 1;
   const int64_t base = (int64_t)(c - a.img_c0[b]) * NPROD * NPIX + qm * N + ql;

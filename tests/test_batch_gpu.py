@@ -147,6 +147,25 @@ def test_mixed_antenna_counts_share_a_launch():
         assert oracle.rel_errors(imgs[k].cpu().numpy(), ref).max() <= 1e-5
 
 
+def test_wide_blocks_of_both_orientations_share_a_launch():
+    """Apertures wider than N/2 at N = 64 in one grouped launch: blocks whose
+    wide block has 40 or 48 rows and whose taps are transposed or not (the
+    deployed ellipse, elongated along the rows, is transposed), plus a block
+    of the N/2 block in its own launch.  Each image matches the oracle."""
+    import torch
+    inputs = [synth.deployment(801, n_time=11, n_chan=2),            # 40 rows, transposed
+              synth.random_problem(131, 64, 200, 2, 2, 11, fill=0.7),  # 48 rows, transposed
+              synth.random_problem(806, 64, 180, 1, 2, 11, fill=0.6),  # 40 rows
+              synth.random_problem(805, 64, 150, 2, 2, 11, fill=0.4)]  # the N/2 block
+    b, ef, g = _batch(inputs)
+    lp = b.launch_plan()
+    print(lp, flush=True)
+    assert [x[0] for x in lp] == [0, 0, 0, 1] and lp[0][1] == 3
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    _check_blocks(imgs, inputs)
+
+
 def test_ungroupable_blocks_run_alone_and_groups_hold_eight():
     """A staged block and a block with autocorrelation removal run through
     their own contexts; nine groupable 32 x 32 blocks form two launches."""

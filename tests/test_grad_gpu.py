@@ -186,13 +186,20 @@ def test_config5_full_shape_gradient():
 
 
 @pytest.mark.parametrize("seed,A,C,P,T,fill,K", [(231, 120, 2, 2, 7, 0.62, 3), (241, 90, 2, 1, 9, 0.7, 3),
-                                                 (242, 600, 1, 2, 3, 0.62, 3), (243, 80, 2, 2, 5, 0.45, 11)])
+                                                 (242, 600, 1, 2, 3, 0.62, 3), (243, 80, 2, 2, 5, 0.45, 11),
+                                                 (244, 256, 2, 2, 6, None, 3)])
 def test_wide_grad_matches_oracle(seed, A, C, P, T, fill, K):
     """Apertures of 33-48 cells at N = 64: the wide fused image and its adjoint
-    (adjoint_wide_kernel) against the oracle's gradient; K > 3 with complex kernels."""
+    (adjoint_wide_kernel) against the oracle's gradient; K > 3 with complex
+    kernels.  The cases cover wide blocks of 40 and 48 rows, with the taps
+    transposed (the narrower extent along the rows) or not; fill None is the
+    deployed ellipse (40 rows, transposed)."""
     import torch
     from paper_1904_11422_amd import Imager
-    inp = synth.random_problem(seed, 64, A, C, P, T, fill=fill)
+    if fill is None:
+        inp = synth.deployment(seed, n_time=T, n_chan=C, n_pol=P)
+    else:
+        inp = synth.random_problem(seed, 64, A, C, P, T, fill=fill)
     if K != 3:
         inp = synth.with_kernels(inp, K, seed + 1)
     print(f"case {seed}: A={A} C={C} P={P} T={T} fill={fill} K={K}", flush=True)

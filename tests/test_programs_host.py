@@ -6,8 +6,9 @@ a thread of the wave that transforms its row; every LDS offset stays inside
 its region; the row-pass lines cover each aperture row of each polarisation
 once, with a wave's rows distinct modulo 4 (N = 64) so the row transform stays
 free of bank conflicts.  Apertures wider than N/2 cells at N = 64 take the wide
-block (48 x 48 cells, a second row-pass line per thread in the header's second
-word, taken by whole waves).  Each wave's step count in the header covers
+block (48 columns and 32, 40 or 48 rows holding the narrower extent, the taps
+transposed when that is the column extent; a second row-pass line per thread
+in the header's second word, taken by whole waves).  Each wave's step count in the header covers
 every step of its lanes that is not padding."""
 import ctypes
 
@@ -32,7 +33,7 @@ def _program(inp, n_pol=None):
     f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
     words = ctypes.c_int64(0)
-    layout = (ctypes.c_int32 * 7)()
+    layout = (ctypes.c_int32 * 10)()
     st = L.epic_gridding_program(ctypes.byref(cfg), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
                                  None, ctypes.byref(words), layout)
     assert st == _lib.EPIC_OK, L.epic_last_error(None)
@@ -41,9 +42,10 @@ def _program(inp, n_pol=None):
                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                                  ctypes.byref(words), layout)
     assert st == _lib.EPIC_OK, L.epic_last_error(None)
-    NT, nsteps, RS, PS, XB, ES, order = list(layout)
+    NT, nsteps, RS, PS, XB, ES, order, transposed, HR, HC = list(layout)
     return out.reshape(inp.n_chan, 1 + nsteps, NT, 2), dict(NT=NT, L=nsteps, RS=RS, PS=PS, XB=XB,
-                                                            ES=ES, P=P, order=order)
+                                                            ES=ES, P=P, order=order,
+                                                            transposed=transposed, HR=HR, HC=HC)
 
 
 def _phys(j, order):
@@ -87,11 +89,17 @@ def test_programs_reproduce_gridding(name, one_pol):
     R = R_OF[N]
     X, Y = oracle.antenna_cells(inp.xy_m, inp.freq_hz, N)
     ii, jj, w = oracle.kernel_taps(X, Y, N)
-    ext = max(int((ii.max(axis=(1, 2)) - ii.min(axis=(1, 2))).max()),
-              int((jj.max(axis=(1, 2)) - jj.min(axis=(1, 2))).max())) + 1
-    wide = ext > N // 2
-    assert not wide or (N == 64 and ext <= 48 and "wide" in name or "deployment" in name)
-    H = 48 if wide else N // 2
+    ext_i = int((ii.max(axis=(1, 2)) - ii.min(axis=(1, 2))).max()) + 1
+    ext_j = int((jj.max(axis=(1, 2)) - jj.min(axis=(1, 2))).max()) + 1
+    wide = max(ext_i, ext_j) > N // 2
+    assert not wide or (N == 64 and max(ext_i, ext_j) <= 48 and "wide" in name or "deployment" in name)
+    # the wide block: the narrower extent along its rows (transposed when
+    # that is the column extent), rows a multiple of 8 and at least N/2
+    tr = wide and ext_j > ext_i
+    HR = max(N // 2, (min(ext_i, ext_j) + 7) // 8 * 8) if wide else (64 if N == 128 else N // 2)
+    HC = 48 if wide else (64 if N == 128 else N // 2)
+    assert (g["transposed"], g["HR"], g["HC"]) == (int(tr), HR, HC)
+    H = HR
     rng = np.random.default_rng(0)
     phys = _phys(np.arange(H), g["order"])
     assert sorted(phys) == list(range(H))
@@ -106,13 +114,14 @@ def test_programs_reproduce_gridding(name, one_pol):
         for wv in range(NT // 64):
             lw = steps_w[64 * wv:64 * wv + 64]
             assert np.all(lw == lw[0]) and 0 < lw[0] <= nsteps
-        # a wave's second-pass lines are all present or all absent, and at
-        # P = 2 the two-pass waves are waves 0-3
+        # a wave's second-pass lines are all present or all absent; at P = 2
+        # the two-pass waves are waves 0-3 (48 rows) or 0 and 1 (40 rows)
         if wide:
             two = [bool(np.all(hdr2[64 * wv:64 * wv + 64] >= 0)) for wv in range(NT // 64)]
             for wv in range(NT // 64):
                 assert two[wv] or np.all(hdr2[64 * wv:64 * wv + 64] < 0)
-            assert two == ([True] * 4 + [False] * 4 if P == 2 else [False] * 8)
+            want = {48: [0, 1, 2, 3], 40: [0, 1], 32: []}[HR] if P == 2 else []
+            assert two == [wv in want for wv in range(8)]
         rows_of_wave = {}
         seen = {}
         for hh in ([hdr, hdr2] if wide else [hdr]):
@@ -170,15 +179,15 @@ def test_programs_reproduce_gridding(name, one_pol):
             np.add.at(stores, cell[st, idx], 1)
             for t in idx:                       # stored by the wave owning the row
                 j, i = divmod(int(cell[st, t]), RS)
-                assert j < H and i < H and j in rows_of_wave[t // 64]
+                assert j < HR and i < HC and j in rows_of_wave[t // 64]
             s[idx] = 0.0
         ti = ii[c] - ii[c].min()
         tj = jj[c] - jj[c].min()
-        ref = np.zeros((H, H))
-        np.add.at(ref, (tj, ti), w[c] * E[:A, None])
-        got = grid.reshape(N, RS)[phys, :H]
-        assert np.all(stores.reshape(N, RS)[:H, :H] == 1)
-        assert stores.sum() == H * H
+        ref = np.zeros((HR, HC))
+        np.add.at(ref, (ti, tj) if tr else (tj, ti), w[c] * E[:A, None])
+        got = grid.reshape(N, RS)[phys, :HC]
+        assert np.all(stores.reshape(N, RS)[:HR, :HC] == 1)
+        assert stores.sum() == HR * HC
         assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
 
 
@@ -188,7 +197,7 @@ def test_program_query_and_errors():
     dp = ctypes.POINTER(ctypes.c_double)
     xy = np.ascontiguousarray(inp.xy_m, dtype=np.float64)
     f = np.ascontiguousarray(inp.freq_hz, dtype=np.float64)
-    layout = (ctypes.c_int32 * 7)()
+    layout = (ctypes.c_int32 * 10)()
     words = ctypes.c_int64(0)
     staged = _lib.EpicConfig(32, 1, 1, 16, 3, 0.5, 0.5, _lib.EPIC_FP32, _lib.EPIC_FLAG_STAGED)
     assert L.epic_gridding_program(ctypes.byref(staged), xy.ctypes.data_as(dp), f.ctypes.data_as(dp),
