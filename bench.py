@@ -338,42 +338,43 @@ def bench_grad(args) -> int:
     return 0
 
 
-def bench_autos(args) -> int:
+def autos_results(steps: int, warmup: int, inp=None) -> dict:
     """The default workload with the antenna autocorrelations removed: one
     imaging call per step, then the removal (a second pass over the E-field
     for the exact per-antenna sums, a per-channel table, a pass over the image)."""
     import torch
     import synth
     from paper_1904_11422_amd import Imager
-    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
-    inp = synth.config2()
+    if inp is None:
+        print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+        inp = synth.config2()
     N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
     ef = torch.from_numpy(inp.efield).cuda()
     g = torch.from_numpy(inp.gains).cuda()
     im = Imager(N, C, P, A, timing=True, remove_autos=True)
     im.set_antennas(inp.xy_m, inp.freq_hz)
     img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         im.accumulate(ef, g, image=img)
     torch.cuda.synchronize()
     print("bench: timing imaging with autocorrelation removal", file=sys.stderr, flush=True)
     main_ms, sum_ms, rem_ms = [], [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         im.accumulate(ef, g, image=img)
         main_ms.append(im.last_timing()[0])
         s, r = im.last_autos_timing()
         sum_ms.append(s)
         rem_ms.append(r)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     nq = 4 if P == 2 else 1
     # algorithmic bytes of the sum pass: every sample byte once, the exact
     # per-antenna sums (nq int32) out once
     alg = C * T * P * A + C * A * nq * 4
     s_ms = float(np.mean(sum_ms))
     out = {"metric": "channel-images/s with autocorrelations removed", "value": C / dt,
-           "unit": "channel-images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "unit": "channel-images/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "LWA-like: 256 dual-pol antennas, 132 channels, 64x64 grid, "
@@ -386,11 +387,16 @@ def bench_autos(args) -> int:
                         "unit": "GB/s", "frac": alg / (s_ms * 1e-3) / PEAK_HBM,
                         "traffic": measured_traffic(AUTOS_PROFILE, AUTOS_SOURCES),
                         "bytes_per_launch": alg}}
-    print(json.dumps(out))
+    im.close()
+    return out
+
+
+def bench_autos(args) -> int:
+    print(json.dumps(autos_results(args.steps, args.warmup)))
     return 0
 
 
-def bench_stream(args) -> int:
+def stream_results(steps: int, warmup: int, inp=None) -> dict:
     """Streaming ingest: gulps of the LWA-like workload arriving as 264 channels
     [T][C][A][P] in pinned host memory, the central 132 channels selected (a
     contiguous sub-band, so only it crosses the host link), transposed and
@@ -399,7 +405,8 @@ def bench_stream(args) -> int:
     import synth
     from paper_1904_11422_amd import Imager, Pipeline
     print("bench: generating two raw gulps", file=sys.stderr, flush=True)
-    inp = synth.config2()
+    if inp is None:
+        inp = synth.config2()
     N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
     c_in, c0 = 2 * C, C // 2
     gulps = [torch.from_numpy(synth.raw_gulp(9000 + k, T, c_in, A, P)).pin_memory() for k in range(2)]
@@ -422,19 +429,19 @@ def bench_stream(args) -> int:
     fe_bytes = 2 * T * C * P * A
     del dev_raw
     pipe = Pipeline(im, T, c_in, c0, 1, sample_s=40e-6)
-    for k in range(args.warmup):
+    for k in range(warmup):
         pipe.push(gulps[k % 2], g, img)
     pipe.report()
     pipe.close()
     pipe = Pipeline(im, T, c_in, c0, 1, sample_s=40e-6)
     print("bench: streaming", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         pipe.push(gulps[k % 2], g, img)
     st = pipe.report()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     out = {"metric": "streamed channel-images/s (host gulps -> images)", "value": C / dt,
-           "unit": "channel-images/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "unit": "channel-images/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
            "ms_per_step": dt * 1e3, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "LWA-like gulps: 264 channels arriving [T][C][A][P] in pinned "
                                   "host memory, central 132 imaged (64x64, 256 dual-pol antennas), "
@@ -447,12 +454,17 @@ def bench_stream(args) -> int:
                         "achieved": fe_bytes / (fe_ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9,
                         "unit": "GB/s", "frac": fe_bytes / (fe_ms * 1e-3) / PEAK_HBM,
                         "traffic": None, "kernel_ms": fe_ms, "bytes_per_launch": fe_bytes}}
-    print(json.dumps(out))
     pipe.close()
+    im.close()
+    return out
+
+
+def bench_stream(args) -> int:
+    print(json.dumps(stream_results(args.steps, args.warmup)))
     return 0
 
 
-def bench_kernels(args) -> int:
+def kernels_results(steps: int, warmup: int, inp=None) -> dict:
     """The LWA-like workload gridded with seeded complex kernels per channel and
     antenna (A-projection-like): 5 x 5 on the 64 x 64 grid (the largest support
     whose taps keep this aperture inside N/2 cells, so the N/2 fused kernel runs),
@@ -460,8 +472,10 @@ def bench_kernels(args) -> int:
     import torch
     import synth
     from paper_1904_11422_amd import Imager
-    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
-    base = synth.config2()
+    if inp is None:
+        print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+        inp = synth.config2()
+    base = inp
     ef = torch.from_numpy(base.efield).cuda()
     g = torch.from_numpy(base.gains).cuda()
     out = {}
@@ -471,11 +485,11 @@ def bench_kernels(args) -> int:
         im = Imager(N, C, P, A, kernel_support=K, timing=True)
         im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
         img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             im.accumulate(ef, g, image=img)
         torch.cuda.synchronize()
         ks = []
-        steps = args.steps if N == 64 else max(3, args.steps // 4)
+        steps = steps if N == 64 else max(3, steps // 4)
         t0 = time.perf_counter()
         for _ in range(steps):
             im.accumulate(ef, g, image=img)
@@ -494,7 +508,7 @@ def bench_kernels(args) -> int:
         im.close()
     main = out["n64_k5"]
     line = {"metric": "channel-images/s with complex per-antenna kernels", "value": main["value"],
-            "unit": "channel-images/s", "n_gpus": 1, "steps": main["steps"], "warmup": args.warmup,
+            "unit": "channel-images/s", "n_gpus": 1, "steps": main["steps"], "warmup": warmup,
             "ms_per_step": main["ms_per_step"], "higher_is_better": True, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": "LWA-like (256 dual-pol antennas, 132 channels, 1000 samples) "
@@ -502,11 +516,15 @@ def bench_kernels(args) -> int:
                                    "antenna on 64x64; also 15x15 on 128x128",
                        "grid_n": 64, "kernel_support": 5},
             "roofline": main["roofline"], "results": out}
-    print(json.dumps(line))
+    return line
+
+
+def bench_kernels(args) -> int:
+    print(json.dumps(kernels_results(args.steps, args.warmup)))
     return 0
 
 
-def bench_deployment(args) -> int:
+def deployment_results(steps: int, warmup: int, inp=None) -> dict:
     """The paper's deployed geometry (Sec. 4.1-4.2: 256 antennas in a 110 m x
     100 m ellipse, lambda / 2 cells, 64 x 64 grid) over 132 channels of 25 kHz
     centred on 55.25 MHz, one 50 ms image (1250 samples of 40 us) per step.
@@ -525,10 +543,10 @@ def bench_deployment(args) -> int:
         im = Imager(N, C, P, A, staged=staged, timing=True)
         im.set_antennas(inp.xy_m, inp.freq_hz)
         img = torch.empty(im.image_shape(), dtype=torch.complex128, device="cuda")
-        for _ in range(args.warmup if not staged else 1):
+        for _ in range(warmup if not staged else 1):
             im.accumulate(ef, g, image=img)
         torch.cuda.synchronize()
-        steps = args.steps if not staged else max(2, args.steps // 5)
+        steps = steps if not staged else max(2, steps // 5)
         ks = []
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -565,14 +583,18 @@ def bench_deployment(args) -> int:
                                             / main["gradient_ms_per_call"])
     line = {"metric": "channel-images/s (4-pol, 64\u00b2 grid), the paper's deployed geometry",
             "value": main["value"], "unit": "channel-images/s", "n_gpus": 1,
-            "steps": main["steps"], "warmup": args.warmup, "ms_per_step": main["ms_per_step"],
+            "steps": main["steps"], "warmup": warmup, "ms_per_step": main["ms_per_step"],
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "256 dual-pol antennas uniform in a 110 m x 100 m ellipse, "
                                    "132 x 25 kHz channels at 55.25 MHz, 64x64 grid at lambda/2, "
                                    "3x3 Gaussian, 1250 samples (one 50 ms image)",
                        "grid_n": 64, "n_time": T},
             "roofline": main["roofline"], "results": out}
-    print(json.dumps(line))
+    return line
+
+
+def bench_deployment(args) -> int:
+    print(json.dumps(deployment_results(args.steps, args.warmup)))
     return 0
 
 
@@ -627,30 +649,31 @@ def bench_arrays(args) -> int:
     return 0
 
 
-def bench_post(args) -> int:
+def post_results(steps: int, warmup: int, inp=None) -> dict:
     """Post-processing of the LWA-like image (132 channels, 64 x 64, 4 products):
     pseudo-Stokes I, Q, U, V with the kernel taper divided out, then FITS export."""
     import tempfile
     import torch
     import synth
     from paper_1904_11422_amd import Imager, fits
-    print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
-    inp = synth.config2()
+    if inp is None:
+        print("bench: generating the LWA-like workload", file=sys.stderr, flush=True)
+        inp = synth.config2()
     N, C, P, A, T = inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.n_time
     im = Imager(N, C, P, A)
     im.set_antennas(inp.xy_m, inp.freq_hz)
     img = im.accumulate(torch.from_numpy(inp.efield).cuda(), torch.from_numpy(inp.gains).cuda())
     out = im.postprocess(img, 1e-3)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         im.postprocess(img, 1e-3, out=out)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for _ in range(args.steps):
+    for _ in range(steps):
         im.postprocess(img, 1e-3, out=out)
     e1.record()
     torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.steps
+    k_ms = e0.elapsed_time(e1) / steps
     # algorithmic bytes: the four complex128 products in, the taper, four float64 planes out
     alg = C * N * N * (4 * 16 + 8 + 4 * 8)
     with tempfile.TemporaryDirectory() as d:
@@ -660,7 +683,7 @@ def bench_post(args) -> int:
         fits_s = time.perf_counter() - t0
     line = {"metric": "post-processed channel images/s (pseudo-Stokes, taper-corrected)",
             "value": C / (k_ms * 1e-3), "unit": "channel-images/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": k_ms,
+            "steps": steps, "warmup": warmup, "ms_per_step": k_ms,
             "higher_is_better": True, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "LWA-like image: 132 channels, 4 products, 64x64, "
                                    "taper floor 1e-3", "grid_n": N, "n_chan": C},
@@ -669,7 +692,12 @@ def bench_post(args) -> int:
                          "unit": "GB/s", "frac": alg / (k_ms * 1e-3) / PEAK_HBM,
                          "traffic": None, "bytes_per_launch": alg, "kernel_ms": k_ms},
             "fits_write_s": fits_s, "fits_bytes": C * 4 * N * N * 4}
-    print(json.dumps(line))
+    im.close()
+    return line
+
+
+def bench_post(args) -> int:
+    print(json.dumps(post_results(args.steps, args.warmup)))
     return 0
 
 
@@ -723,7 +751,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-staged", action="store_true")
     ap.add_argument("--no-rows", action="store_true",
-                    help="leave out the compact split-precision, gradient and batch results")
+                    help="leave out the compact results of the other rows (split precision, gradient, "
+                         "batch, deployed geometry, autocorrelations, complex kernels, post-processing, "
+                         "streaming)")
     ap.add_argument("--batch", action="store_true",
                     help="measure the heterogeneous batch (grids 32/64/128, 64/256/1024 "
                          "antennas, 16-264 channels, 200 samples) instead of the default line")
@@ -855,6 +885,14 @@ def main() -> int:
         subs["split_precision"] = split_results(sub_steps, with_oracle=not args.no_cpu)
         subs["gradient"] = grad_results(sub_steps, args.warmup)
         subs["batch"] = batch_results(sub_steps, args.warmup, sequential=False)
+        # the paper's deployed geometry (wide aperture block) and the further rows:
+        # autocorrelation removal, per-antenna complex kernels, post-processing,
+        # streamed ingest from host gulps
+        subs["deployed_geometry"] = deployment_results(sub_steps, args.warmup)
+        subs["autocorrelation_removal"] = autos_results(sub_steps, args.warmup, inp)
+        subs["complex_kernels"] = kernels_results(sub_steps, args.warmup, inp)
+        subs["post_processing"] = post_results(sub_steps, args.warmup, inp)
+        subs["streaming"] = stream_results(sub_steps, args.warmup, inp)
 
     cpu = None
     if not args.no_cpu:
