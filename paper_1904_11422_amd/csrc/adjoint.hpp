@@ -68,8 +68,10 @@ __global__ void __launch_bounds__(256) grad_table_kernel(GradTableArgs a) {
   a.gtab[idx] = t;
 }
 
-// WIDE (N = 64): the wide block of the forward (rows and columns < HW, a
-// second row-pass line per thread in the program header's second word).
+// WIDE (N = 64): the wide block of the forward (columns < HW, rows < wrows, a
+// second row-pass line per thread in the program header's second word); the
+// adjoint column transforms write back rows < HW, of which the adjoint row
+// passes and the degridding read those of the block.
 template <int N, int P, int GPT, bool CPX, bool WIDE>
 __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
   using SH = FusedShape<N>;

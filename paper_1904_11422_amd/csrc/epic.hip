@@ -61,7 +61,8 @@ struct Geometry {
   std::vector<float> w;               // [C][A][KK] (real parts for complex kernels)
   std::vector<float> wi;              // [C][A][KK] imaginary parts, empty for real kernels
   bool fits_half = true;              // every channel's taps fit an N/2 x N/2 block
-  bool fits_wide = true;              // ... a 3N/4 x 3N/4 block (the wide fused variant)
+  bool fits_wide = true;              // ... a 3N/4 x 3N/4 block (the wide fused variant,
+                                      // whose rows orient_wide then trims)
   int ext_j = 0, ext_i = 0;           // largest extent of a channel's taps in rows, columns
   // the wide block (orient_wide): rows transformed in the row pass (a multiple
   // of 8, at least N/2), and whether tcell holds the taps transposed (row and

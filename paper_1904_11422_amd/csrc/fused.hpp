@@ -508,10 +508,11 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
   }
 }
 
-// The whole per-workgroup loop.  WIDE (N = 64): apertures up to HW x HW
-// cells; the programs' header gives each thread a second row-pass line
-// (header_line2, -1: none; whole waves have none, so they skip the pass) and
-// both passes take their lines' inputs n1 < HW / R.
+// The whole per-workgroup loop.  WIDE (N = 64): the wide block of up to HW
+// columns and wrows (32, 40 or 48) rows; the programs' header gives each
+// thread a second row-pass line (header_line2, -1: none; whole waves have
+// none, so they skip the pass); the row passes take their lines' inputs
+// n1 < HW / R, the column pass those of rows below wrows.
 // MULTI: the launch walks several blocks (FusedArgs::blk); a workgroup whose
 // range crosses into the next block switches inputs, gains, programs and the
 // E' layout of its antenna count at that channel boundary.  Without MULTI
