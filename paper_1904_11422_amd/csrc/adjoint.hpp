@@ -22,7 +22,7 @@ struct AdjointArgs {
   const uint2* prog;        // gridding programs and row-pass lines, as the imager
   const float* wim;         // imaginary step weights (complex kernels), or null
   const float* tapim;       // [C][A][KK] imaginary tap weights (complex kernels), or null
-  const uint2* taps;        // [C][A][KK] {physical translated cell j*N+i, w bits}
+  const uint2* taps;        // [C][A][KK] {translated cell's grid offset phys_row(j)*RS + i, w bits}
   const float2* twiddle;
   double2* gpartial;        // [W + C - 1][P*A]
   int64_t n_time, total;
@@ -202,7 +202,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
           const uint2 t = tp[q];
           const int cell = (int)t.x;
           const float w = __uint_as_float(t.y);
-          const float2 h = X[p * PS + (cell / N) * RS + cell % N];
+          const float2 h = X[p * PS + cell];
           s.x = fmaf(w, h.x, s.x);
           s.y = fmaf(w, h.y, s.y);
           if (CPX) {

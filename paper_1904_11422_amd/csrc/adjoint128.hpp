@@ -233,7 +233,7 @@ adjoint128_kernel(AdjointArgs a) {
           const uint2 t = tp[q];
           const int cell = (int)t.x;
           const float w = __uint_as_float(t.y);
-          const float2 hv = X[p * PS + (cell / N) * RS + cell % N];
+          const float2 hv = X[p * PS + cell];
           s.x = fmaf(w, hv.x, s.x);
           s.y = fmaf(w, hv.y, s.y);
           if (CPX) {

@@ -1878,11 +1878,14 @@ epic_status epic_set_antennas_kernels(epic_ctx* x, const double* xy_m, const dou
   x->transposed = x->wide && g.transposed;
 
   if (x->fused) {
-    // adjoint taps [C][A][KK] {translated cell, w}
+    // adjoint taps [C][A][KK] {translated cell as a float2 offset in the
+    // kernels' LDS grid (physical row times the row stride, plus column), w}
+    const int RSN = N == 32 ? epic::FusedShape<32>::RS : N == 64 ? epic::FusedShape<64>::RS
+                                                                 : epic::FusedShape<128>::RS;
     std::vector<uint32_t> taps((size_t)C * A * g.KK * 2);
     for (size_t o = 0; o < (size_t)C * A * g.KK; ++o) {
       const int j = g.tcell[o] / N, i = g.tcell[o] % N;
-      taps[2 * o] = (uint32_t)((N == 64 ? epic::FusedShape<64>::phys_row(j) : j) * N + i);
+      taps[2 * o] = (uint32_t)((N == 64 ? epic::FusedShape<64>::phys_row(j) : j) * RSN + i);
       std::memcpy(&taps[2 * o + 1], &g.w[o], 4);
     }
     std::vector<uint32_t> prog;
