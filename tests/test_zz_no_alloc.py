@@ -37,12 +37,14 @@ def _call(im, name, ef, n_time, g, img, reset=1):
 CASES = {
     # the LWA-like shape with fewer channels and samples (two sample bytes per
     # 512-thread workgroup pass), a ragged N = 32 case, N = 128 at one and
-    # two polarisations, and a wide aperture at N = 64
+    # two polarisations, and wide apertures at N = 64 (the deployed ellipse
+    # runs transposed in a 40-row block)
     "n64_p2_lwa": lambda: synth.config2(n_time=120, n_chan=12),
     "n32_p2_ragged": lambda: synth.random_problem(901, 32, 64, 3, 2, 37),
     "n128_p2": lambda: synth.random_problem(902, 128, 400, 2, 2, 9, fill=0.45),
     "n128_p1": lambda: synth.random_problem(903, 128, 300, 3, 1, 7, fill=0.45),
     "n64_wide": lambda: synth.random_problem(904, 64, 200, 2, 2, 11, fill=0.62),
+    "n64_wide_transposed": lambda: synth.deployment(906, n_time=14, n_chan=3),
 }
 
 
