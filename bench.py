@@ -240,13 +240,12 @@ def split_results(steps: int, with_oracle: bool = True) -> dict:
         im.set_antennas(inp.xy_m, inp.freq_hz)
         img = im.accumulate(ef, g)
         torch.cuda.synchronize()
-        ks = []
         t1 = time.perf_counter()
         for _ in range(steps):
             im.accumulate(ef, g, image=img)
-            ks.append(im.last_timing()[0])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t1) / steps
+        ks = im.timing_history(steps)             # HIP events around each main kernel
         r = {"samples_per_s": T / dt, "ms_per_call": dt * 1e3, "kernel": im.last_kernel_name(),
              "kernel_ms": float(np.mean(ks))}
         if ref is not None:
@@ -299,16 +298,15 @@ def grad_results(steps: int, warmup: int) -> dict:
         im.accumulate(ef, g, image=img)
         im.backward(ef, g, gam)
     torch.cuda.synchronize()
-    fw, bw = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         im.accumulate(ef, g, image=img)
-        fw.append(im.last_timing()[0])
         fname = im.last_kernel_name()
         im.backward(ef, g, gam)
-        bw.append(im.last_timing()[0])
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    hist = im.timing_history(2 * steps)          # forward and adjoint kernels, alternating
+    fw, bw = hist[0::2], hist[1::2]
     bname = im.last_kernel_name()
     im.close()
     # adjoint work per (t,c): the forward recompute without the products, dL/dF*
@@ -488,14 +486,13 @@ def kernels_results(steps: int, warmup: int, inp=None) -> dict:
         for _ in range(warmup):
             im.accumulate(ef, g, image=img)
         torch.cuda.synchronize()
-        ks = []
         steps = steps if N == 64 else max(3, steps // 4)
         t0 = time.perf_counter()
         for _ in range(steps):
             im.accumulate(ef, g, image=img)
-            ks.append(im.last_timing()[0])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        ks = im.timing_history(steps)
         k_ms = float(np.mean(ks))
         fl = flops_per_tc(N, P, A, K, complex_kernel=True)
         out[f"n{N}_k{K}"] = {
@@ -547,13 +544,12 @@ def deployment_results(steps: int, warmup: int, inp=None) -> dict:
             im.accumulate(ef, g, image=img)
         torch.cuda.synchronize()
         steps = steps if not staged else max(2, steps // 5)
-        ks = []
         t0 = time.perf_counter()
         for _ in range(steps):
             im.accumulate(ef, g, image=img)
-            ks.append(im.last_timing()[0])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        ks = im.timing_history(steps)
         k_ms = float(np.mean(ks))
         kname = im.last_kernel_name()              # the image kernel, before the gradient runs
         fl = flops_per_tc(N, P, A) * C * T
@@ -620,13 +616,12 @@ def bench_arrays(args) -> int:
         for _ in range(args.warmup):
             im.accumulate(ef, g, image=img)
         torch.cuda.synchronize()
-        ks = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             im.accumulate(ef, g, image=img)
-            ks.append(im.last_timing()[0])
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
+        ks = im.timing_history(args.steps)
         k_ms = float(np.mean(ks))
         fl = flops_per_tc(N, P, A)
         out[f"a{A}"] = {"bytes_per_thread": -(-P * A // 512), "kernel": im.last_kernel_name(),
@@ -849,13 +844,14 @@ def main() -> int:
     torch.cuda.synchronize()
     print("bench: timing the fused path", file=sys.stderr, flush=True)
 
-    kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         im.accumulate(ef, g, image=img, reset=True)
-        kernel_ms.append(im.last_timing()[0])      # HIP events around the main kernel
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # HIP events the library records around each call's main kernel, read
+    # after the timed region (no wait inside it)
+    kernel_ms = im.timing_history(args.steps)
     ms_per_step = dt * 1e3 / args.steps
     value = C * args.steps / dt
     kname = im.last_kernel_name()

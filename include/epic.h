@@ -262,6 +262,16 @@ epic_status epic_kernel_taper(epic_ctx *ctx, double *taper);
  * call yet or flag not set). */
 epic_status epic_last_timing(epic_ctx *ctx, float *main_kernel_ms, float *call_ms);
 
+/* With EPIC_FLAG_TIMING: the main-kernel durations, in milliseconds, of the
+ * last n timed calls (imaging and gradient calls alike), oldest first, from
+ * HIP events recorded on the context's stream around each call's main kernel
+ * (kept for the last 256 calls).  Waits for the last of them only, so a caller
+ * can time a run of calls without waiting after each.  Not an operation of
+ * the paper (measurement).  main_ms: host float [n].  Errors: EPIC_E_STATE
+ * (flag not set, or fewer than n timed calls), EPIC_E_INVALID (n outside
+ * 1 .. 256, null pointer). */
+epic_status epic_timing_history(epic_ctx *ctx, int32_t n, float *main_ms);
+
 /* With EPIC_FLAG_TIMING and EPIC_FLAG_REMOVE_AUTOS: wait for the last imaging
  * call and report the duration of its autocorrelation-sum kernel (the pass
  * over efield) and of the whole removal (sums, table and subtraction), in

@@ -210,6 +210,13 @@ class Imager:
         _lib.check(self.L, self._ctx, st)
         return m.value, c.value
 
+    def timing_history(self, n):
+        """Main-kernel ms of the last n timed calls, oldest first (timing=True);
+        waits only for the last of them."""
+        buf = (ctypes.c_float * int(n))()
+        _lib.check(self.L, self._ctx, self.L.epic_timing_history(self._ctx, int(n), buf))
+        return list(buf)
+
     def last_autos_timing(self):
         """(autocorrelation-sum kernel ms, whole removal ms) of the last call
         (timing=True, remove_autos=True)."""

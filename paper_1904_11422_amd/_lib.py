@@ -19,7 +19,7 @@ EPIC_FLAG_STAGED, EPIC_FLAG_TIMING, EPIC_FLAG_REMOVE_AUTOS = 1, 2, 4
 EXPORTS = ("epic_init", "epic_set_stream", "epic_set_antennas", "epic_set_antennas_kernels",
            "epic_gridding_program",
            "epic_image_accumulate", "epic_image_accumulate_noalloc",
-           "epic_image_backward", "epic_last_timing", "epic_last_autos_timing",
+           "epic_image_backward", "epic_last_timing", "epic_timing_history", "epic_last_autos_timing",
            "epic_last_kernel_name",
            "epic_destroy", "epic_last_error",
            "epic_batch_create", "epic_batch_set_antennas", "epic_batch_accumulate",
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.epic_image_backward.restype = ctypes.c_int
     L.epic_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
     L.epic_last_timing.restype = ctypes.c_int
+    L.epic_timing_history.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
+    L.epic_timing_history.restype = ctypes.c_int
     L.epic_last_autos_timing.argtypes = L.epic_last_timing.argtypes
     L.epic_last_autos_timing.restype = ctypes.c_int
     L.epic_last_kernel_name.argtypes = [vp]

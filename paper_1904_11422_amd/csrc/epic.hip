@@ -180,6 +180,11 @@ struct epic_ctx {
   // timing
   bool timing = false, timed = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // the main kernels of the last kTimingRing timed calls: event pairs
+  // [slot][begin, end], slot = call index mod kTimingRing
+  static constexpr int kTimingRing = 256;
+  std::vector<hipEvent_t> ring;
+  int64_t ring_calls = 0;
   bool autos_timed = false;
 
   // autocorrelation removal (EPIC_FLAG_REMOVE_AUTOS)
@@ -201,6 +206,21 @@ struct epic_ctx {
 };
 
 namespace {
+
+// Timing events around a call's main kernel (EPIC_FLAG_TIMING): the pair
+// that epic_last_timing reads, and the call's slot of the ring that
+// epic_timing_history reads.
+void mark_main_begin(epic_ctx* x) {
+  if (!x->timing) return;
+  (void)hipEventRecord(x->ev[0], x->stream);
+  (void)hipEventRecord(x->ring[2 * (x->ring_calls % epic_ctx::kTimingRing)], x->stream);
+}
+void mark_main_end(epic_ctx* x) {
+  if (!x->timing) return;
+  (void)hipEventRecord(x->ev[1], x->stream);
+  (void)hipEventRecord(x->ring[2 * (x->ring_calls % epic_ctx::kTimingRing) + 1], x->stream);
+  ++x->ring_calls;
+}
 
 epic_status check_config(const epic_config* c, std::string& m) {
   if (!c) { m = "config is NULL"; return EPIC_E_INVALID; }
@@ -1141,10 +1161,10 @@ epic_status run_split(epic_ctx* x, const uint8_t* efield, int64_t n_time, const 
   sa.n_chunks = n_chunks;
   sa.tile_wgs = (NG / 32 / tpw + 3) / 4;
   const dim3 grid((unsigned)((int64_t)sa.tile_wgs * n_chunks * C));
-  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  mark_main_begin(x);
   split_dispatch(P, bf, qb, SplitLaunch{x, &sa, grid, vec});
   x->last_kernel = "split_image_kernel";
-  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  mark_main_end(x);
   epic::SplitReduceArgs ra;
   ra.partial = x->sp_partial.as<double>();
   ra.scale = x->sp_scale.as<float>();
@@ -1395,7 +1415,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
                      double* image, int32_t reset, double* partial, int max_team = kMaxTeam) {
   const int N = x->cfg.grid_n, C = x->cfg.n_chan, P = x->cfg.n_pol;
   const int64_t total = (int64_t)C * n_time;
-  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  mark_main_begin(x);
   if (x->fused && N == 128) {
     epic::FusedArgs a = single_block_args(x, efield, gains, partial, n_time);
     a.total = 2 * total;
@@ -1404,7 +1424,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.team = fg.team;
     if (!launch_fused128(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = "fused_image128_kernel";
-    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    mark_main_end(x);
     epic::Reduce128Args r;
     r.partial = partial;
     r.image[0] = image;
@@ -1432,7 +1452,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
     a.team = fg.team;
     if (!launch_fused(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no fused kernel for this shape");
     x->last_kernel = x->wide ? "fused_wide_image_kernel" : "fused_image_kernel";
-    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    mark_main_end(x);
     epic::ReduceArgs r;
     r.partial = partial;
     r.image[0] = image;
@@ -1502,7 +1522,7 @@ epic_status run_fp32(epic_ctx* x, const uint8_t* efield, int64_t n_time, const f
                            dim3(256), 0, x->stream, ac);
     }
     x->last_kernel = "staged_fft_kernel";
-    if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+    mark_main_end(x);
     epic::ReduceArgs r;
     r.partial = x->st_acc.as<double>();
     r.image[0] = image;
@@ -1547,7 +1567,7 @@ epic_status staged_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time, 
     if (P == 2) hipLaunchKernelGGL(epic::staged_grad_table_kernel<2>, tg, dim3(256), 0, x->stream, ta);
     else hipLaunchKernelGGL(epic::staged_grad_table_kernel<1>, tg, dim3(256), 0, x->stream, ta);
   }
-  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  mark_main_begin(x);
   const int tbu = x->tb_override > 0 ? std::min(x->tb_override, x->tb) : x->tb;
   for (int64_t t0 = 0; t0 < n_time; t0 += tbu) {
     const int tb = (int)std::min<int64_t>(tbu, n_time - t0);
@@ -1601,7 +1621,7 @@ epic_status staged_backward(epic_ctx* x, const uint8_t* efield, int64_t n_time, 
                        dim3(256), 0, x->stream, dg);
   }
   x->last_kernel = "staged_degrid_kernel";
-  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  mark_main_end(x);
   if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
   // 2 dL/dg* (minus the autocorrelation term) from the single slot per channel
   epic::GradReduceArgs r;
@@ -1767,12 +1787,15 @@ epic_status epic_init(const epic_config* cfg, int device, void* hip_stream, epic
   }
   if (cfg->flags & EPIC_FLAG_TIMING) {
     x->timing = true;
-    for (auto& e : x->ev)
-      if (hipEventCreate(&e) != hipSuccess) {
-        g_init_error = "hipEventCreate failed";
-        epic_destroy(x);
-        return EPIC_E_DEVICE;
-      }
+    x->ring.assign(2 * epic_ctx::kTimingRing, nullptr);
+    bool ok = true;
+    for (auto& e : x->ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    for (auto& e : x->ring) ok = ok && hipEventCreate(&e) == hipSuccess;
+    if (!ok) {
+      g_init_error = "hipEventCreate failed";
+      epic_destroy(x);
+      return EPIC_E_DEVICE;
+    }
   }
   *out = x;
   return EPIC_OK;
@@ -2034,7 +2057,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
     else if (P == 1) hipLaunchKernelGGL((epic::grad_table128_kernel<1>), tg, dim3(256), 0, x->stream, ta);
     else hipLaunchKernelGGL((epic::grad_table128_kernel<2>), tg, dim3(256), 0, x->stream, ta);
   }
-  if (x->timing) (void)hipEventRecord(x->ev[0], x->stream);
+  mark_main_begin(x);
   epic::AdjointArgs a;
   a.efield = efield;
   a.gains = reinterpret_cast<const float2*>(gains);
@@ -2056,7 +2079,7 @@ epic_status epic_image_backward(epic_ctx* x, const uint8_t* efield, int64_t n_ti
   a.W = (int)std::min<int64_t>(aw, total);
   if (!launch_adjoint(x, a)) return x->fail(EPIC_E_UNSUPPORTED, "no adjoint kernel for this shape");
   x->last_kernel = x->cfg.grid_n == 128 ? "adjoint128_kernel" : x->wide ? "adjoint_wide_kernel" : "adjoint_kernel";
-  if (x->timing) (void)hipEventRecord(x->ev[1], x->stream);
+  mark_main_end(x);
   if (x->autos) launch_autos_grad(x, efield, n_time, gains, grad_image);
   epic::GradReduceArgs r;
   r.gpartial = x->gpartial.as<double2>();
@@ -2090,6 +2113,26 @@ epic_status epic_last_timing(epic_ctx* x, float* main_ms, float* call_ms) {
   (void)hipEventElapsedTime(&c, x->ev[0], x->ev[2]);
   if (main_ms) *main_ms = m;
   if (call_ms) *call_ms = c;
+  return EPIC_OK;
+}
+
+epic_status epic_timing_history(epic_ctx* x, int32_t n, float* main_ms) {
+  if (!x) return EPIC_E_INVALID;
+  if (!x->timing) return x->fail(EPIC_E_STATE, "timing history needs EPIC_FLAG_TIMING");
+  if (!main_ms || n < 1 || n > epic_ctx::kTimingRing)
+    return x->fail(EPIC_E_INVALID, "n must be 1 .. 256 with an output array");
+  if (x->ring_calls < n) return x->fail(EPIC_E_STATE, "fewer timed calls than requested");
+  DeviceGuard guard(x->device);
+  const int64_t last = x->ring_calls - 1;
+  if (hipEventSynchronize(x->ring[2 * (last % epic_ctx::kTimingRing) + 1]) != hipSuccess)
+    return x->fail(EPIC_E_DEVICE, "event wait failed");
+  for (int32_t i = 0; i < n; ++i) {
+    const int64_t slot = (x->ring_calls - n + i) % epic_ctx::kTimingRing;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, x->ring[2 * slot], x->ring[2 * slot + 1]) != hipSuccess)
+      return x->fail(EPIC_E_DEVICE, "event timing failed");
+    main_ms[i] = ms;
+  }
   return EPIC_OK;
 }
 
@@ -2151,6 +2194,8 @@ void epic_destroy(epic_ctx* x) {
     DeviceGuard guard(x->device);
     (void)hipStreamSynchronize(x->stream);
     for (auto& e : x->ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& e : x->ring)
       if (e) (void)hipEventDestroy(e);
     x->prog.reset(); x->twiddle.reset(); x->taps.reset(); x->prog_im.reset(); x->taps_im.reset();
     x->csr_im.reset(); x->taper.reset(); x->tmax.reset();

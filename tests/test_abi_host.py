@@ -67,6 +67,7 @@ def test_calls_on_null_context_are_rejected():
     assert L.epic_set_antennas(None, None, None) == _lib.EPIC_E_INVALID
     assert L.epic_image_accumulate(None, None, 1, None, None, 1) == _lib.EPIC_E_INVALID
     assert L.epic_image_backward(None, None, 1, None, None, None) == _lib.EPIC_E_INVALID
+    assert L.epic_timing_history(None, 1, None) == _lib.EPIC_E_INVALID
     L.epic_destroy(None)
     assert L.epic_last_kernel_name(None) == b"none"
 

@@ -118,6 +118,34 @@ def test_wide_aperture_matches_oracle_and_staged(name):
         assert np.array_equal(got[:, 2], np.conj(got[:, 1]))
 
 
+def test_timing_history_reads_every_call():
+    """epic_timing_history: the main-kernel times of a run of calls, read after
+    the run without a wait per call, imaging and gradient calls alike; the
+    last one is the kernel that epic_last_timing reports."""
+    import torch
+    from paper_1904_11422_amd import _lib
+    inp = synth.random_problem(140, 64, 200, 3, 2, 20)
+    im = _imager(inp, timing=True)
+    ef, g = _dev(inp)
+    with pytest.raises(_lib.EpicError):
+        im.timing_history(1)                    # no timed call yet
+    img = im.accumulate(ef, g)
+    gam = torch.ones_like(img)
+    for _ in range(3):
+        im.accumulate(ef, g, image=img)
+        im.backward(ef, g, gam)
+    hist = im.timing_history(7)
+    print(f"  history {hist}", flush=True)
+    assert len(hist) == 7 and all(h > 0 for h in hist)
+    last = im.last_timing()[0]
+    assert abs(hist[-1] - last) <= 0.05 * last + 0.01
+    with pytest.raises(_lib.EpicError):
+        im.timing_history(8)                    # seven timed calls so far
+    with pytest.raises(_lib.EpicError):
+        im.timing_history(257)
+    im.close()
+
+
 def test_wide_aperture_is_deterministic_and_continues():
     import torch
     inp = synth.random_problem(135, 64, 180, 2, 2, 10, fill=0.66)
