@@ -300,6 +300,7 @@ def test_config2_full_size_sampled_channels():
 @pytest.mark.parametrize("seed,N,A,C,P,T,fill,route", [
     (801, 128, 4096, 1, 2, 2, 0.9, "staged_fft_kernel"),     # the largest antenna count taken
     (802, 64, 1024, 2, 1, 3, 0.48, "fused_image_kernel"),    # 2 samples per thread
+    (804, 64, 1024, 2, 2, 3, 0.48, "fused_image_kernel"),    # 4 samples per thread, all used
     (803, 64, 2048, 1, 2, 2, 0.9, "staged_fft_kernel"),      # beyond 4 samples per thread
 ])
 def test_maximum_antenna_counts(seed, N, A, C, P, T, fill, route):
