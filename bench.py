@@ -598,8 +598,9 @@ def bench_arrays(args) -> int:
     """Denser arrays on the LWA-like grid: 256, 512 and 1024 dual-pol antennas
     in one 26-cell disk (64 x 64 grid, 132 channels, 250 samples).  The three
     counts select the kernel variants that stage 1, 2 and 4 sample bytes per
-    thread; the 4-byte variant's E' region makes its LDS footprint 87 KB, so
-    one workgroup fits a CU instead of two."""
+    thread; the 4-byte variant stages E' in grid rows that only the column
+    transforms use (one more barrier per sample), so that its LDS footprint
+    (69.8 KB) lets two workgroups share a CU."""
     import torch
     import synth
     from paper_1904_11422_amd import Imager

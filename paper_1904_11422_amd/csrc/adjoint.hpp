@@ -151,7 +151,7 @@ __device__ __forceinline__ void adjoint_body(const AdjointArgs& a) {
     if (tt == a.n_time) { tt = 0; ++cc; }
     if (left > 1) load_bytes(cc, tt, nxt);
 
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, lds + XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();

@@ -138,7 +138,7 @@ adjoint128_kernel(AdjointArgs a) {
 
     // forward: stage and grid the aperture, row transforms onto the columns
     // of parity h (as fused_image128_kernel)
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, lds + XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     const int rb = (line & 0xFFFF) * RS;
     if (line >= 0) {
       float2 v[P][8];

@@ -254,8 +254,8 @@ __device__ __forceinline__ float2 unpack_ci4(uint32_t b) {
 
 // Slots of E' for this thread's items k = tid + i*NT (k = p*A + a), and the
 // 16 zero slots (a = A .. A+15, one per LDS bank pair of a quarter-wave) of
-// each polarisation.
-template <int NT, int GPT, int ES>
+// each polarisation (ZEROS; else staging writes them with every sample).
+template <int NT, int GPT, int ES, bool ZEROS = true>
 __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid, int n_ant, int P) {
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
@@ -263,26 +263,38 @@ __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid,
     const int p = k >= n_ant ? 1 : 0;
     eidx[i] = k + p * (ES - n_ant);
   }
-  if (tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
+  if (ZEROS && tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
 }
 
-// 1. E'[p][a] = g * e.
-template <int NT, int GPT>
+// 1. E'[p][a] = g * e.  EINGRID: E' lies in grid rows that the previous
+// sample's column transforms used as exchange space, so the workgroup first
+// waits for them, and the zero slots (PA / P .. PA / P + 15 of each
+// polarisation) are written again.
+template <int NT, int GPT, int ES, int P, bool EINGRID>
 __device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[GPT],
                                               const float2 (&g)[GPT], const int (&eidx)[GPT],
                                               int tid, int PA) {
+  // EINGRID: slots are recomputed with every sample from an opaque copy of
+  // tid, so that they are not held (or spilled) across the sample loop
+  int t = tid;
+  if constexpr (EINGRID) {
+    asm volatile("" : "+v"(t));
+    __syncthreads();
+    if (t < 16 * P) E[(t >> 4) * ES + PA / P + (t & 15)] = make_float2(0.f, 0.f);
+  }
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
-    const int k = tid + i * NT;
-    if (k < PA) E[eidx[i]] = cmul(g[i], unpack_ci4(cur[i]));
+    const int k = t + i * NT;
+    const int slot = EINGRID ? k + (k >= PA / P ? ES - PA / P : 0) : eidx[i];
+    if (k < PA) E[slot] = cmul(g[i], unpack_ci4(cur[i]));
   }
 }
 
 // One gridding step on the running sums (s0, s1) of the current cell.
-// lds is the start of the shared buffer: E' at byte 0, the grid at xbase.
-// CPX: the weight is w + i wi.
+// xlds is the start of the grid in the shared buffer (the step's cell offset
+// is relative to it).  CPX: the weight is w + i wi.
 template <int N, int P, int RS, int ES, bool CPX>
-__device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, float wi, float2 e0,
+__device__ __forceinline__ void grid_step(char* xlds, uint2 step, float wi, float2 e0,
                                           float2 e1, float2& s0, float2& s1) {
   const float w = __uint_as_float(step.y);
   s0.x = fmaf(w, e0.x, s0.x);
@@ -300,7 +312,7 @@ __device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, floa
     }
   }
   if (step.x & STEP_LAST_BIT) {                 // last entry of the cell
-    float2* cell = reinterpret_cast<float2*>(lds + xbase + (step.x >> STEP_CELL_SHIFT));
+    float2* cell = reinterpret_cast<float2*>(xlds + (step.x >> STEP_CELL_SHIFT));
     cell[0] = s0;
     if (P == 2) cell[FusedShape<N>::PSTRIDE] = s1;
     s0 = make_float2(0.f, 0.f);
@@ -308,9 +320,11 @@ __device__ __forceinline__ void grid_step(char* lds, int xbase, uint2 step, floa
   }
 }
 
+// elds: the start of E' in the shared buffer (the step's E' offset is
+// relative to it).
 template <int P, int ES>
-__device__ __forceinline__ void read_e(const char* lds, uint2 step, float2& e0, float2& e1) {
-  const float2* e = reinterpret_cast<const float2*>(lds + (step.x & STEP_E_MASK));
+__device__ __forceinline__ void read_e(const char* elds, uint2 step, float2& e0, float2& e1) {
+  const float2* e = reinterpret_cast<const float2*>(elds + (step.x & STEP_E_MASK));
   e0 = e[0];
   if (P == 2) e1 = e[ES];
 }
@@ -319,7 +333,7 @@ __device__ __forceinline__ void read_e(const char* lds, uint2 step, float2& e0, 
 // loaded into registers (wis: the imaginary weights, read only when CPX);
 // s0, s1 carry the sums of a cell whose entries continue in the next call.
 template <int N, int P, int RS, int ES, int LS, bool CPX, int OFF = 0, int SZ>
-__device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&steps)[SZ],
+__device__ __forceinline__ void grid_fixed(const char* elds, char* xlds, const uint2 (&steps)[SZ],
                                            const float (&wis)[SZ], float2& s0, float2& s1) {
   static_assert(OFF + LS <= SZ, "more steps than loaded");
 #pragma unroll
@@ -328,11 +342,11 @@ __device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&s
     float2 e0[G], e1[G];
 #pragma unroll
     for (int st = 0; st < G; ++st)
-      if (st0 + st < OFF + LS) read_e<P, ES>(lds, steps[st0 + st], e0[st], e1[st]);
+      if (st0 + st < OFF + LS) read_e<P, ES>(elds, steps[st0 + st], e0[st], e1[st]);
 #pragma unroll
     for (int st = 0; st < G; ++st)
       if (st0 + st < OFF + LS)
-        grid_step<N, P, RS, ES, CPX>(lds, xbase, steps[st0 + st], wis[st0 + st], e0[st], e1[st], s0, s1);
+        grid_step<N, P, RS, ES, CPX>(xlds, steps[st0 + st], wis[st0 + st], e0[st], e1[st], s0, s1);
   }
 }
 
@@ -340,7 +354,7 @@ __device__ __forceinline__ void grid_fixed(char* lds, int xbase, const uint2 (&s
 // steps come from global memory (L2) a chunk at a time; the next chunk is
 // loaded while the current one is gridded, so its latency is hidden.
 template <int N, int P, int RS, int ES, bool CPX>
-__device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* prog, const float* wim,
+__device__ __forceinline__ void grid_chunked(const char* elds, char* xlds, const uint2* prog, const float* wim,
                                              int stride, int L) {
   float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
   uint2 nsteps[kStepChunk];
@@ -367,26 +381,26 @@ __device__ __forceinline__ void grid_chunked(char* lds, int xbase, const uint2* 
       }
     }
 #pragma unroll
-    for (int st = 0; st < kStepChunk; ++st) read_e<P, ES>(lds, steps[st], e0[st], e1[st]);
+    for (int st = 0; st < kStepChunk; ++st) read_e<P, ES>(elds, steps[st], e0[st], e1[st]);
 #pragma unroll
     for (int st = 0; st < kStepChunk; ++st)
-      grid_step<N, P, RS, ES, CPX>(lds, xbase, steps[st], wis[st], e0[st], e1[st], s0, s1);
+      grid_step<N, P, RS, ES, CPX>(xlds, steps[st], wis[st], e0[st], e1[st], s0, s1);
   }
 }
 
 // Steps 1-2 of one sample: load the gridding program (exactly L steps for
 // L <= kMaxFixedSteps + kStepChunk), stage E', barrier, grid.  A thread grids
 // only cells of rows its own wave transforms next, so gridding ends with a
-// wave-level fence.  prog is the channel's step list (wim: its imaginary
-// weights when CPX), of at least L steps; L is the wave's own step count,
-// uniform over the wave.  Steps past kMaxFixedSteps are loaded after the
-// barrier, once the first G are gridded (their registers free), while the
-// next G are.
-template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX>
-__device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, const uint2* prog,
-                                               const float* wim, int L, const uint32_t (&cur)[GPT],
-                                               const float2 (&g)[GPT], const int (&eidx)[GPT],
-                                               int tid, int PA) {
+// wave-level fence.  E (= elds) is E' and xlds the grid in the shared buffer;
+// prog is the channel's step list (wim: its imaginary weights when CPX), of
+// at least L steps; L is the wave's own step count, uniform over the wave.
+// Steps past kMaxFixedSteps are loaded after the barrier, once the first G
+// are gridded (their registers free), while the next G are.
+template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX, bool EINGRID = false>
+__device__ __forceinline__ void stage_and_grid(const char* elds, char* xlds, float2* E,
+                                               const uint2* prog, const float* wim, int L,
+                                               const uint32_t (&cur)[GPT], const float2 (&g)[GPT],
+                                               const int (&eidx)[GPT], int tid, int PA) {
   constexpr int F = kMaxFixedSteps, G = kStepChunk;
   if (L <= F + G) {
     uint2 steps[F];
@@ -396,12 +410,12 @@ __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, 
       if (st < L) steps[st] = prog[st * NT + tid];
       wis[st] = (CPX && st < L) ? wim[st * NT + tid] : 0.f;
     }
-    stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
+    stage_samples<NT, GPT, ES, P, EINGRID>(E, cur, g, eidx, tid, PA);
     __syncthreads();
     float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
     if (L > F) {
       static_assert(F == 2 * G, "the first G steps are gridded before the rest load");
-      grid_fixed<N, P, RS, ES, G, CPX>(lds, xbase, steps, wis, s0, s1);
+      grid_fixed<N, P, RS, ES, G, CPX>(elds, xlds, steps, wis, s0, s1);
       uint2 more[G];
       float wmore[G];
 #pragma unroll
@@ -409,29 +423,29 @@ __device__ __forceinline__ void stage_and_grid(char* lds, int xbase, float2* E, 
         if (F + st < L) more[st] = prog[(F + st) * NT + tid];
         wmore[st] = (CPX && F + st < L) ? wim[(F + st) * NT + tid] : 0.f;
       }
-      grid_fixed<N, P, RS, ES, G, CPX, G>(lds, xbase, steps, wis, s0, s1);
+      grid_fixed<N, P, RS, ES, G, CPX, G>(elds, xlds, steps, wis, s0, s1);
       switch (L - F) {
-        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, more, wmore, s0, s1); break;
-        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, more, wmore, s0, s1); break;
-        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, more, wmore, s0, s1); break;
-        default: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, more, wmore, s0, s1); break;
+        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, more, wmore, s0, s1); break;
+        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, more, wmore, s0, s1); break;
+        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, more, wmore, s0, s1); break;
+        default: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, more, wmore, s0, s1); break;
       }
     } else {
       switch (L) {
-        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 4: grid_fixed<N, P, RS, ES, 4, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 5: grid_fixed<N, P, RS, ES, 5, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 6: grid_fixed<N, P, RS, ES, 6, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        case 7: grid_fixed<N, P, RS, ES, 7, CPX>(lds, xbase, steps, wis, s0, s1); break;
-        default: grid_fixed<N, P, RS, ES, 8, CPX>(lds, xbase, steps, wis, s0, s1); break;
+        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 4: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 5: grid_fixed<N, P, RS, ES, 5, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 6: grid_fixed<N, P, RS, ES, 6, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        case 7: grid_fixed<N, P, RS, ES, 7, CPX>(elds, xlds, steps, wis, s0, s1); break;
+        default: grid_fixed<N, P, RS, ES, 8, CPX>(elds, xlds, steps, wis, s0, s1); break;
       }
     }
   } else {
-    stage_samples<NT, GPT>(E, cur, g, eidx, tid, PA);
+    stage_samples<NT, GPT, ES, P, EINGRID>(E, cur, g, eidx, tid, PA);
     __syncthreads();
-    grid_chunked<N, P, RS, ES, CPX>(lds, xbase, prog + tid, CPX ? wim + tid : nullptr, NT, L);
+    grid_chunked<N, P, RS, ES, CPX>(elds, xlds, prog + tid, CPX ? wim + tid : nullptr, NT, L);
   }
   wave_lds_sync();
 }
@@ -523,12 +537,17 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   constexpr int S = SH::S, NT = SH::NT, RS = SH::RS;
   constexpr int NACC = (P == 2) ? 4 : 1;
   constexpr int ES = EStride<NT, GPT, P>::value;
-  constexpr int XBASE = P * ES * (int)sizeof(float2);
-  // E'[p][a] (zero slots at a = A .. A+15), then the grid
-  __shared__ __attribute__((aligned(16))) float2 lds2[P * ES + (P - 1) * SH::PSTRIDE + N * RS];
-  char* lds = reinterpret_cast<char*>(lds2);
-  float2* E = lds2;
-  float2* X = lds2 + P * ES;
+  // E'[p][a] (zero slots at a = A .. A+15), then the grid.  EINGRID: E' of
+  // more than 512 antennas does not fit beside the grid if two workgroups
+  // are to share a CU; it takes the grid's rows N/2 .. N-1 of the first
+  // polarisation instead (rows that only the column transforms use, as
+  // exchange space), at the cost of one more barrier per sample.
+  constexpr bool EINGRID = N == 64 && P == 2 && GPT == 4 && !WIDE;
+  static_assert(!EINGRID || P * ES <= (N / 2) * RS, "E' fits the upper rows");
+  constexpr int EB = EINGRID ? 0 : P * ES;     // float2 before the grid
+  __shared__ __attribute__((aligned(16))) float2 lds2[EB + (P - 1) * SH::PSTRIDE + N * RS];
+  float2* X = lds2 + EB;
+  float2* E = EINGRID ? X + (N / 2) * RS : lds2;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -558,7 +577,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
   const uint8_t* n_src = a.blk[nb].efield;
   int eidx[GPT];
-  init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+  init_stage<NT, GPT, ES, !EINGRID>(E, eidx, tid, a.blk[b].n_ant, P);
   int wrows = a.blk[b].wrows;                  // wide block rows of block b
 
   float acc[S][NACC];                          // float32 sums over <= KB samples
@@ -617,7 +636,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
         b = nb;
         PA = P * a.blk[b].n_ant;
         L = a.blk[b].L;
-        init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
+        init_stage<NT, GPT, ES, !EINGRID>(E, eidx, tid, a.blk[b].n_ant, P);
         wrows = a.blk[b].wrows;
       }
       const int64_t cl = c - a.blk[b].c0;      // channel within the block
@@ -657,7 +676,9 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
       load_bytes((int)it.s, it.t, nxt);
     }
 
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX, EINGRID>(reinterpret_cast<const char*>(E),
+                                                        reinterpret_cast<char*>(X), E, prog, wim, Lw,
+                                                        cur, g, eidx, tid, PA);
     row_pass<N, P, +1, WIDE>(X, r, tw, line);
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();

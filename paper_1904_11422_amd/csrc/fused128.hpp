@@ -202,7 +202,7 @@ __device__ __forceinline__ void fused_image128_body(const FusedArgs& a) {
     }
 
     // 1. stage and grid the aperture (both parities grid the whole aperture)
-    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX>(lds, lds + XBASE, E, prog, wim, Lw, cur, g, eidx, tid, PA);
     // 2. row transforms of row `line` of both polarisations onto the
     //    columns of parity h (h is uniform over the workgroup)
     if (line >= 0) {

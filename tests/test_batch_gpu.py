@@ -147,6 +147,24 @@ def test_mixed_antenna_counts_share_a_launch():
         assert oracle.rel_errors(imgs[k].cpu().numpy(), ref).max() <= 1e-5
 
 
+def test_many_antenna_blocks_share_a_launch():
+    """64^2 blocks of 600, 1000 and 777 dual-pol antennas (four sample bytes
+    per thread, E' staged in the grid rows the column transforms exchange
+    through) in one grouped launch: workgroups that cross a block boundary
+    take the next block's antenna count, E' layout and zero slots."""
+    import torch
+    inputs = [synth.random_problem(821, 64, 600, 3, 2, 9, fill=0.45),
+              synth.random_problem(822, 64, 1000, 2, 2, 9, fill=0.48),
+              synth.random_problem(823, 64, 777, 1, 2, 9, fill=0.4)]
+    b, ef, g = _batch(inputs)
+    lp = b.launch_plan()
+    print(lp, flush=True)
+    assert [x[0] for x in lp] == [0, 0, 0] and lp[0][1] == 3
+    imgs = b.accumulate(ef, g, b.new_images())
+    torch.cuda.synchronize()
+    _check_blocks(imgs, inputs)
+
+
 def test_wide_blocks_of_both_orientations_share_a_launch():
     """Apertures wider than N/2 at N = 64 in one grouped launch: blocks whose
     wide block has 40 or 48 rows and whose taps are transposed or not (the

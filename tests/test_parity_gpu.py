@@ -20,7 +20,7 @@ def _imager(inp, staged=False, timing=False):
     from paper_1904_11422_amd import Imager
     im = Imager(inp.grid_n, inp.n_chan, inp.n_pol, inp.n_ant, inp.kernel_support,
                 inp.kernel_sigma_cells, inp.cell_wavelengths, staged=staged, timing=timing)
-    im.set_antennas(inp.xy_m, inp.freq_hz)
+    im.set_antennas(inp.xy_m, inp.freq_hz, kernels=inp.kernels)
     return im
 
 
@@ -311,6 +311,28 @@ def test_maximum_antenna_counts(seed, N, A, C, P, T, fill, route):
     got, im = _run(inp)
     assert im.last_kernel_name() == route
     assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
+
+
+@pytest.mark.parametrize("seed,A,C,T,K,cpx", [
+    (811, 513, 2, 7, 3, False),     # one past two bytes per thread
+    (812, 1000, 2, 131, 3, False),  # float64 flushes after 128 samples, ragged
+    (813, 900, 2, 5, 7, True),      # complex 7 x 7 kernels: step lists read in chunks
+])
+def test_many_antennas_stage_in_the_grid_rows(seed, A, C, T, K, cpx):
+    """More than 512 dual-pol antennas at N = 64 (four sample bytes per
+    thread): E' is staged in the first polarisation's grid rows N/2 .. N-1,
+    which the column transforms use as exchange space, behind one more
+    barrier per sample, so that two workgroups share a CU.  The image matches
+    the oracle, and the Hermitian pair XY = conj(YX) holds exactly."""
+    inp = synth.random_problem(seed, 64, A, C, 2, T, fill=0.42 if K > 3 else 0.48)
+    if cpx:
+        inp = synth.with_kernels(inp, K, seed + 7)
+    got, im = _run(inp)
+    assert im.last_kernel_name() == "fused_image_kernel"
+    err = oracle.rel_errors(got, oracle.image_from(inp))
+    print(f"  max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= TOL_FP32, f"{err.max():.3e}"
+    assert np.array_equal(got[:, 2], np.conj(got[:, 1]))
 
 
 def test_antenna_limit_is_enforced():
