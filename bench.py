@@ -598,9 +598,10 @@ def bench_arrays(args) -> int:
     """Denser arrays on the LWA-like grid: 256, 512 and 1024 dual-pol antennas
     in one 26-cell disk (64 x 64 grid, 132 channels, 250 samples).  The three
     counts select the kernel variants that stage 1, 2 and 4 sample bytes per
-    thread; the 4-byte variant stages E' in grid rows that only the column
-    transforms use (one more barrier per sample), so that its LDS footprint
-    (69.8 KB) lets two workgroups share a CU."""
+    thread; the 4-byte variant stages E' in grid rows of the second
+    polarisation that nothing else uses (its column transforms exchange
+    through the first one's columns), so that its LDS footprint (70.1 KB)
+    lets two workgroups share a CU."""
     import torch
     import synth
     from paper_1904_11422_amd import Imager

@@ -254,8 +254,8 @@ __device__ __forceinline__ float2 unpack_ci4(uint32_t b) {
 
 // Slots of E' for this thread's items k = tid + i*NT (k = p*A + a), and the
 // 16 zero slots (a = A .. A+15, one per LDS bank pair of a quarter-wave) of
-// each polarisation (ZEROS; else staging writes them with every sample).
-template <int NT, int GPT, int ES, bool ZEROS = true>
+// each polarisation.
+template <int NT, int GPT, int ES>
 __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid, int n_ant, int P) {
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
@@ -263,25 +263,18 @@ __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid,
     const int p = k >= n_ant ? 1 : 0;
     eidx[i] = k + p * (ES - n_ant);
   }
-  if (ZEROS && tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
+  if (tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
 }
 
-// 1. E'[p][a] = g * e.  EINGRID: E' lies in grid rows that the previous
-// sample's column transforms used as exchange space, so the workgroup first
-// waits for them, and the zero slots (PA / P .. PA / P + 15 of each
-// polarisation) are written again.
+// 1. E'[p][a] = g * e.  EINGRID (E' inside the grid, registers short): the
+// slots are recomputed with every sample from an opaque copy of tid, so that
+// they are not held (or spilled) across the sample loop.
 template <int NT, int GPT, int ES, int P, bool EINGRID>
 __device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[GPT],
                                               const float2 (&g)[GPT], const int (&eidx)[GPT],
                                               int tid, int PA) {
-  // EINGRID: slots are recomputed with every sample from an opaque copy of
-  // tid, so that they are not held (or spilled) across the sample loop
   int t = tid;
-  if constexpr (EINGRID) {
-    asm volatile("" : "+v"(t));
-    __syncthreads();
-    if (t < 16 * P) E[(t >> 4) * ES + PA / P + (t & 15)] = make_float2(0.f, 0.f);
-  }
+  if constexpr (EINGRID) asm volatile("" : "+v"(t));
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
     const int k = t + i * NT;
@@ -502,7 +495,11 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 // H to HW, uniform) are nonzero (stored at their physical rows, which for
 // whole groups of R rows are the same rows); the other rows of the grid are
 // not read.  Out: v[p][q R + k1] = F_p[n0 D + q + S k1][kl].
-template <int N, int P, bool WIDE = false>
+// XSHARE: every polarisation exchanges through the first one's column (a
+// column belongs to the lanes of one wave, which finish each polarisation's
+// transform before the next one writes), leaving the rows >= H of the
+// others untouched.
+template <int N, int P, bool WIDE = false, bool XSHARE = false>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
                                                 const Roles<N>& r, const float2* tw, int rows = 0) {
   using SH = FusedShape<N>;
@@ -517,7 +514,7 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
       if (n1 < S / 2 || (n1 < NIN && R * n1 < rows))
         vp[0][n1] = X[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
       else if (WIDE) vp[0][n1] = make_float2(0.f, 0.f);
-    line_transform<N, +1, 1, NIN, SH::COL_SKEW>(vp, tw, r.n0, X + p * PS,
+    line_transform<N, +1, 1, NIN, SH::COL_SKEW>(vp, tw, r.n0, XSHARE ? X : X + p * PS,
                                     [kl](int, int s) { return s * RS + kl; });
   }
 }
@@ -539,15 +536,19 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   constexpr int ES = EStride<NT, GPT, P>::value;
   // E'[p][a] (zero slots at a = A .. A+15), then the grid.  EINGRID: E' of
   // more than 512 antennas does not fit beside the grid if two workgroups
-  // are to share a CU; it takes the grid's rows N/2 .. N-1 of the first
-  // polarisation instead (rows that only the column transforms use, as
-  // exchange space), at the cost of one more barrier per sample.
+  // are to share a CU.  It takes the second polarisation's grid rows
+  // N/2 .. N-1 instead (from a multiple of 64 float2, so that the paired
+  // E' read keeps its offsets; 48 float2 past the grid's end): the column
+  // transforms of that polarisation exchange through the first one's
+  // column (which the same wave has just finished with), so nothing else
+  // touches those rows and staging needs no extra barrier.
   constexpr bool EINGRID = N == 64 && P == 2 && GPT == 4 && !WIDE;
-  static_assert(!EINGRID || P * ES <= (N / 2) * RS, "E' fits the upper rows");
-  constexpr int EB = EINGRID ? 0 : P * ES;     // float2 before the grid
-  __shared__ __attribute__((aligned(16))) float2 lds2[EB + (P - 1) * SH::PSTRIDE + N * RS];
-  float2* X = lds2 + EB;
-  float2* E = EINGRID ? X + (N / 2) * RS : lds2;
+  constexpr int GRID = (P - 1) * SH::PSTRIDE + N * RS;           // float2
+  constexpr int EOFF = (SH::PSTRIDE + (N / 2) * RS + 63) / 64 * 64;
+  constexpr int LDS = EINGRID ? (EOFF + P * ES > GRID ? EOFF + P * ES : GRID) : P * ES + GRID;
+  __shared__ __attribute__((aligned(16))) float2 lds2[LDS];
+  float2* X = lds2 + (EINGRID ? 0 : P * ES);
+  float2* E = EINGRID ? lds2 + EOFF : lds2;
 
   const Roles<N> r(threadIdx.x);
   const int tid = r.tid;
@@ -577,7 +578,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   int n_pa = P * a.blk[nb].n_ant, n_c0 = a.blk[nb].c0;
   const uint8_t* n_src = a.blk[nb].efield;
   int eidx[GPT];
-  init_stage<NT, GPT, ES, !EINGRID>(E, eidx, tid, a.blk[b].n_ant, P);
+  init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
   int wrows = a.blk[b].wrows;                  // wide block rows of block b
 
   float acc[S][NACC];                          // float32 sums over <= KB samples
@@ -636,7 +637,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
         b = nb;
         PA = P * a.blk[b].n_ant;
         L = a.blk[b].L;
-        init_stage<NT, GPT, ES, !EINGRID>(E, eidx, tid, a.blk[b].n_ant, P);
+        init_stage<NT, GPT, ES>(E, eidx, tid, a.blk[b].n_ant, P);
         wrows = a.blk[b].wrows;
       }
       const int64_t cl = c - a.blk[b].c0;      // channel within the block
@@ -683,7 +684,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P, WIDE>(v, X, r, tw, wrows);
+    column_pass_fwd<N, P, WIDE, EINGRID>(v, X, r, tw, wrows);
 
     // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
 #pragma unroll

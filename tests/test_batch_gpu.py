@@ -149,9 +149,9 @@ def test_mixed_antenna_counts_share_a_launch():
 
 def test_many_antenna_blocks_share_a_launch():
     """64^2 blocks of 600, 1000 and 777 dual-pol antennas (four sample bytes
-    per thread, E' staged in the grid rows the column transforms exchange
-    through) in one grouped launch: workgroups that cross a block boundary
-    take the next block's antenna count, E' layout and zero slots."""
+    per thread, E' staged in the second polarisation's upper grid rows) in
+    one grouped launch: workgroups that cross a block boundary take the next
+    block's antenna count, E' layout and zero slots."""
     import torch
     inputs = [synth.random_problem(821, 64, 600, 3, 2, 9, fill=0.45),
               synth.random_problem(822, 64, 1000, 2, 2, 9, fill=0.48),

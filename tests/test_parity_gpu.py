@@ -320,9 +320,9 @@ def test_maximum_antenna_counts(seed, N, A, C, P, T, fill, route):
 ])
 def test_many_antennas_stage_in_the_grid_rows(seed, A, C, T, K, cpx):
     """More than 512 dual-pol antennas at N = 64 (four sample bytes per
-    thread): E' is staged in the first polarisation's grid rows N/2 .. N-1,
-    which the column transforms use as exchange space, behind one more
-    barrier per sample, so that two workgroups share a CU.  The image matches
+    thread): E' is staged in the second polarisation's grid rows N/2 .. N-1,
+    whose column transforms exchange through the first polarisation's
+    columns instead, so that two workgroups share a CU.  The image matches
     the oracle, and the Hermitian pair XY = conj(YX) holds exactly."""
     inp = synth.random_problem(seed, 64, A, C, 2, T, fill=0.42 if K > 3 else 0.48)
     if cpx:
