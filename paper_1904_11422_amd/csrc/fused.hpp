@@ -266,19 +266,19 @@ __device__ __forceinline__ void init_stage(float2* E, int (&eidx)[GPT], int tid,
   if (tid < 16 * P) E[(tid >> 4) * ES + n_ant + (tid & 15)] = make_float2(0.f, 0.f);
 }
 
-// 1. E'[p][a] = g * e.  EINGRID (E' inside the grid, registers short): the
-// slots are recomputed with every sample from an opaque copy of tid, so that
-// they are not held (or spilled) across the sample loop.
-template <int NT, int GPT, int ES, int P, bool EINGRID>
+// 1. E'[p][a] = g * e.  RECOMPUTE (where registers are short): the slots are
+// recomputed with every sample from an opaque copy of tid, so that they are
+// not held (or spilled) across the sample loop.
+template <int NT, int GPT, int ES, int P, bool RECOMPUTE>
 __device__ __forceinline__ void stage_samples(float2* E, const uint32_t (&cur)[GPT],
                                               const float2 (&g)[GPT], const int (&eidx)[GPT],
                                               int tid, int PA) {
   int t = tid;
-  if constexpr (EINGRID) asm volatile("" : "+v"(t));
+  if constexpr (RECOMPUTE) asm volatile("" : "+v"(t));
 #pragma unroll
   for (int i = 0; i < GPT; ++i) {
     const int k = t + i * NT;
-    const int slot = EINGRID ? k + (k >= PA / P ? ES - PA / P : 0) : eidx[i];
+    const int slot = RECOMPUTE ? k + (k >= PA / P ? ES - PA / P : 0) : eidx[i];
     if (k < PA) E[slot] = cmul(g[i], unpack_ci4(cur[i]));
   }
 }
@@ -381,6 +381,47 @@ __device__ __forceinline__ void grid_chunked(const char* elds, char* xlds, const
   }
 }
 
+// 2. (fixed path) Gridding of L <= kMaxFixedSteps + kStepChunk steps whose
+// first kMaxFixedSteps are loaded (steps, wis); steps past them are loaded
+// from prog (wim) once the first G are gridded.
+template <int N, int P, int NT, int RS, int ES, bool CPX>
+__device__ __forceinline__ void grid_loaded(const char* elds, char* xlds,
+                                            const uint2 (&steps)[kMaxFixedSteps],
+                                            const float (&wis)[kMaxFixedSteps], const uint2* prog,
+                                            const float* wim, int L, int tid) {
+  constexpr int F = kMaxFixedSteps, G = kStepChunk;
+  float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
+  if (L > F) {
+    static_assert(F == 2 * G, "the first G steps are gridded before the rest load");
+    grid_fixed<N, P, RS, ES, G, CPX>(elds, xlds, steps, wis, s0, s1);
+    uint2 more[G];
+    float wmore[G];
+#pragma unroll
+    for (int st = 0; st < G; ++st) {
+      if (F + st < L) more[st] = prog[(F + st) * NT + tid];
+      wmore[st] = (CPX && F + st < L) ? wim[(F + st) * NT + tid] : 0.f;
+    }
+    grid_fixed<N, P, RS, ES, G, CPX, G>(elds, xlds, steps, wis, s0, s1);
+    switch (L - F) {
+      case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, more, wmore, s0, s1); break;
+      case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, more, wmore, s0, s1); break;
+      case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, more, wmore, s0, s1); break;
+      default: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, more, wmore, s0, s1); break;
+    }
+  } else {
+    switch (L) {
+      case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 4: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 5: grid_fixed<N, P, RS, ES, 5, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 6: grid_fixed<N, P, RS, ES, 6, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      case 7: grid_fixed<N, P, RS, ES, 7, CPX>(elds, xlds, steps, wis, s0, s1); break;
+      default: grid_fixed<N, P, RS, ES, 8, CPX>(elds, xlds, steps, wis, s0, s1); break;
+    }
+  }
+}
+
 // Steps 1-2 of one sample: load the gridding program (exactly L steps for
 // L <= kMaxFixedSteps + kStepChunk), stage E', barrier, grid.  A thread grids
 // only cells of rows its own wave transforms next, so gridding ends with a
@@ -389,12 +430,25 @@ __device__ __forceinline__ void grid_chunked(const char* elds, char* xlds, const
 // at least L steps; L is the wave's own step count, uniform over the wave.
 // Steps past kMaxFixedSteps are loaded after the barrier, once the first G
 // are gridded (their registers free), while the next G are.
-template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX, bool EINGRID = false>
+template <int N, int P, int NT, int RS, int ES, int GPT, bool CPX, bool RECOMPUTE = false,
+          bool AHEAD = false>
 __device__ __forceinline__ void stage_and_grid(const char* elds, char* xlds, float2* E,
                                                const uint2* prog, const float* wim, int L,
                                                const uint32_t (&cur)[GPT], const float2 (&g)[GPT],
-                                               const int (&eidx)[GPT], int tid, int PA) {
+                                               const int (&eidx)[GPT], int tid, int PA,
+                                               bool stage = true) {
   constexpr int F = kMaxFixedSteps, G = kStepChunk;
+  // AHEAD: the sample gridded here is already staged and visible (elds); E
+  // is the other buffer, into which the next sample is staged (if stage)
+  // while the steps load, with no barrier.
+  auto stage_e = [&]() {
+    if (AHEAD) {
+      if (stage) stage_samples<NT, GPT, ES, P, RECOMPUTE>(E, cur, g, eidx, tid, PA);
+    } else {
+      stage_samples<NT, GPT, ES, P, RECOMPUTE>(E, cur, g, eidx, tid, PA);
+      __syncthreads();
+    }
+  };
   if (L <= F + G) {
     uint2 steps[F];
     float wis[F];
@@ -403,41 +457,10 @@ __device__ __forceinline__ void stage_and_grid(const char* elds, char* xlds, flo
       if (st < L) steps[st] = prog[st * NT + tid];
       wis[st] = (CPX && st < L) ? wim[st * NT + tid] : 0.f;
     }
-    stage_samples<NT, GPT, ES, P, EINGRID>(E, cur, g, eidx, tid, PA);
-    __syncthreads();
-    float2 s0 = make_float2(0.f, 0.f), s1 = make_float2(0.f, 0.f);
-    if (L > F) {
-      static_assert(F == 2 * G, "the first G steps are gridded before the rest load");
-      grid_fixed<N, P, RS, ES, G, CPX>(elds, xlds, steps, wis, s0, s1);
-      uint2 more[G];
-      float wmore[G];
-#pragma unroll
-      for (int st = 0; st < G; ++st) {
-        if (F + st < L) more[st] = prog[(F + st) * NT + tid];
-        wmore[st] = (CPX && F + st < L) ? wim[(F + st) * NT + tid] : 0.f;
-      }
-      grid_fixed<N, P, RS, ES, G, CPX, G>(elds, xlds, steps, wis, s0, s1);
-      switch (L - F) {
-        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, more, wmore, s0, s1); break;
-        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, more, wmore, s0, s1); break;
-        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, more, wmore, s0, s1); break;
-        default: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, more, wmore, s0, s1); break;
-      }
-    } else {
-      switch (L) {
-        case 1: grid_fixed<N, P, RS, ES, 1, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 2: grid_fixed<N, P, RS, ES, 2, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 3: grid_fixed<N, P, RS, ES, 3, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 4: grid_fixed<N, P, RS, ES, 4, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 5: grid_fixed<N, P, RS, ES, 5, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 6: grid_fixed<N, P, RS, ES, 6, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        case 7: grid_fixed<N, P, RS, ES, 7, CPX>(elds, xlds, steps, wis, s0, s1); break;
-        default: grid_fixed<N, P, RS, ES, 8, CPX>(elds, xlds, steps, wis, s0, s1); break;
-      }
-    }
+    stage_e();
+    grid_loaded<N, P, NT, RS, ES, CPX>(elds, xlds, steps, wis, prog, wim, L, tid);
   } else {
-    stage_samples<NT, GPT, ES, P, EINGRID>(E, cur, g, eidx, tid, PA);
-    __syncthreads();
+    stage_e();
     grid_chunked<N, P, RS, ES, CPX>(elds, xlds, prog + tid, CPX ? wim + tid : nullptr, NT, L);
   }
   wave_lds_sync();
@@ -703,11 +726,216 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   flush();
 }
 
+template <int V> struct IntC { static constexpr int value = V; };
+
+// 3b'. Forward column transforms of column r.kl of both polarisations from
+// the aperture buffer Xb (rows < H of each polarisation at stride PSTRIDE),
+// exchanging through the 2H slots that this column's rows < H of the two
+// polarisations form (slot j < H: first polarisation, row j; j >= H:
+// second, row j - H).  Both polarisations' inputs are read before the first
+// exchange; nothing outside the buffer is touched.  A column belongs to the
+// lanes of one wave, so the second polarisation's exchange follows the
+// first's behind the transform's own wave-level fences.
+template <int N>
+__device__ __forceinline__ void column_pass_buf(float2 (&v)[2][Line<N>::S], float2* Xb,
+                                                const Roles<N>& r, const float2* tw) {
+  using SH = FusedShape<N>;
+  constexpr int S = Line<N>::S, R = Line<N>::R, RS = SH::RS, PS = SH::PSTRIDE, H = N / 2;
+  const int kl = r.kl;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int n1 = 0; n1 < S / 2; ++n1) v[p][n1] = Xb[p * PS + SH::phys_row(R * n1 + r.n0) * RS + kl];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    float2 (&vp)[1][S] = *reinterpret_cast<float2 (*)[1][S]>(&v[p]);
+    line_transform<N, +1, 1, S / 2, SH::COL_SKEW>(vp, tw, r.n0, Xb, [kl](int, int j) {
+      return j * RS + kl + (j / H) * (PS - H * RS);
+    });
+  }
+}
+
+// The per-workgroup loop with one workgroup barrier per sample (N = 64, two
+// polarisations, at most 256 antennas, Gaussian taps, one block).  E' and
+// the aperture rows are double-buffered: sample s grids from E' buffer s & 1
+// into aperture buffer s & 1 (grid rows 32 (s & 1) .. 32 (s & 1) + 31 of each
+// polarisation) and transforms its rows; sample s + 1 is staged into the
+// other E' buffer while sample s's gridding program loads.  After the
+// barrier the column transforms of sample s run inside buffer s & 1 while
+// faster waves grid sample s + 1 into the other.  A buffer is written again
+// two samples after it was last read, behind the next barrier, by which
+// every wave has finished with it.  The loop is unrolled by two so that the
+// buffers' offsets are immediates.
+template <int N, int P, int GPT>
+__device__ __forceinline__ void fused_image_body_pipe(const FusedArgs& a) {
+  static_assert(N == 64 && P == 2 && GPT == 1, "the double-buffered form: N = 64, P = 2, GPT = 1");
+  constexpr bool CPX = false;
+  using SH = FusedShape<N>;
+  constexpr int S = SH::S, NT = SH::NT, RS = SH::RS, NACC = 4;
+  constexpr int ES = EStride<NT, GPT, P>::value;
+  constexpr int EB = P * ES;                   // one E' buffer (float2)
+  constexpr int HB = (N / 2) * RS;             // the second aperture buffer, 32 rows down
+  __shared__ __attribute__((aligned(16))) float2 lds2[2 * EB + (P - 1) * SH::PSTRIDE + N * RS];
+  float2* X = lds2 + 2 * EB;
+
+  const Roles<N> r(threadIdx.x);
+  const int tid = r.tid;
+  const int wl = wg_range_index((int)blockIdx.x, (int)gridDim.x, a.xcd);
+  const int m = a.team, tm = wl / m, mk = wl - tm * m, n_team = a.W / m;
+  UnitWalk w;                                  // the unit being imaged
+  w.T = a.n_time;
+  w.ra = range_begin(tm, a.total, n_team);
+  w.rb = range_begin(tm + 1, a.total, n_team);
+  w.m = m;
+  w.k = mk;
+  if (tm >= n_team || !w.seek(w.ra / a.n_time)) return;
+  int64_t left = member_units(a.n_time, w.ra, w.rb, m, mk);
+
+  float2 tw[S];
+#pragma unroll
+  for (int k0 = 0; k0 < S; ++k0) tw[k0] = a.twiddle[(r.n0 * k0) % N];
+
+  const int PA = P * a.blk[0].n_ant, L = a.blk[0].L, KB = a.kblock, c0 = a.blk[0].c0;
+  const int64_t n_row = (int64_t)a.blk[0].n_chan * PA;
+  int eidx[GPT];
+  init_stage<NT, GPT, ES>(lds2 + EB, eidx, tid, a.blk[0].n_ant, P);
+  init_stage<NT, GPT, ES>(lds2, eidx, tid, a.blk[0].n_ant, P);
+
+  auto load_bytes = [&](int ch, int64_t t, uint32_t (&dst)[GPT]) {
+    const uint8_t* src = a.blk[0].efield + t * n_row + (int64_t)(ch - c0) * PA;
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = tid + i * NT;
+      dst[i] = (k < PA) ? (uint32_t)src[k] : 0u;
+    }
+  };
+  auto load_gains = [&](int ch, float2 (&dst)[GPT]) {
+    int t = tid;                               // opaque: the address is not held across the loop
+    asm volatile("" : "+v"(t));
+#pragma unroll
+    for (int i = 0; i < GPT; ++i) {
+      const int k = t + i * NT;
+      dst[i] = (k < PA) ? a.blk[0].gains[(int64_t)(ch - c0) * PA + k] : make_float2(0.f, 0.f);
+    }
+  };
+
+  float acc[S][NACC];
+  int c = -1, nblk = 0, nflush = 0, line = -1, Lw = L;
+  int64_t part_len = 0, slot = 0;
+  const uint2* prog = nullptr;
+  const float* wim = nullptr;
+  auto flush = [&]() {
+    double* out = a.partial + slot * (NACC * S * NT) + tid;
+    if (part_len <= KB) {
+      float* o32 = reinterpret_cast<float*>(a.partial + slot * (NACC * S * NT)) + tid;
+#pragma unroll
+      for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          o32[(u * S + i) * NT] = acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    } else {
+#pragma unroll
+      for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+          double* o = out + (u * S + i) * NT;
+          *o = (nflush ? *o : 0.0) + (double)acc[i][u];
+          acc[i][u] = 0.f;
+        }
+    }
+    ++nflush;
+    nblk = 0;
+  };
+
+  // the first unit: staged into E' buffer 0 before the loop
+  float2 g[GPT];
+  uint32_t nxt[GPT];
+  int gch = (int)w.s;                          // channel of the gains in g
+  load_gains(gch, g);
+  load_bytes(gch, w.t, nxt);
+  stage_samples<NT, GPT, ES, P, true>(lds2, nxt, g, eidx, tid, PA);
+  if (left > 1) {
+    UnitWalk wn = w;
+    wn.next();
+    load_bytes((int)wn.s, wn.t, nxt);
+  }
+  __syncthreads();
+
+  auto step = [&](auto bc) -> bool {
+    constexpr int BUF = decltype(bc)::value;
+    float2* Eb = lds2 + BUF * EB;              // E' of this unit
+    float2* Xb = X + BUF * HB;                 // its aperture rows
+    const int cc = (int)w.s;
+    if (cc != c) {                             // a part (accumulation segment) starts
+      if (c >= 0) flush();
+      c = cc;
+      nflush = 0;
+      part_len = w.left;
+      slot = ((int64_t)c + tm) * m + mk;
+      const int64_t cl = c - c0;
+      prog = a.blk[0].prog + cl * (L + 1) * NT;
+      if (CPX) wim = a.blk[0].wim + cl * (L + 1) * NT + NT;
+      line = (int)prog[tid].x;
+      Lw = header_steps(prog[tid].y, L);
+      prog += NT;
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int u = 0; u < NACC; ++u) acc[i][u] = 0.f;
+    } else if (nblk == KB) {
+      flush();
+    }
+    const bool more = left > 1;                // the next unit: staged into the other buffer
+    UnitWalk wn = w;
+    if (more) {
+      wn.next();
+      if ((int)wn.s != gch) {
+        gch = (int)wn.s;
+        load_gains(gch, g);
+      }
+    }
+    stage_and_grid<N, P, NT, RS, ES, GPT, CPX, true, true>(reinterpret_cast<const char*>(Eb),
+                                                           reinterpret_cast<char*>(Xb),
+                                                           lds2 + (1 - BUF) * EB, prog, wim, Lw,
+                                                           nxt, g, eidx, tid, PA, more);
+    row_pass<N, P, +1, false>(Xb, r, tw, line);
+    if (more) {
+      if (left > 2) {                          // prefetch the unit after it
+        UnitWalk wnn = wn;
+        wnn.next();
+        load_bytes((int)wnn.s, wnn.t, nxt);
+      }
+      w = wn;
+    }
+    __syncthreads();
+    float2 v[P][S];
+    column_pass_buf<N>(v, Xb, r, tw);
+
+    // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      const float2 fx = v[0][i], fy = v[1][i];
+      acc[i][0] = fmaf(fx.y, fx.y, fmaf(fx.x, fx.x, acc[i][0]));
+      acc[i][1] = fmaf(fy.y, fy.y, fmaf(fy.x, fy.x, acc[i][1]));
+      acc[i][2] = fmaf(fx.y, fy.y, fmaf(fx.x, fy.x, acc[i][2]));
+      acc[i][3] = fmaf(-fx.x, fy.y, fmaf(fx.y, fy.x, acc[i][3]));
+    }
+    ++nblk;
+    return --left > 0;
+  };
+  while (step(IntC<0>{}) && step(IntC<1>{})) {
+  }
+  flush();
+}
+
 template <int N, int P, int GPT, bool CPX>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_image_kernel(FusedArgs a) {
-  fused_image_body<N, P, GPT, CPX, false, false>(a);
+  if constexpr (N == 64 && P == 2 && GPT == 1 && !CPX) fused_image_body_pipe<N, P, GPT>(a);
+  else fused_image_body<N, P, GPT, CPX, false, false>(a);
 }
 
 // Apertures wider than N/2 cells (up to 3N/4) at N = 64.
