@@ -542,7 +542,9 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
   }
 }
 
-// The whole per-workgroup loop.  WIDE (N = 64): the wide block of up to HW
+// The whole per-workgroup loop, two workgroup barriers per sample (the
+// N = 64 dual-polarisation form with at most 256 antennas and Gaussian taps
+// runs fused_image_body_pipe instead).  WIDE (N = 64): the wide block of up to HW
 // columns and wrows (32, 40 or 48) rows; the programs' header gives each
 // thread a second row-pass line (header_line2, -1: none; whole waves have
 // none, so they skip the pass); the row passes take their lines' inputs
