@@ -145,6 +145,29 @@ template <int SG> __device__ __forceinline__ void dft8_six(float2* x) {
   x[3] = cadd(e3, t3); x[7] = csub(e3, t3);
 }
 
+// 8-point DFT whose inputs x[5], x[6], x[7] are zero (they are not read):
+// dft8_six with the odd half's first butterfly (x[1], x[5]) reduced to x[1].
+template <int SG> __device__ __forceinline__ void dft8_five(float2* x) {
+  const float2 te = cadd(x[0], x[4]), ue = csub(x[0], x[4]), ie = mul_i<SG>(x[2]);
+  const float2 io = mul_i<SG>(x[3]);
+  const float2 e0 = cadd(te, x[2]), e1 = cadd(ue, ie), e2 = csub(te, x[2]), e3 = csub(ue, ie);
+  const float2 o0 = cadd(x[1], x[3]), o1 = cadd(x[1], io), o2 = csub(x[1], x[3]), o3 = csub(x[1], io);
+  const float r = 0.70710678118654752440f;
+  float2 t1, t3;
+  if (SG > 0) {
+    t1 = make_float2((o1.x - o1.y) * r, (o1.x + o1.y) * r);
+    t3 = make_float2((-o3.x - o3.y) * r, (o3.x - o3.y) * r);
+  } else {
+    t1 = make_float2((o1.x + o1.y) * r, (o1.y - o1.x) * r);
+    t3 = make_float2((o3.y - o3.x) * r, (-o3.x - o3.y) * r);
+  }
+  const float2 t2 = mul_i<SG>(o2);
+  x[0] = cadd(e0, o0); x[4] = csub(e0, o0);
+  x[1] = cadd(e1, t1); x[5] = csub(e1, t1);
+  x[2] = cadd(e2, t2); x[6] = csub(e2, t2);
+  x[3] = cadd(e3, t3); x[7] = csub(e3, t3);
+}
+
 // 16-point DFT whose inputs x[8..15] are zero (they are not read): the 4 x 4
 // form of dft16 with a first stage of two-input 4-point DFTs.
 template <int SG> __device__ __forceinline__ void dft16_half(float2* x) {
@@ -214,18 +237,20 @@ template <> struct Line<128> { static constexpr int S = 16, R = 8, D = 2; };
 // of lane n0 goes to slot k0 R + (n0 + SKEW k0) mod R, a skew chosen per
 // access pattern so that the lanes of the exchange hit different LDS banks.
 // NZ > 0: only the inputs n1 < NZ are nonzero (the others are not read);
-// taken for NZ = S/2 (radix 8 and 16) and NZ = 6 (radix 8).  NZ = 0: all.
+// taken for NZ = S/2 (radix 8 and 16) and NZ = 5, 6 (radix 8).  NZ = 0: all.
 template <int N, int SG, int NP, int NZ = 0, int SKEW = 1, typename SlotF>
 __device__ __forceinline__ void line_transform(float2 (&v)[NP][Line<N>::S], const float2* tw,
                                                int n0, float2* lds, SlotF slot) {
   constexpr int S = Line<N>::S, R = Line<N>::R, D = Line<N>::D;
-  static_assert(NZ == 0 || NZ == S || (NZ == S / 2 && (S == 8 || S == 16)) || (NZ == 6 && S == 8),
-                "zero-input forms implemented: half of radix 8 and 16, six of radix 8");
+  static_assert(NZ == 0 || NZ == S || (NZ == S / 2 && (S == 8 || S == 16)) ||
+                    ((NZ == 5 || NZ == 6) && S == 8),
+                "zero-input forms implemented: half of radix 8 and 16, five and six of radix 8");
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     if constexpr (NZ == S / 2 && S == 8) dft8_half<SG>(v[p]);
     else if constexpr (NZ == S / 2) dft16_half<SG>(v[p]);
     else if constexpr (NZ == 6) dft8_six<SG>(v[p]);
+    else if constexpr (NZ == 5) dft8_five<SG>(v[p]);
     else dft<S, SG>(v[p]);
 #pragma unroll
     for (int k0 = 1; k0 < S; ++k0) v[p][k0] = twiddle_mul<SG>(v[p][k0], tw[k0]);

@@ -819,6 +819,10 @@ bool launch_fused(epic_ctx* x, const epic::FusedArgs& a) {
   const dim3 grid(a.W), block(fused_threads(N));
   if (x->wide) {
     if (N != 64) return false;
+    if (P == 2 && G == 1 && !x->cpx && x->wide_rows == 40) {   // the deployed array's block
+      hipLaunchKernelGGL((epic::fused_wide_image_kernel<64, 2, 1, false, 40>), grid, block, 0, x->stream, a);
+      return true;
+    }
 #define EPIC_LW(PP, GG)                                                                      \
     if (P == PP && G == GG) {                                                                \
       if (x->cpx) hipLaunchKernelGGL((epic::fused_wide_image_kernel<64, PP, GG, true>), grid, block, 0, \

@@ -522,12 +522,16 @@ __device__ __forceinline__ void row_pass(float2* X, const Roles<N>& r, const flo
 // column belongs to the lanes of one wave, which finish each polarisation's
 // transform before the next one writes), leaving the rows >= H of the
 // others untouched.
-template <int N, int P, bool WIDE = false, bool XSHARE = false>
+// WR > 0 (WIDE): the block's row count is WR, fixed at compile time: only
+// the WR / R inputs that can be nonzero are read and transformed.
+template <int N, int P, bool WIDE = false, bool XSHARE = false, int WR = 0>
 __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], float2* X,
                                                 const Roles<N>& r, const float2* tw, int rows = 0) {
   using SH = FusedShape<N>;
   constexpr int S = Line<N>::S, R = Line<N>::R, RS = SH::RS, PS = SH::PSTRIDE;
-  constexpr int NIN = WIDE ? SH::HW / R : S / 2;
+  static_assert(WR == 0 || (WIDE && WR % R == 0 && WR >= SH::H && WR <= SH::HW), "wide block rows");
+  constexpr int NIN = WR > 0 ? WR / R : WIDE ? SH::HW / R : S / 2;
+  if constexpr (WR > 0) rows = WR;
   const int kl = r.kl;
 #pragma unroll
   for (int p = 0; p < P; ++p) {                 // one polarisation at a time
@@ -553,7 +557,7 @@ __device__ __forceinline__ void column_pass_fwd(float2 (&v)[P][Line<N>::S], floa
 // range crosses into the next block switches inputs, gains, programs and the
 // E' layout of its antenna count at that channel boundary.  Without MULTI
 // the launch has one block.
-template <int N, int P, int GPT, bool CPX, bool WIDE, bool MULTI>
+template <int N, int P, int GPT, bool CPX, bool WIDE, bool MULTI, int WR = 0>
 __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
   using SH = FusedShape<N>;
   constexpr int S = SH::S, NT = SH::NT, RS = SH::RS;
@@ -709,7 +713,7 @@ __device__ __forceinline__ void fused_image_body(const FusedArgs& a) {
     if (WIDE) row_pass<N, P, +1, WIDE>(X, r, tw, line2);
     __syncthreads();
     float2 v[P][S];
-    column_pass_fwd<N, P, WIDE, EINGRID>(v, X, r, tw, wrows);
+    column_pass_fwd<N, P, WIDE, EINGRID, WR>(v, X, r, tw, wrows);
 
     // 4. polarisation products: XX, YY, Re XY, Im XY (XY = F_X conj(F_Y))
 #pragma unroll
@@ -940,13 +944,15 @@ fused_image_kernel(FusedArgs a) {
   else fused_image_body<N, P, GPT, CPX, false, false>(a);
 }
 
-// Apertures wider than N/2 cells (up to 3N/4) at N = 64.
-template <int N, int P, int GPT, bool CPX>
+// Apertures wider than N/2 cells (up to 3N/4) at N = 64.  WR > 0: a wide
+// block of exactly WR rows (the host launches WR = 40, the deployed array's
+// block, with its row count fixed at compile time).
+template <int N, int P, int GPT, bool CPX, int WR = 0>
 __global__ void __launch_bounds__(FusedShape<N>::NT)
 __attribute__((amdgpu_waves_per_eu(FusedShape<N>::MIN_WAVES_PER_EU)))
 fused_wide_image_kernel(FusedArgs a) {
   static_assert(N == 64, "the wide variant is built for N = 64");
-  fused_image_body<N, P, GPT, CPX, true, false>(a);
+  fused_image_body<N, P, GPT, CPX, true, false, WR>(a);
 }
 
 // The heterogeneous batch: one launch over the channels of several blocks
