@@ -229,6 +229,35 @@ def test_fewer_samples_than_workgroups():
     assert oracle.rel_errors(got, oracle.image_from(inp)).max() <= TOL_FP32
 
 
+@pytest.mark.parametrize("seed,C,T", [
+    (821, 5, 1),      # one unit per workgroup: nothing staged ahead
+    (822, 3, 2),      # two units: staged ahead, nothing prefetched
+    (823, 600, 1),    # more channels than workgroups: the next unit's gains reloaded
+    (824, 300, 3),    # parts crossing channels inside a workgroup's range
+    (825, 2, 257),    # parts longer than the float32 block: float64 flushes
+])
+def test_one_barrier_form_edges(seed, C, T):
+    """The double-buffered one-barrier form (N = 64, two polarisations, at most
+    256 antennas, Gaussian taps) at its edges: workgroups with one or two
+    units, units whose successor is in another channel, and parts longer than
+    the float32 block.  The image matches the oracle, and a second call with
+    reset = 0 adds the same samples again."""
+    import torch
+    inp = synth.random_problem(seed, 64, 200, C, 2, T, fill=0.45)
+    im = _imager(inp)
+    ef, g = _dev(inp)
+    got = im.accumulate(ef, g)
+    torch.cuda.synchronize()
+    assert im.last_kernel_name() == "fused_image_kernel"
+    ref = oracle.image_from(inp)
+    err = oracle.rel_errors(got.cpu().numpy(), ref)
+    print(f"  max rel err {err.max():.3e}", flush=True)
+    assert err.max() <= TOL_FP32, f"{err.max():.3e}"
+    im.accumulate(ef, g, image=got, reset=False)
+    torch.cuda.synchronize()
+    assert oracle.rel_errors(got.cpu().numpy(), 2.0 * ref).max() <= TOL_FP32
+
+
 def test_fused_and_staged_agree():
     inp = synth.random_problem(114, 64, 256, 3, 2, 20)
     a, _ = _run(inp, staged=False)
