@@ -234,7 +234,8 @@ def test_fewer_samples_than_workgroups():
     (822, 3, 2),      # two units: staged ahead, nothing prefetched
     (823, 600, 1),    # more channels than workgroups: the next unit's gains reloaded
     (824, 300, 3),    # parts crossing channels inside a workgroup's range
-    (825, 2, 257),    # parts longer than the float32 block: float64 flushes
+    (825, 2, 257),    # ragged parts of 64-65 samples (teams of 4)
+    (826, 1, 1100),   # parts of 137-138 samples (teams of 8): float64 flushes
 ])
 def test_one_barrier_form_edges(seed, C, T):
     """The double-buffered one-barrier form (N = 64, two polarisations, at most
